@@ -1,0 +1,246 @@
+"""Benchmark of the HSS-ULV factorization + solve on one MI355X.
+
+Workload (default): N = 262144 points uniform in the unit cube, Matern nu=3/2
+kernel with length 0.2 plus 1e-6 on the diagonal, leaf 256 (10 levels), rank
+96, one N(0,1) right-hand side; the HSS matrix is built on the GPU (scaled
+randomized compression, untimed). A step is one factorization + one solve
+(plus the refinement corrections and their FP64 matvecs for the mixed form).
+
+Prints ONE JSON line. `value` is seconds per factor+solve (lower is better).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+MFMA_FP64_PEAK_TFLOPS = 78.6
+HBM_PEAK_GBS = 8000.0
+
+
+
+
+def step_flops(step, n, r):
+    """Algorithmic flops of one node for the profiled step classes."""
+    m = n - r
+    if step == "gemm_W=MV":
+        return 2.0 * n * n * r
+    if step == "gemm_two_sided_update":
+        return 4.0 * n * n * r
+    if step == "gemm_small_wy":
+        return 6.0 * n * r * r + 4.0 * r ** 3
+    if step == "partial_cholesky":
+        return m ** 3 / 3.0 + r * m * m + r * r * m
+    if step == "basis_qr":
+        return 2.0 * n * r * r - 2.0 / 3.0 * r ** 3
+    return 0.0
+
+
+def step_bytes(step, n, r):
+    """Algorithmic HBM bytes of one node (each operand read once, result written once)."""
+    m = n - r
+    if step == "gemm_W=MV":
+        return 8.0 * (n * n + 2 * n * r)
+    if step == "gemm_two_sided_update":
+        return 8.0 * (2 * n * n + 4 * n * r)
+    if step in ("solve_forward", "solve_backward"):
+        return 8.0 * (n * r + r * r + m * (m + 1) / 2 + r * m + 2 * n)
+    if step == "partial_cholesky":
+        return 8.0 * 2 * n * n
+    return 0.0
+
+
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="matern32_n262144")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-level", type=int, default=3,
+                    help="oracle timed on the subtree under one node of this level")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2311_00921_amd import hss
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    w = synth.WORKLOADS[args.workload]
+    s = (w.rank if w.rank > 0 else 128) + w.oversample
+    X = torch.from_numpy(w.points()).cuda()
+    Om = torch.from_numpy(np.ascontiguousarray(w.omega(s).T)).cuda().t()
+    b = torch.from_numpy(np.ascontiguousarray(w.rhs()[:, 0])).cuda()
+    ctx = hss.hss_ctx_create(0)
+    print(f"# building HSS: N={w.n} leaf={w.leaf} rank={w.rank} s={s}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    m = hss.hss_construct(ctx, X, w.kernel, w.leaf, rank=w.rank, tol=w.tol, omega=Om, length=w.length,
+                          nugget=w.nugget)
+    torch.cuda.synchronize()
+    construct_s = time.perf_counter() - t0
+    del Om
+    print(f"# construct {construct_s:.2f} s", file=sys.stderr, flush=True)
+
+    exp = hss.hss_export(ctx, m)
+    L = exp["levels"]
+    leaf_lo = exp["leaf_lo"]
+    rank = exp["rank"]
+    nodes = []  # (heap index, level, n, r)
+    for k in range(2 ** (L + 1) - 1):
+        l = int(math.floor(math.log2(k + 1)))
+        if l == L:
+            i = k - (2 ** L - 1)
+            n = int(leaf_lo[i + 1] - leaf_lo[i])
+        else:
+            n = int(rank[2 * k + 1] + rank[2 * k + 2])
+        nodes.append((k, l, n, int(rank[k]) if k > 0 else 0))
+
+    def run_fp64(steps, profile=False):
+        if profile:
+            hss.hss_profile_enable(ctx, True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        x = None
+        for _ in range(steps):
+            hss.hss_ulv_factor(ctx, m, hss.HSS_P_FP64)
+            x = hss.hss_ulv_solve(ctx, m, b)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t) / steps
+        prof = hss.hss_profile_read(ctx) if profile else None
+        if profile:
+            hss.hss_profile_enable(ctx, False)
+        return dt, x, prof
+
+    for _ in range(args.warmup):
+        run_fp64(1)
+    print("# timing FP64 factor+solve", file=sys.stderr, flush=True)
+    t_fp64, x, _ = run_fp64(args.steps)
+    # relative residual with the FP64 HSS matvec
+    r = b - hss.hss_matvec(ctx, m, x)
+    relres = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+    logdet = hss.hss_logdet(ctx, m)
+    info = hss.hss_get_info(m)
+    # per-launch events over a second timed region: the dominant kernel's average duration
+    t_prof, _, prof = run_fp64(args.steps, profile=True)
+    by_step = {}
+    for (step, lvl), (cnt, ms) in prof.items():
+        by_step.setdefault(step, 0.0)
+        by_step[step] += ms
+    dom_key = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    dom_step, dom_level = dom_key
+    cnt, ms_total = prof[dom_key]
+    avg_ms = ms_total / cnt
+    lvl_nodes = [nd for nd in nodes if nd[1] == dom_level]
+    flops = sum(step_flops(dom_step, n, rr) for _, _, n, rr in lvl_nodes)
+    byts = sum(step_bytes(dom_step, n, rr) for _, _, n, rr in lvl_nodes)
+    if dom_step.startswith("gemm") or dom_step in ("partial_cholesky", "basis_qr"):
+        ach = flops / (avg_ms * 1e-3) / 1e12
+        roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": MFMA_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": round(ach / MFMA_FP64_PEAK_TFLOPS, 4), "traffic": None}
+    else:
+        ach = byts / (avg_ms * 1e-3) / 1e9
+        roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    roof.update({"kernel": f"{dom_step}@level{dom_level}", "avg_launch_ms": round(avg_ms, 4),
+                 "algorithmic_per_launch": flops if roof["unit"] == "TFLOP/s" else byts})
+    total_factor_flops = sum(step_flops(sname, n, rr) for _, l, n, rr in nodes if l > 0
+                             for sname in ("gemm_W=MV", "gemm_two_sided_update", "gemm_small_wy",
+                                           "partial_cholesky", "basis_qr"))
+
+    result = {
+        "metric": "HSS-ULV factor+solve s at N=262144; mixed+IR vs FP64 at rel. residual 1e-8",
+        "value": round(t_fp64, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_fp64 * 1e3, 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "N": w.n, "dim": w.dim, "kernel": w.kernel, "length": w.length,
+                   "nugget": w.nugget, "leaf": w.leaf, "levels": L, "rank": w.rank, "nrhs": 1,
+                   "compression": "scaled randomized", "samples": s, "precision": "fp64"},
+        "roofline": roof,
+        "fp64": {"factor_plus_solve_s": round(t_fp64, 6), "relres": relres, "logdet": logdet,
+                 "factor_ms_events": round(info.factor_ms, 3), "algorithmic_factor_gflop": round(total_factor_flops / 1e9, 2),
+                 "factor_gflops_per_s": round(total_factor_flops / 1e9 / (info.factor_ms * 1e-3), 1),
+                 "profiled_step_s": round(t_prof, 6),
+                 "ms_by_step": {k: round(v / args.steps, 3) for k, v in sorted(by_step.items(), key=lambda kv: -kv[1])}},
+        "construct_s": round(construct_s, 3),
+    }
+
+    if not args.no_cpu_baseline:
+        result["cpu_baseline"] = cpu_baseline(exp, nodes, args.cpu_sample_level, w)
+    hss.hss_matrix_destroy(m)
+    hss.hss_ctx_destroy(ctx)
+    print(json.dumps(result))
+
+
+def cpu_baseline(exp, nodes, level, w):
+    """Times the oracle's factor + solve on the subtree below node 0 of `level`
+    of the same HSS matrix and scales it by N / N_sub (the method is linear in N
+    at fixed leaf size and rank)."""
+    import numpy as np
+
+    from oracle import hss_oracle as O
+    from paper_2311_00921_amd import hss
+
+    full = hss.unpack_desc(exp)
+    L = full["levels"]
+    level = max(0, min(level, L))
+    sub_L = L - level
+    nleaf = 2 ** sub_L
+    lo0 = full["ranges"][L][0][0]
+    ranges = []
+    for l in range(sub_L + 1):
+        gl = level + l
+        ranges.append([(full["ranges"][gl][i][0] - lo0, full["ranges"][gl][i][1] - lo0) for i in range(2 ** l)])
+    n_sub = ranges[0][0][1]
+    rank = [[] for _ in range(sub_L + 1)]
+    E = [[] for _ in range(max(sub_L, 1))]
+    S = [[] for _ in range(max(sub_L, 1))]
+    for l in range(1, sub_L + 1):
+        rank[l] = full["rank"][level + l][: 2 ** l]
+    for l in range(1, sub_L):
+        E[l] = full["E"][level + l][: 2 ** l]
+    for l in range(sub_L):
+        S[l] = full["S"][level + l][: 2 ** l]
+    h = O.HSS(n_sub, sub_L, ranges, rank, full["D"][:nleaf], full["U"][:nleaf], E, S)
+    rng = np.random.default_rng(2000 + w.seed_k)
+    bsub = rng.standard_normal(n_sub)
+    try:
+        from threadpoolctl import threadpool_info
+
+        cores = max([t.get("num_threads", 1) for t in threadpool_info()] + [1])
+    except Exception:
+        cores = os.cpu_count()
+    t = time.perf_counter()
+    F = O.ulv_factor(h)
+    x = O.ulv_solve(h, F, bsub)
+    dt = time.perf_counter() - t
+    scale = w.n / n_sub
+    return {"value": round(dt * scale, 3), "unit": "s", "cores": int(cores), "kind": "oracle",
+            "sample": f"oracle ULV factor+solve of the subtree under one level-{level} node (N_sub={n_sub}, "
+                      f"{nleaf} leaves) of the same HSS matrix took {dt:.2f} s; scaled by N/N_sub={scale:g}"}
+
+
+if __name__ == "__main__":
+    main()

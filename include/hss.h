@@ -1,0 +1,250 @@
+/*
+ * hss.h - C ABI of the MI355X HSS-ULV library (libhss.so).
+ *
+ * The library builds a Hierarchically Semi-Separable (HSS) approximation of an
+ * SPD kernel matrix on a point set, factors it with the HSS-ULV algorithm and
+ * solves with the ULV forward/backward sweeps (Deshmukh, Ma, Yokota, Bosilca,
+ * "O(N) distributed direct factorization of structured dense matrices using
+ * runtime systems", ICPP 2023: Sec. 2 construction and notation, Sec. 3.2
+ * Alg. 2 factorization and Eq. 17 solve).
+ *
+ * Conventions
+ *  - Every matrix is column-major FP64 unless stated. Leading dimensions are
+ *    in elements.
+ *  - Device pointers are HIP device memory owned by the caller; the library
+ *    never frees or retains them beyond the call. Host pointers are read
+ *    during the call only.
+ *  - Work is enqueued on the context's HIP stream. Calls that return host
+ *    values (status of a factorization, log-determinant, ranks during
+ *    construction, refinement statistics) synchronize that stream.
+ *  - Vectors passed to solve/matvec are in the caller's point order; the
+ *    library gathers and scatters through the tree permutation.
+ *  - No C++ exception crosses this boundary. Each call returns an hss_status;
+ *    hss_last_error() gives a thread-local message for the last failure.
+ *  - One context per host thread. Calls that overlap on one matrix race.
+ */
+#ifndef HSS_H_
+#define HSS_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hss_ctx_s* hss_ctx_t;
+typedef struct hss_matrix_s* hss_matrix_t;
+
+typedef enum {
+  HSS_OK = 0,
+  HSS_ERR_INVALID_ARGUMENT = 1,
+  HSS_ERR_NOT_SPD = 2,        /* a pivot block was not positive definite */
+  HSS_ERR_OUT_OF_MEMORY = 3,
+  HSS_ERR_DEVICE = 4,         /* a HIP runtime call failed */
+  HSS_ERR_BAD_STATE = 5,      /* e.g. solve before factor */
+  HSS_ERR_NOT_CONVERGED = 6,  /* iterative refinement did not reach its tolerance */
+  HSS_ERR_UNSUPPORTED = 7
+} hss_status;
+
+/* Kernel families: the covariance kernels of the workloads and the Green's
+ * functions of Table 3 (Laplace 2D, Yukawa; the paper's Matern with nu = 1/2
+ * is HSS_K_EXPONENTIAL with length = mu). A_ij = f(|x_i - x_j|) + nugget*delta_ij. */
+typedef enum {
+  HSS_K_EXPONENTIAL = 0, /* sigma2 * exp(-d/length) */
+  HSS_K_MATERN32 = 1,    /* sigma2 * (1 + sqrt3 d/length) exp(-sqrt3 d/length) */
+  HSS_K_GAUSSIAN = 2,    /* sigma2 * exp(-d^2/length^2) */
+  HSS_K_LAPLACE2D = 3,   /* -ln(eps + d) */
+  HSS_K_YUKAWA = 4       /* exp(-alpha (eps + d)) / (eps + d) */
+} hss_kernel_kind;
+
+typedef struct {
+  int32_t kind;     /* hss_kernel_kind */
+  double length;    /* > 0 for the covariance kernels */
+  double sigma2;    /* variance scale of the covariance kernels (usually 1) */
+  double nugget;    /* >= 0, added on the diagonal only */
+  double alpha;     /* Yukawa decay (Table 3: 1) */
+  double eps;       /* Laplace/Yukawa regulariser (Table 3: 1e-9) */
+} hss_kernel;
+
+/* Construction modes. SCALED compresses each node's off-diagonal row block
+ * after scaling by the inverse Cholesky factor of its diagonal block, which
+ * keeps the HSS matrix SPD for any truncation; the output is in the paper's
+ * format (orthonormal nested bases U/E and couplings S, Sec. 2 Eq. 6). */
+typedef enum { HSS_COMPRESS_SCALED = 1 } hss_compress_mode;
+
+typedef struct {
+  int32_t leaf_size;   /* >= 2: maximum points per leaf */
+  int32_t levels;      /* 0 = derive ceil(log2(N/leaf_size)); otherwise must equal it */
+  int32_t rank;        /* > 0 fixed rank per node; 0 = adaptive by tol */
+  int32_t max_rank;    /* cap for adaptive ranks (0 = none) */
+  double tol;          /* adaptive truncation: keep pivots with |R_jj| > tol*|R_00| */
+  int32_t mode;        /* hss_compress_mode */
+} hss_construct_opts;
+
+typedef enum {
+  HSS_P_FP64 = 0, /* every step in FP64 */
+  HSS_P_FP32 = 1  /* basis transforms, TRSM and Schur GEMMs in FP32; pivots and root FP64 */
+} hss_precision;
+
+typedef struct {
+  int32_t precision;   /* hss_precision */
+} hss_factor_opts;
+
+/* Host description of an HSS matrix, used by hss_import and hss_export.
+ * Nodes are numbered in heap order: node 0 is the root, node k has children
+ * 2k+1 and 2k+2; the leaves are nodes 2^L - 1 .. 2^(L+1) - 2 (L = levels).
+ *  leaf_lo: 2^L + 1 entries; leaf i owns tree positions [leaf_lo[i], leaf_lo[i+1]).
+ *  rank:    2^(L+1) - 1 entries, basis columns of each node (rank[0] ignored).
+ *  D:       leaf diagonal blocks n_i x n_i, packed leaf after leaf.
+ *  U:       leaf bases n_i x rank_i, packed leaf after leaf.
+ *  E:       transfer matrices of nodes 1 .. 2^L - 2 (levels 1..L-1) in heap order,
+ *           (rank[2k+1] + rank[2k+2]) x rank[k] each, packed.
+ *  S:       couplings of the children of nodes 0 .. 2^L - 2 in heap order,
+ *           rank[2k+1] x rank[2k+2] each, packed.
+ *  perm:    N entries, tree position -> caller's point index (NULL = identity).
+ * For L = 0 the matrix is the single block D (N x N). */
+typedef struct {
+  int64_t n;
+  int32_t levels;
+  const int64_t* leaf_lo;
+  const int32_t* rank;
+  const double* D;
+  const double* U;
+  const double* E;
+  const double* S;
+  const int64_t* perm;
+} hss_desc;
+
+/* Output view for hss_export: the caller provides buffers of at least the
+ * sizes that hss_export_sizes reports. */
+typedef struct {
+  int64_t* leaf_lo;
+  int32_t* rank;
+  double* D;
+  double* U;
+  double* E;
+  double* S;
+  int64_t* perm;
+} hss_desc_out;
+
+typedef struct {
+  int64_t n;
+  int32_t levels;
+  int32_t factored;          /* 1 after a successful hss_ulv_factor */
+  int32_t precision;         /* precision of the last factorization */
+  int32_t max_rank;          /* largest basis rank */
+  int32_t failed_level;      /* on HSS_ERR_NOT_SPD: level of the failing node, else -1 */
+  int32_t failed_node;       /* heap index of the failing node, else -1 */
+  int32_t failed_pivot;      /* local pivot index that failed, else -1 */
+  int64_t bytes_representation;
+  int64_t bytes_factor;
+  double factor_ms;          /* device time of the last factorization (HIP events) */
+  double solve_ms;           /* device time of the last solve */
+} hss_info;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Creates a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t; NULL = the default stream). */
+hss_status hss_ctx_create(int32_t device, void* hip_stream, hss_ctx_t* out);
+hss_status hss_ctx_destroy(hss_ctx_t ctx);
+/* Replaces the stream work is enqueued on. */
+hss_status hss_ctx_set_stream(hss_ctx_t ctx, void* hip_stream);
+
+/* ---- construction (Sec. 2) ----------------------------------------------- */
+
+/* Builds the HSS approximation of the kernel matrix on the points.
+ *  d_points: N x dim, row-major (point-major), device memory, caller's order.
+ *  d_omega:  N x s Gaussian test matrix, column-major with ld = N, rows in the
+ *            caller's point order, device memory; s >= rank (fixed rank) or
+ *            s >= the largest rank to be found (adaptive).
+ * Steps: recursive coordinate bisection (longest box side, ties -> lowest
+ * axis, order by (coordinate, index), left child = ceil(size/2)); leaf blocks
+ * by kernel evaluation; scaled randomized compression level by level with
+ * column-pivoted QR truncation (Eq. 2). Synchronizes once per level when
+ * ranks are adaptive. Errors: INVALID_ARGUMENT for bad sizes or options,
+ * NOT_SPD if a diagonal block is not positive definite. */
+hss_status hss_construct(hss_ctx_t ctx, const double* d_points, int64_t n, int32_t dim,
+                         const hss_kernel* kernel, const hss_construct_opts* opts,
+                         const double* d_omega, int32_t s, hss_matrix_t* out);
+
+/* Uploads a host HSS description (see hss_desc). Copies everything. */
+hss_status hss_import(hss_ctx_t ctx, const hss_desc* desc, hss_matrix_t* out);
+
+/* Sizes (in elements) of the arrays hss_export writes: leaf_lo, rank, D, U, E, S, perm. */
+hss_status hss_export_sizes(hss_matrix_t m, int64_t sizes[7]);
+/* Copies the representation to host buffers. Synchronizes. */
+hss_status hss_export(hss_ctx_t ctx, hss_matrix_t m, hss_desc_out* out);
+
+/* ---- factorization and solve (Sec. 3.2) --------------------------------- */
+
+/* HSS-ULV factorization (Alg. 2): per level from the leaves, the full-basis
+ * QR [U^R U^S] of each node's basis, the diagonal product Q^T A Q (Eq. 7),
+ * the partial Cholesky of the redundant rows (Eq. 10-12), the merge of sibling
+ * Schur complements with their coupling into the parent block; then the
+ * Cholesky of the root block. D/U/E/S are not modified. opts may be NULL (FP64).
+ * Synchronizes to read the pivot status. Errors: NOT_SPD with the failing
+ * (level, node, pivot) in hss_info. */
+hss_status hss_ulv_factor(hss_ctx_t ctx, hss_matrix_t m, const hss_factor_opts* opts);
+
+/* ULV solve (Eq. 17): x = A^{-1} b for nrhs columns. d_b, d_x: N x nrhs,
+ * column-major with leading dimension ld >= N, caller's order, device memory;
+ * d_x may equal d_b. Requires a successful factorization (BAD_STATE otherwise).
+ * The solve runs in the precision of the factorization. */
+hss_status hss_ulv_solve(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, double* d_x,
+                         int64_t nrhs, int64_t ld);
+
+/* Solve with iterative refinement: x_{k+1} = x_k + solve(b - A x_k), the
+ * residual by the FP64 HSS matvec, until |b - A x|_2 <= tol |b|_2 for every
+ * column, or max_iters corrections. If the residual stalls, switches to
+ * preconditioned conjugate gradients with the factorization as preconditioner.
+ * iters_out / relres_out (host, nullable) receive the correction count and the
+ * largest final relative residual. Errors: NOT_CONVERGED (x holds the best iterate). */
+hss_status hss_ulv_solve_refined(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, double* d_x,
+                                 int64_t nrhs, int64_t ld, double tol, int32_t max_iters,
+                                 int32_t* iters_out, double* relres_out);
+
+/* FP64 HSS matrix-vector product y = A x (up-sweep, couplings, down-sweep,
+ * leaf blocks). Allowed in any state after construction/import. */
+hss_status hss_matvec(hss_ctx_t ctx, hss_matrix_t m, const double* d_x, double* d_y,
+                      int64_t nrhs, int64_t ld);
+
+/* log det A = 2 * sum of log pivots of every L_RR and of the root factor
+ * (the orthogonal transforms have |det| = 1). Requires FACTORED. Synchronizes. */
+hss_status hss_logdet(hss_ctx_t ctx, hss_matrix_t m, double* h_out);
+
+hss_status hss_get_info(hss_matrix_t m, hss_info* out);
+/* N entries: tree position -> caller's point index. */
+hss_status hss_get_permutation(hss_ctx_t ctx, hss_matrix_t m, int64_t* d_perm);
+
+/* Reads one intermediate block of the factorization to host memory, for
+ * checking the steps of Alg. 2 one by one. what = 0: the node's Schur
+ * complement Sigma (rank x rank) in the coordinates of its basis; what = 1:
+ * the node's merged diagonal block before the transform (n x n; for the root,
+ * the block that the final Cholesky factors); what = 2..5: the stored factor
+ * data of the node as laid out on the device (2: Householder vectors V, n x r;
+ * 3: the WY triangle T, r x r; 4: the factor block, n x n, [R;S] order;
+ * 5: the r coordinate signs). Requires FACTORED. */
+hss_status hss_debug_node_block(hss_ctx_t ctx, hss_matrix_t m, int32_t node, int32_t what,
+                                double* h_out, int64_t capacity);
+
+/* Per-launch timing: when enabled, every kernel launch of the factorization
+ * and solve is bracketed by two HIP events on the context stream (this adds a
+ * small gap per launch). Enabling or disabling clears the records. */
+hss_status hss_profile_enable(hss_ctx_t ctx, int32_t on);
+/* Writes one line per (step, level): "<step> <level> <launches> <total ms>\n"
+ * into buf (NUL-terminated, truncated to capacity); *needed receives the full
+ * size. Synchronizes. */
+hss_status hss_profile_read(hss_ctx_t ctx, char* buf, int64_t capacity, int64_t* needed);
+
+hss_status hss_matrix_destroy(hss_matrix_t m);
+
+const char* hss_status_string(hss_status s);
+const char* hss_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSS_H_ */

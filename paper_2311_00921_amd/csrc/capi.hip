@@ -1,0 +1,570 @@
+// C ABI of libhss.so: argument validation, the matrix state machine, the
+// device layout of the HSS representation, import and export.
+#include <cmath>
+#include <cstring>
+#include <new>
+
+#include "hss_internal.h"
+
+namespace hss {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+void* dev_alloc(size_t bytes) {
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, bytes == 0 ? 8 : bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Error{HSS_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
+  return p;
+}
+
+void dev_free(void* p) {
+  if (p) (void)hipFree(p);
+}
+
+static hipEvent_t pool_event(hss_ctx_t c) {
+  if (c->ev_used == c->ev_pool.size()) {
+    hipEvent_t e;
+    HSS_HIP(hipEventCreate(&e));
+    c->ev_pool.push_back(e);
+  }
+  return c->ev_pool[c->ev_used++];
+}
+
+Prof::Prof(hss_ctx_t c, const char* name, int level) : ctx(c) {
+  if (!ctx || !ctx->prof) return;
+  ProfRec r{name, level, pool_event(ctx), pool_event(ctx)};
+  HSS_HIP(hipEventRecord(r.a, ctx->stream));
+  idx = ctx->prof_recs.size();
+  ctx->prof_recs.push_back(r);
+}
+
+Prof::~Prof() {
+  if (idx == (size_t)-1) return;
+  (void)hipEventRecord(ctx->prof_recs[idx].b, ctx->stream);
+}
+
+static int level_of(int k) {
+  int l = 0;
+  while ((2 << l) - 1 <= k) ++l;
+  return l;
+}
+
+// Fills the node table from (n, L, lo/npts of leaves, ranks) and assigns every
+// offset; allocates the representation buffers.
+void layout_representation(hss_matrix_t m) {
+  const int L = m->L;
+  const int nn = m->nnodes;
+  auto& nd = m->nodes;
+  // upper node ranges from the leaves
+  for (int k = (1 << L) - 2; k >= 0; --k) {
+    nd[k].lo = nd[2 * k + 1].lo;
+    nd[k].npts = nd[2 * k + 1].npts + nd[2 * k + 2].npts;
+  }
+  for (int k = 0; k < nn; ++k) nd[k].level = level_of(k);
+  if (L == 0) {
+    nd[0].n = nd[0].npts;
+    nd[0].r = 0;
+  } else {
+    for (int k = nn - 1; k >= 0; --k) {
+      if (nd[k].level == L)
+        nd[k].n = nd[k].npts;
+      else
+        nd[k].n = nd[2 * k + 1].r + nd[2 * k + 2].r;
+      if (k == 0) nd[k].r = 0;
+    }
+  }
+  int64_t oD = 0, oB = 0, oS = 0, oF = 0, oM = 0, oV = 0, oT = 0, oSg = 0, oW = 0, oX = 0, oVec = 0, oR = 0;
+  m->max_rank = 0;
+  for (int k = 0; k < nn; ++k) {
+    NodeDesc& d = nd[k];
+    const bool leaf = d.level == L;
+    d.m = d.n - d.r;
+    HSS_CHECK(d.r >= 0 && d.r <= d.n, HSS_ERR_INVALID_ARGUMENT,
+              "node " + std::to_string(k) + ": rank exceeds block size");
+    HSS_CHECK(k == 0 || d.r >= 1, HSS_ERR_INVALID_ARGUMENT, "node " + std::to_string(k) + ": rank must be >= 1");
+    m->max_rank = std::max(m->max_rank, d.r);
+    d.offD = leaf ? oD : -1;
+    if (leaf) oD += (int64_t)d.n * d.n;
+    d.offB = (k > 0) ? oB : -1;
+    if (k > 0) oB += (int64_t)d.n * d.r;
+    d.offS = leaf ? -1 : oS;
+    if (!leaf) oS += (int64_t)nd[2 * k + 1].r * nd[2 * k + 2].r;
+    d.offF = oF;
+    oF += (int64_t)d.n * d.n;
+    d.offM = leaf ? -1 : oM;
+    if (!leaf) oM += (int64_t)d.n * d.n;
+    d.offV = oV;
+    oV += (int64_t)d.n * d.r;
+    d.offT = oT;
+    oT += (int64_t)d.r * d.r;
+    d.offSg = oSg;
+    oSg += d.r;
+    d.offW = oW;
+    oW += 2 * (int64_t)d.n * d.r;
+    d.offX = oX;
+    oX += 2 * (int64_t)d.r * d.r;
+    d.offVec = oVec;
+    oVec += d.n;
+    d.offR = oR;
+    oR += d.r;
+    d.child_row = 0;
+  }
+  for (int k = 1; k < nn; ++k)
+    nd[k].child_row = (k % 2 == 1) ? 0 : nd[k - 1].r;
+  m->lenD = oD;
+  m->lenB = oB;
+  m->lenS = oS;
+  m->lenF = oF;
+  m->lenM = oM;
+  m->lenV = oV;
+  m->lenT = oT;
+  m->lenSg = oSg;
+  m->lenW = oW;
+  m->lenX = oX;
+  m->sum_n = oVec;
+  m->sum_r = oR;
+  m->levels.clear();
+  for (int l = 0; l <= L; ++l) {
+    LevelPlan lp{};
+    lp.level = l;
+    lp.first = (1 << l) - 1;
+    lp.count = 1 << l;
+    for (int k = lp.first; k < lp.first + lp.count; ++k) {
+      lp.nmax = std::max(lp.nmax, nd[k].n);
+      lp.rmax = std::max(lp.rmax, nd[k].r);
+      lp.mmax = std::max(lp.mmax, nd[k].m);
+    }
+    m->levels.push_back(lp);
+  }
+  if (!m->dnodes) m->dnodes = (NodeDesc*)dev_alloc(sizeof(NodeDesc) * nn);
+  HSS_HIP(hipMemcpyAsync(m->dnodes, nd.data(), sizeof(NodeDesc) * nn, hipMemcpyHostToDevice, m->ctx->stream));
+  if (!m->dD) m->dD = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(oD, 1));
+  if (!m->dB) m->dB = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(oB, 1));
+  if (!m->dS) m->dS = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(oS, 1));
+  if (!m->dperm) m->dperm = (int64_t*)dev_alloc(sizeof(int64_t) * m->n);
+}
+
+static void destroy_matrix(hss_matrix_t m) {
+  if (!m) return;
+  free_factor(m);
+  void* ptrs[] = {m->dnodes, m->dD, m->dB, m->dS, m->dperm, m->dvec, m->dxt, m->dyt, m->fvec, m->dtmp,
+                  m->dRootNode};
+  for (void* p : ptrs)
+    if (p) dev_free(p);
+  delete m;
+}
+
+}  // namespace hss
+
+using namespace hss;
+
+#define HSS_API_BEGIN try {
+#define HSS_API_END                                 \
+  }                                                 \
+  catch (const hss::Error& e) {                     \
+    hss::set_error(e.msg);                          \
+    return e.st;                                    \
+  }                                                 \
+  catch (const std::bad_alloc&) {                   \
+    hss::set_error("host allocation failed");       \
+    return HSS_ERR_OUT_OF_MEMORY;                   \
+  }                                                 \
+  catch (...) {                                     \
+    hss::set_error("unexpected internal exception"); \
+    return HSS_ERR_DEVICE;                          \
+  }                                                 \
+  return HSS_OK;
+
+extern "C" {
+
+const char* hss_status_string(hss_status s) {
+  switch (s) {
+    case HSS_OK: return "ok";
+    case HSS_ERR_INVALID_ARGUMENT: return "invalid argument";
+    case HSS_ERR_NOT_SPD: return "matrix not positive definite";
+    case HSS_ERR_OUT_OF_MEMORY: return "out of memory";
+    case HSS_ERR_DEVICE: return "device error";
+    case HSS_ERR_BAD_STATE: return "bad state";
+    case HSS_ERR_NOT_CONVERGED: return "not converged";
+    case HSS_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* hss_last_error(void) { return g_last_error.c_str(); }
+
+hss_status hss_ctx_create(int32_t device, void* hip_stream, hss_ctx_t* out) {
+  HSS_API_BEGIN
+  HSS_CHECK(out != nullptr, HSS_ERR_INVALID_ARGUMENT, "out is NULL");
+  int count = 0;
+  HSS_HIP(hipGetDeviceCount(&count));
+  HSS_CHECK(device >= 0 && device < count, HSS_ERR_INVALID_ARGUMENT, "device index out of range");
+  HSS_HIP(hipSetDevice(device));
+  hss_ctx_t c = new hss_ctx_s();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  HSS_HIP(hipEventCreate(&c->ev0));
+  HSS_HIP(hipEventCreate(&c->ev1));
+  *out = c;
+  HSS_API_END
+}
+
+hss_status hss_ctx_destroy(hss_ctx_t ctx) {
+  HSS_API_BEGIN
+  if (!ctx) return HSS_OK;
+  for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  delete ctx;
+  HSS_API_END
+}
+
+hss_status hss_ctx_set_stream(hss_ctx_t ctx, void* hip_stream) {
+  HSS_API_BEGIN
+  HSS_CHECK(ctx != nullptr, HSS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+  ctx->stream = (hipStream_t)hip_stream;
+  HSS_API_END
+}
+
+hss_status hss_profile_enable(hss_ctx_t ctx, int32_t on) {
+  HSS_API_BEGIN
+  HSS_CHECK(ctx != nullptr, HSS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+  HSS_HIP(hipStreamSynchronize(ctx->stream));
+  ctx->prof = on != 0;
+  ctx->prof_recs.clear();
+  ctx->ev_used = 0;
+  HSS_API_END
+}
+
+hss_status hss_profile_read(hss_ctx_t ctx, char* buf, int64_t capacity, int64_t* needed) {
+  HSS_API_BEGIN
+  HSS_CHECK(ctx != nullptr, HSS_ERR_INVALID_ARGUMENT, "ctx is NULL");
+  HSS_HIP(hipStreamSynchronize(ctx->stream));
+  // aggregate by (name, level): launches and total milliseconds
+  struct Agg {
+    std::string name;
+    int level;
+    int64_t count;
+    double ms;
+  };
+  std::vector<Agg> agg;
+  for (auto& r : ctx->prof_recs) {
+    float ms = 0.f;
+    HSS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+    bool found = false;
+    for (auto& a : agg)
+      if (a.name == r.name && a.level == r.level) {
+        a.count++;
+        a.ms += ms;
+        found = true;
+        break;
+      }
+    if (!found) agg.push_back({r.name, r.level, 1, (double)ms});
+  }
+  std::string out;
+  for (auto& a : agg)
+    out += a.name + " " + std::to_string(a.level) + " " + std::to_string(a.count) + " " + std::to_string(a.ms) + "\n";
+  if (needed) *needed = (int64_t)out.size() + 1;
+  if (buf && capacity > 0) {
+    const size_t n = std::min<size_t>(out.size(), (size_t)capacity - 1);
+    std::memcpy(buf, out.data(), n);
+    buf[n] = 0;
+  }
+  HSS_API_END
+}
+
+hss_status hss_import(hss_ctx_t ctx, const hss_desc* d, hss_matrix_t* out) {
+  hss_matrix_t m = nullptr;
+  HSS_API_BEGIN
+  HSS_CHECK(ctx && d && out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  HSS_CHECK(d->n >= 1, HSS_ERR_INVALID_ARGUMENT, "n must be >= 1");
+  HSS_CHECK(d->levels >= 0 && d->levels <= 24, HSS_ERR_INVALID_ARGUMENT, "levels out of range");
+  HSS_CHECK(d->leaf_lo && d->D, HSS_ERR_INVALID_ARGUMENT, "leaf_lo and D are required");
+  const int L = d->levels;
+  HSS_CHECK(L == 0 || (d->rank && d->U && d->S), HSS_ERR_INVALID_ARGUMENT, "rank, U and S are required");
+  HSS_CHECK(L <= 1 || d->E, HSS_ERR_INVALID_ARGUMENT, "E is required for levels >= 2");
+  m = new hss_matrix_s();
+  m->ctx = ctx;
+  m->n = d->n;
+  m->L = L;
+  m->nnodes = (2 << L) - 1;
+  m->nodes.assign(m->nnodes, NodeDesc{});
+  const int nleaves = 1 << L;
+  HSS_CHECK(d->leaf_lo[0] == 0 && d->leaf_lo[nleaves] == d->n, HSS_ERR_INVALID_ARGUMENT,
+            "leaf boundaries must span [0, n)");
+  for (int i = 0; i < nleaves; ++i) {
+    NodeDesc& nd = m->nodes[nleaves - 1 + i];
+    nd.lo = d->leaf_lo[i];
+    nd.npts = (int32_t)(d->leaf_lo[i + 1] - d->leaf_lo[i]);
+    HSS_CHECK(nd.npts >= 1 && nd.npts <= 512, HSS_ERR_INVALID_ARGUMENT, "leaf sizes must be in [1, 512]");
+  }
+  for (int k = 1; k < m->nnodes; ++k) m->nodes[k].r = d->rank[k];
+  layout_representation(m);
+  for (int k = 1; k < m->nnodes; ++k)
+    HSS_CHECK(m->nodes[k].n <= 512 && m->nodes[k].r <= 128, HSS_ERR_UNSUPPORTED,
+              "blocks above 512 rows or ranks above 128 are not supported");
+  HSS_CHECK(m->nodes[0].n <= 512, HSS_ERR_UNSUPPORTED, "root block above 512 rows");
+  hipStream_t s = ctx->stream;
+  HSS_HIP(hipMemcpyAsync(m->dD, d->D, sizeof(double) * m->lenD, hipMemcpyHostToDevice, s));
+  if (L > 0) {
+    // dB = [E of nodes 1..2^L-2 | U of the leaves] in heap order
+    int64_t lenE = 0;
+    for (int k = 1; k < nleaves - 1; ++k) lenE += (int64_t)m->nodes[k].n * m->nodes[k].r;
+    if (lenE > 0) HSS_HIP(hipMemcpyAsync(m->dB, d->E, sizeof(double) * lenE, hipMemcpyHostToDevice, s));
+    HSS_HIP(hipMemcpyAsync(m->dB + lenE, d->U, sizeof(double) * (m->lenB - lenE), hipMemcpyHostToDevice, s));
+    HSS_HIP(hipMemcpyAsync(m->dS, d->S, sizeof(double) * m->lenS, hipMemcpyHostToDevice, s));
+  }
+  std::vector<int64_t> perm(m->n);
+  if (d->perm) {
+    std::vector<char> seen(m->n, 0);
+    for (int64_t i = 0; i < m->n; ++i) {
+      HSS_CHECK(d->perm[i] >= 0 && d->perm[i] < m->n && !seen[d->perm[i]], HSS_ERR_INVALID_ARGUMENT,
+                "perm is not a permutation");
+      seen[d->perm[i]] = 1;
+      perm[i] = d->perm[i];
+    }
+  } else {
+    for (int64_t i = 0; i < m->n; ++i) perm[i] = i;
+  }
+  HSS_HIP(hipMemcpyAsync(m->dperm, perm.data(), sizeof(int64_t) * m->n, hipMemcpyHostToDevice, s));
+  HSS_HIP(hipStreamSynchronize(s));
+  *out = m;
+  m = nullptr;
+  return HSS_OK;
+  }
+  catch (const hss::Error& e) {
+    hss::set_error(e.msg);
+    destroy_matrix(m);
+    return e.st;
+  }
+  catch (...) {
+    hss::set_error("unexpected internal exception");
+    destroy_matrix(m);
+    return HSS_ERR_DEVICE;
+  }
+}
+
+hss_status hss_construct(hss_ctx_t ctx, const double* d_points, int64_t n, int32_t dim, const hss_kernel* kernel,
+                         const hss_construct_opts* opts, const double* d_omega, int32_t s, hss_matrix_t* out) {
+  hss_matrix_t m = nullptr;
+  try {
+    HSS_CHECK(ctx && d_points && kernel && opts && out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+    HSS_CHECK(n >= 1, HSS_ERR_INVALID_ARGUMENT, "n must be >= 1");
+    HSS_CHECK(dim >= 1 && dim <= 3, HSS_ERR_INVALID_ARGUMENT, "dim must be 1, 2 or 3");
+    HSS_CHECK(opts->leaf_size >= 2 && opts->leaf_size <= 512, HSS_ERR_INVALID_ARGUMENT, "leaf_size must be in [2, 512]");
+    HSS_CHECK(opts->rank >= 0 && opts->rank <= 128, HSS_ERR_INVALID_ARGUMENT, "rank must be in [0, 128]");
+    HSS_CHECK(opts->rank > 0 || opts->tol > 0.0, HSS_ERR_INVALID_ARGUMENT, "adaptive rank needs tol > 0");
+    HSS_CHECK(opts->max_rank >= 0, HSS_ERR_INVALID_ARGUMENT, "max_rank must be >= 0");
+    HSS_CHECK(opts->mode == HSS_COMPRESS_SCALED, HSS_ERR_INVALID_ARGUMENT, "unknown compression mode");
+    HSS_CHECK(kernel->kind >= 0 && kernel->kind <= 4, HSS_ERR_INVALID_ARGUMENT, "unknown kernel");
+    HSS_CHECK(kernel->kind >= HSS_K_LAPLACE2D || kernel->length > 0.0, HSS_ERR_INVALID_ARGUMENT,
+              "kernel length must be > 0");
+    HSS_CHECK(kernel->nugget >= 0.0, HSS_ERR_INVALID_ARGUMENT, "nugget must be >= 0");
+    int L = 0;
+    while (((int64_t)opts->leaf_size << L) < n) ++L;
+    HSS_CHECK(opts->levels == 0 || opts->levels == L, HSS_ERR_INVALID_ARGUMENT,
+              "levels must equal ceil(log2(N / leaf_size)) = " + std::to_string(L));
+    HSS_CHECK(L <= 20, HSS_ERR_UNSUPPORTED, "too many levels");
+    HSS_CHECK(L == 0 || (d_omega && s >= 1 && s <= 512), HSS_ERR_INVALID_ARGUMENT, "need a test matrix with 1..512 columns");
+    HSS_CHECK(L == 0 || opts->rank == 0 || s >= opts->rank, HSS_ERR_INVALID_ARGUMENT, "need s >= rank");
+    m = new hss_matrix_s();
+    m->ctx = ctx;
+    m->n = n;
+    m->L = L;
+    construct(m, d_points, dim, *kernel, *opts, d_omega, s);
+    *out = m;
+    return HSS_OK;
+  } catch (const hss::Error& e) {
+    hss::set_error(e.msg);
+    destroy_matrix(m);
+    return e.st;
+  } catch (...) {
+    hss::set_error("unexpected internal exception");
+    destroy_matrix(m);
+    return HSS_ERR_DEVICE;
+  }
+}
+
+hss_status hss_export_sizes(hss_matrix_t m, int64_t sizes[7]) {
+  HSS_API_BEGIN
+  HSS_CHECK(m && sizes, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  sizes[0] = (1 << m->L) + 1;
+  sizes[1] = m->nnodes;
+  sizes[2] = m->lenD;
+  int64_t lenE = 0;
+  for (int k = 1; k < (1 << m->L) - 1; ++k) lenE += (int64_t)m->nodes[k].n * m->nodes[k].r;
+  sizes[3] = m->lenB - lenE;
+  sizes[4] = lenE;
+  sizes[5] = m->lenS;
+  sizes[6] = m->n;
+  HSS_API_END
+}
+
+hss_status hss_export(hss_ctx_t ctx, hss_matrix_t m, hss_desc_out* o) {
+  HSS_API_BEGIN
+  HSS_CHECK(ctx && m && o, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  hipStream_t s = ctx->stream;
+  const int nleaves = 1 << m->L;
+  if (o->leaf_lo) {
+    for (int i = 0; i < nleaves; ++i) o->leaf_lo[i] = m->nodes[nleaves - 1 + i].lo;
+    o->leaf_lo[nleaves] = m->n;
+  }
+  if (o->rank)
+    for (int k = 0; k < m->nnodes; ++k) o->rank[k] = m->nodes[k].r;
+  int64_t lenE = 0;
+  for (int k = 1; k < nleaves - 1; ++k) lenE += (int64_t)m->nodes[k].n * m->nodes[k].r;
+  if (o->D) HSS_HIP(hipMemcpyAsync(o->D, m->dD, sizeof(double) * m->lenD, hipMemcpyDeviceToHost, s));
+  if (m->L > 0) {
+    if (o->E && lenE > 0) HSS_HIP(hipMemcpyAsync(o->E, m->dB, sizeof(double) * lenE, hipMemcpyDeviceToHost, s));
+    if (o->U)
+      HSS_HIP(hipMemcpyAsync(o->U, m->dB + lenE, sizeof(double) * (m->lenB - lenE), hipMemcpyDeviceToHost, s));
+    if (o->S) HSS_HIP(hipMemcpyAsync(o->S, m->dS, sizeof(double) * m->lenS, hipMemcpyDeviceToHost, s));
+  }
+  if (o->perm) HSS_HIP(hipMemcpyAsync(o->perm, m->dperm, sizeof(int64_t) * m->n, hipMemcpyDeviceToHost, s));
+  HSS_HIP(hipStreamSynchronize(s));
+  HSS_API_END
+}
+
+hss_status hss_ulv_factor(hss_ctx_t ctx, hss_matrix_t m, const hss_factor_opts* opts) {
+  HSS_API_BEGIN
+  HSS_CHECK(ctx && m, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  const int prec = opts ? opts->precision : HSS_P_FP64;
+  HSS_CHECK(prec == HSS_P_FP64 || prec == HSS_P_FP32, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
+  hipStream_t s = ctx->stream;
+  m->state = 0;
+  m->failed_level = m->failed_node = m->failed_pivot = -1;
+  HSS_HIP(hipEventRecord(ctx->ev0, s));
+  if (prec == HSS_P_FP64)
+    factor_fp64(m);
+  else
+    factor_fp32(m);
+  HSS_HIP(hipEventRecord(ctx->ev1, s));
+  int32_t info[4] = {0, 0, 0, 0};
+  HSS_HIP(hipMemcpyAsync(info, m->dinfo, sizeof(info), hipMemcpyDeviceToHost, s));
+  HSS_HIP(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HSS_HIP(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  m->factor_ms = ms;
+  m->precision = prec;
+  if (info[0] != 0) {
+    m->state = 2;
+    m->failed_node = info[1];
+    m->failed_level = level_of(info[1]);
+    m->failed_pivot = info[2];
+    throw Error{HSS_ERR_NOT_SPD, "non-positive pivot at level " + std::to_string(m->failed_level) + ", node " +
+                                     std::to_string(info[1]) + ", pivot " + std::to_string(info[2])};
+  }
+  m->state = 1;
+  HSS_API_END
+}
+
+hss_status hss_ulv_solve(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, double* d_x, int64_t nrhs, int64_t ld) {
+  HSS_API_BEGIN
+  HSS_CHECK(ctx && m && d_b && d_x, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  HSS_CHECK(nrhs >= 1 && ld >= m->n, HSS_ERR_INVALID_ARGUMENT, "need nrhs >= 1 and ld >= n");
+  HSS_CHECK(m->state == 1, HSS_ERR_BAD_STATE, "matrix is not factored");
+  hipStream_t s = ctx->stream;
+  HSS_HIP(hipEventRecord(ctx->ev0, s));
+  if (m->precision == HSS_P_FP64)
+    solve_fp64(m, d_b, d_x, nrhs, ld);
+  else
+    solve_fp32(m, d_b, d_x, nrhs, ld);
+  HSS_HIP(hipEventRecord(ctx->ev1, s));
+  HSS_API_END
+}
+
+hss_status hss_matvec(hss_ctx_t ctx, hss_matrix_t m, const double* d_x, double* d_y, int64_t nrhs, int64_t ld) {
+  HSS_API_BEGIN
+  HSS_CHECK(ctx && m && d_x && d_y, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  HSS_CHECK(nrhs >= 1 && ld >= m->n, HSS_ERR_INVALID_ARGUMENT, "need nrhs >= 1 and ld >= n");
+  HSS_CHECK(d_x != d_y, HSS_ERR_INVALID_ARGUMENT, "x and y must not alias");
+  matvec_fp64(m, d_x, d_y, nrhs, ld);
+  HSS_API_END
+}
+
+hss_status hss_logdet(hss_ctx_t ctx, hss_matrix_t m, double* h_out) {
+  HSS_API_BEGIN
+  HSS_CHECK(ctx && m && h_out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  HSS_CHECK(m->state == 1, HSS_ERR_BAD_STATE, "matrix is not factored");
+  *h_out = read_logdet(m);
+  HSS_API_END
+}
+
+hss_status hss_get_info(hss_matrix_t m, hss_info* o) {
+  HSS_API_BEGIN
+  HSS_CHECK(m && o, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  std::memset(o, 0, sizeof(*o));
+  o->n = m->n;
+  o->levels = m->L;
+  o->factored = m->state == 1;
+  o->precision = m->precision;
+  o->max_rank = m->max_rank;
+  o->failed_level = m->failed_level;
+  o->failed_node = m->failed_node;
+  o->failed_pivot = m->failed_pivot;
+  o->bytes_representation = 8 * (m->lenD + m->lenB + m->lenS);
+  o->bytes_factor = 8 * (m->lenF + m->lenV + m->lenT + m->lenSg);
+  o->factor_ms = m->factor_ms;
+  o->solve_ms = m->solve_ms;
+  HSS_API_END
+}
+
+hss_status hss_get_permutation(hss_ctx_t ctx, hss_matrix_t m, int64_t* d_perm) {
+  HSS_API_BEGIN
+  HSS_CHECK(ctx && m && d_perm, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  HSS_HIP(hipMemcpyAsync(d_perm, m->dperm, sizeof(int64_t) * m->n, hipMemcpyDeviceToDevice, ctx->stream));
+  HSS_API_END
+}
+
+hss_status hss_debug_node_block(hss_ctx_t ctx, hss_matrix_t m, int32_t node, int32_t what, double* h_out,
+                                int64_t capacity) {
+  HSS_API_BEGIN
+  HSS_CHECK(ctx && m && h_out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  HSS_CHECK(node >= 0 && node < m->nnodes, HSS_ERR_INVALID_ARGUMENT, "node out of range");
+  HSS_CHECK(m->state == 1 && m->precision == HSS_P_FP64, HSS_ERR_BAD_STATE, "needs an FP64 factorization");
+  const NodeDesc& nd = m->nodes[node];
+  hipStream_t s = ctx->stream;
+  if (what == 0) {
+    HSS_CHECK(node > 0, HSS_ERR_INVALID_ARGUMENT, "the root has no Schur complement");
+    HSS_CHECK(capacity >= (int64_t)nd.r * nd.r, HSS_ERR_INVALID_ARGUMENT, "capacity too small");
+    std::vector<double> F((size_t)nd.n * nd.n), sg(nd.r);
+    HSS_HIP(hipMemcpyAsync(F.data(), m->dF + nd.offF, sizeof(double) * F.size(), hipMemcpyDeviceToHost, s));
+    HSS_HIP(hipMemcpyAsync(sg.data(), m->dSg + nd.offSg, sizeof(double) * nd.r, hipMemcpyDeviceToHost, s));
+    HSS_HIP(hipStreamSynchronize(s));
+    for (int j = 0; j < nd.r; ++j)
+      for (int i = 0; i < nd.r; ++i) {
+        const int a = std::max(i, j), b = std::min(i, j);
+        h_out[i + (int64_t)j * nd.r] = sg[i] * sg[j] * F[(nd.m + a) + (int64_t)(nd.m + b) * nd.n];
+      }
+  } else if (what == 1) {
+    HSS_CHECK(nd.level < m->L, HSS_ERR_INVALID_ARGUMENT, "leaves have no merged block");
+    HSS_CHECK(capacity >= (int64_t)nd.n * nd.n, HSS_ERR_INVALID_ARGUMENT, "capacity too small");
+    HSS_HIP(hipMemcpyAsync(h_out, m->dM + nd.offM, sizeof(double) * nd.n * nd.n, hipMemcpyDeviceToHost, s));
+    HSS_HIP(hipStreamSynchronize(s));
+  } else if (what >= 2 && what <= 5) {
+    // raw factor data: 2 = V (n x r), 3 = T (r x r), 4 = F block (n x n, [R;S] order), 5 = signs (r)
+    const int64_t len = what == 2 ? (int64_t)nd.n * nd.r : what == 3 ? (int64_t)nd.r * nd.r
+                        : what == 4 ? (int64_t)nd.n * nd.n : nd.r;
+    const double* src = what == 2 ? m->dV + nd.offV : what == 3 ? m->dT + nd.offT
+                        : what == 4 ? m->dF + nd.offF : m->dSg + nd.offSg;
+    HSS_CHECK(capacity >= len, HSS_ERR_INVALID_ARGUMENT, "capacity too small");
+    HSS_HIP(hipMemcpyAsync(h_out, src, sizeof(double) * len, hipMemcpyDeviceToHost, s));
+    HSS_HIP(hipStreamSynchronize(s));
+  } else {
+    throw Error{HSS_ERR_INVALID_ARGUMENT, "unknown block kind"};
+  }
+  HSS_API_END
+}
+
+hss_status hss_matrix_destroy(hss_matrix_t m) {
+  HSS_API_BEGIN
+  destroy_matrix(m);
+  HSS_API_END
+}
+
+}  // extern "C"

@@ -1,0 +1,642 @@
+// HSS-ULV factorization (Sec. 3.2, Alg. 2) on one GPU: one kernel boundary per
+// step and level, every node of a level in the same launch.
+//
+// Per level l = L..1 and node p (block size n, basis rank r, m = n - r):
+//   merge     M_p = [[Sg1 Sigma_c1 Sg1, S_p], [S_p^T, Sg2 Sigma_c2 Sg2]]  (upper levels)
+//   basis QR  the orthogonal Q = [U^R U^S] of Eq. 3 / Eq. 9 in compact WY form
+//             H = I - V T V^T with H[:, :r] = B diag(Sg)  (B = U or E)
+//   product   F = P^T (H^T M_p H) P   (Eq. 7; P orders the coordinates [R; S])
+//   partial   the first m columns of a right-looking Cholesky of F: L_RR, L_SR
+//   Cholesky  and the Schur complement Sigma_p in F's trailing block (Eq. 10-12)
+// then the root block is merged and factored completely.
+//
+// The basis QR uses the Householder reconstruction of an orthonormal matrix
+// (Ballard, Demmel, Grigori, Jacquelin, Knight, Nguyen, "Reconstructing
+// Householder vectors from tall-skinny QR", JPDC 2015): an LU factorization
+// without pivoting of B - [Sg; 0] gives V (unit lower trapezoidal) and
+// U_lu = -T V_1^T Sg, from which T = -U_lu Sg V_1^{-T}.
+#include <cmath>
+
+#include "hss_internal.h"
+
+namespace hss {
+
+typedef double v4d __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ v4d mfma16x(double a, double b, v4d c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ v4f mfma16x(float a, float b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ int mfma_out_row(double, int lane, int v) { return (lane >> 4) + 4 * v; }
+__device__ __forceinline__ int mfma_out_row(float, int lane, int v) { return 4 * (lane >> 4) + v; }
+
+template <typename T>
+struct Acc4;
+template <>
+struct Acc4<double> {
+  typedef v4d type;
+};
+template <>
+struct Acc4<float> {
+  typedef v4f type;
+};
+
+// ---------------------------------------------------------------------------
+// Householder reconstruction: B (n x r, orthonormal) -> V, T, Sg
+// One workgroup per node; thread t owns rows t + 256*q (q < ROWS) in registers.
+// ---------------------------------------------------------------------------
+
+template <typename T, int RMAX, int ROWS>
+__global__ __launch_bounds__(256) void k_hh_recon(const NodeDesc* __restrict__ nodes, int first,
+                                                  const T* __restrict__ Bbase, T* __restrict__ Vbase,
+                                                  T* __restrict__ Tbase, T* __restrict__ Sgbase) {
+  const NodeDesc nd = nodes[first + blockIdx.x];
+  const int n = nd.n, r = nd.r;
+  const T* B = Bbase + nd.offB;
+  T* V = Vbase + nd.offV;
+  T* Tm = Tbase + nd.offT;
+  T* Sg = Sgbase + nd.offSg;
+  __shared__ T prow[RMAX];
+  __shared__ T sg[RMAX];
+  __shared__ T piv;
+  const int tid = threadIdx.x;
+  T a[ROWS][RMAX];
+#pragma unroll
+  for (int q = 0; q < ROWS; ++q) {
+    const int i = tid + 256 * q;
+#pragma unroll
+    for (int c = 0; c < RMAX; ++c) a[q][c] = (i < n && c < r) ? B[i + (int64_t)c * n] : (T)0;
+  }
+  for (int j = 0; j < r; ++j) {
+    // the owner of row j fixes the sign, forms the pivot and publishes the row
+#pragma unroll
+    for (int q = 0; q < ROWS; ++q) {
+      const int i = tid + 256 * q;
+      if (i == j) {
+        T u = 0;
+#pragma unroll
+        for (int c = 0; c < RMAX; ++c)
+          if (c == j) u = a[q][c];
+        const T s = (u >= (T)0) ? (T)-1 : (T)1;
+        const T p = u - s;
+#pragma unroll
+        for (int c = 0; c < RMAX; ++c) {
+          if (c == j) a[q][c] = p;
+          prow[c] = a[q][c];
+        }
+        sg[j] = s;
+        piv = p;
+      }
+    }
+    __syncthreads();
+    const T p = piv;
+#pragma unroll
+    for (int q = 0; q < ROWS; ++q) {
+      const int i = tid + 256 * q;
+      if (i > j && i < n) {
+        T l = 0;
+#pragma unroll
+        for (int c = 0; c < RMAX; ++c)
+          if (c == j) l = a[q][c] / p;
+#pragma unroll
+        for (int c = 0; c < RMAX; ++c) {
+          if (c == j) a[q][c] = l;
+          if (c > j && c < r) a[q][c] -= l * prow[c];
+        }
+      }
+    }
+    __syncthreads();
+  }
+  // write V (unit lower trapezoidal)
+#pragma unroll
+  for (int q = 0; q < ROWS; ++q) {
+    const int i = tid + 256 * q;
+    if (i < n) {
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c)
+        if (c < r) V[i + (int64_t)c * n] = (c < i) ? a[q][c] : (c == i ? (T)1 : (T)0);
+    }
+  }
+  // G = -U_lu Sg (upper triangular) goes to the T buffer; k_hh_t turns it into T
+#pragma unroll
+  for (int q = 0; q < ROWS; ++q) {
+    const int i = tid + 256 * q;
+    if (i < r) {
+#pragma unroll
+      for (int c = 0; c < RMAX; ++c)
+        if (c < r) Tm[i + (int64_t)c * r] = (c >= i) ? -a[q][c] * sg[c] : (T)0;
+    }
+  }
+  for (int c = tid; c < r; c += 256) Sg[c] = sg[c];
+}
+
+// T = G V_1^{-T}: row i of T solves t V_1^T = g (forward substitution over the
+// columns), with V_1 the unit lower r x r top of V. Separate launch so that V
+// and G are read only after the kernel that wrote them has completed.
+template <typename T>
+__global__ __launch_bounds__(256) void k_hh_t(const NodeDesc* __restrict__ nodes, int first,
+                                              const T* __restrict__ Vbase, T* __restrict__ Tbase) {
+  const NodeDesc nd = nodes[first + blockIdx.x];
+  const int n = nd.n, r = nd.r;
+  const T* V = Vbase + nd.offV;
+  T* Tm = Tbase + nd.offT;
+  for (int i = threadIdx.x; i < r; i += blockDim.x) {
+    for (int c = i + 1; c < r; ++c) {
+      T acc = Tm[i + (int64_t)c * r];
+      for (int k = i; k < c; ++k) acc -= V[c + (int64_t)k * n] * Tm[i + (int64_t)k * r];
+      Tm[i + (int64_t)c * r] = acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// merge: parent block from the children's Schur complements and the coupling
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_merge(const NodeDesc* __restrict__ nodes, int first,
+                                               const T* __restrict__ Fbase, const T* __restrict__ Sgbase,
+                                               const T* __restrict__ Sbase, T* __restrict__ Mbase,
+                                               T* __restrict__ Fout, int to_factor) {
+  const int p = first + blockIdx.x;
+  const NodeDesc nd = nodes[p];
+  const NodeDesc c1 = nodes[2 * p + 1], c2 = nodes[2 * p + 2];
+  const int n = nd.n, r1 = c1.r;
+  T* M = Mbase + nd.offM;
+  T* Fo = Fout + nd.offF;  // the root block is also written where it is factored
+  const T* F1 = Fbase + c1.offF;
+  const T* F2 = Fbase + c2.offF;
+  const T* s1 = Sgbase + c1.offSg;
+  const T* s2 = Sgbase + c2.offSg;
+  const T* S = Sbase + nd.offS;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e % n, j = e / n;
+    T v;
+    if (i < r1 && j < r1) {
+      const int a = max(i, j), b = min(i, j);
+      v = s1[i] * s1[j] * F1[(c1.m + a) + (int64_t)(c1.m + b) * c1.n];
+    } else if (i >= r1 && j >= r1) {
+      const int ii = i - r1, jj = j - r1;
+      const int a = max(ii, jj), b = min(ii, jj);
+      v = s2[ii] * s2[jj] * F2[(c2.m + a) + (int64_t)(c2.m + b) * c2.n];
+    } else if (i < r1) {
+      v = S[i + (int64_t)(j - r1) * r1];
+    } else {
+      v = S[j + (int64_t)(i - r1) * r1];
+    }
+    M[e] = v;
+    if (to_factor) Fo[e] = v;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// partial Cholesky: first m columns of a right-looking Cholesky of F (n x n)
+// 16-column panels; the trailing lower triangle is updated with MFMA tiles.
+// ---------------------------------------------------------------------------
+
+constexpr int PNB = 16;
+
+template <typename T, int NMAX>
+__global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ nodes, int first,
+                                               T* __restrict__ Fbase, int32_t* __restrict__ info,
+                                               double* __restrict__ logdet) {
+  const int node = first + blockIdx.x;
+  const NodeDesc nd = nodes[node];
+  const int n = nd.n, m = nd.m;
+  T* F = Fbase + nd.offF;
+  __shared__ double Ld[PNB][PNB + 1];  // pivot blocks are always factored in FP64
+  __shared__ T P[PNB][NMAX + 1];
+  __shared__ int fail;
+  __shared__ double lacc;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid == 0) {
+    fail = -1;
+    lacc = 0.0;
+  }
+  __syncthreads();
+  for (int j0 = 0; j0 < m; j0 += PNB) {
+    const int jb = min(PNB, m - j0);
+    // (1) diagonal block
+    if (tid < PNB * PNB) {
+      const int i = tid % PNB, c = tid / PNB;
+      Ld[i][c] = (i < jb && c < jb && i >= c) ? (double)F[(j0 + i) + (int64_t)(j0 + c) * n] : 0.0;
+    }
+    __syncthreads();
+    for (int c = 0; c < jb; ++c) {
+      if (tid == 0) {
+        const double d = Ld[c][c];
+        if (!(d > 0.0)) {
+          fail = j0 + c;
+          Ld[c][c] = 1.0;
+        } else {
+          const double s = sqrt(d);
+          Ld[c][c] = s;
+          lacc += log(s);
+        }
+      }
+      __syncthreads();
+      if (tid > c && tid < jb) Ld[tid][c] /= Ld[c][c];
+      __syncthreads();
+      if (tid < PNB * PNB) {
+        const int i = tid % PNB, cc = tid / PNB;
+        if (cc > c && i >= cc && i < jb) Ld[i][cc] -= Ld[i][c] * Ld[cc][c];
+      }
+      __syncthreads();
+    }
+    if (fail >= 0) break;
+    if (tid < PNB * PNB) {
+      const int i = tid % PNB, c = tid / PNB;
+      if (i < jb && c < jb && i >= c) F[(j0 + i) + (int64_t)(j0 + c) * n] = (T)Ld[i][c];
+    }
+    // (2) panel below the diagonal block: rows j0+jb .. n-1
+    const int t0 = j0 + jb, nt = n - t0;
+    for (int i = tid; i < nt; i += 256) {
+      double x[PNB];
+#pragma unroll
+      for (int c = 0; c < PNB; ++c) x[c] = (c < jb) ? (double)F[(t0 + i) + (int64_t)(j0 + c) * n] : 0.0;
+#pragma unroll
+      for (int c = 0; c < PNB; ++c) {
+        if (c < jb) {
+          double acc = x[c];
+#pragma unroll
+          for (int k = 0; k < PNB; ++k)
+            if (k < c) acc -= x[k] * Ld[c][k];
+          x[c] = acc / Ld[c][c];
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < PNB; ++c) {
+        if (c < jb) F[(t0 + i) + (int64_t)(j0 + c) * n] = (T)x[c];
+        P[c][i] = (c < jb) ? (T)x[c] : (T)0;
+      }
+    }
+    __syncthreads();
+    // (3) trailing update of the lower triangle: F[t0:, t0:] -= P P^T
+    const int nb = (nt + 15) / 16;
+    const int ntiles = nb * (nb + 1) / 2;
+    for (int t = wid; t < ntiles; t += 4) {
+      // tile t -> (ti >= tj)
+      int ti = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+      while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+      while (ti * (ti + 1) / 2 > t) --ti;
+      const int tj = t - ti * (ti + 1) / 2;
+      typename Acc4<T>::type acc;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] = 0;
+      const int ra = ti * 16 + (lane & 15), rb = tj * 16 + (lane & 15);
+#pragma unroll
+      for (int kk = 0; kk < PNB; kk += 4) {
+        const int k = kk + (lane >> 4);
+        const T av = (ra < nt) ? P[k][ra] : (T)0;
+        const T bv = (rb < nt) ? P[k][rb] : (T)0;
+        acc = mfma16x(av, bv, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int row = ti * 16 + mfma_out_row((T)0, lane, v);
+        const int col = tj * 16 + (lane & 15);
+        if (row < nt && col < nt && row >= col)
+          F[(t0 + row) + (int64_t)(t0 + col) * n] -= acc[v];
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (fail >= 0) {
+      if (atomicCAS(&info[0], 0, 1) == 0) {
+        info[1] = node;
+        info[2] = fail;
+      }
+    }
+    logdet[node] = 2.0 * lacc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// log-determinant: fixed-order sum of the per-node partial sums
+// ---------------------------------------------------------------------------
+
+__global__ void k_sum_logdet(const double* __restrict__ part, int count, double* __restrict__ out) {
+  __shared__ double s[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < count; i += 256) acc += part[i];
+  s[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+
+template <typename T>
+static void launch_recon(const hss_matrix_t m, const LevelPlan& lp, const T* B, T* V, T* Tm, T* Sg,
+                         hipStream_t s) {
+  const int r = lp.rmax, nmax = lp.nmax;
+  HSS_CHECK(nmax <= 512, HSS_ERR_UNSUPPORTED, "basis with more than 512 rows");
+  dim3 grid(lp.count), block(256);
+#define RECON(RM, RW) \
+  hipLaunchKernelGGL((k_hh_recon<T, RM, RW>), grid, block, 0, s, m->dnodes, lp.first, B, V, Tm, Sg)
+  if (nmax <= 256) {
+    if (r <= 32) RECON(32, 1);
+    else if (r <= 64) RECON(64, 1);
+    else if (r <= 96) RECON(96, 1);
+    else if (r <= 128) RECON(128, 1);
+    else HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "basis rank above 128");
+  } else {
+    if (r <= 32) RECON(32, 2);
+    else if (r <= 64) RECON(64, 2);
+    else if (r <= 96) RECON(96, 2);
+    else if (r <= 128) RECON(128, 2);
+    else HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "basis rank above 128");
+  }
+#undef RECON
+  HSS_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_hh_t<T>), grid, dim3(128), 0, s, m->dnodes, lp.first, (const T*)V, Tm);
+  HSS_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void launch_pchol(const hss_matrix_t m, int first, int count, int nmax, T* F, hipStream_t s) {
+  dim3 grid(count), block(256);
+  if (nmax <= 256)
+    hipLaunchKernelGGL((k_pchol<T, 256>), grid, block, 0, s, m->dnodes, first, F, m->dinfo, m->dlogdet);
+  else if (nmax <= 512)
+    hipLaunchKernelGGL((k_pchol<T, 512>), grid, block, 0, s, m->dnodes, first, F, m->dinfo, m->dlogdet);
+  else
+    HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "diagonal block larger than 512");
+  HSS_HIP(hipGetLastError());
+}
+
+// Full Cholesky of a batch of blocks (NodeDesc n = m = block size, offF = offset).
+void launch_pchol_external(const NodeDesc* nodes, int first, int count, int nmax, double* F, int32_t* info,
+                           double* logdet, hipStream_t s) {
+  dim3 grid(count), block(256);
+  if (nmax <= 256)
+    hipLaunchKernelGGL((k_pchol<double, 256>), grid, block, 0, s, nodes, first, F, info, logdet);
+  else if (nmax <= 512)
+    hipLaunchKernelGGL((k_pchol<double, 512>), grid, block, 0, s, nodes, first, F, info, logdet);
+  else
+    HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "diagonal block larger than 512");
+  HSS_HIP(hipGetLastError());
+}
+
+template <typename T>
+struct FBufs {
+  const T* D;
+  const T* B;
+  const T* S;
+  T *F, *M, *V, *Tm, *Sg, *W, *X;
+};
+
+// Builds the per-level GEMM batches of the diagonal product (once per matrix and type).
+template <typename T>
+static std::vector<std::vector<GemmBatch>> build_gemm_plan(hss_matrix_t m, const FBufs<T>& b) {
+  hipStream_t s = m->ctx->stream;
+  std::vector<std::vector<GemmBatch>> plan(m->L + 1);
+  for (auto& lp : m->levels) {
+    if (lp.level == 0) continue;
+    std::vector<GemmBatch> steps(8);
+    for (int p = lp.first; p < lp.first + lp.count; ++p) {
+      const NodeDesc& nd = m->nodes[p];
+      const int n = nd.n, r = nd.r;
+      const T* Mp = (lp.level == m->L) ? b.D + nd.offD : b.M + nd.offM;
+      T* V = b.V + nd.offV;
+      T* Tm = b.Tm + nd.offT;
+      T* W = b.W + nd.offW;
+      T* Z = W + (int64_t)n * r;
+      T* X = b.X + nd.offX;
+      T* Y = X + (int64_t)r * r;
+      T* F = b.F + nd.offF;
+      steps[0].host.push_back({Mp, V, nullptr, W, n, r, n, n, n, 0, n, 0, 0});        // W = M V
+      steps[1].host.push_back({V, W, nullptr, X, r, r, n, n, n, 0, r, 0, 0});         // X = V^T W
+      steps[2].host.push_back({X, Tm, nullptr, Y, r, r, r, r, r, 0, r, 0, 0});        // Y = X T
+      steps[3].host.push_back({Tm, Y, nullptr, X, r, r, r, r, r, 0, r, 0, 0});        // X = T^T Y
+      steps[4].host.push_back({W, Tm, nullptr, Z, n, r, r, n, r, 0, n, 0, 0});        // Z = W T
+      steps[5].host.push_back({V, X, Z, Z, n, r, r, n, r, n, n, 0, 0});               // Z -= V X / 2
+      steps[6].host.push_back({Z, V, Mp, F, n, n, r, n, n, n, n, r, 0});              // F = P^T (M - Z V^T) P
+      steps[7].host.push_back({V, Z, F, F, n, n, r, n, n, n, n, r, 1});               // F -= P^T V Z^T P
+    }
+    for (auto& g : steps) gemm_upload(g, s);
+    plan[lp.level] = std::move(steps);
+  }
+  return plan;
+}
+
+template <typename T>
+static void gemm_run(const GemmBatch& g, bool ta, bool tb, double alpha, double beta, hipStream_t s);
+template <>
+void gemm_run<double>(const GemmBatch& g, bool ta, bool tb, double alpha, double beta, hipStream_t s) {
+  gemm_launch_f64(g, ta, tb, alpha, beta, s);
+}
+template <>
+void gemm_run<float>(const GemmBatch& g, bool ta, bool tb, double alpha, double beta, hipStream_t s) {
+  gemm_launch_f32(g, ta, tb, (float)alpha, (float)beta, s);
+}
+
+template <typename A, typename B>
+__global__ void k_cast(const A* __restrict__ src, B* __restrict__ dst, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (B)src[i];
+}
+
+template <typename A, typename B>
+static void cast(const A* src, B* dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return;
+  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL((k_cast<A, B>), dim3(blocks), dim3(256), 0, s, src, dst, n);
+  HSS_HIP(hipGetLastError());
+}
+
+static void alloc_common(hss_matrix_t m) {
+  if (!m->dinfo) m->dinfo = (int32_t*)dev_alloc(sizeof(int32_t) * 4);
+  if (!m->dlogdet) m->dlogdet = (double*)dev_alloc(sizeof(double) * (m->nnodes + 1));
+}
+
+static void alloc_factor(hss_matrix_t m) {
+  alloc_common(m);
+  if (m->factor_ready) return;
+  m->dF = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenF, 1));
+  m->dM = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenM, 1));
+  m->dV = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenV, 1));
+  m->dT = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenT, 1));
+  m->dSg = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenSg, 1));
+  m->dW = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenW, 1));
+  m->dX = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenX, 1));
+  FBufs<double> b{m->dD, m->dB, m->dS, m->dF, m->dM, m->dV, m->dT, m->dSg, m->dW, m->dX};
+  m->gemm_plan = build_gemm_plan<double>(m, b);
+  m->factor_ready = true;
+}
+
+static void alloc_factor32(hss_matrix_t m) {
+  alloc_common(m);
+  if (m->factor32_ready) return;
+  auto fa = [](int64_t n) { return (float*)dev_alloc(sizeof(float) * std::max<int64_t>(n, 1)); };
+  m->fD = fa(m->lenD);
+  m->fB = fa(m->lenB);
+  m->fS = fa(m->lenS);
+  m->fF = fa(m->lenF);
+  m->fM = fa(m->lenM);
+  m->fV = fa(m->lenV);
+  m->fT = fa(m->lenT);
+  m->fSg = fa(m->lenSg);
+  m->fW = fa(m->lenW);
+  m->fX = fa(m->lenX);
+  // FP64 scratch for the root block
+  const NodeDesc& root = m->nodes[0];
+  m->dRoot = (double*)dev_alloc(sizeof(double) * (int64_t)root.n * root.n);
+  FBufs<float> b{m->fD, m->fB, m->fS, m->fF, m->fM, m->fV, m->fT, m->fSg, m->fW, m->fX};
+  m->gemm_plan32 = build_gemm_plan<float>(m, b);
+  m->factor32_ready = true;
+}
+
+void free_factor(hss_matrix_t m) {
+  for (auto& lv : m->gemm_plan)
+    for (auto& b : lv) gemm_free(b);
+  for (auto& lv : m->gemm_plan32)
+    for (auto& b : lv) gemm_free(b);
+  m->gemm_plan.clear();
+  m->gemm_plan32.clear();
+  void* ptrs[] = {m->dF, m->dM, m->dV, m->dT, m->dSg, m->dW, m->dX, m->dinfo, m->dlogdet, m->dRoot,
+                  m->fF, m->fM, m->fV, m->fT, m->fSg, m->fW, m->fX, m->fD, m->fB, m->fS};
+  for (void* p : ptrs)
+    if (p) dev_free(p);
+  m->dF = m->dM = m->dV = m->dT = m->dSg = m->dW = m->dX = m->dRoot = nullptr;
+  m->dinfo = nullptr;
+  m->dlogdet = nullptr;
+  m->fF = m->fM = m->fV = m->fT = m->fSg = m->fW = m->fX = m->fD = m->fB = m->fS = nullptr;
+  m->factor_ready = m->factor32_ready = false;
+}
+
+// One level-by-level sweep of Alg. 2 in compute type T (the root separately).
+template <typename T>
+static void factor_levels(hss_matrix_t m, const FBufs<T>& b, std::vector<std::vector<GemmBatch>>& plan) {
+  hipStream_t s = m->ctx->stream;
+  hss_ctx_t cx = m->ctx;
+  for (int l = m->L; l >= 1; --l) {
+    const LevelPlan& lp = m->levels[l];
+    if (l < m->L) {
+      Prof pf(cx, "merge", l);
+      hipLaunchKernelGGL((k_merge<T>), dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const T*)b.F,
+                         (const T*)b.Sg, b.S, b.M, b.F, 0);
+      HSS_HIP(hipGetLastError());
+    }
+    {
+      Prof pf(cx, "basis_qr", l);
+      launch_recon<T>(m, lp, b.B, b.V, b.Tm, b.Sg, s);
+    }
+    auto& st = plan[l];
+    {
+      Prof pf(cx, "gemm_W=MV", l);
+      gemm_run<T>(st[0], false, false, 1.0, 0.0, s);
+    }
+    {
+      Prof pf(cx, "gemm_small_wy", l);
+      gemm_run<T>(st[1], true, false, 1.0, 0.0, s);
+      gemm_run<T>(st[2], false, false, 1.0, 0.0, s);
+      gemm_run<T>(st[3], true, false, 1.0, 0.0, s);
+      gemm_run<T>(st[4], false, false, 1.0, 0.0, s);
+      gemm_run<T>(st[5], false, false, -0.5, 1.0, s);
+    }
+    {
+      Prof pf(cx, "gemm_two_sided_update", l);
+      gemm_run<T>(st[6], false, true, -1.0, 1.0, s);
+      gemm_run<T>(st[7], false, true, -1.0, 1.0, s);
+    }
+    {
+      Prof pf(cx, "partial_cholesky", l);
+      launch_pchol<T>(m, lp.first, lp.count, lp.nmax, b.F, s);
+    }
+  }
+}
+
+void factor_fp64(hss_matrix_t m) {
+  hipStream_t s = m->ctx->stream;
+  alloc_factor(m);
+  HSS_HIP(hipMemsetAsync(m->dinfo, 0, sizeof(int32_t) * 4, s));
+  HSS_HIP(hipMemsetAsync(m->dlogdet, 0, sizeof(double) * (m->nnodes + 1), s));
+  if (m->L == 0) {
+    const NodeDesc& nd = m->nodes[0];
+    HSS_HIP(hipMemcpyAsync(m->dF + nd.offF, m->dD + nd.offD, sizeof(double) * nd.n * nd.n,
+                           hipMemcpyDeviceToDevice, s));
+    launch_pchol<double>(m, 0, 1, nd.n, m->dF, s);
+  } else {
+    FBufs<double> b{m->dD, m->dB, m->dS, m->dF, m->dM, m->dV, m->dT, m->dSg, m->dW, m->dX};
+    factor_levels<double>(m, b, m->gemm_plan);
+    const LevelPlan& root = m->levels[0];
+    HSS_CHECK(m->dM != m->dF, HSS_ERR_DEVICE, "merge buffers alias");
+    Prof pf(m->ctx, "root", 0);
+    hipLaunchKernelGGL((k_merge<double>), dim3(1), dim3(256), 0, s, m->dnodes, 0, (const double*)m->dF,
+                       (const double*)m->dSg, (const double*)m->dS, m->dM, m->dF, 1);
+    HSS_HIP(hipGetLastError());
+    launch_pchol<double>(m, 0, 1, root.nmax, m->dF, s);
+  }
+  hipLaunchKernelGGL(k_sum_logdet, dim3(1), dim3(256), 0, s, (const double*)m->dlogdet, m->nnodes,
+                     m->dlogdet + m->nnodes);
+  HSS_HIP(hipGetLastError());
+}
+
+// Mixed precision: the representation is rounded to FP32, the basis QR, the
+// diagonal product, the panel TRSM and the Schur updates run in FP32 (FP32
+// MFMA, FP32 accumulation); the 16x16 pivot blocks of every partial Cholesky
+// and the whole root Cholesky run in FP64.
+void factor_fp32(hss_matrix_t m) {
+  hipStream_t s = m->ctx->stream;
+  alloc_factor32(m);
+  HSS_HIP(hipMemsetAsync(m->dinfo, 0, sizeof(int32_t) * 4, s));
+  HSS_HIP(hipMemsetAsync(m->dlogdet, 0, sizeof(double) * (m->nnodes + 1), s));
+  {
+    Prof pf(m->ctx, "convert_fp32", m->L);
+    cast<double, float>(m->dD, m->fD, m->lenD, s);
+    cast<double, float>(m->dB, m->fB, m->lenB, s);
+    cast<double, float>(m->dS, m->fS, m->lenS, s);
+  }
+  const NodeDesc& rt = m->nodes[0];
+  if (m->L > 0) {
+    FBufs<float> b{m->fD, m->fB, m->fS, m->fF, m->fM, m->fV, m->fT, m->fSg, m->fW, m->fX};
+    factor_levels<float>(m, b, m->gemm_plan32);
+    Prof pf(m->ctx, "root", 0);
+    hipLaunchKernelGGL((k_merge<float>), dim3(1), dim3(256), 0, s, m->dnodes, 0, (const float*)m->fF,
+                       (const float*)m->fSg, (const float*)m->fS, m->fM, m->fF, 1);
+    HSS_HIP(hipGetLastError());
+    cast<float, double>(m->fF + rt.offF, m->dRoot, (int64_t)rt.n * rt.n, s);
+  } else {
+    cast<double, double>(m->dD + rt.offD, m->dRoot, (int64_t)rt.n * rt.n, s);
+  }
+  // root block in FP64: a one-node table whose block starts at offset 0 of dRoot
+  std::vector<NodeDesc> one(1, rt);
+  one[0].offF = 0;
+  one[0].m = rt.n;
+  if (!m->dRootNode) m->dRootNode = (NodeDesc*)dev_alloc(sizeof(NodeDesc));
+  HSS_HIP(hipMemcpyAsync(m->dRootNode, one.data(), sizeof(NodeDesc), hipMemcpyHostToDevice, s));
+  {
+    dim3 grid(1), block(256);
+    if (rt.n <= 256)
+      hipLaunchKernelGGL((k_pchol<double, 256>), grid, block, 0, s, (const NodeDesc*)m->dRootNode, 0, m->dRoot,
+                         m->dinfo, m->dlogdet);
+    else
+      hipLaunchKernelGGL((k_pchol<double, 512>), grid, block, 0, s, (const NodeDesc*)m->dRootNode, 0, m->dRoot,
+                         m->dinfo, m->dlogdet);
+    HSS_HIP(hipGetLastError());
+  }
+  cast<double, float>(m->dRoot, m->fF + rt.offF, (int64_t)rt.n * rt.n, s);
+  hipLaunchKernelGGL(k_sum_logdet, dim3(1), dim3(256), 0, s, (const double*)m->dlogdet, m->nnodes,
+                     m->dlogdet + m->nnodes);
+  HSS_HIP(hipGetLastError());
+}
+
+double read_logdet(hss_matrix_t m) {
+  double v = 0.0;
+  HSS_HIP(hipMemcpyAsync(&v, m->dlogdet + m->nnodes, sizeof(double), hipMemcpyDeviceToHost, m->ctx->stream));
+  HSS_HIP(hipStreamSynchronize(m->ctx->stream));
+  return v;
+}
+
+}  // namespace hss

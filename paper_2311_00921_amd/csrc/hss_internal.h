@@ -1,0 +1,219 @@
+// Internal definitions shared by the HIP translation units of libhss.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "hss.h"
+
+// ---------------------------------------------------------------------------
+// error plumbing
+// ---------------------------------------------------------------------------
+
+namespace hss {
+
+void set_error(const std::string& msg);
+
+struct Error {
+  hss_status st;
+  std::string msg;
+};
+
+#define HSS_HIP(call)                                                                  \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess)                                                              \
+      throw ::hss::Error{HSS_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+
+#define HSS_CHECK(cond, code, msg)                  \
+  do {                                              \
+    if (!(cond)) throw ::hss::Error{(code), (msg)}; \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// per-node descriptor (heap order: node 0 = root, children 2k+1, 2k+2)
+// ---------------------------------------------------------------------------
+
+struct NodeDesc {
+  int64_t lo;     // first tree position of the node's points
+  int64_t offD;   // leaf: dense block D (n x n), else -1
+  int64_t offB;   // basis (n x r): U at a leaf, E above; -1 at the root
+  int64_t offS;   // coupling of the children (r_c1 x r_c2); -1 at a leaf
+  int64_t offF;   // factor block (n x n) in [R;S] order
+  int64_t offM;   // merged diagonal block (n x n), upper nodes only
+  int64_t offV;   // Householder vectors (n x r)
+  int64_t offT;   // triangular factor T of the compact WY form (r x r)
+  int64_t offSg;  // signs of the S coordinates (r)
+  int64_t offW;   // level scratch for W and Z (n x r each, 2 n r)
+  int64_t offX;   // level scratch for r x r products (2 r r)
+  int64_t offVec; // per-node vector slot (n rows) in solve workspaces
+  int64_t offR;   // per-node rank slot (r rows) in matvec workspaces
+  int32_t npts;   // points below the node
+  int32_t n;      // size of the node's diagonal block in the ULV sweep
+  int32_t r;      // basis rank (0 at the root)
+  int32_t m;      // n - r (redundant rows eliminated at this node)
+  int32_t level;
+  int32_t child_row;  // row offset of this node's skeleton part in the parent's block
+};
+
+struct LevelPlan {
+  int32_t level;
+  int32_t first;   // first heap index on this level
+  int32_t count;   // nodes on this level
+  int32_t nmax, rmax, mmax;
+};
+
+// Batched GEMM entry: C = alpha * op(A) op(B) + beta * Cin, optional symmetric
+// permutation of the output from [S;R] to [R;S] order (perm_r = r > 0).
+struct GemmDesc {
+  const void* A;
+  const void* B;
+  const void* Cin;
+  void* C;
+  int32_t m, n, k;
+  int32_t lda, ldb, ldcin, ldc;
+  int32_t perm_r;  // 0: plain store; r > 0: index t -> (t < r ? t + (dim - r) : t - r)
+  int32_t perm_in; // 1: Cin is read at the permuted position too (in-place update)
+};
+
+struct GemmBatch {
+  std::vector<GemmDesc> host;
+  GemmDesc* dev = nullptr;
+  int32_t count = 0;
+  int32_t mmax = 0, nmax = 0;
+};
+
+}  // namespace hss
+
+// ---------------------------------------------------------------------------
+// context and matrix objects
+// ---------------------------------------------------------------------------
+
+namespace hss {
+struct ProfRec {
+  const char* name;
+  int32_t level;
+  hipEvent_t a, b;
+};
+}  // namespace hss
+
+struct hss_ctx_s {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // per-launch event profiling (off unless enabled)
+  bool prof = false;
+  std::vector<hss::ProfRec> prof_recs;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+};
+
+struct hss_matrix_s {
+  hss_ctx_t ctx = nullptr;
+  int64_t n = 0;
+  int32_t L = 0;
+  int32_t nnodes = 0;
+  int32_t state = 0;  // 0 constructed, 1 factored, 2 failed
+  int32_t precision = 0;
+  int32_t failed_level = -1, failed_node = -1, failed_pivot = -1;
+
+  std::vector<hss::NodeDesc> nodes;  // host copy
+  hss::NodeDesc* dnodes = nullptr;   // device copy
+  std::vector<hss::LevelPlan> levels;
+
+  // representation (device)
+  double* dD = nullptr;
+  double* dB = nullptr;
+  double* dS = nullptr;
+  int64_t* dperm = nullptr;  // tree position -> caller index
+  int64_t lenD = 0, lenB = 0, lenS = 0;
+
+  // factor (device)
+  double* dF = nullptr;
+  double* dM = nullptr;
+  double* dV = nullptr;
+  double* dT = nullptr;
+  double* dSg = nullptr;
+  double* dW = nullptr;
+  double* dX = nullptr;
+  int32_t* dinfo = nullptr;  // [0] status, [1] node, [2] pivot
+  double* dlogdet = nullptr; // per node partial sums
+  int64_t lenF = 0, lenM = 0, lenV = 0, lenT = 0, lenSg = 0, lenW = 0, lenX = 0;
+  bool factor_ready = false;
+  std::vector<std::vector<hss::GemmBatch>> gemm_plan;  // per level, per step
+
+  // FP32 factor (mixed precision)
+  float* fF = nullptr;
+  float* fM = nullptr;
+  float* fV = nullptr;
+  float* fT = nullptr;
+  float* fW = nullptr;
+  float* fX = nullptr;
+  float* fD = nullptr;
+  float* fB = nullptr;
+  float* fS = nullptr;
+  float* fSg = nullptr;
+  double* dRoot = nullptr;          // FP64 root block of the mixed factorization
+  hss::NodeDesc* dRootNode = nullptr;
+  bool factor32_ready = false;
+  std::vector<std::vector<hss::GemmBatch>> gemm_plan32;
+
+  // solve / matvec workspaces (device), sized for ws_nrhs columns
+  double* dvec = nullptr;   // per-node vectors, sum(n) x nrhs
+  double* dxt = nullptr;    // matvec up-sweep, sum(r) x nrhs
+  double* dyt = nullptr;    // matvec down-sweep, sum(r) x nrhs
+  float* fvec = nullptr;
+  int64_t ws_nrhs = 0;
+  int64_t sum_n = 0, sum_r = 0;
+  double* dtmp = nullptr;   // refinement temporaries (4 x N x nrhs)
+  int64_t tmp_len = 0;
+
+  double factor_ms = 0.0, solve_ms = 0.0;
+  int32_t max_rank = 0;
+};
+
+namespace hss {
+
+// Brackets the launches issued in its scope with two events on the context
+// stream when profiling is enabled.
+struct Prof {
+  hss_ctx_t ctx;
+  size_t idx = (size_t)-1;
+  Prof(hss_ctx_t c, const char* name, int level);
+  ~Prof();
+};
+
+// allocation helpers (throw on failure)
+void* dev_alloc(size_t bytes);
+void dev_free(void* p);
+
+// representation setup (capi.cpp)
+void layout_representation(hss_matrix_t m);
+
+// gemm.hip
+void gemm_upload(GemmBatch& b, hipStream_t s);
+void gemm_free(GemmBatch& b);
+void gemm_launch_f64(const GemmBatch& b, bool ta, bool tb, double alpha, double beta, hipStream_t s);
+void gemm_launch_f32(const GemmBatch& b, bool ta, bool tb, float alpha, float beta, hipStream_t s);
+
+// factor.hip
+void factor_fp64(hss_matrix_t m);
+void factor_fp32(hss_matrix_t m);
+double read_logdet(hss_matrix_t m);
+void free_factor(hss_matrix_t m);
+
+// solve.hip
+void ensure_vec_ws(hss_matrix_t m, int64_t nrhs);
+void solve_fp64(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld);
+void solve_fp32(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld);
+void matvec_fp64(hss_matrix_t m, const double* x, double* y, int64_t nrhs, int64_t ld);
+
+// construct.hip
+void construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_kernel& kern,
+               const hss_construct_opts& opts, const double* d_omega, int32_t s);
+
+}  // namespace hss

@@ -1,0 +1,538 @@
+// ULV solve (Sec. 3.2, Eq. 17, applied as ordered products) and the FP64 HSS
+// matrix-vector product, one kernel boundary per level.
+//
+// Forward, leaf to root, node p with block size n, rank r, m = n - r:
+//   b^ = H^T b            (H = I - V T V^T, H[:, :r] = B diag(Sg))
+//   y_R = L_RR^{-1} b^_R  (redundant part, coordinates r..n-1 of b^)
+//   z_S = b^_S - L_SR y_R (skeleton part, coordinates 0..r-1 of b^)
+//   parent's right-hand side rows = Sg * z_S (back to the basis coordinates)
+// Root: L0 L0^T w = z. Backward, root to leaf:
+//   x_S = Sg * (parent's solution rows); x_R = L_RR^{-T} (y_R - L_SR^T x_S)
+//   x = H [x_S; x_R]
+// One wavefront per node; RC right-hand sides are carried together.
+#include "hss_internal.h"
+
+namespace hss {
+
+constexpr int SW = 64;    // threads per node in the solve kernels
+constexpr int SNB = 16;   // block size of the blocked triangular solves
+constexpr int RC = 4;     // right-hand sides per pass
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// t[j, c] = sum_i V[i, j] x[i, c] for j < r (V is n x r, x in LDS with ld n)
+template <typename T>
+__device__ void vt_times(const T* __restrict__ V, int n, int r, const T* x, T* t, int nc) {
+  for (int j = threadIdx.x; j < r; j += SW) {
+    T acc[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc[c] = 0;
+    const T* col = V + (int64_t)j * n;
+    for (int i = 0; i < n; ++i) {
+      const T v = col[i];
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (c < nc) acc[c] += v * x[i + c * n];
+    }
+#pragma unroll
+    for (int c = 0; c < RC; ++c)
+      if (c < nc) t[j + c * r] = acc[c];
+  }
+}
+
+// x[i, c] -= sum_j V[i, j] u[j, c]
+template <typename T>
+__device__ void sub_v_times(const T* __restrict__ V, int n, int r, const T* u, T* x, int nc) {
+  for (int i = threadIdx.x; i < n; i += SW) {
+    T acc[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc[c] = 0;
+    for (int j = 0; j < r; ++j) {
+      const T v = V[i + (int64_t)j * n];
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (c < nc) acc[c] += v * u[j + c * r];
+    }
+#pragma unroll
+    for (int c = 0; c < RC; ++c)
+      if (c < nc) x[i + c * n] -= acc[c];
+  }
+}
+
+// u = T^T t (trans) or u = T t, T upper triangular r x r
+template <typename T>
+__device__ void tri_t_times(const T* __restrict__ Tm, int r, const T* t, T* u, int nc, bool trans) {
+  for (int j = threadIdx.x; j < r; j += SW) {
+    T acc[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc[c] = 0;
+    if (trans) {
+      for (int k = 0; k <= j; ++k) {
+        const T v = Tm[k + (int64_t)j * r];
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+          if (c < nc) acc[c] += v * t[k + c * r];
+      }
+    } else {
+      for (int k = j; k < r; ++k) {
+        const T v = Tm[j + (int64_t)k * r];
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+          if (c < nc) acc[c] += v * t[k + c * r];
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < RC; ++c)
+      if (c < nc) u[j + c * r] = acc[c];
+  }
+}
+
+// In place y = L^{-1} y, L = F[0:m, 0:m] lower (ld = ldf); y in LDS with ld ldy.
+template <typename T>
+__device__ void lower_solve(const T* __restrict__ F, int ldf, int m, T* y, int ldy, int nc) {
+  for (int b0 = 0; b0 < m; b0 += SNB) {
+    const int bb = min(SNB, m - b0);
+    for (int c = 0; c < bb; ++c) {
+      const int k = b0 + c;
+      const T d = F[k + (int64_t)k * ldf];
+      __syncthreads();
+      if (threadIdx.x < nc) y[k + threadIdx.x * ldy] /= d;
+      __syncthreads();
+      // update the rest of this block
+      for (int kk = b0 + c + 1 + threadIdx.x; kk < b0 + bb; kk += SW) {
+        const T l = F[kk + (int64_t)k * ldf];
+#pragma unroll
+        for (int cc = 0; cc < RC; ++cc)
+          if (cc < nc) y[kk + cc * ldy] -= l * y[k + cc * ldy];
+      }
+    }
+    __syncthreads();
+    // panel update of the rows below the block
+    for (int i = b0 + bb + threadIdx.x; i < m; i += SW) {
+      T acc[RC];
+#pragma unroll
+      for (int cc = 0; cc < RC; ++cc) acc[cc] = 0;
+      for (int c = 0; c < bb; ++c) {
+        const T l = F[i + (int64_t)(b0 + c) * ldf];
+#pragma unroll
+        for (int cc = 0; cc < RC; ++cc)
+          if (cc < nc) acc[cc] += l * y[b0 + c + cc * ldy];
+      }
+#pragma unroll
+      for (int cc = 0; cc < RC; ++cc)
+        if (cc < nc) y[i + cc * ldy] -= acc[cc];
+    }
+    __syncthreads();
+  }
+}
+
+// In place x = L^{-T} x, L = F[0:m, 0:m] lower.
+template <typename T>
+__device__ void lower_t_solve(const T* __restrict__ F, int ldf, int m, T* x, int ldx, int nc) {
+  const int nblk = (m + SNB - 1) / SNB;
+  for (int bi = nblk - 1; bi >= 0; --bi) {
+    const int b0 = bi * SNB, bb = min(SNB, m - b0);
+    // x_blk -= L[b0+bb:m, blk]^T x[b0+bb:m]
+    for (int c = 0; c < bb; ++c) {
+      T part[RC];
+#pragma unroll
+      for (int cc = 0; cc < RC; ++cc) part[cc] = 0;
+      for (int i = b0 + bb + threadIdx.x; i < m; i += SW) {
+        const T l = F[i + (int64_t)(b0 + c) * ldf];
+#pragma unroll
+        for (int cc = 0; cc < RC; ++cc)
+          if (cc < nc) part[cc] += l * x[i + cc * ldx];
+      }
+#pragma unroll
+      for (int cc = 0; cc < RC; ++cc) part[cc] = wave_sum(part[cc]);
+      __syncthreads();
+      if (threadIdx.x == 0) {
+#pragma unroll
+        for (int cc = 0; cc < RC; ++cc)
+          if (cc < nc) x[b0 + c + cc * ldx] -= part[cc];
+      }
+    }
+    __syncthreads();
+    // solve the diagonal block backwards
+    for (int c = bb - 1; c >= 0; --c) {
+      const int k = b0 + c;
+      const T d = F[k + (int64_t)k * ldf];
+      if (threadIdx.x < nc) x[k + threadIdx.x * ldx] /= d;
+      __syncthreads();
+      for (int kk = b0 + threadIdx.x; kk < k; kk += SW) {
+        const T l = F[k + (int64_t)kk * ldf];
+#pragma unroll
+        for (int cc = 0; cc < RC; ++cc)
+          if (cc < nc) x[kk + cc * ldx] -= l * x[k + cc * ldx];
+      }
+      __syncthreads();
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(SW) void k_solve_fwd(const NodeDesc* __restrict__ nodes, int first,
+                                                  const T* __restrict__ Fb, const T* __restrict__ Vb,
+                                                  const T* __restrict__ Tb, const T* __restrict__ Sgb,
+                                                  T* __restrict__ vec, int64_t nrhs, int c0, int nc,
+                                                  const double* __restrict__ b, int64_t ld,
+                                                  const int64_t* __restrict__ perm, int leaf) {
+  const int p = first + blockIdx.x;
+  const NodeDesc nd = nodes[p];
+  const int n = nd.n, r = nd.r, m = nd.m;
+  __shared__ T sb[512 * RC];
+  __shared__ T st[128 * RC];
+  __shared__ T su[128 * RC];
+  T* vp = vec + nd.offVec * nrhs;
+  const T* F = Fb + nd.offF;
+  const T* V = Vb + nd.offV;
+  const T* Tm = Tb + nd.offT;
+  const T* Sg = Sgb + nd.offSg;
+  for (int i = threadIdx.x; i < n; i += SW)
+    for (int c = 0; c < nc; ++c)
+      sb[i + c * n] = leaf ? (T)b[perm[nd.lo + i] + (int64_t)(c0 + c) * ld] : vp[i + (int64_t)(c0 + c) * n];
+  __syncthreads();
+  // b^ = b - V T^T V^T b
+  vt_times(V, n, r, sb, st, nc);
+  __syncthreads();
+  tri_t_times(Tm, r, st, su, nc, true);
+  __syncthreads();
+  sub_v_times(V, n, r, su, sb, nc);
+  __syncthreads();
+  // y_R = L_RR^{-1} b^_R  (b^_R = sb[r:n])
+  lower_solve(F, n, m, sb + r, n, nc);
+  __syncthreads();
+  // z_S = b^_S - L_SR y_R
+  for (int j = threadIdx.x; j < r; j += SW) {
+    T acc[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc[c] = 0;
+    for (int k = 0; k < m; ++k) {
+      const T l = F[(m + j) + (int64_t)k * n];
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (c < nc) acc[c] += l * sb[r + k + c * n];
+    }
+#pragma unroll
+    for (int c = 0; c < RC; ++c)
+      if (c < nc) st[j + c * r] = sb[j + c * n] - acc[c];
+  }
+  __syncthreads();
+  // store y_R into this node's slot, Sg * z_S into the parent's
+  for (int i = threadIdx.x; i < m; i += SW)
+    for (int c = 0; c < nc; ++c) vp[i + (int64_t)(c0 + c) * n] = sb[r + i + c * n];
+  const NodeDesc par = nodes[(p - 1) / 2];
+  T* pp = vec + par.offVec * nrhs;
+  for (int j = threadIdx.x; j < r; j += SW)
+    for (int c = 0; c < nc; ++c) pp[nd.child_row + j + (int64_t)(c0 + c) * par.n] = Sg[j] * st[j + c * r];
+}
+
+template <typename T>
+__global__ __launch_bounds__(SW) void k_solve_root(const NodeDesc* __restrict__ nodes, const T* __restrict__ Fb,
+                                                   T* __restrict__ vec, int64_t nrhs, int c0, int nc,
+                                                   const double* __restrict__ b, double* __restrict__ x,
+                                                   int64_t ld, const int64_t* __restrict__ perm, int single) {
+  const NodeDesc nd = nodes[0];
+  const int n = nd.n;
+  __shared__ T sb[512 * RC];
+  T* vp = vec + nd.offVec * nrhs;
+  const T* F = Fb + nd.offF;
+  for (int i = threadIdx.x; i < n; i += SW)
+    for (int c = 0; c < nc; ++c)
+      sb[i + c * n] = single ? (T)b[perm[i] + (int64_t)(c0 + c) * ld] : vp[i + (int64_t)(c0 + c) * n];
+  __syncthreads();
+  lower_solve(F, n, n, sb, n, nc);
+  __syncthreads();
+  lower_t_solve(F, n, n, sb, n, nc);
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += SW)
+    for (int c = 0; c < nc; ++c) {
+      if (single)
+        x[perm[i] + (int64_t)(c0 + c) * ld] = (double)sb[i + c * n];
+      else
+        vp[i + (int64_t)(c0 + c) * n] = sb[i + c * n];
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(SW) void k_solve_bwd(const NodeDesc* __restrict__ nodes, int first,
+                                                  const T* __restrict__ Fb, const T* __restrict__ Vb,
+                                                  const T* __restrict__ Tb, const T* __restrict__ Sgb,
+                                                  T* __restrict__ vec, int64_t nrhs, int c0, int nc,
+                                                  double* __restrict__ x, int64_t ld,
+                                                  const int64_t* __restrict__ perm, int leaf) {
+  const int p = first + blockIdx.x;
+  const NodeDesc nd = nodes[p];
+  const int n = nd.n, r = nd.r, m = nd.m;
+  __shared__ T sx[512 * RC];
+  __shared__ T st[128 * RC];
+  __shared__ T su[128 * RC];
+  T* vp = vec + nd.offVec * nrhs;
+  const T* F = Fb + nd.offF;
+  const T* V = Vb + nd.offV;
+  const T* Tm = Tb + nd.offT;
+  const T* Sg = Sgb + nd.offSg;
+  const NodeDesc par = nodes[(p - 1) / 2];
+  const T* pp = vec + par.offVec * nrhs;
+  // x_S (H coordinates) into sx[0:r], y_R into sx[r:n]
+  for (int j = threadIdx.x; j < r; j += SW)
+    for (int c = 0; c < nc; ++c) sx[j + c * n] = Sg[j] * pp[nd.child_row + j + (int64_t)(c0 + c) * par.n];
+  for (int i = threadIdx.x; i < m; i += SW)
+    for (int c = 0; c < nc; ++c) sx[r + i + c * n] = vp[i + (int64_t)(c0 + c) * n];
+  __syncthreads();
+  // t = y_R - L_SR^T x_S
+  for (int k = threadIdx.x; k < m; k += SW) {
+    T acc[RC];
+#pragma unroll
+    for (int c = 0; c < RC; ++c) acc[c] = 0;
+    const T* col = F + m + (int64_t)k * n;
+    for (int j = 0; j < r; ++j) {
+      const T l = col[j];
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (c < nc) acc[c] += l * sx[j + c * n];
+    }
+#pragma unroll
+    for (int c = 0; c < RC; ++c)
+      if (c < nc) sx[r + k + c * n] -= acc[c];
+  }
+  __syncthreads();
+  lower_t_solve(F, n, m, sx + r, n, nc);
+  __syncthreads();
+  // x = H x^ = x^ - V T V^T x^
+  vt_times(V, n, r, sx, st, nc);
+  __syncthreads();
+  tri_t_times(Tm, r, st, su, nc, false);
+  __syncthreads();
+  sub_v_times(V, n, r, su, sx, nc);
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += SW)
+    for (int c = 0; c < nc; ++c) {
+      if (leaf)
+        x[perm[nd.lo + i] + (int64_t)(c0 + c) * ld] = (double)sx[i + c * n];
+      else
+        vp[i + (int64_t)(c0 + c) * n] = sx[i + c * n];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 HSS matvec
+// ---------------------------------------------------------------------------
+
+// leaves: xt_i = U_i^T x_i (x gathered through perm)
+__global__ __launch_bounds__(256) void k_mv_up_leaf(const NodeDesc* __restrict__ nodes, int first,
+                                                    const double* __restrict__ Bb, const double* __restrict__ x,
+                                                    int64_t ld, int64_t nrhs, const int64_t* __restrict__ perm,
+                                                    double* __restrict__ xt) {
+  const NodeDesc nd = nodes[first + blockIdx.x];
+  const int n = nd.n, r = nd.r;
+  __shared__ double sx[512];
+  const double* U = Bb + nd.offB;
+  for (int64_t c = 0; c < nrhs; ++c) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sx[i] = x[perm[nd.lo + i] + c * ld];
+    __syncthreads();
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int j = wid; j < r; j += blockDim.x >> 6) {
+      double acc = 0.0;
+      for (int i = lane; i < n; i += 64) acc += U[i + (int64_t)j * n] * sx[i];
+      acc = wave_sum(acc);
+      if (lane == 0) xt[nd.offR * nrhs + j + c * r] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// upper: xt_p = E_p^T [xt_c1; xt_c2]
+__global__ __launch_bounds__(256) void k_mv_up(const NodeDesc* __restrict__ nodes, int first,
+                                               const double* __restrict__ Bb, int64_t nrhs,
+                                               double* __restrict__ xt) {
+  const int p = first + blockIdx.x;
+  const NodeDesc nd = nodes[p];
+  const NodeDesc c1 = nodes[2 * p + 1], c2 = nodes[2 * p + 2];
+  const int n = nd.n, r = nd.r;
+  const double* E = Bb + nd.offB;
+  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int64_t c = 0; c < nrhs; ++c) {
+    for (int j = wid; j < r; j += blockDim.x >> 6) {
+      double acc = 0.0;
+      for (int i = lane; i < n; i += 64) {
+        const double v = (i < c1.r) ? xt[c1.offR * nrhs + i + c * c1.r] : xt[c2.offR * nrhs + (i - c1.r) + c * c2.r];
+        acc += E[i + (int64_t)j * n] * v;
+      }
+      acc = wave_sum(acc);
+      if (lane == 0) xt[nd.offR * nrhs + j + c * r] = acc;
+    }
+  }
+}
+
+// couplings of the children of each node on a level: yt_c1 = S xt_c2, yt_c2 = S^T xt_c1
+__global__ __launch_bounds__(256) void k_mv_coupling(const NodeDesc* __restrict__ nodes, int first,
+                                                     const double* __restrict__ Sb, int64_t nrhs,
+                                                     const double* __restrict__ xt, double* __restrict__ yt) {
+  const int p = first + blockIdx.x;
+  const NodeDesc nd = nodes[p];
+  const NodeDesc c1 = nodes[2 * p + 1], c2 = nodes[2 * p + 2];
+  const int r1 = c1.r, r2 = c2.r;
+  const double* S = Sb + nd.offS;
+  for (int64_t c = 0; c < nrhs; ++c) {
+    for (int i = threadIdx.x; i < r1; i += blockDim.x) {
+      double acc = 0.0;
+      for (int j = 0; j < r2; ++j) acc += S[i + (int64_t)j * r1] * xt[c2.offR * nrhs + j + c * r2];
+      yt[c1.offR * nrhs + i + c * r1] = acc;
+    }
+    for (int j = threadIdx.x; j < r2; j += blockDim.x) {
+      double acc = 0.0;
+      for (int i = 0; i < r1; ++i) acc += S[i + (int64_t)j * r1] * xt[c1.offR * nrhs + i + c * r1];
+      yt[c2.offR * nrhs + j + c * r2] = acc;
+    }
+  }
+}
+
+// down-sweep: [yt_c1; yt_c2] += E_p yt_p
+__global__ __launch_bounds__(256) void k_mv_down(const NodeDesc* __restrict__ nodes, int first,
+                                                 const double* __restrict__ Bb, int64_t nrhs,
+                                                 double* __restrict__ yt) {
+  const int p = first + blockIdx.x;
+  const NodeDesc nd = nodes[p];
+  const NodeDesc c1 = nodes[2 * p + 1], c2 = nodes[2 * p + 2];
+  const int n = nd.n, r = nd.r;
+  const double* E = Bb + nd.offB;
+  for (int64_t c = 0; c < nrhs; ++c) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double acc = 0.0;
+      for (int j = 0; j < r; ++j) acc += E[i + (int64_t)j * n] * yt[nd.offR * nrhs + j + c * r];
+      if (i < c1.r)
+        yt[c1.offR * nrhs + i + c * c1.r] += acc;
+      else
+        yt[c2.offR * nrhs + (i - c1.r) + c * c2.r] += acc;
+    }
+  }
+}
+
+// leaves: y_i = D_i x_i + U_i yt_i, scattered through perm
+__global__ __launch_bounds__(256) void k_mv_leaf(const NodeDesc* __restrict__ nodes, int first,
+                                                 const double* __restrict__ Db, const double* __restrict__ Bb,
+                                                 const double* __restrict__ x, double* __restrict__ y, int64_t ld,
+                                                 int64_t nrhs, const int64_t* __restrict__ perm,
+                                                 const double* __restrict__ yt, int has_yt) {
+  const NodeDesc nd = nodes[first + blockIdx.x];
+  const int n = nd.n, r = nd.r;
+  __shared__ double sx[512];
+  __shared__ double sy[128];
+  const double* D = Db + nd.offD;
+  const double* U = Bb + nd.offB;
+  for (int64_t c = 0; c < nrhs; ++c) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) sx[i] = x[perm[nd.lo + i] + c * ld];
+    if (has_yt)
+      for (int j = threadIdx.x; j < r; j += blockDim.x) sy[j] = yt[nd.offR * nrhs + j + c * r];
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+      double acc = 0.0;
+      for (int k = 0; k < n; ++k) acc += D[i + (int64_t)k * n] * sx[k];
+      if (has_yt)
+        for (int j = 0; j < r; ++j) acc += U[i + (int64_t)j * n] * sy[j];
+      y[perm[nd.lo + i] + c * ld] = acc;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host drivers
+// ---------------------------------------------------------------------------
+
+void ensure_vec_ws(hss_matrix_t m, int64_t nrhs) {
+  if (m->ws_nrhs >= nrhs) return;
+  if (m->dvec) dev_free(m->dvec);
+  if (m->dxt) dev_free(m->dxt);
+  if (m->dyt) dev_free(m->dyt);
+  if (m->fvec) dev_free(m->fvec);
+  m->fvec = nullptr;
+  m->dvec = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->sum_n * nrhs, 1));
+  m->dxt = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->sum_r * nrhs, 1));
+  m->dyt = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->sum_r * nrhs, 1));
+  m->ws_nrhs = nrhs;
+}
+
+template <typename T>
+static void solve_impl(hss_matrix_t m, const T* F, const T* V, const T* Tm, const T* Sg, T* vec,
+                       const double* b, double* x, int64_t nrhs, int64_t ld) {
+  hipStream_t s = m->ctx->stream;
+  for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
+    const int nc = (int)std::min<int64_t>(RC, nrhs - c0);
+    if (m->L == 0) {
+      hipLaunchKernelGGL((k_solve_root<T>), dim3(1), dim3(SW), 0, s, m->dnodes, F, vec, nrhs, (int)c0, nc, b, x,
+                         ld, (const int64_t*)m->dperm, 1);
+      HSS_HIP(hipGetLastError());
+      continue;
+    }
+    for (int l = m->L; l >= 1; --l) {
+      const LevelPlan& lp = m->levels[l];
+      Prof pf(m->ctx, "solve_forward", l);
+      hipLaunchKernelGGL((k_solve_fwd<T>), dim3(lp.count), dim3(SW), 0, s, m->dnodes, lp.first, F, V, Tm, Sg, vec,
+                         nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, l == m->L ? 1 : 0);
+      HSS_HIP(hipGetLastError());
+    }
+    hipLaunchKernelGGL((k_solve_root<T>), dim3(1), dim3(SW), 0, s, m->dnodes, F, vec, nrhs, (int)c0, nc, b, x, ld,
+                       (const int64_t*)m->dperm, 0);
+    HSS_HIP(hipGetLastError());
+    for (int l = 1; l <= m->L; ++l) {
+      const LevelPlan& lp = m->levels[l];
+      Prof pf(m->ctx, "solve_backward", l);
+      hipLaunchKernelGGL((k_solve_bwd<T>), dim3(lp.count), dim3(SW), 0, s, m->dnodes, lp.first, F, V, Tm, Sg, vec,
+                         nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, l == m->L ? 1 : 0);
+      HSS_HIP(hipGetLastError());
+    }
+  }
+}
+
+void solve_fp64(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld) {
+  ensure_vec_ws(m, nrhs);
+  HSS_CHECK(b != x || true, HSS_ERR_INVALID_ARGUMENT, "");
+  solve_impl<double>(m, m->dF, m->dV, m->dT, m->dSg, m->dvec, b, x, nrhs, ld);
+}
+
+void matvec_fp64(hss_matrix_t m, const double* x, double* y, int64_t nrhs, int64_t ld) {
+  hipStream_t s = m->ctx->stream;
+  ensure_vec_ws(m, nrhs);
+  const int L = m->L;
+  const int64_t* perm = m->dperm;
+  if (L == 0) {
+    hipLaunchKernelGGL(k_mv_leaf, dim3(1), dim3(256), 0, s, m->dnodes, 0, (const double*)m->dD,
+                       (const double*)m->dB, x, y, ld, nrhs, perm, (const double*)m->dyt, 0);
+    HSS_HIP(hipGetLastError());
+    return;
+  }
+  const LevelPlan& leaves = m->levels[L];
+  hipLaunchKernelGGL(k_mv_up_leaf, dim3(leaves.count), dim3(256), 0, s, m->dnodes, leaves.first,
+                     (const double*)m->dB, x, ld, nrhs, perm, m->dxt);
+  HSS_HIP(hipGetLastError());
+  for (int l = L - 1; l >= 1; --l) {
+    const LevelPlan& lp = m->levels[l];
+    hipLaunchKernelGGL(k_mv_up, dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const double*)m->dB, nrhs,
+                       m->dxt);
+    HSS_HIP(hipGetLastError());
+  }
+  for (int l = 0; l < L; ++l) {
+    const LevelPlan& lp = m->levels[l];
+    hipLaunchKernelGGL(k_mv_coupling, dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const double*)m->dS,
+                       nrhs, (const double*)m->dxt, m->dyt);
+    HSS_HIP(hipGetLastError());
+  }
+  for (int l = 1; l < L; ++l) {
+    const LevelPlan& lp = m->levels[l];
+    hipLaunchKernelGGL(k_mv_down, dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const double*)m->dB, nrhs,
+                       m->dyt);
+    HSS_HIP(hipGetLastError());
+  }
+  hipLaunchKernelGGL(k_mv_leaf, dim3(leaves.count), dim3(256), 0, s, m->dnodes, leaves.first, (const double*)m->dD,
+                     (const double*)m->dB, x, y, ld, nrhs, perm, (const double*)m->dyt, 1);
+  HSS_HIP(hipGetLastError());
+}
+
+}  // namespace hss

@@ -1,0 +1,389 @@
+"""Python binding of libhss.so: the C entry points under the same names.
+
+Argument marshalling only: torch tensors (device memory, streams) are turned
+into raw pointers and sizes, host arrays into packed FP64 buffers in the layout
+that include/hss.h documents. Every step of the computation runs in the HIP
+library; if the library is missing the import fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhss.so")
+
+HSS_OK = 0
+HSS_ERR_INVALID_ARGUMENT = 1
+HSS_ERR_NOT_SPD = 2
+HSS_ERR_OUT_OF_MEMORY = 3
+HSS_ERR_DEVICE = 4
+HSS_ERR_BAD_STATE = 5
+HSS_ERR_NOT_CONVERGED = 6
+HSS_ERR_UNSUPPORTED = 7
+
+KERNELS = {"exponential": 0, "matern32": 1, "gaussian": 2, "laplace2d": 3, "yukawa": 4}
+HSS_P_FP64 = 0
+HSS_P_FP32 = 1
+HSS_COMPRESS_SCALED = 1
+
+
+class HSSError(RuntimeError):
+    def __init__(self, status: int, where: str, msg: str):
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+class hss_kernel(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("length", C.c_double), ("sigma2", C.c_double),
+                ("nugget", C.c_double), ("alpha", C.c_double), ("eps", C.c_double)]
+
+
+class hss_construct_opts(C.Structure):
+    _fields_ = [("leaf_size", C.c_int32), ("levels", C.c_int32), ("rank", C.c_int32),
+                ("max_rank", C.c_int32), ("tol", C.c_double), ("mode", C.c_int32)]
+
+
+class hss_factor_opts(C.Structure):
+    _fields_ = [("precision", C.c_int32)]
+
+
+class hss_desc(C.Structure):
+    _fields_ = [("n", C.c_int64), ("levels", C.c_int32),
+                ("leaf_lo", C.POINTER(C.c_int64)), ("rank", C.POINTER(C.c_int32)),
+                ("D", C.POINTER(C.c_double)), ("U", C.POINTER(C.c_double)),
+                ("E", C.POINTER(C.c_double)), ("S", C.POINTER(C.c_double)),
+                ("perm", C.POINTER(C.c_int64))]
+
+
+class hss_desc_out(C.Structure):
+    _fields_ = [("leaf_lo", C.POINTER(C.c_int64)), ("rank", C.POINTER(C.c_int32)),
+                ("D", C.POINTER(C.c_double)), ("U", C.POINTER(C.c_double)),
+                ("E", C.POINTER(C.c_double)), ("S", C.POINTER(C.c_double)),
+                ("perm", C.POINTER(C.c_int64))]
+
+
+class hss_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("levels", C.c_int32), ("factored", C.c_int32),
+                ("precision", C.c_int32), ("max_rank", C.c_int32), ("failed_level", C.c_int32),
+                ("failed_node", C.c_int32), ("failed_pivot", C.c_int32),
+                ("bytes_representation", C.c_int64), ("bytes_factor", C.c_int64),
+                ("factor_ms", C.c_double), ("solve_ms", C.c_double)]
+
+
+# Every symbol include/hss.h declares, with its ctypes signature.
+_P = C.c_void_p
+SIGNATURES = {
+    "hss_ctx_create": (C.c_int, [C.c_int32, _P, C.POINTER(_P)]),
+    "hss_ctx_destroy": (C.c_int, [_P]),
+    "hss_ctx_set_stream": (C.c_int, [_P, _P]),
+    "hss_construct": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.POINTER(hss_kernel),
+                                C.POINTER(hss_construct_opts), _P, C.c_int32, C.POINTER(_P)]),
+    "hss_import": (C.c_int, [_P, C.POINTER(hss_desc), C.POINTER(_P)]),
+    "hss_export_sizes": (C.c_int, [_P, C.POINTER(C.c_int64)]),
+    "hss_export": (C.c_int, [_P, _P, C.POINTER(hss_desc_out)]),
+    "hss_ulv_factor": (C.c_int, [_P, _P, C.POINTER(hss_factor_opts)]),
+    "hss_ulv_solve": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64]),
+    "hss_ulv_solve_refined": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64, C.c_double, C.c_int32,
+                                        C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+    "hss_matvec": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64]),
+    "hss_logdet": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
+    "hss_get_info": (C.c_int, [_P, C.POINTER(hss_info)]),
+    "hss_get_permutation": (C.c_int, [_P, _P, _P]),
+    "hss_debug_node_block": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
+    "hss_profile_enable": (C.c_int, [_P, C.c_int32]),
+    "hss_profile_read": (C.c_int, [_P, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)]),
+    "hss_matrix_destroy": (C.c_int, [_P]),
+    "hss_status_string": (C.c_char_p, [C.c_int]),
+    "hss_last_error": (C.c_char_p, []),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libhss.so; raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python -m paper_2311_00921_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status != HSS_OK:
+        lib = load()
+        raise HSSError(status, where, lib.hss_last_error().decode())
+
+
+def _ptr(t) -> int:
+    return t.data_ptr()
+
+
+def _stream_ptr(stream) -> int:
+    if stream is None:
+        import torch
+
+        stream = torch.cuda.current_stream()
+    return int(stream.cuda_stream)
+
+
+def _colmajor(t, n):
+    """View a (n,) or (n, k) tensor as column-major n x k: returns (tensor, k, ld)."""
+    if t.dim() == 1:
+        return t.contiguous(), 1, n
+    if t.stride(0) == 1 and t.stride(1) >= n:
+        return t, t.shape[1], t.stride(1)
+    tc = t.t().contiguous().t()
+    return tc, t.shape[1], n
+
+
+# --------------------------------------------------------------------------
+# entry points
+# --------------------------------------------------------------------------
+
+
+def hss_ctx_create(device: int = 0, stream=None):
+    lib = load()
+    out = C.c_void_p()
+    _check(lib.hss_ctx_create(device, _stream_ptr(stream), C.byref(out)), "hss_ctx_create")
+    return out
+
+
+def hss_ctx_destroy(ctx):
+    _check(load().hss_ctx_destroy(ctx), "hss_ctx_destroy")
+
+
+def hss_ctx_set_stream(ctx, stream):
+    _check(load().hss_ctx_set_stream(ctx, _stream_ptr(stream)), "hss_ctx_set_stream")
+
+
+def pack_desc(h: dict):
+    """Packs an HSS matrix given per level (dict with n, levels, ranges, rank,
+    D, U, E, S as lists; optional perm) into the heap-ordered hss_desc arrays."""
+    L = int(h["levels"])
+    n = int(h["n"])
+    leaf_lo = np.array([lo for lo, _ in h["ranges"][L]] + [n], dtype=np.int64)
+    nnodes = 2 ** (L + 1) - 1
+    rank = np.zeros(nnodes, dtype=np.int32)
+    for l in range(1, L + 1):
+        for i in range(2 ** l):
+            rank[2 ** l - 1 + i] = int(h["rank"][l][i])
+
+    def cat(mats):
+        if not mats:
+            return np.zeros(1)
+        return np.concatenate([np.asarray(M, dtype=np.float64).ravel(order="F") for M in mats])
+
+    D = cat(h["D"])
+    U = cat(h["U"]) if L > 0 else np.zeros(1)
+    E = cat([h["E"][l][i] for l in range(1, L) for i in range(2 ** l)]) if L > 1 else np.zeros(1)
+    S = cat([h["S"][l][i] for l in range(L) for i in range(2 ** l)]) if L > 0 else np.zeros(1)
+    perm = h.get("perm")
+    perm = None if perm is None else np.ascontiguousarray(perm, dtype=np.int64)
+    return dict(n=n, levels=L, leaf_lo=leaf_lo, rank=rank, D=D, U=U, E=E, S=S, perm=perm)
+
+
+def hss_import(ctx, h: dict):
+    """Uploads an HSS matrix (see pack_desc for the accepted dict)."""
+    lib = load()
+    p = pack_desc(h)
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    desc = hss_desc(p["n"], p["levels"], p["leaf_lo"].ctypes.data_as(C.POINTER(C.c_int64)),
+                    p["rank"].ctypes.data_as(C.POINTER(C.c_int32)), dp(p["D"]), dp(p["U"]), dp(p["E"]),
+                    dp(p["S"]),
+                    None if p["perm"] is None else p["perm"].ctypes.data_as(C.POINTER(C.c_int64)))
+    out = C.c_void_p()
+    _check(lib.hss_import(ctx, C.byref(desc), C.byref(out)), "hss_import")
+    return out
+
+
+def hss_export(ctx, m):
+    """Downloads the representation: returns dict(n, levels, leaf_lo, rank (heap
+    order), D, U, E, S (packed, heap order as in include/hss.h), perm)."""
+    lib = load()
+    sizes = (C.c_int64 * 7)()
+    _check(lib.hss_export_sizes(m, sizes), "hss_export_sizes")
+    leaf_lo = np.zeros(sizes[0], np.int64)
+    rank = np.zeros(sizes[1], np.int32)
+    D = np.zeros(max(sizes[2], 1))
+    U = np.zeros(max(sizes[3], 1))
+    E = np.zeros(max(sizes[4], 1))
+    S = np.zeros(max(sizes[5], 1))
+    perm = np.zeros(sizes[6], np.int64)
+    dp = lambda a: a.ctypes.data_as(C.POINTER(C.c_double))
+    o = hss_desc_out(leaf_lo.ctypes.data_as(C.POINTER(C.c_int64)), rank.ctypes.data_as(C.POINTER(C.c_int32)),
+                     dp(D), dp(U), dp(E), dp(S), perm.ctypes.data_as(C.POINTER(C.c_int64)))
+    _check(lib.hss_export(ctx, m, C.byref(o)), "hss_export")
+    info = hss_get_info(m)
+    return dict(n=int(info.n), levels=int(info.levels), leaf_lo=leaf_lo, rank=rank, D=D[:sizes[2]],
+                U=U[:sizes[3]], E=E[:sizes[4]], S=S[:sizes[5]], perm=perm)
+
+
+def unpack_desc(p: dict) -> dict:
+    """Inverse of pack_desc: per-level lists from the packed heap-order arrays."""
+    L, n = p["levels"], p["n"]
+    leaf_lo = p["leaf_lo"]
+    rank = p["rank"]
+    ranges = [[(int(leaf_lo[i * 2 ** (L - l)]), int(leaf_lo[(i + 1) * 2 ** (L - l)])) for i in range(2 ** l)]
+              for l in range(L + 1)]
+    rk = [[] for _ in range(L + 1)]
+    for l in range(1, L + 1):
+        rk[l] = [int(rank[2 ** l - 1 + i]) for i in range(2 ** l)]
+
+    def rows(l, i):
+        if l == L:
+            lo, hi = ranges[L][i]
+            return hi - lo
+        return rk[l + 1][2 * i] + rk[l + 1][2 * i + 1]
+
+    D, U, E, S = [], [], [[] for _ in range(max(L, 1))], [[] for _ in range(max(L, 1))]
+    o = 0
+    for i in range(2 ** L):
+        k = rows(L, i)
+        D.append(p["D"][o:o + k * k].reshape((k, k), order="F"))
+        o += k * k
+    if L > 0:
+        o = 0
+        for i in range(2 ** L):
+            k, r = rows(L, i), rk[L][i]
+            U.append(p["U"][o:o + k * r].reshape((k, r), order="F"))
+            o += k * r
+        o = 0
+        for l in range(1, L):
+            for i in range(2 ** l):
+                k, r = rows(l, i), rk[l][i]
+                E[l].append(p["E"][o:o + k * r].reshape((k, r), order="F"))
+                o += k * r
+        o = 0
+        for l in range(L):
+            for i in range(2 ** l):
+                a, b = rk[l + 1][2 * i], rk[l + 1][2 * i + 1]
+                S[l].append(p["S"][o:o + a * b].reshape((a, b), order="F"))
+                o += a * b
+    return dict(n=n, levels=L, ranges=ranges, rank=rk, D=D, U=U, E=E, S=S, perm=p.get("perm"))
+
+
+def hss_construct(ctx, points, kernel: str, leaf: int, rank: int = 0, tol: float = 0.0, max_rank: int = 0,
+                  omega=None, length: float = 1.0, nugget: float = 0.0, sigma2: float = 1.0,
+                  alpha: float = 1.0, eps: float = 1e-9, levels: int = 0):
+    """Builds the HSS approximation of the kernel matrix on device points (N x dim, row-major)."""
+    lib = load()
+    pts = points.contiguous()
+    n, dim = pts.shape
+    om, s, ld = _colmajor(omega, n)
+    if ld != n:
+        om = om.t().contiguous().t()
+    k = hss_kernel(KERNELS[kernel], length, sigma2, nugget, alpha, eps)
+    o = hss_construct_opts(leaf, levels, rank, max_rank, tol, HSS_COMPRESS_SCALED)
+    out = C.c_void_p()
+    _check(lib.hss_construct(ctx, _ptr(pts), n, dim, C.byref(k), C.byref(o), _ptr(om), s, C.byref(out)),
+           "hss_construct")
+    return out
+
+
+def hss_ulv_factor(ctx, m, precision: int = HSS_P_FP64):
+    o = hss_factor_opts(precision)
+    _check(load().hss_ulv_factor(ctx, m, C.byref(o)), "hss_ulv_factor")
+
+
+def hss_ulv_solve(ctx, m, b, x=None):
+    """x = A^{-1} b for a (N,) or (N, nrhs) float64 device tensor b."""
+    import torch
+
+    n = b.shape[0]
+    bc, k, ld = _colmajor(b, n)
+    if x is None:
+        x = torch.empty_strided(bc.shape, bc.stride(), dtype=torch.float64, device=b.device)
+    _check(load().hss_ulv_solve(ctx, m, _ptr(bc), _ptr(x), k, ld), "hss_ulv_solve")
+    return x
+
+
+def hss_ulv_solve_refined(ctx, m, b, tol: float, max_iters: int = 50, x=None):
+    import torch
+
+    n = b.shape[0]
+    bc, k, ld = _colmajor(b, n)
+    if x is None:
+        x = torch.empty_strided(bc.shape, bc.stride(), dtype=torch.float64, device=b.device)
+    iters = C.c_int32(0)
+    rr = C.c_double(0.0)
+    st = load().hss_ulv_solve_refined(ctx, m, _ptr(bc), _ptr(x), k, ld, tol, max_iters, C.byref(iters),
+                                      C.byref(rr))
+    if st not in (HSS_OK, HSS_ERR_NOT_CONVERGED):
+        _check(st, "hss_ulv_solve_refined")
+    return x, int(iters.value), float(rr.value), st == HSS_OK
+
+
+def hss_matvec(ctx, m, x, y=None):
+    import torch
+
+    n = x.shape[0]
+    xc, k, ld = _colmajor(x, n)
+    if y is None:
+        y = torch.empty_strided(xc.shape, xc.stride(), dtype=torch.float64, device=x.device)
+    _check(load().hss_matvec(ctx, m, _ptr(xc), _ptr(y), k, ld), "hss_matvec")
+    return y
+
+
+def hss_logdet(ctx, m) -> float:
+    out = C.c_double()
+    _check(load().hss_logdet(ctx, m, C.byref(out)), "hss_logdet")
+    return float(out.value)
+
+
+def hss_get_info(m) -> hss_info:
+    info = hss_info()
+    _check(load().hss_get_info(m, C.byref(info)), "hss_get_info")
+    return info
+
+
+def hss_get_permutation(ctx, m, out):
+    _check(load().hss_get_permutation(ctx, m, _ptr(out)), "hss_get_permutation")
+    return out
+
+
+def hss_debug_node_block(ctx, m, node: int, what: int, rows: int) -> np.ndarray:
+    buf = np.zeros(rows * rows)
+    _check(load().hss_debug_node_block(ctx, m, node, what, buf.ctypes.data_as(C.POINTER(C.c_double)), buf.size),
+           "hss_debug_node_block")
+    return buf.reshape((rows, rows), order="F")
+
+
+def hss_profile_enable(ctx, on: bool):
+    _check(load().hss_profile_enable(ctx, 1 if on else 0), "hss_profile_enable")
+
+
+def hss_profile_read(ctx):
+    """Returns {(step, level): (launch groups, total ms)} of the recorded launches."""
+    lib = load()
+    need = C.c_int64(0)
+    _check(lib.hss_profile_read(ctx, None, 0, C.byref(need)), "hss_profile_read")
+    buf = C.create_string_buffer(int(need.value) + 1)
+    _check(lib.hss_profile_read(ctx, buf, len(buf), C.byref(need)), "hss_profile_read")
+    out = {}
+    for line in buf.value.decode().splitlines():
+        name, level, cnt, ms = line.split()
+        out[(name, int(level))] = (int(cnt), float(ms))
+    return out
+
+
+def hss_matrix_destroy(m):
+    _check(load().hss_matrix_destroy(m), "hss_matrix_destroy")
+
+
+def hss_status_string(status: int) -> str:
+    return load().hss_status_string(status).decode()
+
+
+def hss_last_error() -> str:
+    return load().hss_last_error().decode()
