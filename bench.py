@@ -158,32 +158,63 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
     roof.update({"kernel": f"{dom_step}@level{dom_level}", "avg_launch_ms": round(avg_ms, 4),
                  "algorithmic_per_launch": flops if roof["unit"] == "TFLOP/s" else byts})
+    # mixed form: FP32 factorization + refinement with the FP64 HSS matvec to rel. residual 1e-8
+    mixed = None
+    try:
+        def run_mixed(steps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            out = None
+            for _ in range(steps):
+                hss.hss_ulv_factor(ctx, m, hss.HSS_P_FP32)
+                out = hss.hss_ulv_solve_refined(ctx, m, b, 1e-8, 50)
+            torch.cuda.synchronize()
+            return (time.perf_counter() - t) / steps, out
+
+        for _ in range(args.warmup):
+            run_mixed(1)
+        print("# timing mixed factor+refined solve", file=sys.stderr, flush=True)
+        t_mixed, (xm, iters, rr_m, ok_m) = run_mixed(args.steps)
+        err_vs_fp64 = float(torch.linalg.norm(xm - x) / torch.linalg.norm(x))
+        logdet32 = hss.hss_logdet(ctx, m)
+        mixed = {"factor_plus_refined_solve_s": round(t_mixed, 6), "converged": bool(ok_m), "corrections": iters,
+                 "relres": rr_m, "rel_diff_x_vs_fp64": err_vs_fp64, "logdet": logdet32,
+                 "rel_diff_logdet_vs_fp64": abs(logdet32 - logdet) / abs(logdet)}
+    except Exception as e:  # report, keep the FP64 result
+        mixed = {"error": str(e)}
+    # leave the matrix factored in FP64 for anything after
+    hss.hss_ulv_factor(ctx, m, hss.HSS_P_FP64)
     total_factor_flops = sum(step_flops(sname, n, rr) for _, l, n, rr in nodes if l > 0
                              for sname in ("gemm_W=MV", "gemm_two_sided_update", "gemm_small_wy",
                                            "partial_cholesky", "basis_qr"))
 
+    use_mixed = bool(mixed and mixed.get("converged"))
+    value = mixed["factor_plus_refined_solve_s"] if use_mixed else t_fp64
     result = {
         "metric": "HSS-ULV factor+solve s at N=262144; mixed+IR vs FP64 at rel. residual 1e-8",
-        "value": round(t_fp64, 6),
+        "value": round(value, 6),
         "unit": "s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(t_fp64 * 1e3, 3),
+        "ms_per_step": round(value * 1e3, 3),
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64" if use_mixed else "f64",
         "data": "synthetic",
         "config": {"workload": w.name, "N": w.n, "dim": w.dim, "kernel": w.kernel, "length": w.length,
                    "nugget": w.nugget, "leaf": w.leaf, "levels": L, "rank": w.rank, "nrhs": 1,
-                   "compression": "scaled randomized", "samples": s, "precision": "fp64"},
+                   "compression": "scaled randomized", "samples": s,
+                   "precision": "mixed fp32/fp64 + refinement" if use_mixed else "fp64"},
         "roofline": roof,
         "fp64": {"factor_plus_solve_s": round(t_fp64, 6), "relres": relres, "logdet": logdet,
                  "factor_ms_events": round(info.factor_ms, 3), "algorithmic_factor_gflop": round(total_factor_flops / 1e9, 2),
                  "factor_gflops_per_s": round(total_factor_flops / 1e9 / (info.factor_ms * 1e-3), 1),
                  "profiled_step_s": round(t_prof, 6),
                  "ms_by_step": {k: round(v / args.steps, 3) for k, v in sorted(by_step.items(), key=lambda kv: -kv[1])}},
+        "mixed": mixed,
+        "speedup_mixed_vs_fp64": round(t_fp64 / value, 3) if use_mixed else None,
         "construct_s": round(construct_s, 3),
     }
 

@@ -98,8 +98,10 @@ void layout_representation(hss_matrix_t m) {
     oF += (int64_t)d.n * d.n;
     d.offM = leaf ? -1 : oM;
     if (!leaf) oM += (int64_t)d.n * d.n;
-    d.offV = oV;
-    oV += (int64_t)d.n * d.r;
+    // V sits in the middle of an n x 3r slot: [Z V Z] lets the two-sided update
+    // read [Z V] and [V Z] as contiguous n x 2r operands
+    d.offV = oV + (int64_t)d.n * d.r;
+    oV += 3 * (int64_t)d.n * d.r;
     d.offT = oT;
     oT += (int64_t)d.r * d.r;
     d.offSg = oSg;

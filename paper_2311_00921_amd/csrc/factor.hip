@@ -45,110 +45,143 @@ struct Acc4<float> {
 };
 
 // ---------------------------------------------------------------------------
-// Householder reconstruction: B (n x r, orthonormal) -> V, T, Sg
-// One workgroup per node; thread t owns rows t + 256*q (q < ROWS) in registers.
+// Householder reconstruction of an orthonormal basis B (n x r) -> V, T, Sg.
+// With Sg chosen during the LU, B - [Sg; 0] = V U_lu where V is unit lower
+// trapezoidal. The LU only needs the top r x r block (rows below follow from
+// V_2 = B_2 U_1^{-1}), and T follows from T^{-1} = striu(V^T V) + diag(V^T V)/2.
+//   k_lu_top       LU of the top block in LDS: V_1 -> V, U_1 -> T buffer, Sg
+//   k_tri_inv      inverse of an upper triangular r x r matrix in LDS
+//   (GEMMs)        V_2 = B_2 U_1^{-1};  G = V^T V
+//   k_tri_inv      T = (striu(G) + diag(G)/2)^{-1}
 // ---------------------------------------------------------------------------
 
-template <typename T, int RMAX, int ROWS>
-__global__ __launch_bounds__(256) void k_hh_recon(const NodeDesc* __restrict__ nodes, int first,
-                                                  const T* __restrict__ Bbase, T* __restrict__ Vbase,
-                                                  T* __restrict__ Tbase, T* __restrict__ Sgbase) {
+template <typename T, int RMAX>
+__global__ __launch_bounds__(256) void k_lu_top(const NodeDesc* __restrict__ nodes, int first,
+                                                const T* __restrict__ Bbase, T* __restrict__ Vbase,
+                                                T* __restrict__ Ubase, T* __restrict__ Sgbase) {
   const NodeDesc nd = nodes[first + blockIdx.x];
   const int n = nd.n, r = nd.r;
   const T* B = Bbase + nd.offB;
   T* V = Vbase + nd.offV;
-  T* Tm = Tbase + nd.offT;
+  T* U = Ubase + nd.offT;
   T* Sg = Sgbase + nd.offSg;
-  __shared__ T prow[RMAX];
-  __shared__ T sg[RMAX];
-  __shared__ T piv;
+  __shared__ double X[RMAX][RMAX + 1];
+  __shared__ double sg[RMAX];
   const int tid = threadIdx.x;
-  T a[ROWS][RMAX];
-#pragma unroll
-  for (int q = 0; q < ROWS; ++q) {
-    const int i = tid + 256 * q;
-#pragma unroll
-    for (int c = 0; c < RMAX; ++c) a[q][c] = (i < n && c < r) ? B[i + (int64_t)c * n] : (T)0;
+  for (int e = tid; e < r * r; e += 256) {
+    const int i = e % r, c = e / r;
+    X[i][c] = (double)B[i + (int64_t)c * n];
   }
+  __syncthreads();
+  const int tx = tid & 15, ty = tid >> 4;  // 16 x 16 thread grid over the trailing block
   for (int j = 0; j < r; ++j) {
-    // the owner of row j fixes the sign, forms the pivot and publishes the row
-#pragma unroll
-    for (int q = 0; q < ROWS; ++q) {
-      const int i = tid + 256 * q;
-      if (i == j) {
-        T u = 0;
-#pragma unroll
-        for (int c = 0; c < RMAX; ++c)
-          if (c == j) u = a[q][c];
-        const T s = (u >= (T)0) ? (T)-1 : (T)1;
-        const T p = u - s;
-#pragma unroll
-        for (int c = 0; c < RMAX; ++c) {
-          if (c == j) a[q][c] = p;
-          prow[c] = a[q][c];
-        }
-        sg[j] = s;
-        piv = p;
-      }
+    if (tid == 0) {
+      const double u = X[j][j];
+      const double s = (u >= 0.0) ? -1.0 : 1.0;
+      X[j][j] = u - s;
+      sg[j] = s;
     }
     __syncthreads();
-    const T p = piv;
-#pragma unroll
-    for (int q = 0; q < ROWS; ++q) {
-      const int i = tid + 256 * q;
-      if (i > j && i < n) {
-        T l = 0;
-#pragma unroll
-        for (int c = 0; c < RMAX; ++c)
-          if (c == j) l = a[q][c] / p;
-#pragma unroll
-        for (int c = 0; c < RMAX; ++c) {
-          if (c == j) a[q][c] = l;
-          if (c > j && c < r) a[q][c] -= l * prow[c];
-        }
-      }
+    const double pinv = 1.0 / X[j][j];
+    for (int i = j + 1 + tid; i < r; i += 256) X[i][j] *= pinv;
+    __syncthreads();
+    for (int i = j + 1 + tx; i < r; i += 16) {
+      const double l = X[i][j];
+      for (int c = j + 1 + ty; c < r; c += 16) X[i][c] -= l * X[j][c];
     }
     __syncthreads();
   }
-  // write V (unit lower trapezoidal)
-#pragma unroll
-  for (int q = 0; q < ROWS; ++q) {
-    const int i = tid + 256 * q;
-    if (i < n) {
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c)
-        if (c < r) V[i + (int64_t)c * n] = (c < i) ? a[q][c] : (c == i ? (T)1 : (T)0);
-    }
+  for (int e = tid; e < r * r; e += 256) {
+    const int i = e % r, c = e / r;
+    V[i + (int64_t)c * n] = (T)(c < i ? X[i][c] : (c == i ? 1.0 : 0.0));
+    U[e] = (T)(c >= i ? X[i][c] : 0.0);
   }
-  // G = -U_lu Sg (upper triangular) goes to the T buffer; k_hh_t turns it into T
-#pragma unroll
-  for (int q = 0; q < ROWS; ++q) {
-    const int i = tid + 256 * q;
-    if (i < r) {
-#pragma unroll
-      for (int c = 0; c < RMAX; ++c)
-        if (c < r) Tm[i + (int64_t)c * r] = (c >= i) ? -a[q][c] * sg[c] : (T)0;
-    }
-  }
-  for (int c = tid; c < r; c += 256) Sg[c] = sg[c];
+  for (int c = tid; c < r; c += 256) Sg[c] = (T)sg[c];
 }
 
-// T = G V_1^{-T}: row i of T solves t V_1^T = g (forward substitution over the
-// columns), with V_1 the unit lower r x r top of V. Separate launch so that V
-// and G are read only after the kernel that wrote them has completed.
-template <typename T>
-__global__ __launch_bounds__(256) void k_hh_t(const NodeDesc* __restrict__ nodes, int first,
-                                              const T* __restrict__ Vbase, T* __restrict__ Tbase) {
+// Inverse of an upper triangular r x r matrix (column-major, ld r), blocked in
+// 16 x 16 tiles in LDS (padded to RMAX with the identity): the diagonal tiles are
+// inverted independently, then block rows are finished from the bottom up with
+// X_IJ = -X_II sum_{K=I+1..J} G_IK X_KJ on the matrix cores (FP64 16x16x4).
+// mode 0: the input is the triangle; mode 1: the input is a Gram matrix G and the
+// triangle is striu(G) + diag(G)/2. Selectors: 0 = T slot, 1/2 = first/second half of X.
+template <typename T, int RMAX>
+__global__ __launch_bounds__(256) void k_tri_inv(const NodeDesc* __restrict__ nodes, int first,
+                                                 const T* __restrict__ in, int in_sel, T* __restrict__ out,
+                                                 int out_sel, int mode) {
+  constexpr int NB = RMAX / 16;
   const NodeDesc nd = nodes[first + blockIdx.x];
-  const int n = nd.n, r = nd.r;
-  const T* V = Vbase + nd.offV;
-  T* Tm = Tbase + nd.offT;
-  for (int i = threadIdx.x; i < r; i += blockDim.x) {
-    for (int c = i + 1; c < r; ++c) {
-      T acc = Tm[i + (int64_t)c * r];
-      for (int k = i; k < c; ++k) acc -= V[c + (int64_t)k * n] * Tm[i + (int64_t)k * r];
-      Tm[i + (int64_t)c * r] = acc;
+  const int r = nd.r;
+  const int64_t rr = (int64_t)r * r;
+  const T* A = in + (in_sel == 0 ? nd.offT : nd.offX + (in_sel == 2 ? rr : 0));
+  T* Xo = out + (out_sel == 0 ? nd.offT : nd.offX + (out_sel == 2 ? rr : 0));
+  __shared__ double X[RMAX][RMAX + 1];
+  __shared__ double P[NB][16][17];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int e = tid; e < RMAX * RMAX; e += 256) {
+    const int i = e % RMAX, c = e / RMAX;
+    double v = 0.0;
+    if (i < r && c < r) {
+      if (i < c) v = (double)A[i + (int64_t)c * r];
+      else if (i == c) v = mode ? 0.5 * (double)A[i + (int64_t)c * r] : (double)A[i + (int64_t)c * r];
+    } else if (i == c) {
+      v = 1.0;
     }
+    X[i][c] = v;
+  }
+  __syncthreads();
+  // diagonal tiles: thread (b, c) computes column c of inv(G_bb) by back substitution
+  double x[16];
+  const int b = tid >> 4, cc = tid & 15;
+  if (b < NB) {
+    const int o = b * 16;
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = i + 1; k < 16; ++k) acc += X[o + i][o + k] * x[k];
+      x[i] = (i == cc) ? 1.0 / X[o + i][o + i] : (i < cc ? -acc / X[o + i][o + i] : 0.0);
+    }
+  }
+  __syncthreads();
+  if (b < NB) {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) X[b * 16 + i][b * 16 + cc] = x[i];
+  }
+  __syncthreads();
+  for (int I = NB - 2; I >= 0; --I) {
+    // P_J = sum_{K=I+1..J} G_IK X_KJ for J > I
+    for (int J = I + 1 + wid; J < NB; J += 4) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      for (int K = I + 1; K <= J; ++K) {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const double a = X[I * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
+          const double bb = X[K * 16 + kk + (lane >> 4)][J * 16 + (lane & 15)];
+          acc = mfma16x(a, bb, acc);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) P[J][mfma_out_row(0.0, lane, v)][lane & 15] = acc[v];
+    }
+    __syncthreads();
+    // X_IJ = -X_II P_J
+    for (int J = I + 1 + wid; J < NB; J += 4) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const double a = X[I * 16 + (lane & 15)][I * 16 + kk + (lane >> 4)];
+        const double bb = P[J][kk + (lane >> 4)][lane & 15];
+        acc = mfma16x(a, bb, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[I * 16 + mfma_out_row(0.0, lane, v)][J * 16 + (lane & 15)] = -acc[v];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < r * r; e += 256) {
+    const int i = e % r, c = e / r;
+    Xo[e] = (T)(i <= c ? X[i][c] : 0.0);
   }
 }
 
@@ -219,39 +252,46 @@ __global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ node
   __syncthreads();
   for (int j0 = 0; j0 < m; j0 += PNB) {
     const int jb = min(PNB, m - j0);
-    // (1) diagonal block
-    if (tid < PNB * PNB) {
-      const int i = tid % PNB, c = tid / PNB;
-      Ld[i][c] = (i < jb && c < jb && i >= c) ? (double)F[(j0 + i) + (int64_t)(j0 + c) * n] : 0.0;
-    }
-    __syncthreads();
-    for (int c = 0; c < jb; ++c) {
-      if (tid == 0) {
-        const double d = Ld[c][c];
-        if (!(d > 0.0)) {
-          fail = j0 + c;
-          Ld[c][c] = 1.0;
-        } else {
-          const double s = sqrt(d);
-          Ld[c][c] = s;
-          lacc += log(s);
+    // (1) pivot block: lane i < jb of wave 0 holds row j0+i, factored with shuffles
+    if (wid == 0) {
+      double a[PNB];
+#pragma unroll
+      for (int c = 0; c < PNB; ++c)
+        a[c] = (lane < jb && c <= lane) ? (double)F[(j0 + lane) + (int64_t)(j0 + c) * n] : 0.0;
+      int bad = -1;
+      double lsum = 0.0;
+#pragma unroll
+      for (int k = 0; k < PNB; ++k) {
+        if (k < jb) {
+          double d = __shfl(a[k], k, 64);
+          if (!(d > 0.0)) {
+            if (bad < 0) bad = k;
+            d = 1.0;
+          }
+          d = sqrt(d);
+          lsum += log(d);
+          if (lane == k) a[k] = d;
+          else if (lane > k) a[k] /= d;
+#pragma unroll
+          for (int c = k + 1; c < PNB; ++c) {
+            const double lc = __shfl(a[k], c, 64);
+            if (lane >= c && c < jb) a[c] -= a[k] * lc;
+          }
         }
       }
-      __syncthreads();
-      if (tid > c && tid < jb) Ld[tid][c] /= Ld[c][c];
-      __syncthreads();
-      if (tid < PNB * PNB) {
-        const int i = tid % PNB, cc = tid / PNB;
-        if (cc > c && i >= cc && i < jb) Ld[i][cc] -= Ld[i][c] * Ld[cc][c];
+#pragma unroll
+      for (int c = 0; c < PNB; ++c) {
+        if (lane < jb) Ld[lane][c] = (c <= lane) ? a[c] : 0.0;
+        if (lane < jb && c <= lane) F[(j0 + lane) + (int64_t)(j0 + c) * n] = (T)a[c];
       }
-      __syncthreads();
+      if (lane == 0) {
+        lacc += lsum;
+        if (bad >= 0) fail = j0 + bad;
+      }
     }
+    __syncthreads();
     if (fail >= 0) break;
-    if (tid < PNB * PNB) {
-      const int i = tid % PNB, c = tid / PNB;
-      if (i < jb && c < jb && i >= c) F[(j0 + i) + (int64_t)(j0 + c) * n] = (T)Ld[i][c];
-    }
-    // (2) panel below the diagonal block: rows j0+jb .. n-1
+    // (2) panel below the pivot block: rows j0+jb .. n-1
     const int t0 = j0 + jb, nt = n - t0;
     for (int i = tid; i < nt; i += 256) {
       double x[PNB];
@@ -259,11 +299,11 @@ __global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ node
       for (int c = 0; c < PNB; ++c) x[c] = (c < jb) ? (double)F[(t0 + i) + (int64_t)(j0 + c) * n] : 0.0;
 #pragma unroll
       for (int c = 0; c < PNB; ++c) {
+        asm volatile("" ::: "memory");  // keep the pivot-block reads next to their use
         if (c < jb) {
           double acc = x[c];
 #pragma unroll
-          for (int k = 0; k < PNB; ++k)
-            if (k < c) acc -= x[k] * Ld[c][k];
+          for (int k = 0; k < c; ++k) acc -= x[k] * Ld[c][k];
           x[c] = acc / Ld[c][c];
         }
       }
@@ -274,33 +314,55 @@ __global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ node
       }
     }
     __syncthreads();
-    // (3) trailing update of the lower triangle: F[t0:, t0:] -= P P^T
+    // (3) trailing update of the lower triangle, four tiles per wave at a time
     const int nb = (nt + 15) / 16;
     const int ntiles = nb * (nb + 1) / 2;
-    for (int t = wid; t < ntiles; t += 4) {
-      // tile t -> (ti >= tj)
-      int ti = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
-      while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-      while (ti * (ti + 1) / 2 > t) --ti;
-      const int tj = t - ti * (ti + 1) / 2;
-      typename Acc4<T>::type acc;
+    for (int t4 = wid * 4; t4 < ntiles; t4 += 16) {
+      typename Acc4<T>::type acc[4];
+      int ti[4], tj[4];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) acc[v] = 0;
-      const int ra = ti * 16 + (lane & 15), rb = tj * 16 + (lane & 15);
+      for (int q = 0; q < 4; ++q) {
+        const int t = t4 + q;
+        int a = (int)((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+        while ((a + 1) * (a + 2) / 2 <= t) ++a;
+        while (a * (a + 1) / 2 > t) --a;
+        ti[q] = a;
+        tj[q] = t - a * (a + 1) / 2;
 #pragma unroll
-      for (int kk = 0; kk < PNB; kk += 4) {
-        const int k = kk + (lane >> 4);
-        const T av = (ra < nt) ? P[k][ra] : (T)0;
-        const T bv = (rb < nt) ? P[k][rb] : (T)0;
-        acc = mfma16x(av, bv, acc);
+        for (int v = 0; v < 4; ++v) acc[q][v] = 0;
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int row = ti * 16 + mfma_out_row((T)0, lane, v);
-        const int col = tj * 16 + (lane & 15);
-        if (row < nt && col < nt && row >= col)
-          F[(t0 + row) + (int64_t)(t0 + col) * n] -= acc[v];
+      for (int q = 0; q < 4; ++q) {
+        if (t4 + q < ntiles) {
+          const int ra = ti[q] * 16 + (lane & 15), rb = tj[q] * 16 + (lane & 15);
+#pragma unroll
+          for (int kk = 0; kk < PNB; kk += 4) {
+            const int k = kk + (lane >> 4);
+            const T av = (ra < nt) ? P[k][ra] : (T)0;
+            const T bv = (rb < nt) ? P[k][rb] : (T)0;
+            acc[q] = mfma16x(av, bv, acc[q]);
+          }
+        }
       }
+      T cur[4][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = ti[q] * 16 + mfma_out_row((T)0, lane, v);
+          const int col = tj[q] * 16 + (lane & 15);
+          cur[q][v] = (t4 + q < ntiles && row < nt && col < nt && row >= col)
+                          ? F[(t0 + row) + (int64_t)(t0 + col) * n] : (T)0;
+        }
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int row = ti[q] * 16 + mfma_out_row((T)0, lane, v);
+          const int col = tj[q] * 16 + (lane & 15);
+          if (t4 + q < ntiles && row < nt && col < nt && row >= col)
+            F[(t0 + row) + (int64_t)(t0 + col) * n] = cur[q][v] - acc[q][v];
+        }
     }
     __syncthreads();
   }
@@ -337,29 +399,36 @@ __global__ void k_sum_logdet(const double* __restrict__ part, int count, double*
 // ---------------------------------------------------------------------------
 
 template <typename T>
-static void launch_recon(const hss_matrix_t m, const LevelPlan& lp, const T* B, T* V, T* Tm, T* Sg,
-                         hipStream_t s) {
-  const int r = lp.rmax, nmax = lp.nmax;
-  HSS_CHECK(nmax <= 512, HSS_ERR_UNSUPPORTED, "basis with more than 512 rows");
+static void launch_lu_top(const hss_matrix_t m, const LevelPlan& lp, const T* B, T* V, T* Ubuf, T* Sg,
+                          hipStream_t s) {
   dim3 grid(lp.count), block(256);
-#define RECON(RM, RW) \
-  hipLaunchKernelGGL((k_hh_recon<T, RM, RW>), grid, block, 0, s, m->dnodes, lp.first, B, V, Tm, Sg)
-  if (nmax <= 256) {
-    if (r <= 32) RECON(32, 1);
-    else if (r <= 64) RECON(64, 1);
-    else if (r <= 96) RECON(96, 1);
-    else if (r <= 128) RECON(128, 1);
-    else HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "basis rank above 128");
-  } else {
-    if (r <= 32) RECON(32, 2);
-    else if (r <= 64) RECON(64, 2);
-    else if (r <= 96) RECON(96, 2);
-    else if (r <= 128) RECON(128, 2);
-    else HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "basis rank above 128");
-  }
-#undef RECON
+  const int r = lp.rmax;
+  if (r <= 32)
+    hipLaunchKernelGGL((k_lu_top<T, 32>), grid, block, 0, s, m->dnodes, lp.first, B, V, Ubuf, Sg);
+  else if (r <= 64)
+    hipLaunchKernelGGL((k_lu_top<T, 64>), grid, block, 0, s, m->dnodes, lp.first, B, V, Ubuf, Sg);
+  else if (r <= 96)
+    hipLaunchKernelGGL((k_lu_top<T, 96>), grid, block, 0, s, m->dnodes, lp.first, B, V, Ubuf, Sg);
+  else if (r <= 128)
+    hipLaunchKernelGGL((k_lu_top<T, 128>), grid, block, 0, s, m->dnodes, lp.first, B, V, Ubuf, Sg);
+  else
+    HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "basis rank above 128");
   HSS_HIP(hipGetLastError());
-  hipLaunchKernelGGL((k_hh_t<T>), grid, dim3(128), 0, s, m->dnodes, lp.first, (const T*)V, Tm);
+}
+
+template <typename T>
+static void launch_tri_inv(const hss_matrix_t m, const LevelPlan& lp, const T* in, int in_sel, T* out, int out_sel,
+                           int mode, hipStream_t s) {
+  dim3 grid(lp.count), block(256);
+  const int r = lp.rmax;
+#define TINV(RM) \
+  hipLaunchKernelGGL((k_tri_inv<T, RM>), grid, block, 0, s, m->dnodes, lp.first, in, in_sel, out, out_sel, mode)
+  if (r <= 32) TINV(32);
+  else if (r <= 64) TINV(64);
+  else if (r <= 96) TINV(96);
+  else if (r <= 128) TINV(128);
+  else HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "basis rank above 128");
+#undef TINV
   HSS_HIP(hipGetLastError());
 }
 
@@ -396,33 +465,37 @@ struct FBufs {
   T *F, *M, *V, *Tm, *Sg, *W, *X;
 };
 
-// Builds the per-level GEMM batches of the diagonal product (once per matrix and type).
+// Builds the per-level GEMM batches of the basis QR and the diagonal product
+// (once per matrix and compute type). With Y = V T (so H = I - Y V^T):
+//   W = M Y, C = Y^T W, Z = W - V C / 2, H^T M H = M - Z V^T - V Z^T.
 template <typename T>
 static std::vector<std::vector<GemmBatch>> build_gemm_plan(hss_matrix_t m, const FBufs<T>& b) {
   hipStream_t s = m->ctx->stream;
   std::vector<std::vector<GemmBatch>> plan(m->L + 1);
   for (auto& lp : m->levels) {
     if (lp.level == 0) continue;
-    std::vector<GemmBatch> steps(8);
+    std::vector<GemmBatch> steps(7);
     for (int p = lp.first; p < lp.first + lp.count; ++p) {
       const NodeDesc& nd = m->nodes[p];
       const int n = nd.n, r = nd.r;
       const T* Mp = (lp.level == m->L) ? b.D + nd.offD : b.M + nd.offM;
       T* V = b.V + nd.offV;
+      T* Zl = V - (int64_t)n * r;  // Z copy left of V
+      T* Zr = V + (int64_t)n * r;  // Z copy right of V
       T* Tm = b.Tm + nd.offT;
-      T* W = b.W + nd.offW;
-      T* Z = W + (int64_t)n * r;
-      T* X = b.X + nd.offX;
-      T* Y = X + (int64_t)r * r;
+      T* Y = b.W + nd.offW;
+      T* W = Y + (int64_t)n * r;
+      T* X1 = b.X + nd.offX;
+      T* X2 = X1 + (int64_t)r * r;
       T* F = b.F + nd.offF;
-      steps[0].host.push_back({Mp, V, nullptr, W, n, r, n, n, n, 0, n, 0, 0});        // W = M V
-      steps[1].host.push_back({V, W, nullptr, X, r, r, n, n, n, 0, r, 0, 0});         // X = V^T W
-      steps[2].host.push_back({X, Tm, nullptr, Y, r, r, r, r, r, 0, r, 0, 0});        // Y = X T
-      steps[3].host.push_back({Tm, Y, nullptr, X, r, r, r, r, r, 0, r, 0, 0});        // X = T^T Y
-      steps[4].host.push_back({W, Tm, nullptr, Z, n, r, r, n, r, 0, n, 0, 0});        // Z = W T
-      steps[5].host.push_back({V, X, Z, Z, n, r, r, n, r, n, n, 0, 0});               // Z -= V X / 2
-      steps[6].host.push_back({Z, V, Mp, F, n, n, r, n, n, n, n, r, 0});              // F = P^T (M - Z V^T) P
-      steps[7].host.push_back({V, Z, F, F, n, n, r, n, n, n, n, r, 1});               // F -= P^T V Z^T P
+      const T* Bn = b.B + nd.offB;
+      steps[0].host.push_back({Bn + r, X2, nullptr, V + r, n - r, r, r, n, r, 0, n, 0, 0});  // V_2 = B_2 U_1^{-1}
+      steps[1].host.push_back({V, V, nullptr, X1, r, r, n, n, n, 0, r, 0, 0});             // G = V^T V
+      steps[2].host.push_back({V, Tm, nullptr, Y, n, r, r, n, r, 0, n, 0, 0});            // Y = V T
+      steps[3].host.push_back({Mp, Y, nullptr, W, n, r, n, n, n, 0, n, 0, 0});            // W = M Y
+      steps[4].host.push_back({Y, W, nullptr, X1, r, r, n, n, n, 0, r, 0, 0});            // C = Y^T W
+      steps[5].host.push_back({V, X1, W, Zl, n, r, r, n, r, n, n, 0, 0, Zr});             // Z = W - V C / 2
+      steps[6].host.push_back({Zl, V, Mp, F, n, n, 2 * r, n, n, n, n, r, 0});             // F = P^T (M - [Z V][V Z]^T) P
     }
     for (auto& g : steps) gemm_upload(g, s);
     plan[lp.level] = std::move(steps);
@@ -528,27 +601,31 @@ static void factor_levels(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
                          (const T*)b.Sg, b.S, b.M, b.F, 0);
       HSS_HIP(hipGetLastError());
     }
-    {
-      Prof pf(cx, "basis_qr", l);
-      launch_recon<T>(m, lp, b.B, b.V, b.Tm, b.Sg, s);
-    }
     auto& st = plan[l];
     {
-      Prof pf(cx, "gemm_W=MV", l);
-      gemm_run<T>(st[0], false, false, 1.0, 0.0, s);
+      Prof pf(cx, "basis_qr", l);
+      launch_lu_top<T>(m, lp, b.B, b.V, b.Tm, b.Sg, s);   // V_1, U_1 (in the T slot), Sg
+      launch_tri_inv<T>(m, lp, b.Tm, 0, b.X, 2, 0, s);    // U_1^{-1} -> second half of X
+      gemm_run<T>(st[0], false, false, 1.0, 0.0, s);      // V_2 = B_2 U_1^{-1}
+      gemm_run<T>(st[1], true, false, 1.0, 0.0, s);       // G = V^T V -> first half of X
+      launch_tri_inv<T>(m, lp, b.X, 1, b.Tm, 0, 1, s);    // T = (striu G + diag G / 2)^{-1}
     }
     {
       Prof pf(cx, "gemm_small_wy", l);
-      gemm_run<T>(st[1], true, false, 1.0, 0.0, s);
-      gemm_run<T>(st[2], false, false, 1.0, 0.0, s);
-      gemm_run<T>(st[3], true, false, 1.0, 0.0, s);
-      gemm_run<T>(st[4], false, false, 1.0, 0.0, s);
-      gemm_run<T>(st[5], false, false, -0.5, 1.0, s);
+      gemm_run<T>(st[2], false, false, 1.0, 0.0, s);      // Y = V T
+    }
+    {
+      Prof pf(cx, "gemm_W=MV", l);
+      gemm_run<T>(st[3], false, false, 1.0, 0.0, s);      // W = M Y
+    }
+    {
+      Prof pf(cx, "gemm_small_wy", l);
+      gemm_run<T>(st[4], true, false, 1.0, 0.0, s);       // C = Y^T W
+      gemm_run<T>(st[5], false, false, -0.5, 1.0, s);     // Z = W - V C / 2 (both copies)
     }
     {
       Prof pf(cx, "gemm_two_sided_update", l);
-      gemm_run<T>(st[6], false, true, -1.0, 1.0, s);
-      gemm_run<T>(st[7], false, true, -1.0, 1.0, s);
+      gemm_run<T>(st[6], false, true, -1.0, 1.0, s);      // F = P^T (M - Z V^T - V Z^T) P
     }
     {
       Prof pf(cx, "partial_cholesky", l);

@@ -136,6 +136,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
             val += beta * Cin[irow + (int64_t)icol * d.ldcin];
           }
           C[prow + (int64_t)pcol * d.ldc] = val;
+          if (d.C2) ((T*)d.C2)[prow + (int64_t)pcol * d.ldc] = val;
         }
       }
 }

@@ -78,6 +78,7 @@ struct GemmDesc {
   int32_t lda, ldb, ldcin, ldc;
   int32_t perm_r;  // 0: plain store; r > 0: index t -> (t < r ? t + (dim - r) : t - r)
   int32_t perm_in; // 1: Cin is read at the permuted position too (in-place update)
+  void* C2;        // optional second output (same values, same layout as C)
 };
 
 struct GemmBatch {

@@ -14,7 +14,7 @@
 
 namespace hss {
 
-constexpr int SW = 64;    // threads per node in the solve kernels
+constexpr int SW = 256;   // threads per node in the solve kernels
 constexpr int SNB = 16;   // block size of the blocked triangular solves
 constexpr int RC = 4;     // right-hand sides per pass
 
@@ -25,153 +25,166 @@ __device__ __forceinline__ T wave_sum(T v) {
   return v;
 }
 
-// t[j, c] = sum_i V[i, j] x[i, c] for j < r (V is n x r, x in LDS with ld n)
+// out[j, c] = sum_{i < rows} A[i + j lda] x[i + c ldx] for j < cols: one wave per
+// column (coalesced reads of the column), wave reduction. x, out in LDS.
 template <typename T>
-__device__ void vt_times(const T* __restrict__ V, int n, int r, const T* x, T* t, int nc) {
-  for (int j = threadIdx.x; j < r; j += SW) {
+__device__ void col_dots(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* x, int ldx, T* out,
+                         int ldo, int nc) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j = wid; j < cols; j += SW / 64) {
     T acc[RC];
 #pragma unroll
     for (int c = 0; c < RC; ++c) acc[c] = 0;
-    const T* col = V + (int64_t)j * n;
-    for (int i = 0; i < n; ++i) {
-      const T v = col[i];
+    const T* col = A + (int64_t)j * lda;
+#pragma unroll 4
+    for (int i = lane; i < rows; i += 64) {
+      const T a = col[i];
 #pragma unroll
       for (int c = 0; c < RC; ++c)
-        if (c < nc) acc[c] += v * x[i + c * n];
+        if (c < nc) acc[c] += a * x[i + c * ldx];
     }
 #pragma unroll
-    for (int c = 0; c < RC; ++c)
-      if (c < nc) t[j + c * r] = acc[c];
+    for (int c = 0; c < RC; ++c) {
+      const T v = wave_sum(acc[c]);
+      if (lane == 0 && c < nc) out[j + c * ldo] = v;
+    }
   }
 }
 
-// x[i, c] -= sum_j V[i, j] u[j, c]
+// y[i, c] (+)= sign * sum_{j < cols} A[i + j lda] u[j + c ldu] for i < rows: one thread per row.
 template <typename T>
-__device__ void sub_v_times(const T* __restrict__ V, int n, int r, const T* u, T* x, int nc) {
-  for (int i = threadIdx.x; i < n; i += SW) {
+__device__ void row_gemv(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* u, int ldu, T* y,
+                         int ldy, int nc, T sign) {
+  for (int i = threadIdx.x; i < rows; i += SW) {
     T acc[RC];
 #pragma unroll
     for (int c = 0; c < RC; ++c) acc[c] = 0;
-    for (int j = 0; j < r; ++j) {
-      const T v = V[i + (int64_t)j * n];
+    int j = 0;
+    for (; j + 8 <= cols; j += 8) {
+      T a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = A[i + (int64_t)(j + q) * lda];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+          if (c < nc) acc[c] += a[q] * u[j + q + c * ldu];
+    }
+    for (; j < cols; ++j) {
+      const T a = A[i + (int64_t)j * lda];
 #pragma unroll
       for (int c = 0; c < RC; ++c)
-        if (c < nc) acc[c] += v * u[j + c * r];
+        if (c < nc) acc[c] += a * u[j + c * ldu];
     }
 #pragma unroll
     for (int c = 0; c < RC; ++c)
-      if (c < nc) x[i + c * n] -= acc[c];
+      if (c < nc) y[i + c * ldy] += sign * acc[c];
   }
 }
 
-// u = T^T t (trans) or u = T t, T upper triangular r x r
+// u = T^T t (trans) or u = T t for the upper triangular r x r T (ld r).
 template <typename T>
-__device__ void tri_t_times(const T* __restrict__ Tm, int r, const T* t, T* u, int nc, bool trans) {
-  for (int j = threadIdx.x; j < r; j += SW) {
+__device__ void tri_mult(const T* __restrict__ Tm, int r, const T* t, T* u, int nc, bool trans) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j = wid; j < r; j += SW / 64) {
     T acc[RC];
 #pragma unroll
     for (int c = 0; c < RC; ++c) acc[c] = 0;
-    if (trans) {
-      for (int k = 0; k <= j; ++k) {
-        const T v = Tm[k + (int64_t)j * r];
+    if (trans) {  // (T^T t)_j = sum_{k <= j} T[k, j] t_k : column j, contiguous
+#pragma unroll 2
+      for (int k = lane; k <= j; k += 64) {
+        const T a = Tm[k + (int64_t)j * r];
 #pragma unroll
         for (int c = 0; c < RC; ++c)
-          if (c < nc) acc[c] += v * t[k + c * r];
+          if (c < nc) acc[c] += a * t[k + c * r];
       }
-    } else {
-      for (int k = j; k < r; ++k) {
-        const T v = Tm[j + (int64_t)k * r];
+    } else {      // (T t)_j = sum_{k >= j} T[j, k] t_k : row j
+#pragma unroll 2
+      for (int k = j + lane; k < r; k += 64) {
+        const T a = Tm[j + (int64_t)k * r];
 #pragma unroll
         for (int c = 0; c < RC; ++c)
-          if (c < nc) acc[c] += v * t[k + c * r];
+          if (c < nc) acc[c] += a * t[k + c * r];
       }
     }
 #pragma unroll
-    for (int c = 0; c < RC; ++c)
-      if (c < nc) u[j + c * r] = acc[c];
+    for (int c = 0; c < RC; ++c) {
+      const T v = wave_sum(acc[c]);
+      if (lane == 0 && c < nc) u[j + c * r] = v;
+    }
   }
 }
 
-// In place y = L^{-1} y, L = F[0:m, 0:m] lower (ld = ldf); y in LDS with ld ldy.
+// In place y = L^{-1} y, L = F[0:m, 0:m] lower (ld ldf); y in LDS (ld ldy).
+// 16-row diagonal blocks are solved by one wave; the rows below are updated by all threads.
 template <typename T>
 __device__ void lower_solve(const T* __restrict__ F, int ldf, int m, T* y, int ldy, int nc) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int b0 = 0; b0 < m; b0 += SNB) {
     const int bb = min(SNB, m - b0);
-    for (int c = 0; c < bb; ++c) {
-      const int k = b0 + c;
-      const T d = F[k + (int64_t)k * ldf];
-      __syncthreads();
-      if (threadIdx.x < nc) y[k + threadIdx.x * ldy] /= d;
-      __syncthreads();
-      // update the rest of this block
-      for (int kk = b0 + c + 1 + threadIdx.x; kk < b0 + bb; kk += SW) {
-        const T l = F[kk + (int64_t)k * ldf];
+    if (wid == 0) {
+      // lane i < bb owns row b0 + i of the block
+      T Lrow[SNB];
 #pragma unroll
-        for (int cc = 0; cc < RC; ++cc)
-          if (cc < nc) y[kk + cc * ldy] -= l * y[k + cc * ldy];
+      for (int k = 0; k < SNB; ++k) Lrow[k] = (lane < bb && k <= lane && k < bb) ? F[(b0 + lane) + (int64_t)(b0 + k) * ldf] : (T)0;
+      T v[RC];
+#pragma unroll
+      for (int c = 0; c < RC; ++c) v[c] = (lane < bb && c < nc) ? y[b0 + lane + c * ldy] : (T)0;
+#pragma unroll
+      for (int k = 0; k < SNB; ++k) {
+        if (k < bb) {
+#pragma unroll
+          for (int c = 0; c < RC; ++c) {
+            T yk = __shfl(v[c] / Lrow[k], k, 64);  // lane k holds the solved value after the division
+            if (lane == k) v[c] = yk;
+            else if (lane > k) v[c] -= Lrow[k] * yk;
+          }
+        }
       }
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (lane < bb && c < nc) y[b0 + lane + c * ldy] = v[c];
     }
     __syncthreads();
-    // panel update of the rows below the block
-    for (int i = b0 + bb + threadIdx.x; i < m; i += SW) {
-      T acc[RC];
-#pragma unroll
-      for (int cc = 0; cc < RC; ++cc) acc[cc] = 0;
-      for (int c = 0; c < bb; ++c) {
-        const T l = F[i + (int64_t)(b0 + c) * ldf];
-#pragma unroll
-        for (int cc = 0; cc < RC; ++cc)
-          if (cc < nc) acc[cc] += l * y[b0 + c + cc * ldy];
-      }
-#pragma unroll
-      for (int cc = 0; cc < RC; ++cc)
-        if (cc < nc) y[i + cc * ldy] -= acc[cc];
-    }
+    row_gemv(F + (b0 + bb) + (int64_t)b0 * ldf, ldf, m - b0 - bb, bb, y + b0, ldy, y + b0 + bb, ldy, nc, (T)-1);
     __syncthreads();
   }
 }
 
 // In place x = L^{-T} x, L = F[0:m, 0:m] lower.
 template <typename T>
-__device__ void lower_t_solve(const T* __restrict__ F, int ldf, int m, T* x, int ldx, int nc) {
+__device__ void lower_t_solve(const T* __restrict__ F, int ldf, int m, T* x, int ldx, int nc, T* scratch) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nblk = (m + SNB - 1) / SNB;
   for (int bi = nblk - 1; bi >= 0; --bi) {
     const int b0 = bi * SNB, bb = min(SNB, m - b0);
-    // x_blk -= L[b0+bb:m, blk]^T x[b0+bb:m]
-    for (int c = 0; c < bb; ++c) {
-      T part[RC];
+    // scratch[k] = sum_{i >= b0+bb} L[i, b0+k] x[i]
+    col_dots(F + (b0 + bb) + (int64_t)b0 * ldf, ldf, m - b0 - bb, bb, x + b0 + bb, ldx, scratch, SNB, nc);
+    __syncthreads();
+    if (wid == 0) {
+      // lane i < bb owns column b0 + i of the block (L^T row)
+      T Lcol[SNB];
 #pragma unroll
-      for (int cc = 0; cc < RC; ++cc) part[cc] = 0;
-      for (int i = b0 + bb + threadIdx.x; i < m; i += SW) {
-        const T l = F[i + (int64_t)(b0 + c) * ldf];
+      for (int k = 0; k < SNB; ++k) Lcol[k] = (lane < bb && k >= lane && k < bb) ? F[(b0 + k) + (int64_t)(b0 + lane) * ldf] : (T)0;
+      T v[RC];
 #pragma unroll
-        for (int cc = 0; cc < RC; ++cc)
-          if (cc < nc) part[cc] += l * x[i + cc * ldx];
+      for (int c = 0; c < RC; ++c) v[c] = (lane < bb && c < nc) ? x[b0 + lane + c * ldx] - scratch[lane + c * SNB] : (T)0;
+#pragma unroll
+      for (int kk = SNB - 1; kk >= 0; --kk) {
+        if (kk < bb) {
+#pragma unroll
+          for (int c = 0; c < RC; ++c) {
+            T xk = __shfl(v[c] / Lcol[kk], kk, 64);
+            if (lane == kk) v[c] = xk;
+            else if (lane < kk) v[c] -= Lcol[kk] * xk;
+          }
+        }
       }
 #pragma unroll
-      for (int cc = 0; cc < RC; ++cc) part[cc] = wave_sum(part[cc]);
-      __syncthreads();
-      if (threadIdx.x == 0) {
-#pragma unroll
-        for (int cc = 0; cc < RC; ++cc)
-          if (cc < nc) x[b0 + c + cc * ldx] -= part[cc];
-      }
+      for (int c = 0; c < RC; ++c)
+        if (lane < bb && c < nc) x[b0 + lane + c * ldx] = v[c];
     }
     __syncthreads();
-    // solve the diagonal block backwards
-    for (int c = bb - 1; c >= 0; --c) {
-      const int k = b0 + c;
-      const T d = F[k + (int64_t)k * ldf];
-      if (threadIdx.x < nc) x[k + threadIdx.x * ldx] /= d;
-      __syncthreads();
-      for (int kk = b0 + threadIdx.x; kk < k; kk += SW) {
-        const T l = F[k + (int64_t)kk * ldf];
-#pragma unroll
-        for (int cc = 0; cc < RC; ++cc)
-          if (cc < nc) x[kk + cc * ldx] -= l * x[k + cc * ldx];
-      }
-      __syncthreads();
-    }
   }
 }
 
@@ -198,38 +211,23 @@ __global__ __launch_bounds__(SW) void k_solve_fwd(const NodeDesc* __restrict__ n
       sb[i + c * n] = leaf ? (T)b[perm[nd.lo + i] + (int64_t)(c0 + c) * ld] : vp[i + (int64_t)(c0 + c) * n];
   __syncthreads();
   // b^ = b - V T^T V^T b
-  vt_times(V, n, r, sb, st, nc);
+  col_dots(V, n, n, r, sb, n, st, r, nc);
   __syncthreads();
-  tri_t_times(Tm, r, st, su, nc, true);
+  tri_mult(Tm, r, st, su, nc, true);
   __syncthreads();
-  sub_v_times(V, n, r, su, sb, nc);
+  row_gemv(V, n, n, r, su, r, sb, n, nc, (T)-1);
   __syncthreads();
   // y_R = L_RR^{-1} b^_R  (b^_R = sb[r:n])
   lower_solve(F, n, m, sb + r, n, nc);
+  // z_S = b^_S - L_SR y_R   (L_SR = F[m:n, 0:m])
+  row_gemv(F + m, n, r, m, sb + r, n, sb, n, nc, (T)-1);
   __syncthreads();
-  // z_S = b^_S - L_SR y_R
-  for (int j = threadIdx.x; j < r; j += SW) {
-    T acc[RC];
-#pragma unroll
-    for (int c = 0; c < RC; ++c) acc[c] = 0;
-    for (int k = 0; k < m; ++k) {
-      const T l = F[(m + j) + (int64_t)k * n];
-#pragma unroll
-      for (int c = 0; c < RC; ++c)
-        if (c < nc) acc[c] += l * sb[r + k + c * n];
-    }
-#pragma unroll
-    for (int c = 0; c < RC; ++c)
-      if (c < nc) st[j + c * r] = sb[j + c * n] - acc[c];
-  }
-  __syncthreads();
-  // store y_R into this node's slot, Sg * z_S into the parent's
   for (int i = threadIdx.x; i < m; i += SW)
     for (int c = 0; c < nc; ++c) vp[i + (int64_t)(c0 + c) * n] = sb[r + i + c * n];
   const NodeDesc par = nodes[(p - 1) / 2];
   T* pp = vec + par.offVec * nrhs;
   for (int j = threadIdx.x; j < r; j += SW)
-    for (int c = 0; c < nc; ++c) pp[nd.child_row + j + (int64_t)(c0 + c) * par.n] = Sg[j] * st[j + c * r];
+    for (int c = 0; c < nc; ++c) pp[nd.child_row + j + (int64_t)(c0 + c) * par.n] = Sg[j] * sb[j + c * n];
 }
 
 template <typename T>
@@ -240,6 +238,7 @@ __global__ __launch_bounds__(SW) void k_solve_root(const NodeDesc* __restrict__ 
   const NodeDesc nd = nodes[0];
   const int n = nd.n;
   __shared__ T sb[512 * RC];
+  __shared__ T scr[SNB * RC];
   T* vp = vec + nd.offVec * nrhs;
   const T* F = Fb + nd.offF;
   for (int i = threadIdx.x; i < n; i += SW)
@@ -247,9 +246,7 @@ __global__ __launch_bounds__(SW) void k_solve_root(const NodeDesc* __restrict__ 
       sb[i + c * n] = single ? (T)b[perm[i] + (int64_t)(c0 + c) * ld] : vp[i + (int64_t)(c0 + c) * n];
   __syncthreads();
   lower_solve(F, n, n, sb, n, nc);
-  __syncthreads();
-  lower_t_solve(F, n, n, sb, n, nc);
-  __syncthreads();
+  lower_t_solve(F, n, n, sb, n, nc, scr);
   for (int i = threadIdx.x; i < n; i += SW)
     for (int c = 0; c < nc; ++c) {
       if (single)
@@ -272,6 +269,8 @@ __global__ __launch_bounds__(SW) void k_solve_bwd(const NodeDesc* __restrict__ n
   __shared__ T sx[512 * RC];
   __shared__ T st[128 * RC];
   __shared__ T su[128 * RC];
+  __shared__ T scr[SNB * RC];
+  __shared__ T tm[512 * RC];
   T* vp = vec + nd.offVec * nrhs;
   const T* F = Fb + nd.offF;
   const T* V = Vb + nd.offV;
@@ -285,31 +284,19 @@ __global__ __launch_bounds__(SW) void k_solve_bwd(const NodeDesc* __restrict__ n
   for (int i = threadIdx.x; i < m; i += SW)
     for (int c = 0; c < nc; ++c) sx[r + i + c * n] = vp[i + (int64_t)(c0 + c) * n];
   __syncthreads();
-  // t = y_R - L_SR^T x_S
-  for (int k = threadIdx.x; k < m; k += SW) {
-    T acc[RC];
-#pragma unroll
-    for (int c = 0; c < RC; ++c) acc[c] = 0;
-    const T* col = F + m + (int64_t)k * n;
-    for (int j = 0; j < r; ++j) {
-      const T l = col[j];
-#pragma unroll
-      for (int c = 0; c < RC; ++c)
-        if (c < nc) acc[c] += l * sx[j + c * n];
-    }
-#pragma unroll
-    for (int c = 0; c < RC; ++c)
-      if (c < nc) sx[r + k + c * n] -= acc[c];
-  }
+  // t = y_R - L_SR^T x_S: tm[k] = sum_j L_SR[j, k] x_S[j] (column k of L_SR is contiguous)
+  col_dots(F + m, n, r, m, sx, n, tm, n, nc);
   __syncthreads();
-  lower_t_solve(F, n, m, sx + r, n, nc);
+  for (int k = threadIdx.x; k < m; k += SW)
+    for (int c = 0; c < nc; ++c) sx[r + k + c * n] -= tm[k + c * n];
   __syncthreads();
+  lower_t_solve(F, n, m, sx + r, n, nc, scr);
   // x = H x^ = x^ - V T V^T x^
-  vt_times(V, n, r, sx, st, nc);
+  col_dots(V, n, n, r, sx, n, st, r, nc);
   __syncthreads();
-  tri_t_times(Tm, r, st, su, nc, false);
+  tri_mult(Tm, r, st, su, nc, false);
   __syncthreads();
-  sub_v_times(V, n, r, su, sx, nc);
+  row_gemv(V, n, n, r, su, r, sx, n, nc, (T)-1);
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += SW)
     for (int c = 0; c < nc; ++c) {
@@ -495,6 +482,12 @@ void solve_fp64(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_
   ensure_vec_ws(m, nrhs);
   HSS_CHECK(b != x || true, HSS_ERR_INVALID_ARGUMENT, "");
   solve_impl<double>(m, m->dF, m->dV, m->dT, m->dSg, m->dvec, b, x, nrhs, ld);
+}
+
+void solve_fp32(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld) {
+  ensure_vec_ws(m, nrhs);
+  if (!m->fvec) m->fvec = (float*)dev_alloc(sizeof(float) * std::max<int64_t>(m->sum_n * m->ws_nrhs, 1));
+  solve_impl<float>(m, m->fF, m->fV, m->fT, m->fSg, m->fvec, b, x, nrhs, ld);
 }
 
 void matvec_fp64(hss_matrix_t m, const double* x, double* y, int64_t nrhs, int64_t ld) {
