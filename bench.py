@@ -212,7 +212,8 @@ def main():
                  "factor_ms_events": round(info.factor_ms, 3), "algorithmic_factor_gflop": round(total_factor_flops / 1e9, 2),
                  "factor_gflops_per_s": round(total_factor_flops / 1e9 / (info.factor_ms * 1e-3), 1),
                  "profiled_step_s": round(t_prof, 6),
-                 "ms_by_step": {k: round(v / args.steps, 3) for k, v in sorted(by_step.items(), key=lambda kv: -kv[1])}},
+                 "ms_by_step": {k: round(v / args.steps, 3) for k, v in sorted(by_step.items(), key=lambda kv: -kv[1])},
+                 "ms_by_step_level": {f"{k[0]}@{k[1]}": round(v[1] / args.steps, 4) for k, v in sorted(prof.items())}},
         "mixed": mixed,
         "speedup_mixed_vs_fp64": round(t_fp64 / value, 3) if use_mixed else None,
         "construct_s": round(construct_s, 3),
