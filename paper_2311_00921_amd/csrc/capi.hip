@@ -54,46 +54,44 @@ static int level_of(int k) {
   return l;
 }
 
-// Fills the node table from (n, L, lo/npts of leaves, ranks) and assigns every
-// offset; allocates the representation buffers.
-void layout_representation(hss_matrix_t m) {
-  const int L = m->L;
-  const int nn = m->nnodes;
+// Block sizes, offsets and child rows of every node, given the links, leaf
+// point ranges and ranks (any node order). Allocates nothing.
+void assign_offsets(hss_matrix_t m) {
   auto& nd = m->nodes;
-  // upper node ranges from the leaves
-  for (int k = (1 << L) - 2; k >= 0; --k) {
-    nd[k].lo = nd[2 * k + 1].lo;
-    nd[k].npts = nd[2 * k + 1].npts + nd[2 * k + 2].npts;
-  }
-  for (int k = 0; k < nn; ++k) nd[k].level = level_of(k);
-  if (L == 0) {
-    nd[0].n = nd[0].npts;
-    nd[0].r = 0;
-  } else {
-    for (int k = nn - 1; k >= 0; --k) {
-      if (nd[k].level == L)
-        nd[k].n = nd[k].npts;
-      else
-        nd[k].n = nd[2 * k + 1].r + nd[2 * k + 2].r;
-      if (k == 0) nd[k].r = 0;
-    }
+  const int nn = (int)nd.size();
+  // children before parents: leaves have their size; internal nodes need the children's ranks
+  for (int k = 0; k < nn; ++k)
+    if (nd[k].c1 < 0) nd[k].n = nd[k].npts;
+  bool changed = true;
+  while (changed) {
+    changed = false;
+    for (int k = 0; k < nn; ++k)
+      if (nd[k].c1 >= 0) {
+        const int want = nd[nd[k].c1].r + nd[nd[k].c2].r;
+        if (nd[k].n != want) {
+          nd[k].n = want;
+          changed = true;
+        }
+      }
   }
   int64_t oD = 0, oB = 0, oS = 0, oF = 0, oM = 0, oV = 0, oT = 0, oSg = 0, oW = 0, oX = 0, oVec = 0, oR = 0;
   m->max_rank = 0;
   for (int k = 0; k < nn; ++k) {
     NodeDesc& d = nd[k];
-    const bool leaf = d.level == L;
+    const bool leaf = d.c1 < 0;
+    const bool root = d.parent < 0;
+    if (root) d.r = 0;
     d.m = d.n - d.r;
     HSS_CHECK(d.r >= 0 && d.r <= d.n, HSS_ERR_INVALID_ARGUMENT,
               "node " + std::to_string(k) + ": rank exceeds block size");
-    HSS_CHECK(k == 0 || d.r >= 1, HSS_ERR_INVALID_ARGUMENT, "node " + std::to_string(k) + ": rank must be >= 1");
+    HSS_CHECK(root || d.r >= 1, HSS_ERR_INVALID_ARGUMENT, "node " + std::to_string(k) + ": rank must be >= 1");
     m->max_rank = std::max(m->max_rank, d.r);
     d.offD = leaf ? oD : -1;
     if (leaf) oD += (int64_t)d.n * d.n;
-    d.offB = (k > 0) ? oB : -1;
-    if (k > 0) oB += (int64_t)d.n * d.r;
+    d.offB = root ? -1 : oB;
+    if (!root) oB += (int64_t)d.n * d.r;
     d.offS = leaf ? -1 : oS;
-    if (!leaf) oS += (int64_t)nd[2 * k + 1].r * nd[2 * k + 2].r;
+    if (!leaf) oS += (int64_t)nd[d.c1].r * nd[d.c2].r;
     d.offF = oF;
     oF += (int64_t)d.n * d.n;
     d.offM = leaf ? -1 : oM;
@@ -116,8 +114,11 @@ void layout_representation(hss_matrix_t m) {
     oR += d.r;
     d.child_row = 0;
   }
-  for (int k = 1; k < nn; ++k)
-    nd[k].child_row = (k % 2 == 1) ? 0 : nd[k - 1].r;
+  for (int k = 0; k < nn; ++k)
+    if (nd[k].c1 >= 0) {
+      nd[nd[k].c1].child_row = 0;
+      nd[nd[k].c2].child_row = nd[nd[k].c1].r;
+    }
   m->lenD = oD;
   m->lenB = oB;
   m->lenS = oS;
@@ -130,24 +131,87 @@ void layout_representation(hss_matrix_t m) {
   m->lenX = oX;
   m->sum_n = oVec;
   m->sum_r = oR;
+}
+
+// Per-stage extents, the explicit-inverse choice and the Li / L_SR slots; uploads the node table.
+void finish_stages(hss_matrix_t m) {
+  auto& nd = m->nodes;
+  const int nn = (int)nd.size();
+  m->offLi.assign(nn, 0);
+  m->offS2.assign(nn, 0);
+  int64_t oLi = 0, oS2 = 0;
+  for (auto& lp : m->stages) {
+    lp.nmax = lp.rmax = lp.mmax = 0;
+    lp.root_first = lp.first + lp.count;
+    for (int k = lp.first; k < lp.first + lp.count; ++k) {
+      lp.nmax = std::max(lp.nmax, nd[k].n);
+      lp.rmax = std::max(lp.rmax, nd[k].r);
+      lp.mmax = std::max(lp.mmax, nd[k].m);
+      if (nd[k].parent < 0 && lp.root_first == lp.first + lp.count) lp.root_first = k;
+    }
+    lp.leaf = (nd[lp.first].c1 < 0) ? 1 : 0;
+    lp.inv = (lp.mmax <= 96 && lp.mmax >= 1) ? 1 : 0;
+    if (!lp.inv) continue;
+    for (int k = lp.first; k < lp.first + lp.count; ++k) {
+      m->offLi[k] = oLi;
+      oLi += (int64_t)nd[k].m * nd[k].m;
+      m->offS2[k] = oS2;
+      oS2 += (int64_t)nd[k].r * nd[k].m;
+    }
+  }
+  m->lenLi = oLi;
+  m->lenS2 = oS2;
+  m->inv_used64.assign(m->stages.size(), 0);
+  m->inv_used32.assign(m->stages.size(), 0);
+  if (m->dOffLi) dev_free(m->dOffLi);
+  if (m->dOffS2) dev_free(m->dOffS2);
+  m->dOffLi = (int64_t*)dev_alloc(sizeof(int64_t) * nn);
+  m->dOffS2 = (int64_t*)dev_alloc(sizeof(int64_t) * nn);
+  HSS_HIP(hipMemcpyAsync(m->dOffLi, m->offLi.data(), sizeof(int64_t) * nn, hipMemcpyHostToDevice, m->ctx->stream));
+  HSS_HIP(hipMemcpyAsync(m->dOffS2, m->offS2.data(), sizeof(int64_t) * nn, hipMemcpyHostToDevice, m->ctx->stream));
+  if (m->dnodes) dev_free(m->dnodes);
+  m->dnodes = (NodeDesc*)dev_alloc(sizeof(NodeDesc) * nn);
+  HSS_HIP(hipMemcpyAsync(m->dnodes, nd.data(), sizeof(NodeDesc) * nn, hipMemcpyHostToDevice, m->ctx->stream));
+}
+
+// Single tree in heap order (node k has children 2k+1, 2k+2): links, offsets,
+// one stage per level (leaves first); allocates the representation buffers.
+void layout_representation(hss_matrix_t m) {
+  const int L = m->L;
+  const int nn = m->nnodes;
+  auto& nd = m->nodes;
+  for (int k = (1 << L) - 2; k >= 0; --k) {
+    nd[k].lo = nd[2 * k + 1].lo;
+    nd[k].npts = nd[2 * k + 1].npts + nd[2 * k + 2].npts;
+  }
+  for (int k = 0; k < nn; ++k) {
+    nd[k].level = level_of(k);
+    nd[k].parent = k > 0 ? (k - 1) / 2 : -1;
+    const bool leaf = nd[k].level == L;
+    nd[k].c1 = leaf ? -1 : 2 * k + 1;
+    nd[k].c2 = leaf ? -1 : 2 * k + 2;
+    nd[k].sys = 0;
+  }
+  nd[0].r = 0;
+  assign_offsets(m);
   m->levels.clear();
+  m->stages.clear();
   for (int l = 0; l <= L; ++l) {
     LevelPlan lp{};
     lp.level = l;
     lp.first = (1 << l) - 1;
     lp.count = 1 << l;
-    for (int k = lp.first; k < lp.first + lp.count; ++k) {
-      lp.nmax = std::max(lp.nmax, nd[k].n);
-      lp.rmax = std::max(lp.rmax, nd[k].r);
-      lp.mmax = std::max(lp.mmax, nd[k].m);
-    }
     m->levels.push_back(lp);
   }
-  if (!m->dnodes) m->dnodes = (NodeDesc*)dev_alloc(sizeof(NodeDesc) * nn);
-  HSS_HIP(hipMemcpyAsync(m->dnodes, nd.data(), sizeof(NodeDesc) * nn, hipMemcpyHostToDevice, m->ctx->stream));
-  if (!m->dD) m->dD = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(oD, 1));
-  if (!m->dB) m->dB = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(oB, 1));
-  if (!m->dS) m->dS = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(oS, 1));
+  for (int l = L; l >= 0; --l) m->stages.push_back(m->levels[l]);
+  finish_stages(m);
+  for (auto& st : m->stages) m->levels[st.level] = st;
+  m->nsys = 1;
+  m->sys_lo.assign(1, 0);
+  m->sys_root.assign(1, 0);
+  if (!m->dD) m->dD = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenD, 1));
+  if (!m->dB) m->dB = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenB, 1));
+  if (!m->dS) m->dS = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenS, 1));
   if (!m->dperm) m->dperm = (int64_t*)dev_alloc(sizeof(int64_t) * m->n);
 }
 
@@ -155,7 +219,7 @@ static void destroy_matrix(hss_matrix_t m) {
   if (!m) return;
   free_factor(m);
   void* ptrs[] = {m->dnodes, m->dD, m->dB, m->dS, m->dperm, m->dvec, m->dxt, m->dyt, m->fvec, m->dtmp,
-                  m->dRootNode};
+                  m->dOffLi, m->dOffS2};
   for (void* p : ptrs)
     if (p) dev_free(p);
   delete m;

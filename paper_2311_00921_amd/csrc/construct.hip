@@ -618,7 +618,7 @@ void construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
         tn[i].offF = cur[i].offL;
       }
       dtn.upload(tn, st);
-      std::vector<int32_t> zero(4, 0);
+      std::vector<int32_t> zero(5, 0);  // status words + the flag of system 0
       dinfo.upload(zero, st);
       ldscratch.ensure(cnt + 1);
       launch_pchol_external(dtn.p, 0, cnt, nmax, Lb.p, dinfo.p, ldscratch.p, st);

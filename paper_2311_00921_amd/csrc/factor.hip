@@ -61,6 +61,7 @@ __global__ __launch_bounds__(256) void k_lu_top(const NodeDesc* __restrict__ nod
                                                 T* __restrict__ Ubase, T* __restrict__ Sgbase) {
   const NodeDesc nd = nodes[first + blockIdx.x];
   const int n = nd.n, r = nd.r;
+  if (r == 0) return;
   const T* B = Bbase + nd.offB;
   T* V = Vbase + nd.offV;
   T* U = Ubase + nd.offT;
@@ -112,6 +113,7 @@ __global__ __launch_bounds__(256) void k_tri_inv(const NodeDesc* __restrict__ no
   constexpr int NB = RMAX / 16;
   const NodeDesc nd = nodes[first + blockIdx.x];
   const int r = nd.r;
+  if (r == 0) return;
   const int64_t rr = (int64_t)r * r;
   const T* A = in + (in_sel == 0 ? nd.offT : nd.offX + (in_sel == 2 ? rr : 0));
   T* Xo = out + (out_sel == 0 ? nd.offT : nd.offX + (out_sel == 2 ? rr : 0));
@@ -186,6 +188,238 @@ __global__ __launch_bounds__(256) void k_tri_inv(const NodeDesc* __restrict__ no
 }
 
 // ---------------------------------------------------------------------------
+// Fused basis QR for r <= RM <= 96 (one workgroup per node, everything in LDS):
+//   blocked LU without pivoting of the top r x r block of B - [Sg; 0]
+//   (16-column panels factored by one wave, U_12 by a unit-lower solve per
+//   column, trailing update on the matrix cores), then U_1^{-1} and L_1^{-1}
+//   (blocked MFMA recurrences) and T = -U_1 Sg L_1^{-T}.
+// Writes V_1 (top rows of V), Sg, T, and U_1^{-1} (second half of the X slot)
+// for the GEMM V_2 = B_2 U_1^{-1}.
+// ---------------------------------------------------------------------------
+
+template <typename T, int RM>
+__global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ nodes, int first,
+                                                   const T* __restrict__ Bbase, T* __restrict__ Vbase,
+                                                   T* __restrict__ Tbase, T* __restrict__ Sgbase,
+                                                   T* __restrict__ Xbase) {
+  constexpr int NB = RM / 16;
+  const NodeDesc nd = nodes[first + blockIdx.x];
+  const int n = nd.n, r = nd.r;
+  if (r == 0) return;
+  const T* B = Bbase + nd.offB;
+  T* V = Vbase + nd.offV;
+  T* Tm = Tbase + nd.offT;
+  T* Sg = Sgbase + nd.offSg;
+  T* U1i = Xbase + nd.offX + (int64_t)r * r;
+  __shared__ double X[RM][RM + 1];   // LU in place: strict lower = L_1, upper = U_1
+  __shared__ double Y[RM][RM + 1];   // upper = U_1^{-1}, strict lower = L_1^{-1} (unit diagonal implied)
+  __shared__ double Pt[NB][16][17];
+  __shared__ double sg[RM];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int e = tid; e < RM * RM; e += 256) {
+    const int i = e % RM, c = e / RM;
+    X[i][c] = (i < r && c < r) ? (double)B[i + (int64_t)c * n] : (i == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int J = 0; J < NB; ++J) {
+    const int j0 = J * 16;
+    if (wid == 0) {
+      // lane owns rows j0 + lane and j0 + 64 + lane of the panel (columns j0..j0+15)
+      double a[2][16];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int row = j0 + lane + 64 * h;
+#pragma unroll
+        for (int c = 0; c < 16; ++c) a[h][c] = (row < RM) ? X[row][j0 + c] : 0.0;
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        // pivot row j0 + k is lane k's first row
+        const double u = __shfl(a[0][k], k, 64);
+        const double sgn = (u >= 0.0) ? -1.0 : 1.0;
+        const double p = u - sgn;
+        const double pinv = 1.0 / p;
+        if (lane == k) {
+          a[0][k] = p;
+          sg[j0 + k] = sgn;
+          // publish the pivot row to LDS (columns k+1..15 of this panel)
+#pragma unroll
+          for (int c = 0; c < 16; ++c) X[j0 + k][j0 + c] = a[0][c];
+        }
+        __builtin_amdgcn_wave_barrier();
+        double prow[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) prow[c] = (c > k) ? X[j0 + k][j0 + c] : 0.0;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int row = j0 + lane + 64 * h;
+          if (row > j0 + k && row < RM) {
+            const double l = a[h][k] * pinv;
+            a[h][k] = l;
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+              if (c > k) a[h][c] -= l * prow[c];
+          }
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int row = j0 + lane + 64 * h;
+        if (row < RM)
+#pragma unroll
+          for (int c = 0; c < 16; ++c) X[row][j0 + c] = a[h][c];
+      }
+    }
+    __syncthreads();
+    // U_12 = L_11^{-1} A_12 (rows j0..j0+15, columns beyond the panel), one thread per column
+    for (int c = j0 + 16 + tid; c < RM; c += 256) {
+      double x[16];
+#pragma unroll
+      for (int k = 0; k < 16; ++k) {
+        double acc = X[j0 + k][c];
+#pragma unroll
+        for (int j = 0; j < k; ++j) acc -= X[j0 + k][j0 + j] * x[j];
+        x[k] = acc;
+      }
+#pragma unroll
+      for (int k = 0; k < 16; ++k) X[j0 + k][c] = x[k];
+    }
+    __syncthreads();
+    // trailing update A_22 -= L_21 U_12 on 16 x 16 tiles
+    const int rem = NB - J - 1;
+    for (int t = wid; t < rem * rem; t += 4) {
+      const int I2 = J + 1 + t % rem, J2 = J + 1 + t / rem;
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const double av = X[I2 * 16 + (lane & 15)][j0 + kk + (lane >> 4)];
+        const double bv = X[j0 + kk + (lane >> 4)][J2 * 16 + (lane & 15)];
+        acc = mfma16x(av, bv, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[I2 * 16 + mfma_out_row(0.0, lane, v)][J2 * 16 + (lane & 15)] -= acc[v];
+    }
+    __syncthreads();
+  }
+  // diagonal tiles of U_1^{-1} (upper) and L_1^{-1} (unit lower) into Y
+  {
+    const int b = tid >> 4, cc = tid & 15;
+    if (b < NB) {
+      const int o = b * 16;
+      double xu[16], xl[16];
+#pragma unroll
+      for (int i = 15; i >= 0; --i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = i + 1; k < 16; ++k) acc += X[o + i][o + k] * xu[k];
+        xu[i] = (i == cc) ? 1.0 / X[o + i][o + i] : (i < cc ? -acc / X[o + i][o + i] : 0.0);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc += X[o + i][o + k] * xl[k];
+        xl[i] = (i == cc) ? 1.0 : (i > cc ? -acc : 0.0);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Y[o + i][o + cc] = (i <= cc) ? xu[i] : xl[i];
+    }
+  }
+  __syncthreads();
+  // off-diagonal tiles of U_1^{-1}, block rows bottom-up: Yu_IJ = -Yu_II sum_{K=I+1..J} U_IK Yu_KJ
+  for (int Iu = NB - 2; Iu >= 0; --Iu) {
+    for (int J = Iu + 1 + wid; J < NB; J += 4) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      for (int K = Iu + 1; K <= J; ++K)
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const double av = X[Iu * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
+          const int kr = K * 16 + kk + (lane >> 4), jc = J * 16 + (lane & 15);
+          const double bv = (K == J && kr > jc) ? 0.0 : Y[kr][jc];  // upper part of the diagonal tile
+          acc = mfma16x(av, bv, acc);
+        }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Pt[J][mfma_out_row(0.0, lane, v)][lane & 15] = acc[v];
+    }
+    __syncthreads();
+    for (int J = Iu + 1 + wid; J < NB; J += 4) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int ar = Iu * 16 + (lane & 15), ac = Iu * 16 + kk + (lane >> 4);
+        const double av = (ar <= ac) ? Y[ar][ac] : 0.0;
+        const double bv = Pt[J][kk + (lane >> 4)][lane & 15];
+        acc = mfma16x(av, bv, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Y[Iu * 16 + mfma_out_row(0.0, lane, v)][J * 16 + (lane & 15)] = -acc[v];
+    }
+    __syncthreads();
+  }
+  // off-diagonal tiles of L_1^{-1} (unit lower), block rows top-down:
+  // Yl_IJ = -Yl_II sum_{K=J..I-1} L_IK Yl_KJ
+  for (int Il = 1; Il < NB; ++Il) {
+    for (int J = wid; J < Il; J += 4) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      for (int K = J; K < Il; ++K)
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const double av = X[Il * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
+          const int kr = K * 16 + kk + (lane >> 4), jc = J * 16 + (lane & 15);
+          const double bv = (K == J) ? (kr == jc ? 1.0 : (kr > jc ? Y[kr][jc] : 0.0)) : Y[kr][jc];
+          acc = mfma16x(av, bv, acc);
+        }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Pt[J][mfma_out_row(0.0, lane, v)][lane & 15] = -acc[v];
+    }
+    __syncthreads();
+    for (int J = wid; J < Il; J += 4) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int ar = Il * 16 + (lane & 15), ac = Il * 16 + kk + (lane >> 4);
+        const double av = (ar == ac) ? 1.0 : (ar > ac ? Y[ar][ac] : 0.0);
+        const double bv = Pt[J][kk + (lane >> 4)][lane & 15];
+        acc = mfma16x(av, bv, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Y[Il * 16 + mfma_out_row(0.0, lane, v)][J * 16 + (lane & 15)] = acc[v];
+    }
+    __syncthreads();
+  }
+  // outputs: V_1, Sg, U_1^{-1}
+  for (int e = tid; e < r * r; e += 256) {
+    const int i = e % r, c = e / r;
+    V[i + (int64_t)c * n] = (T)(c < i ? X[i][c] : (c == i ? 1.0 : 0.0));
+    U1i[e] = (T)(i <= c ? Y[i][c] : 0.0);
+  }
+  for (int c = tid; c < r; c += 256) Sg[c] = (T)sg[c];
+  // T = -U_1 Sg L_1^{-T}: tile (I, J), I <= J: -sum_{K=I..J} U_IK Sg_K (Yl_JK)^T
+  for (int t = wid; t < NB * NB; t += 4) {
+    const int I = t % NB, J = t / NB;
+    v4d acc = {0.0, 0.0, 0.0, 0.0};
+    if (I <= J) {
+      for (int K = I; K <= J; ++K)
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const int ar = I * 16 + (lane & 15), ac = K * 16 + kk + (lane >> 4);
+          const double av = (ar <= ac) ? X[ar][ac] * sg[ac] : 0.0;  // U_1 Sg
+          const int br = K * 16 + kk + (lane >> 4), bc = J * 16 + (lane & 15);
+          // (L_1^{-1})^T[br][bc] = Yl[bc][br]: nonzero for bc >= br, unit on the diagonal
+          const double bv = (bc == br) ? 1.0 : (bc > br ? Y[bc][br] : 0.0);
+          acc = mfma16x(av, bv, acc);
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = I * 16 + mfma_out_row(0.0, lane, v), c = J * 16 + (lane & 15);
+      if (i < r && c < r) Tm[i + (int64_t)c * r] = (T)(i <= c ? -acc[v] : 0.0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // merge: parent block from the children's Schur complements and the coupling
 // ---------------------------------------------------------------------------
 
@@ -196,17 +430,18 @@ __global__ __launch_bounds__(256) void k_merge(const NodeDesc* __restrict__ node
                                                T* __restrict__ Fout, int to_factor) {
   const int p = first + blockIdx.x;
   const NodeDesc nd = nodes[p];
-  const NodeDesc c1 = nodes[2 * p + 1], c2 = nodes[2 * p + 2];
+  const NodeDesc c1 = nodes[nd.c1], c2 = nodes[nd.c2];
   const int n = nd.n, r1 = c1.r;
-  T* M = Mbase + nd.offM;
+  T* M = Mbase + nd.offM;  // grid.y splits the columns
   T* Fo = Fout + nd.offF;  // the root block is also written where it is factored
   const T* F1 = Fbase + c1.offF;
   const T* F2 = Fbase + c2.offF;
   const T* s1 = Sgbase + c1.offSg;
   const T* s2 = Sgbase + c2.offSg;
   const T* S = Sbase + nd.offS;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int i = e % n, j = e / n;
+  for (int j = blockIdx.y; j < n; j += gridDim.y)
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const int64_t e = i + (int64_t)j * n;
     T v;
     if (i < r1 && j < r1) {
       const int a = max(i, j), b = min(i, j);
@@ -230,6 +465,41 @@ __global__ __launch_bounds__(256) void k_merge(const NodeDesc* __restrict__ node
 // 16-column panels; the trailing lower triangle is updated with MFMA tiles.
 // ---------------------------------------------------------------------------
 
+// Cholesky of a 16 x 16 pivot block held by one wave: lane i < jb owns row i
+// (a[0..i]); column k of L is published through LDS (col) after each step so the
+// remaining rows read it with independent loads. Returns the first non-positive
+// pivot (or -1) and the sum of log pivots. Call from one full wave.
+__device__ __forceinline__ int pivot_block_chol(double (&a)[16], int jb, double* col, double* dsh, double& lsum) {
+  const int lane = threadIdx.x & 63;
+  int bad = -1;
+  lsum = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) {
+    if (k < jb) {
+      if (lane == k) *dsh = a[k];
+      __builtin_amdgcn_wave_barrier();
+      double d = *dsh;
+      if (!(d > 0.0)) {
+        if (bad < 0) bad = k;
+        d = 1.0;
+      }
+      d = sqrt(d);
+      lsum += log(d);
+      if (lane == k) a[k] = d;
+      else if (lane > k) a[k] /= d;
+      if (lane < 16) col[lane] = a[k];
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int c = k + 1; c < 16; ++c) {
+        const double lc = col[c];
+        if (lane >= c && c < jb) a[c] -= a[k] * lc;
+      }
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  return bad;
+}
+
 constexpr int PNB = 16;
 
 template <typename T, int NMAX>
@@ -242,6 +512,8 @@ __global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ node
   T* F = Fbase + nd.offF;
   __shared__ double Ld[PNB][PNB + 1];  // pivot blocks are always factored in FP64
   __shared__ T P[PNB][NMAX + 1];
+  __shared__ double colb[16];
+  __shared__ double dshb;
   __shared__ int fail;
   __shared__ double lacc;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -258,27 +530,8 @@ __global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ node
 #pragma unroll
       for (int c = 0; c < PNB; ++c)
         a[c] = (lane < jb && c <= lane) ? (double)F[(j0 + lane) + (int64_t)(j0 + c) * n] : 0.0;
-      int bad = -1;
       double lsum = 0.0;
-#pragma unroll
-      for (int k = 0; k < PNB; ++k) {
-        if (k < jb) {
-          double d = __shfl(a[k], k, 64);
-          if (!(d > 0.0)) {
-            if (bad < 0) bad = k;
-            d = 1.0;
-          }
-          d = sqrt(d);
-          lsum += log(d);
-          if (lane == k) a[k] = d;
-          else if (lane > k) a[k] /= d;
-#pragma unroll
-          for (int c = k + 1; c < PNB; ++c) {
-            const double lc = __shfl(a[k], c, 64);
-            if (lane >= c && c < jb) a[c] -= a[k] * lc;
-          }
-        }
-      }
+      const int bad = pivot_block_chol(a, jb, colb, &dshb, lsum);
 #pragma unroll
       for (int c = 0; c < PNB; ++c) {
         if (lane < jb) Ld[lane][c] = (c <= lane) ? a[c] : 0.0;
@@ -372,8 +625,181 @@ __global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ node
         info[1] = node;
         info[2] = fail;
       }
+      info[4 + nd.sys] = 1;  // per-system flag
     }
     logdet[node] = 2.0 * lacc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// partial Cholesky of a level whose redundant blocks are small (m <= RM <= 96):
+// L_RR = chol(F_RR) entirely in LDS (16-column panels, pivot blocks in FP64 by
+// one wave, trailing updates on the matrix cores from LDS), and the explicit
+// inverse L_RR^{-1} (blocked, bottom-up MFMA recurrence). L_RR goes back to F,
+// L_RR^{-1} to Li (m x m, lower). L_SR and Sigma follow by batched GEMMs.
+// ---------------------------------------------------------------------------
+
+template <typename T, int RM>
+__global__ __launch_bounds__(256) void k_chol_lds(const NodeDesc* __restrict__ nodes, int first,
+                                                  T* __restrict__ Fbase, T* __restrict__ Libase,
+                                                  const int64_t* __restrict__ offLi, int32_t* __restrict__ info,
+                                                  double* __restrict__ logdet) {
+  constexpr int NB = RM / 16;
+  const int node = first + blockIdx.x;
+  const NodeDesc nd = nodes[node];
+  const int n = nd.n, m = nd.m;
+  T* F = Fbase + nd.offF;
+  T* Li = Libase + offLi[node];
+  __shared__ double X[RM][RM + 1];
+  __shared__ double Y[RM][RM + 1];
+  __shared__ double Pt[NB][16][17];
+  __shared__ double colb[16];
+  __shared__ double dshb;
+  __shared__ int fail;
+  __shared__ double lacc;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int e = tid; e < RM * RM; e += 256) {
+    const int i = e % RM, j = e / RM;
+    double v = 0.0;
+    if (i < m && j < m) v = (i >= j) ? (double)F[i + (int64_t)j * n] : 0.0;
+    else if (i == j) v = 1.0;
+    X[i][j] = v;
+  }
+  if (tid == 0) {
+    fail = -1;
+    lacc = 0.0;
+  }
+  __syncthreads();
+  for (int J = 0; J < NB; ++J) {
+    const int j0 = J * 16;
+    if (wid == 0) {
+      double a[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) a[c] = (lane < 16 && c <= lane) ? X[j0 + lane][j0 + c] : 0.0;
+      double lsum = 0.0;
+      const int jbl = m - j0 >= 16 ? 16 : (m - j0 > 0 ? m - j0 : 0);
+      int bad = pivot_block_chol(a, 16, colb, &dshb, lsum);
+      if (bad >= jbl) bad = -1;
+      if (lane < 16)
+#pragma unroll
+        for (int c = 0; c < 16; ++c) X[j0 + lane][j0 + c] = (c <= lane) ? a[c] : 0.0;
+      if (lane == 0) {
+        lacc += lsum;
+        if (bad >= 0 && fail < 0) fail = j0 + bad;
+      }
+    }
+    __syncthreads();
+    // panel rows below the pivot block
+    for (int i = j0 + 16 + tid; i < RM; i += 256) {
+      double x[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) x[c] = X[i][j0 + c];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double acc = x[c];
+#pragma unroll
+        for (int k = 0; k < c; ++k) acc -= x[k] * X[j0 + c][j0 + k];
+        x[c] = acc / X[j0 + c][j0 + c];
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c) X[i][j0 + c] = x[c];
+    }
+    __syncthreads();
+    // trailing update: tiles (I2 >= J2 > J) -= P_I2 P_J2^T with P = X[:, j0:j0+16]
+    const int rem = NB - J - 1;
+    const int ntl = rem * (rem + 1) / 2;
+    for (int t = wid; t < ntl; t += 4) {
+      int a = 0;
+      while ((a + 1) * (a + 2) / 2 <= t) ++a;
+      const int b = t - a * (a + 1) / 2;
+      const int I2 = J + 1 + a, J2 = J + 1 + b;
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const double av = X[I2 * 16 + (lane & 15)][j0 + kk + (lane >> 4)];
+        const double bv = X[J2 * 16 + (lane & 15)][j0 + kk + (lane >> 4)];
+        acc = mfma16x(av, bv, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) X[I2 * 16 + mfma_out_row(0.0, lane, v)][J2 * 16 + (lane & 15)] -= acc[v];
+    }
+    __syncthreads();
+  }
+  // inverse: diagonal tiles, then block rows top-down Y_IJ = -Y_II sum_{K=J..I-1} L_IK Y_KJ
+  {
+    const int b = tid >> 4, cc = tid & 15;
+    double x[16];
+    if (b < NB) {
+      const int o = b * 16;
+#pragma unroll
+      for (int i = 0; i < 16; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int k = 0; k < i; ++k) acc += X[o + i][o + k] * x[k];
+        x[i] = (i == cc) ? 1.0 / X[o + i][o + i] : (i > cc ? -acc / X[o + i][o + i] : 0.0);
+      }
+#pragma unroll
+      for (int i = 0; i < 16; ++i) Y[o + i][o + cc] = x[i];
+    }
+  }
+  __syncthreads();
+  for (int I = 1; I < NB; ++I) {
+    for (int J = wid; J < I; J += 4) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      for (int K = J; K < I; ++K) {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const double av = X[I * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
+          const double bv = Y[K * 16 + kk + (lane >> 4)][J * 16 + (lane & 15)];
+          acc = mfma16x(av, bv, acc);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Pt[J][mfma_out_row(0.0, lane, v)][lane & 15] = acc[v];
+    }
+    __syncthreads();
+    for (int J = wid; J < I; J += 4) {
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const double av = Y[I * 16 + (lane & 15)][I * 16 + kk + (lane >> 4)];
+        const double bv = Pt[J][kk + (lane >> 4)][lane & 15];
+        acc = mfma16x(av, bv, acc);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Y[I * 16 + mfma_out_row(0.0, lane, v)][J * 16 + (lane & 15)] = -acc[v];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < m * m; e += 256) {
+    const int i = e % m, j = e / m;
+    if (i >= j) F[i + (int64_t)j * n] = (T)X[i][j];
+    Li[e] = (T)(i >= j ? Y[i][j] : 0.0);
+  }
+  if (tid == 0) {
+    if (fail >= 0) {
+      if (atomicCAS(&info[0], 0, 1) == 0) {
+        info[1] = node;
+        info[2] = fail;
+      }
+      info[4 + nd.sys] = 1;  // per-system flag
+    }
+    logdet[node] = 2.0 * lacc;
+  }
+}
+
+// copies the L_SR block from the scratch into F (r x m at rows m..n-1, columns 0..m-1)
+template <typename T>
+__global__ void k_copy_lsr(const NodeDesc* __restrict__ nodes, int first, const T* __restrict__ src,
+                           const int64_t* __restrict__ offS2, T* __restrict__ Fbase) {
+  const NodeDesc nd = nodes[first + blockIdx.y];
+  const int r = nd.r, m = nd.m, n = nd.n;
+  if (r == 0) return;
+  const T* S2 = src + offS2[first + blockIdx.y];
+  T* F = Fbase + nd.offF;
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < r * m; e += gridDim.x * blockDim.x) {
+    const int i = e % r, j = e / r;
+    F[(m + i) + (int64_t)j * n] = S2[e];
   }
 }
 
@@ -462,7 +888,7 @@ struct FBufs {
   const T* D;
   const T* B;
   const T* S;
-  T *F, *M, *V, *Tm, *Sg, *W, *X;
+  T *F, *M, *V, *Tm, *Sg, *W, *X, *Li, *S2;
 };
 
 // Builds the per-level GEMM batches of the basis QR and the diagonal product
@@ -471,14 +897,14 @@ struct FBufs {
 template <typename T>
 static std::vector<std::vector<GemmBatch>> build_gemm_plan(hss_matrix_t m, const FBufs<T>& b) {
   hipStream_t s = m->ctx->stream;
-  std::vector<std::vector<GemmBatch>> plan(m->L + 1);
-  for (auto& lp : m->levels) {
-    if (lp.level == 0) continue;
-    std::vector<GemmBatch> steps(7);
+  std::vector<std::vector<GemmBatch>> plan(m->stages.size());
+  for (size_t si = 0; si < m->stages.size(); ++si) {
+    const LevelPlan& lp = m->stages[si];
+    std::vector<GemmBatch> steps(9);
     for (int p = lp.first; p < lp.first + lp.count; ++p) {
       const NodeDesc& nd = m->nodes[p];
       const int n = nd.n, r = nd.r;
-      const T* Mp = (lp.level == m->L) ? b.D + nd.offD : b.M + nd.offM;
+      const T* Mp = lp.leaf ? b.D + nd.offD : b.M + nd.offM;
       T* V = b.V + nd.offV;
       T* Zl = V - (int64_t)n * r;  // Z copy left of V
       T* Zr = V + (int64_t)n * r;  // Z copy right of V
@@ -496,9 +922,17 @@ static std::vector<std::vector<GemmBatch>> build_gemm_plan(hss_matrix_t m, const
       steps[4].host.push_back({Y, W, nullptr, X1, r, r, n, n, n, 0, r, 0, 0});            // C = Y^T W
       steps[5].host.push_back({V, X1, W, Zl, n, r, r, n, r, n, n, 0, 0, Zr});             // Z = W - V C / 2
       steps[6].host.push_back({Zl, V, Mp, F, n, n, 2 * r, n, n, n, n, r, 0});             // F = P^T (M - [Z V][V Z]^T) P
+      if (lp.inv) {
+        const int mm = nd.m;
+        T* Li = b.Li + m->offLi[p];
+        T* S2 = b.S2 + m->offS2[p];
+        steps[7].host.push_back({F + mm, Li, nullptr, S2, r, mm, mm, n, mm, 0, r, 0, 0});   // L_SR = F_SR L_RR^{-T}
+        T* Fss = F + mm + (int64_t)mm * n;
+        steps[8].host.push_back({S2, S2, Fss, Fss, r, r, mm, r, r, n, n, 0, 0});          // Sigma = F_SS - L_SR L_SR^T
+      }
     }
     for (auto& g : steps) gemm_upload(g, s);
-    plan[lp.level] = std::move(steps);
+    plan[si] = std::move(steps);
   }
   return plan;
 }
@@ -529,7 +963,7 @@ static void cast(const A* src, B* dst, int64_t n, hipStream_t s) {
 }
 
 static void alloc_common(hss_matrix_t m) {
-  if (!m->dinfo) m->dinfo = (int32_t*)dev_alloc(sizeof(int32_t) * 4);
+  if (!m->dinfo) m->dinfo = (int32_t*)dev_alloc(sizeof(int32_t) * (4 + m->nsys));
   if (!m->dlogdet) m->dlogdet = (double*)dev_alloc(sizeof(double) * (m->nnodes + 1));
 }
 
@@ -543,7 +977,9 @@ static void alloc_factor(hss_matrix_t m) {
   m->dSg = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenSg, 1));
   m->dW = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenW, 1));
   m->dX = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenX, 1));
-  FBufs<double> b{m->dD, m->dB, m->dS, m->dF, m->dM, m->dV, m->dT, m->dSg, m->dW, m->dX};
+  m->dLi = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenLi, 1));
+  m->dS2 = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenS2, 1));
+  FBufs<double> b{m->dD, m->dB, m->dS, m->dF, m->dM, m->dV, m->dT, m->dSg, m->dW, m->dX, m->dLi, m->dS2};
   m->gemm_plan = build_gemm_plan<double>(m, b);
   m->factor_ready = true;
 }
@@ -562,10 +998,11 @@ static void alloc_factor32(hss_matrix_t m) {
   m->fSg = fa(m->lenSg);
   m->fW = fa(m->lenW);
   m->fX = fa(m->lenX);
-  // FP64 scratch for the root block
-  const NodeDesc& root = m->nodes[0];
-  m->dRoot = (double*)dev_alloc(sizeof(double) * (int64_t)root.n * root.n);
-  FBufs<float> b{m->fD, m->fB, m->fS, m->fF, m->fM, m->fV, m->fT, m->fSg, m->fW, m->fX};
+  m->fLi = fa(m->lenLi);
+  m->fS2 = fa(m->lenS2);
+  // FP64 scratch for the root blocks (same offsets as F)
+  m->dRoot = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenF, 1));
+  FBufs<float> b{m->fD, m->fB, m->fS, m->fF, m->fM, m->fV, m->fT, m->fSg, m->fW, m->fX, m->fLi, m->fS2};
   m->gemm_plan32 = build_gemm_plan<float>(m, b);
   m->factor32_ready = true;
 }
@@ -578,37 +1015,81 @@ void free_factor(hss_matrix_t m) {
   m->gemm_plan.clear();
   m->gemm_plan32.clear();
   void* ptrs[] = {m->dF, m->dM, m->dV, m->dT, m->dSg, m->dW, m->dX, m->dinfo, m->dlogdet, m->dRoot,
-                  m->fF, m->fM, m->fV, m->fT, m->fSg, m->fW, m->fX, m->fD, m->fB, m->fS};
+                  m->fF, m->fM, m->fV, m->fT, m->fSg, m->fW, m->fX, m->fD, m->fB, m->fS,
+                  m->dLi, m->dS2, m->fLi, m->fS2};
   for (void* p : ptrs)
     if (p) dev_free(p);
-  m->dF = m->dM = m->dV = m->dT = m->dSg = m->dW = m->dX = m->dRoot = nullptr;
+  m->dF = m->dM = m->dV = m->dT = m->dSg = m->dW = m->dX = m->dRoot = m->dLi = m->dS2 = nullptr;
+  m->fLi = m->fS2 = nullptr;
   m->dinfo = nullptr;
   m->dlogdet = nullptr;
   m->fF = m->fM = m->fV = m->fT = m->fSg = m->fW = m->fX = m->fD = m->fB = m->fS = nullptr;
   m->factor_ready = m->factor32_ready = false;
 }
 
-// One level-by-level sweep of Alg. 2 in compute type T (the root separately).
+// One sweep of Alg. 2 over the stages (leaves first, roots included) in
+// compute type T. A root has rank 0: its transform is the identity and its
+// "partial" Cholesky is complete. With FP32 compute, the roots of a stage are
+// factored in FP64 (their blocks are cast to FP64 and back).
 template <typename T>
-static void factor_levels(hss_matrix_t m, const FBufs<T>& b, std::vector<std::vector<GemmBatch>>& plan) {
+static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::vector<GemmBatch>>& plan);
+
+template <typename T>
+static void root_cholesky_fp64(hss_matrix_t m, const LevelPlan& lp, T* F, hipStream_t s);
+
+template <>
+void root_cholesky_fp64<double>(hss_matrix_t m, const LevelPlan& lp, double* F, hipStream_t s) {
+  launch_pchol<double>(m, lp.root_first, lp.first + lp.count - lp.root_first, lp.nmax, F, s);
+}
+
+template <>
+void root_cholesky_fp64<float>(hss_matrix_t m, const LevelPlan& lp, float* F, hipStream_t s) {
+  for (int k = lp.root_first; k < lp.first + lp.count; ++k) {
+    const NodeDesc& nd = m->nodes[k];
+    cast<float, double>(F + nd.offF, m->dRoot + nd.offF, (int64_t)nd.n * nd.n, s);
+  }
+  launch_pchol<double>(m, lp.root_first, lp.first + lp.count - lp.root_first, lp.nmax, m->dRoot, s);
+  for (int k = lp.root_first; k < lp.first + lp.count; ++k) {
+    const NodeDesc& nd = m->nodes[k];
+    cast<double, float>(m->dRoot + nd.offF, F + nd.offF, (int64_t)nd.n * nd.n, s);
+  }
+}
+
+template <typename T>
+static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::vector<GemmBatch>>& plan) {
   hipStream_t s = m->ctx->stream;
   hss_ctx_t cx = m->ctx;
-  for (int l = m->L; l >= 1; --l) {
-    const LevelPlan& lp = m->levels[l];
-    if (l < m->L) {
+  const bool fp32 = sizeof(T) == 4;
+  for (size_t si = 0; si < m->stages.size(); ++si) {
+    const LevelPlan& lp = m->stages[si];
+    const int l = lp.level;
+    const int nonroot = lp.root_first - lp.first;
+    if (!lp.leaf) {
       Prof pf(cx, "merge", l);
-      hipLaunchKernelGGL((k_merge<T>), dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const T*)b.F,
+      hipLaunchKernelGGL((k_merge<T>), dim3(lp.count, 16), dim3(256), 0, s, m->dnodes, lp.first, (const T*)b.F,
                          (const T*)b.Sg, b.S, b.M, b.F, 0);
       HSS_HIP(hipGetLastError());
     }
-    auto& st = plan[l];
-    {
+    auto& st = plan[si];
+    if (lp.rmax > 0) {
       Prof pf(cx, "basis_qr", l);
-      launch_lu_top<T>(m, lp, b.B, b.V, b.Tm, b.Sg, s);   // V_1, U_1 (in the T slot), Sg
-      launch_tri_inv<T>(m, lp, b.Tm, 0, b.X, 2, 0, s);    // U_1^{-1} -> second half of X
-      gemm_run<T>(st[0], false, false, 1.0, 0.0, s);      // V_2 = B_2 U_1^{-1}
-      gemm_run<T>(st[1], true, false, 1.0, 0.0, s);       // G = V^T V -> first half of X
-      launch_tri_inv<T>(m, lp, b.X, 1, b.Tm, 0, 1, s);    // T = (striu G + diag G / 2)^{-1}
+      if (lp.rmax <= 96) {
+        dim3 grid(lp.count), block(256);
+        if (lp.rmax <= 32)
+          hipLaunchKernelGGL((k_basis_top<T, 32>), grid, block, 0, s, m->dnodes, lp.first, b.B, b.V, b.Tm, b.Sg, b.X);
+        else if (lp.rmax <= 64)
+          hipLaunchKernelGGL((k_basis_top<T, 64>), grid, block, 0, s, m->dnodes, lp.first, b.B, b.V, b.Tm, b.Sg, b.X);
+        else
+          hipLaunchKernelGGL((k_basis_top<T, 96>), grid, block, 0, s, m->dnodes, lp.first, b.B, b.V, b.Tm, b.Sg, b.X);
+        HSS_HIP(hipGetLastError());
+        gemm_run<T>(st[0], false, false, 1.0, 0.0, s);    // V_2 = B_2 U_1^{-1}
+      } else {
+        launch_lu_top<T>(m, lp, b.B, b.V, b.Tm, b.Sg, s);   // V_1, U_1 (in the T slot), Sg
+        launch_tri_inv<T>(m, lp, b.Tm, 0, b.X, 2, 0, s);    // U_1^{-1} -> second half of X
+        gemm_run<T>(st[0], false, false, 1.0, 0.0, s);      // V_2 = B_2 U_1^{-1}
+        gemm_run<T>(st[1], true, false, 1.0, 0.0, s);       // G = V^T V -> first half of X
+        launch_tri_inv<T>(m, lp, b.X, 1, b.Tm, 0, 1, s);    // T = (striu G + diag G / 2)^{-1}
+      }
     }
     {
       Prof pf(cx, "gemm_small_wy", l);
@@ -627,83 +1108,95 @@ static void factor_levels(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
       Prof pf(cx, "gemm_two_sided_update", l);
       gemm_run<T>(st[6], false, true, -1.0, 1.0, s);      // F = P^T (M - Z V^T - V Z^T) P
     }
+    // With FP32 compute a stage that holds roots is factored by the blocked
+    // kernel, so that the roots can be done in FP64.
+    const bool use_inv = lp.inv && !(fp32 && nonroot < lp.count);
+    (fp32 ? m->inv_used32 : m->inv_used64)[si] = use_inv ? 1 : 0;
     {
-      Prof pf(cx, "partial_cholesky", l);
-      launch_pchol<T>(m, lp.first, lp.count, lp.nmax, b.F, s);
+      Prof pf(cx, nonroot == 0 ? "root" : "partial_cholesky", l);
+      if (use_inv) {
+        const int mm = lp.mmax;
+        dim3 grid(lp.count), block(256);
+        if (mm <= 32)
+          hipLaunchKernelGGL((k_chol_lds<T, 32>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
+                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet);
+        else if (mm <= 64)
+          hipLaunchKernelGGL((k_chol_lds<T, 64>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
+                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet);
+        else
+          hipLaunchKernelGGL((k_chol_lds<T, 96>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
+                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet);
+        HSS_HIP(hipGetLastError());
+        gemm_run<T>(st[7], false, true, 1.0, 0.0, s);
+        gemm_run<T>(st[8], false, true, -1.0, 1.0, s);
+        hipLaunchKernelGGL((k_copy_lsr<T>), dim3(16, lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const T*)b.S2,
+                           (const int64_t*)m->dOffS2, b.F);
+        HSS_HIP(hipGetLastError());
+      } else {
+        if (nonroot > 0) launch_pchol<T>(m, lp.first, nonroot, lp.nmax, b.F, s);
+        if (nonroot < lp.count) {
+          if (fp32)
+            root_cholesky_fp64<T>(m, lp, b.F, s);
+          else
+            launch_pchol<T>(m, lp.root_first, lp.count - nonroot, lp.nmax, b.F, s);
+        }
+      }
     }
   }
+}
+
+// Clears the status words and the per-node log-determinant sums with a kernel
+// (not a memset node), so that the sequence can be recorded into a HIP graph.
+__global__ void k_clear_status(int32_t* __restrict__ info, int ninfo, double* __restrict__ logdet, int nld) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ninfo + nld; i += gridDim.x * blockDim.x) {
+    if (i < ninfo)
+      info[i] = 0;
+    else
+      logdet[i - ninfo] = 0.0;
+  }
+}
+
+static void clear_status(hss_matrix_t m, hipStream_t s) {
+  const int tot = 4 + m->nsys + m->nnodes + 1;
+  hipLaunchKernelGGL(k_clear_status, dim3(std::min((tot + 255) / 256, 1024)), dim3(256), 0, s, m->dinfo,
+                     4 + m->nsys, m->dlogdet, m->nnodes + 1);
+  HSS_HIP(hipGetLastError());
+}
+
+void prepare_factor(hss_matrix_t m, int precision) {
+  if (precision == HSS_P_FP64)
+    alloc_factor(m);
+  else
+    alloc_factor32(m);
 }
 
 void factor_fp64(hss_matrix_t m) {
   hipStream_t s = m->ctx->stream;
   alloc_factor(m);
-  HSS_HIP(hipMemsetAsync(m->dinfo, 0, sizeof(int32_t) * 4, s));
-  HSS_HIP(hipMemsetAsync(m->dlogdet, 0, sizeof(double) * (m->nnodes + 1), s));
-  if (m->L == 0) {
-    const NodeDesc& nd = m->nodes[0];
-    HSS_HIP(hipMemcpyAsync(m->dF + nd.offF, m->dD + nd.offD, sizeof(double) * nd.n * nd.n,
-                           hipMemcpyDeviceToDevice, s));
-    launch_pchol<double>(m, 0, 1, nd.n, m->dF, s);
-  } else {
-    FBufs<double> b{m->dD, m->dB, m->dS, m->dF, m->dM, m->dV, m->dT, m->dSg, m->dW, m->dX};
-    factor_levels<double>(m, b, m->gemm_plan);
-    const LevelPlan& root = m->levels[0];
-    HSS_CHECK(m->dM != m->dF, HSS_ERR_DEVICE, "merge buffers alias");
-    Prof pf(m->ctx, "root", 0);
-    hipLaunchKernelGGL((k_merge<double>), dim3(1), dim3(256), 0, s, m->dnodes, 0, (const double*)m->dF,
-                       (const double*)m->dSg, (const double*)m->dS, m->dM, m->dF, 1);
-    HSS_HIP(hipGetLastError());
-    launch_pchol<double>(m, 0, 1, root.nmax, m->dF, s);
-  }
+  clear_status(m, s);
+  FBufs<double> b{m->dD, m->dB, m->dS, m->dF, m->dM, m->dV, m->dT, m->dSg, m->dW, m->dX, m->dLi, m->dS2};
+  factor_stages<double>(m, b, m->gemm_plan);
   hipLaunchKernelGGL(k_sum_logdet, dim3(1), dim3(256), 0, s, (const double*)m->dlogdet, m->nnodes,
                      m->dlogdet + m->nnodes);
   HSS_HIP(hipGetLastError());
 }
 
-// Mixed precision: the representation is rounded to FP32, the basis QR, the
+// Mixed precision: the representation is rounded to FP32; the basis QR, the
 // diagonal product, the panel TRSM and the Schur updates run in FP32 (FP32
 // MFMA, FP32 accumulation); the 16x16 pivot blocks of every partial Cholesky
-// and the whole root Cholesky run in FP64.
+// and the whole Cholesky of every root run in FP64.
 void factor_fp32(hss_matrix_t m) {
   hipStream_t s = m->ctx->stream;
   alloc_factor32(m);
-  HSS_HIP(hipMemsetAsync(m->dinfo, 0, sizeof(int32_t) * 4, s));
-  HSS_HIP(hipMemsetAsync(m->dlogdet, 0, sizeof(double) * (m->nnodes + 1), s));
+  clear_status(m, s);
   {
     Prof pf(m->ctx, "convert_fp32", m->L);
     cast<double, float>(m->dD, m->fD, m->lenD, s);
     cast<double, float>(m->dB, m->fB, m->lenB, s);
     cast<double, float>(m->dS, m->fS, m->lenS, s);
   }
-  const NodeDesc& rt = m->nodes[0];
-  if (m->L > 0) {
-    FBufs<float> b{m->fD, m->fB, m->fS, m->fF, m->fM, m->fV, m->fT, m->fSg, m->fW, m->fX};
-    factor_levels<float>(m, b, m->gemm_plan32);
-    Prof pf(m->ctx, "root", 0);
-    hipLaunchKernelGGL((k_merge<float>), dim3(1), dim3(256), 0, s, m->dnodes, 0, (const float*)m->fF,
-                       (const float*)m->fSg, (const float*)m->fS, m->fM, m->fF, 1);
-    HSS_HIP(hipGetLastError());
-    cast<float, double>(m->fF + rt.offF, m->dRoot, (int64_t)rt.n * rt.n, s);
-  } else {
-    cast<double, double>(m->dD + rt.offD, m->dRoot, (int64_t)rt.n * rt.n, s);
-  }
-  // root block in FP64: a one-node table whose block starts at offset 0 of dRoot
-  std::vector<NodeDesc> one(1, rt);
-  one[0].offF = 0;
-  one[0].m = rt.n;
-  if (!m->dRootNode) m->dRootNode = (NodeDesc*)dev_alloc(sizeof(NodeDesc));
-  HSS_HIP(hipMemcpyAsync(m->dRootNode, one.data(), sizeof(NodeDesc), hipMemcpyHostToDevice, s));
-  {
-    dim3 grid(1), block(256);
-    if (rt.n <= 256)
-      hipLaunchKernelGGL((k_pchol<double, 256>), grid, block, 0, s, (const NodeDesc*)m->dRootNode, 0, m->dRoot,
-                         m->dinfo, m->dlogdet);
-    else
-      hipLaunchKernelGGL((k_pchol<double, 512>), grid, block, 0, s, (const NodeDesc*)m->dRootNode, 0, m->dRoot,
-                         m->dinfo, m->dlogdet);
-    HSS_HIP(hipGetLastError());
-  }
-  cast<double, float>(m->dRoot, m->fF + rt.offF, (int64_t)rt.n * rt.n, s);
+  FBufs<float> b{m->fD, m->fB, m->fS, m->fF, m->fM, m->fV, m->fT, m->fSg, m->fW, m->fX, m->fLi, m->fS2};
+  factor_stages<float>(m, b, m->gemm_plan32);
   hipLaunchKernelGGL(k_sum_logdet, dim3(1), dim3(256), 0, s, (const double*)m->dlogdet, m->nnodes,
                      m->dlogdet + m->nnodes);
   HSS_HIP(hipGetLastError());

@@ -2,10 +2,12 @@
 // contraction steps of the HSS-ULV factorization: the diagonal product
 // Q^T A Q in compact WY form (Eq. 7) and the products around it.
 //
-// One launch covers every node of a level: grid.y indexes the batch entry,
-// grid.x the 64x64 output tiles of that entry. Each 256-thread workgroup
-// stages 64x16 slices of op(A) and 16x64 slices of op(B) in LDS; each of its
-// four waves owns a 32x32 quadrant of the tile as 2x2 MFMA accumulators.
+// One launch covers every node of a stage: grid.y indexes the batch entry,
+// grid.x the BM x BN output tiles of that entry. Each 256-thread workgroup
+// stages BM x 16 slices of op(A) and 16 x BN slices of op(B) in LDS; each of
+// its four waves owns a (BM/2) x (BN/2) quadrant of the tile as a grid of
+// 16x16 MFMA accumulators. The tile shape is one of a few compiled variants,
+// picked per batch by the autotuner (default 64 x 64).
 #include "hss_internal.h"
 
 namespace hss {
@@ -31,7 +33,11 @@ __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BK = 16;
+
+// tile variants: {BM, BN}
+constexpr int kTileM[kGemmVariants] = {64, 32, 128, 64};
+constexpr int kTileN[kGemmVariants] = {64, 32, 64, 128};
 
 // Row of the 16x16 MFMA output held by lane `lane` in accumulator slot v.
 // FP64 16x16x4 interleaves rows across slots; FP32 16x16x4 stacks them.
@@ -42,8 +48,70 @@ __device__ __forceinline__ int perm_index(int t, int dim, int r) {
   return r > 0 ? (t < r ? t + (dim - r) : t - r) : t;
 }
 
-template <typename T, bool TA, bool TB>
+template <typename T, bool TA, bool TB, int BM, int BN>
+__device__ __forceinline__ void load_tiles(const GemmDesc& d, const T* __restrict__ A, const T* __restrict__ B,
+                                           int row0, int col0, int k0, T (&ra)[BM * BK / 256],
+                                           T (&rb)[BN * BK / 256]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < BM * BK / 256; ++q) {
+    const int e = q * 256 + tid;
+    int r, kk;
+    if (!TA) {
+      r = e % BM;
+      kk = e / BM;
+    } else {
+      kk = e % BK;
+      r = e / BK;
+    }
+    const int gr = row0 + r, gk = k0 + kk;
+    T v = 0;
+    if (gr < d.m && gk < d.k) v = TA ? A[gk + (int64_t)gr * d.lda] : A[gr + (int64_t)gk * d.lda];
+    ra[q] = v;
+  }
+#pragma unroll
+  for (int q = 0; q < BN * BK / 256; ++q) {
+    const int e = q * 256 + tid;
+    int c, kk;
+    if (!TB) {
+      kk = e % BK;
+      c = e / BK;
+    } else {
+      c = e % BN;
+      kk = e / BN;
+    }
+    const int gc = col0 + c, gk = k0 + kk;
+    T v = 0;
+    if (gc < d.n && gk < d.k) v = TB ? B[gc + (int64_t)gk * d.ldb] : B[gk + (int64_t)gc * d.ldb];
+    rb[q] = v;
+  }
+}
+
+template <typename T, bool TA, bool TB, int BM, int BN>
+__device__ __forceinline__ void store_tiles(T (&As)[BK][BM + 1], T (&Bs)[BK][BN + 1], const T (&ra)[BM * BK / 256],
+                                            const T (&rb)[BN * BK / 256]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < BM * BK / 256; ++q) {
+    const int e = q * 256 + tid;
+    if (!TA)
+      As[e / BM][e % BM] = ra[q];
+    else
+      As[e % BK][e / BK] = ra[q];
+  }
+#pragma unroll
+  for (int q = 0; q < BN * BK / 256; ++q) {
+    const int e = q * 256 + tid;
+    if (!TB)
+      Bs[e % BK][e / BK] = rb[q];
+    else
+      Bs[e / BN][e % BN] = rb[q];
+  }
+}
+
+template <typename T, bool TA, bool TB, int BM, int BN>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs, T alpha, T beta) {
+  constexpr int IM = BM / 32, JN = BN / 32;  // 16x16 accumulators per wave
   const GemmDesc d = descs[blockIdx.y];
   const int tilesM = (d.m + BM - 1) / BM;
   const int tilesN = (d.n + BN - 1) / BN;
@@ -55,63 +123,34 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   const T* __restrict__ A = (const T*)d.A;
   const T* __restrict__ B = (const T*)d.B;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  const int wm = (wid >> 1) * 32, wn = (wid & 1) * 32;
+  const int wm = (wid >> 1) * (BM / 2), wn = (wid & 1) * (BN / 2);
   const int lr = lane & 15, lk = lane >> 4;
-  typename AccT<T>::type acc[2][2];
+  typename AccT<T>::type acc[IM][JN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < JN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
-
+  T ra[BM * BK / 256], rb[BN * BK / 256];
+  // software pipeline: the next K slice is fetched into registers while the
+  // matrix cores consume the current one from LDS
+  if (d.k > 0) load_tiles<T, TA, TB, BM, BN>(d, A, B, row0, col0, 0, ra, rb);
   for (int k0 = 0; k0 < d.k; k0 += BK) {
-#pragma unroll
-    for (int e0 = 0; e0 < BM * BK; e0 += 256) {
-      const int e = e0 + tid;
-      int r, kk;
-      if (!TA) {
-        r = e % BM;
-        kk = e / BM;
-      } else {
-        kk = e % BK;
-        r = e / BK;
-      }
-      const int gr = row0 + r, gk = k0 + kk;
-      T v = 0;
-      if (gr < d.m && gk < d.k)
-        v = TA ? A[gk + (int64_t)gr * d.lda] : A[gr + (int64_t)gk * d.lda];
-      As[kk][r] = v;
-    }
-#pragma unroll
-    for (int e0 = 0; e0 < BN * BK; e0 += 256) {
-      const int e = e0 + tid;
-      int c, kk;
-      if (!TB) {
-        kk = e % BK;
-        c = e / BK;
-      } else {
-        c = e % BN;
-        kk = e / BN;
-      }
-      const int gc = col0 + c, gk = k0 + kk;
-      T v = 0;
-      if (gc < d.n && gk < d.k)
-        v = TB ? B[gc + (int64_t)gk * d.ldb] : B[gk + (int64_t)gc * d.ldb];
-      Bs[kk][c] = v;
-    }
+    store_tiles<T, TA, TB, BM, BN>(As, Bs, ra, rb);
     __syncthreads();
+    if (k0 + BK < d.k) load_tiles<T, TA, TB, BM, BN>(d, A, B, row0, col0, k0 + BK, ra, rb);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      T a[2], b[2];
+      T a[IM], b[JN];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = As[kk + lk][wm + 16 * i + lr];
+      for (int i = 0; i < IM; ++i) a[i] = As[kk + lk][wm + 16 * i + lr];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Bs[kk + lk][wn + 16 * j + lr];
+      for (int j = 0; j < JN; ++j) b[j] = Bs[kk + lk][wn + 16 * j + lr];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < IM; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < JN; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
     }
     __syncthreads();
   }
@@ -119,9 +158,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   T* __restrict__ C = (T*)d.C;
   const T* __restrict__ Cin = (const T*)d.Cin;
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < IM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < JN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + wm + 16 * i + mfma_row((T)0, lane, v);
@@ -139,6 +178,31 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
           if (d.C2) ((T*)d.C2)[prow + (int64_t)pcol * d.ldc] = val;
         }
       }
+}
+
+thread_local TuneRec* g_tune = nullptr;
+
+static hipEvent_t tune_event(TuneRec* t) {
+  if (t->used == t->pool.size()) {
+    hipEvent_t e;
+    HSS_HIP(hipEventCreate(&e));
+    t->pool.push_back(e);
+  }
+  return t->pool[t->used++];
+}
+
+GemmTimer::GemmTimer(const GemmBatch& g, hipStream_t st) {
+  if (!g_tune) return;
+  t = g_tune;
+  s = st;
+  hipEvent_t a = tune_event(t);
+  b = tune_event(t);
+  HSS_HIP(hipEventRecord(a, s));
+  t->recs.push_back({&g, a, b});
+}
+
+GemmTimer::~GemmTimer() {
+  if (t) (void)hipEventRecord(b, s);
 }
 
 void gemm_upload(GemmBatch& b, hipStream_t s) {
@@ -160,21 +224,32 @@ void gemm_free(GemmBatch& b) {
   b.dev = nullptr;
 }
 
+template <typename T, int BM, int BN>
+static void launch_tile(const GemmBatch& b, bool ta, bool tb, T alpha, T beta, hipStream_t s) {
+  const int tiles = ((b.mmax + BM - 1) / BM) * ((b.nmax + BN - 1) / BN);
+  dim3 grid(tiles, b.count);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((k_gemm<T, false, false, BM, BN>), grid, dim3(256), 0, s, b.dev, alpha, beta);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((k_gemm<T, true, false, BM, BN>), grid, dim3(256), 0, s, b.dev, alpha, beta);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((k_gemm<T, false, true, BM, BN>), grid, dim3(256), 0, s, b.dev, alpha, beta);
+  else
+    hipLaunchKernelGGL((k_gemm<T, true, true, BM, BN>), grid, dim3(256), 0, s, b.dev, alpha, beta);
+  HSS_HIP(hipGetLastError());
+}
+
 template <typename T>
 static void launch(const GemmBatch& b, bool ta, bool tb, T alpha, T beta, hipStream_t s) {
   if (b.count == 0 || b.mmax == 0 || b.nmax == 0) return;
-  const int tiles = ((b.mmax + BM - 1) / BM) * ((b.nmax + BN - 1) / BN);
   HSS_CHECK(b.count <= 65535, HSS_ERR_UNSUPPORTED, "too many GEMM batch entries in one launch");
-  dim3 grid(tiles, b.count);
-  if (!ta && !tb)
-    hipLaunchKernelGGL((k_gemm<T, false, false>), grid, dim3(256), 0, s, b.dev, alpha, beta);
-  else if (ta && !tb)
-    hipLaunchKernelGGL((k_gemm<T, true, false>), grid, dim3(256), 0, s, b.dev, alpha, beta);
-  else if (!ta && tb)
-    hipLaunchKernelGGL((k_gemm<T, false, true>), grid, dim3(256), 0, s, b.dev, alpha, beta);
-  else
-    hipLaunchKernelGGL((k_gemm<T, true, true>), grid, dim3(256), 0, s, b.dev, alpha, beta);
-  HSS_HIP(hipGetLastError());
+  GemmTimer t(b, s);
+  switch (b.variant) {
+    case 1: launch_tile<T, kTileM[1], kTileN[1]>(b, ta, tb, alpha, beta, s); break;
+    case 2: launch_tile<T, kTileM[2], kTileN[2]>(b, ta, tb, alpha, beta, s); break;
+    case 3: launch_tile<T, kTileM[3], kTileN[3]>(b, ta, tb, alpha, beta, s); break;
+    default: launch_tile<T, kTileM[0], kTileN[0]>(b, ta, tb, alpha, beta, s); break;
+  }
 }
 
 void gemm_launch_f64(const GemmBatch& b, bool ta, bool tb, double alpha, double beta, hipStream_t s) {

@@ -35,7 +35,8 @@ struct Error {
   } while (0)
 
 // ---------------------------------------------------------------------------
-// per-node descriptor (heap order: node 0 = root, children 2k+1, 2k+2)
+// per-node descriptor; every stage is a contiguous range of node indices and
+// the tree links are explicit, so one object can hold a forest of trees
 // ---------------------------------------------------------------------------
 
 struct NodeDesc {
@@ -58,13 +59,22 @@ struct NodeDesc {
   int32_t m;      // n - r (redundant rows eliminated at this node)
   int32_t level;
   int32_t child_row;  // row offset of this node's skeleton part in the parent's block
+  int32_t parent;     // index of the parent node, -1 at a root
+  int32_t c1, c2;     // indices of the children, -1 at a leaf
+  int32_t sys;        // system (tree) the node belongs to
 };
 
+// A stage is a contiguous range of nodes processed by one launch of each step:
+// one tree level for a single matrix (leaves first), one height above the
+// leaves for a forest of several matrices. Roots of a stage come last.
 struct LevelPlan {
-  int32_t level;
-  int32_t first;   // first heap index on this level
-  int32_t count;   // nodes on this level
+  int32_t level;       // tree level (single matrix) or height (forest), for labels
+  int32_t first;       // first node index of the stage
+  int32_t count;       // nodes in the stage
   int32_t nmax, rmax, mmax;
+  int32_t leaf;        // 1 for the stage of the leaves
+  int32_t inv;         // 1 if the LDS Cholesky + explicit inverse path is used
+  int32_t root_first;  // first root of the stage (first + count if none)
 };
 
 // Batched GEMM entry: C = alpha * op(A) op(B) + beta * Cin, optional symmetric
@@ -81,11 +91,35 @@ struct GemmDesc {
   void* C2;        // optional second output (same values, same layout as C)
 };
 
+constexpr int kGemmVariants = 4;  // compiled tile shapes of the batched GEMM
+
 struct GemmBatch {
   std::vector<GemmDesc> host;
   GemmDesc* dev = nullptr;
   int32_t count = 0;
   int32_t mmax = 0, nmax = 0;
+  int32_t variant = 0;  // tile shape, set by the autotuner
+};
+
+// Autotuning: while a recorder is installed on the calling thread, every
+// batched GEMM launch is bracketed by two HIP events.
+struct TuneRec {
+  struct Rec {
+    const GemmBatch* batch;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  size_t used = 0;
+};
+extern thread_local TuneRec* g_tune;
+
+struct GemmTimer {
+  TuneRec* t = nullptr;
+  hipEvent_t b = nullptr;
+  hipStream_t s = nullptr;
+  GemmTimer(const GemmBatch& g, hipStream_t st);
+  ~GemmTimer();
 };
 
 }  // namespace hss
@@ -111,6 +145,7 @@ struct hss_ctx_s {
   std::vector<hss::ProfRec> prof_recs;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
+  hipStream_t cap_stream = nullptr;  // non-blocking stream used only to record graphs
 };
 
 struct hss_matrix_s {
@@ -124,7 +159,11 @@ struct hss_matrix_s {
 
   std::vector<hss::NodeDesc> nodes;  // host copy
   hss::NodeDesc* dnodes = nullptr;   // device copy
-  std::vector<hss::LevelPlan> levels;
+  std::vector<hss::LevelPlan> levels;  // single matrix: indexed by tree level
+  std::vector<hss::LevelPlan> stages;  // processing order, leaves first
+  int32_t nsys = 1;                    // systems in the matrix (a forest for batches)
+  std::vector<int64_t> sys_lo;         // first global row of each system
+  std::vector<int32_t> sys_root;       // root node of each system
 
   // representation (device)
   double* dD = nullptr;
@@ -141,11 +180,21 @@ struct hss_matrix_s {
   double* dSg = nullptr;
   double* dW = nullptr;
   double* dX = nullptr;
+  // explicit L_RR^{-1} (levels whose m <= 96) and the L_SR scratch of those levels
+  std::vector<int64_t> offLi, offS2;
+  int64_t* dOffLi = nullptr;
+  int64_t* dOffS2 = nullptr;
+  double* dLi = nullptr;
+  double* dS2 = nullptr;
+  float* fLi = nullptr;
+  float* fS2 = nullptr;
+  int64_t lenLi = 0, lenS2 = 0;
   int32_t* dinfo = nullptr;  // [0] status, [1] node, [2] pivot
   double* dlogdet = nullptr; // per node partial sums
   int64_t lenF = 0, lenM = 0, lenV = 0, lenT = 0, lenSg = 0, lenW = 0, lenX = 0;
   bool factor_ready = false;
-  std::vector<std::vector<hss::GemmBatch>> gemm_plan;  // per level, per step
+  std::vector<std::vector<hss::GemmBatch>> gemm_plan;  // per stage, per step
+  std::vector<char> inv_used64, inv_used32;  // per stage: explicit inverse factor present
 
   // FP32 factor (mixed precision)
   float* fF = nullptr;
@@ -158,8 +207,7 @@ struct hss_matrix_s {
   float* fB = nullptr;
   float* fS = nullptr;
   float* fSg = nullptr;
-  double* dRoot = nullptr;          // FP64 root block of the mixed factorization
-  hss::NodeDesc* dRootNode = nullptr;
+  double* dRoot = nullptr;          // FP64 root blocks of the mixed factorization (F offsets)
   bool factor32_ready = false;
   std::vector<std::vector<hss::GemmBatch>> gemm_plan32;
 
@@ -175,6 +223,20 @@ struct hss_matrix_s {
 
   double factor_ms = 0.0, solve_ms = 0.0;
   int32_t max_rank = 0;
+
+  // HIP graphs of the factorization (per precision) and of the last solve
+  bool use_graph = false;
+  hipGraphExec_t gexec_factor[2] = {nullptr, nullptr};
+  hipGraphExec_t gexec_solve = nullptr;
+  struct SolveKey {
+    int prec = -1;
+    const double* b = nullptr;
+    double* x = nullptr;
+    int64_t nrhs = 0, ld = 0;
+    bool operator==(const SolveKey& o) const {
+      return prec == o.prec && b == o.b && x == o.x && nrhs == o.nrhs && ld == o.ld;
+    }
+  } solve_key;
 };
 
 namespace hss {
@@ -192,8 +254,10 @@ struct Prof {
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
 
-// representation setup (capi.cpp)
+// representation setup (capi.hip)
 void layout_representation(hss_matrix_t m);
+void assign_offsets(hss_matrix_t m);
+void finish_stages(hss_matrix_t m);
 
 // gemm.hip
 void gemm_upload(GemmBatch& b, hipStream_t s);
@@ -206,6 +270,13 @@ void factor_fp64(hss_matrix_t m);
 void factor_fp32(hss_matrix_t m);
 double read_logdet(hss_matrix_t m);
 void free_factor(hss_matrix_t m);
+
+void prepare_factor(hss_matrix_t m, int precision);
+
+// batch.hip: forest layout, graph replay, autotuning
+void factor_run(hss_matrix_t m, int precision);
+void solve_run(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld);
+void drop_graphs(hss_matrix_t m);
 
 // solve.hip
 void ensure_vec_ws(hss_matrix_t m, int64_t nrhs);

@@ -31,23 +31,32 @@ template <typename T>
 __device__ void col_dots(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* x, int ldx, T* out,
                          int ldo, int nc) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int j = wid; j < cols; j += SW / 64) {
-    T acc[RC];
+  constexpr int CW = 4;  // columns per wave per pass
+  for (int j0 = wid * CW; j0 < cols; j0 += (SW / 64) * CW) {
+    T acc[CW][RC];
 #pragma unroll
-    for (int c = 0; c < RC; ++c) acc[c] = 0;
-    const T* col = A + (int64_t)j * lda;
-#pragma unroll 4
+    for (int q = 0; q < CW; ++q)
+#pragma unroll
+      for (int c = 0; c < RC; ++c) acc[q][c] = 0;
     for (int i = lane; i < rows; i += 64) {
-      const T a = col[i];
+      T a[CW];
 #pragma unroll
-      for (int c = 0; c < RC; ++c)
-        if (c < nc) acc[c] += a * x[i + c * ldx];
+      for (int q = 0; q < CW; ++q) a[q] = (j0 + q < cols) ? A[i + (int64_t)(j0 + q) * lda] : (T)0;
+#pragma unroll
+      for (int q = 0; q < CW; ++q)
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+          if (c < nc) acc[q][c] += a[q] * x[i + c * ldx];
     }
 #pragma unroll
-    for (int c = 0; c < RC; ++c) {
-      const T v = wave_sum(acc[c]);
-      if (lane == 0 && c < nc) out[j + c * ldo] = v;
-    }
+    for (int q = 0; q < CW; ++q)
+#pragma unroll
+      for (int c = 0; c < RC; ++c) {
+        if (c < nc) {
+          const T v = wave_sum(acc[q][c]);
+          if (lane == 0 && j0 + q < cols) out[j0 + q + c * ldo] = v;
+        }
+      }
   }
 }
 
@@ -60,12 +69,12 @@ __device__ void row_gemv(const T* __restrict__ A, int64_t lda, int rows, int col
 #pragma unroll
     for (int c = 0; c < RC; ++c) acc[c] = 0;
     int j = 0;
-    for (; j + 8 <= cols; j += 8) {
-      T a[8];
+    for (; j + 16 <= cols; j += 16) {
+      T a[16];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) a[q] = A[i + (int64_t)(j + q) * lda];
+      for (int q = 0; q < 16; ++q) a[q] = A[i + (int64_t)(j + q) * lda];
 #pragma unroll
-      for (int q = 0; q < 8; ++q)
+      for (int q = 0; q < 16; ++q)
 #pragma unroll
         for (int c = 0; c < RC; ++c)
           if (c < nc) acc[c] += a[q] * u[j + q + c * ldu];
@@ -191,78 +200,67 @@ __device__ void lower_t_solve(const T* __restrict__ F, int ldf, int m, T* x, int
 template <typename T>
 __global__ __launch_bounds__(SW) void k_solve_fwd(const NodeDesc* __restrict__ nodes, int first,
                                                   const T* __restrict__ Fb, const T* __restrict__ Vb,
-                                                  const T* __restrict__ Tb, const T* __restrict__ Sgb,
+                                                  const T* __restrict__ Yb, const T* __restrict__ Sgb,
                                                   T* __restrict__ vec, int64_t nrhs, int c0, int nc,
                                                   const double* __restrict__ b, int64_t ld,
-                                                  const int64_t* __restrict__ perm, int leaf) {
+                                                  const int64_t* __restrict__ perm, int leaf,
+                                                  const T* __restrict__ Lib, const int64_t* __restrict__ offLi,
+                                                  int use_inv) {
   const int p = first + blockIdx.x;
   const NodeDesc nd = nodes[p];
   const int n = nd.n, r = nd.r, m = nd.m;
   __shared__ T sb[512 * RC];
   __shared__ T st[128 * RC];
   __shared__ T su[128 * RC];
+  __shared__ T tm[128 * RC];
   T* vp = vec + nd.offVec * nrhs;
   const T* F = Fb + nd.offF;
   const T* V = Vb + nd.offV;
-  const T* Tm = Tb + nd.offT;
+  const T* Y = Yb + nd.offW;
   const T* Sg = Sgb + nd.offSg;
   for (int i = threadIdx.x; i < n; i += SW)
     for (int c = 0; c < nc; ++c)
       sb[i + c * n] = leaf ? (T)b[perm[nd.lo + i] + (int64_t)(c0 + c) * ld] : vp[i + (int64_t)(c0 + c) * n];
   __syncthreads();
-  // b^ = b - V T^T V^T b
-  col_dots(V, n, n, r, sb, n, st, r, nc);
+  // b^ = H^T b = b - V (Y^T b) with Y = V T kept by the factorization
+  col_dots(Y, n, n, r, sb, n, st, r, nc);
   __syncthreads();
-  tri_mult(Tm, r, st, su, nc, true);
-  __syncthreads();
-  row_gemv(V, n, n, r, su, r, sb, n, nc, (T)-1);
+  row_gemv(V, n, n, r, st, r, sb, n, nc, (T)-1);
   __syncthreads();
   // y_R = L_RR^{-1} b^_R  (b^_R = sb[r:n])
-  lower_solve(F, n, m, sb + r, n, nc);
+  if (use_inv) {
+    const T* Li = Lib + offLi[p];
+    for (int i = threadIdx.x; i < m * RC; i += SW) tm[i] = 0;
+    __syncthreads();
+    row_gemv(Li, m, m, m, sb + r, n, tm, m, nc, (T)1);
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += SW)
+      for (int c = 0; c < nc; ++c) sb[r + i + c * n] = tm[i + c * m];
+    __syncthreads();
+  } else {
+    lower_solve(F, n, m, sb + r, n, nc);
+  }
   // z_S = b^_S - L_SR y_R   (L_SR = F[m:n, 0:m])
   row_gemv(F + m, n, r, m, sb + r, n, sb, n, nc, (T)-1);
   __syncthreads();
   for (int i = threadIdx.x; i < m; i += SW)
     for (int c = 0; c < nc; ++c) vp[i + (int64_t)(c0 + c) * n] = sb[r + i + c * n];
-  const NodeDesc par = nodes[(p - 1) / 2];
+  if (nd.parent < 0) return;  // a root: y = L^{-1} b is all that is left
+  const NodeDesc par = nodes[nd.parent];
   T* pp = vec + par.offVec * nrhs;
   for (int j = threadIdx.x; j < r; j += SW)
     for (int c = 0; c < nc; ++c) pp[nd.child_row + j + (int64_t)(c0 + c) * par.n] = Sg[j] * sb[j + c * n];
 }
 
 template <typename T>
-__global__ __launch_bounds__(SW) void k_solve_root(const NodeDesc* __restrict__ nodes, const T* __restrict__ Fb,
-                                                   T* __restrict__ vec, int64_t nrhs, int c0, int nc,
-                                                   const double* __restrict__ b, double* __restrict__ x,
-                                                   int64_t ld, const int64_t* __restrict__ perm, int single) {
-  const NodeDesc nd = nodes[0];
-  const int n = nd.n;
-  __shared__ T sb[512 * RC];
-  __shared__ T scr[SNB * RC];
-  T* vp = vec + nd.offVec * nrhs;
-  const T* F = Fb + nd.offF;
-  for (int i = threadIdx.x; i < n; i += SW)
-    for (int c = 0; c < nc; ++c)
-      sb[i + c * n] = single ? (T)b[perm[i] + (int64_t)(c0 + c) * ld] : vp[i + (int64_t)(c0 + c) * n];
-  __syncthreads();
-  lower_solve(F, n, n, sb, n, nc);
-  lower_t_solve(F, n, n, sb, n, nc, scr);
-  for (int i = threadIdx.x; i < n; i += SW)
-    for (int c = 0; c < nc; ++c) {
-      if (single)
-        x[perm[i] + (int64_t)(c0 + c) * ld] = (double)sb[i + c * n];
-      else
-        vp[i + (int64_t)(c0 + c) * n] = sb[i + c * n];
-    }
-}
-
-template <typename T>
 __global__ __launch_bounds__(SW) void k_solve_bwd(const NodeDesc* __restrict__ nodes, int first,
                                                   const T* __restrict__ Fb, const T* __restrict__ Vb,
-                                                  const T* __restrict__ Tb, const T* __restrict__ Sgb,
+                                                  const T* __restrict__ Yb, const T* __restrict__ Sgb,
                                                   T* __restrict__ vec, int64_t nrhs, int c0, int nc,
                                                   double* __restrict__ x, int64_t ld,
-                                                  const int64_t* __restrict__ perm, int leaf) {
+                                                  const int64_t* __restrict__ perm, int leaf,
+                                                  const T* __restrict__ Lib, const int64_t* __restrict__ offLi,
+                                                  int use_inv) {
   const int p = first + blockIdx.x;
   const NodeDesc nd = nodes[p];
   const int n = nd.n, r = nd.r, m = nd.m;
@@ -274,13 +272,15 @@ __global__ __launch_bounds__(SW) void k_solve_bwd(const NodeDesc* __restrict__ n
   T* vp = vec + nd.offVec * nrhs;
   const T* F = Fb + nd.offF;
   const T* V = Vb + nd.offV;
-  const T* Tm = Tb + nd.offT;
+  const T* Y = Yb + nd.offW;
   const T* Sg = Sgb + nd.offSg;
-  const NodeDesc par = nodes[(p - 1) / 2];
-  const T* pp = vec + par.offVec * nrhs;
-  // x_S (H coordinates) into sx[0:r], y_R into sx[r:n]
-  for (int j = threadIdx.x; j < r; j += SW)
-    for (int c = 0; c < nc; ++c) sx[j + c * n] = Sg[j] * pp[nd.child_row + j + (int64_t)(c0 + c) * par.n];
+  // x_S (H coordinates) into sx[0:r], y_R into sx[r:n]; a root has r = 0
+  if (nd.parent >= 0) {
+    const NodeDesc par = nodes[nd.parent];
+    const T* pp = vec + par.offVec * nrhs;
+    for (int j = threadIdx.x; j < r; j += SW)
+      for (int c = 0; c < nc; ++c) sx[j + c * n] = Sg[j] * pp[nd.child_row + j + (int64_t)(c0 + c) * par.n];
+  }
   for (int i = threadIdx.x; i < m; i += SW)
     for (int c = 0; c < nc; ++c) sx[r + i + c * n] = vp[i + (int64_t)(c0 + c) * n];
   __syncthreads();
@@ -290,13 +290,21 @@ __global__ __launch_bounds__(SW) void k_solve_bwd(const NodeDesc* __restrict__ n
   for (int k = threadIdx.x; k < m; k += SW)
     for (int c = 0; c < nc; ++c) sx[r + k + c * n] -= tm[k + c * n];
   __syncthreads();
-  lower_t_solve(F, n, m, sx + r, n, nc, scr);
-  // x = H x^ = x^ - V T V^T x^
+  if (use_inv) {
+    // x_R = L_RR^{-T} t: x_R[j] = sum_i Li[i, j] t_i  (columns of Li are contiguous)
+    const T* Li = Lib + offLi[p];
+    col_dots(Li, m, m, m, sx + r, n, tm, n, nc);
+    __syncthreads();
+    for (int i = threadIdx.x; i < m; i += SW)
+      for (int c = 0; c < nc; ++c) sx[r + i + c * n] = tm[i + c * n];
+    __syncthreads();
+  } else {
+    lower_t_solve(F, n, m, sx + r, n, nc, scr);
+  }
+  // x = H x^ = x^ - Y (V^T x^)
   col_dots(V, n, n, r, sx, n, st, r, nc);
   __syncthreads();
-  tri_mult(Tm, r, st, su, nc, false);
-  __syncthreads();
-  row_gemv(V, n, n, r, su, r, sx, n, nc, (T)-1);
+  row_gemv(Y, n, n, r, st, r, sx, n, nc, (T)-1);
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += SW)
     for (int c = 0; c < nc; ++c) {
@@ -340,7 +348,7 @@ __global__ __launch_bounds__(256) void k_mv_up(const NodeDesc* __restrict__ node
                                                double* __restrict__ xt) {
   const int p = first + blockIdx.x;
   const NodeDesc nd = nodes[p];
-  const NodeDesc c1 = nodes[2 * p + 1], c2 = nodes[2 * p + 2];
+  const NodeDesc c1 = nodes[nd.c1], c2 = nodes[nd.c2];
   const int n = nd.n, r = nd.r;
   const double* E = Bb + nd.offB;
   const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -363,7 +371,7 @@ __global__ __launch_bounds__(256) void k_mv_coupling(const NodeDesc* __restrict_
                                                      const double* __restrict__ xt, double* __restrict__ yt) {
   const int p = first + blockIdx.x;
   const NodeDesc nd = nodes[p];
-  const NodeDesc c1 = nodes[2 * p + 1], c2 = nodes[2 * p + 2];
+  const NodeDesc c1 = nodes[nd.c1], c2 = nodes[nd.c2];
   const int r1 = c1.r, r2 = c2.r;
   const double* S = Sb + nd.offS;
   for (int64_t c = 0; c < nrhs; ++c) {
@@ -386,7 +394,7 @@ __global__ __launch_bounds__(256) void k_mv_down(const NodeDesc* __restrict__ no
                                                  double* __restrict__ yt) {
   const int p = first + blockIdx.x;
   const NodeDesc nd = nodes[p];
-  const NodeDesc c1 = nodes[2 * p + 1], c2 = nodes[2 * p + 2];
+  const NodeDesc c1 = nodes[nd.c1], c2 = nodes[nd.c2];
   const int n = nd.n, r = nd.r;
   const double* E = Bb + nd.offB;
   for (int64_t c = 0; c < nrhs; ++c) {
@@ -446,33 +454,29 @@ void ensure_vec_ws(hss_matrix_t m, int64_t nrhs) {
   m->ws_nrhs = nrhs;
 }
 
+// Forward sweep over the stages leaves-first (roots finish with y = L^{-1} b),
+// then the backward sweep in the reverse order, RC right-hand sides at a time.
 template <typename T>
-static void solve_impl(hss_matrix_t m, const T* F, const T* V, const T* Tm, const T* Sg, T* vec,
-                       const double* b, double* x, int64_t nrhs, int64_t ld) {
+static void solve_impl(hss_matrix_t m, const T* F, const T* V, const T* Yw, const T* Sg, T* vec, const T* Li,
+                       const std::vector<char>& inv_used, const double* b, double* x, int64_t nrhs, int64_t ld) {
   hipStream_t s = m->ctx->stream;
+  const int ns = (int)m->stages.size();
   for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
     const int nc = (int)std::min<int64_t>(RC, nrhs - c0);
-    if (m->L == 0) {
-      hipLaunchKernelGGL((k_solve_root<T>), dim3(1), dim3(SW), 0, s, m->dnodes, F, vec, nrhs, (int)c0, nc, b, x,
-                         ld, (const int64_t*)m->dperm, 1);
-      HSS_HIP(hipGetLastError());
-      continue;
-    }
-    for (int l = m->L; l >= 1; --l) {
-      const LevelPlan& lp = m->levels[l];
-      Prof pf(m->ctx, "solve_forward", l);
-      hipLaunchKernelGGL((k_solve_fwd<T>), dim3(lp.count), dim3(SW), 0, s, m->dnodes, lp.first, F, V, Tm, Sg, vec,
-                         nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, l == m->L ? 1 : 0);
+    for (int si = 0; si < ns; ++si) {
+      const LevelPlan& lp = m->stages[si];
+      Prof pf(m->ctx, "solve_forward", lp.level);
+      hipLaunchKernelGGL((k_solve_fwd<T>), dim3(lp.count), dim3(SW), 0, s, m->dnodes, lp.first, F, V, Yw, Sg, vec,
+                         nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, lp.leaf, Li,
+                         (const int64_t*)m->dOffLi, (int)inv_used[si]);
       HSS_HIP(hipGetLastError());
     }
-    hipLaunchKernelGGL((k_solve_root<T>), dim3(1), dim3(SW), 0, s, m->dnodes, F, vec, nrhs, (int)c0, nc, b, x, ld,
-                       (const int64_t*)m->dperm, 0);
-    HSS_HIP(hipGetLastError());
-    for (int l = 1; l <= m->L; ++l) {
-      const LevelPlan& lp = m->levels[l];
-      Prof pf(m->ctx, "solve_backward", l);
-      hipLaunchKernelGGL((k_solve_bwd<T>), dim3(lp.count), dim3(SW), 0, s, m->dnodes, lp.first, F, V, Tm, Sg, vec,
-                         nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, l == m->L ? 1 : 0);
+    for (int si = ns - 1; si >= 0; --si) {
+      const LevelPlan& lp = m->stages[si];
+      Prof pf(m->ctx, "solve_backward", lp.level);
+      hipLaunchKernelGGL((k_solve_bwd<T>), dim3(lp.count), dim3(SW), 0, s, m->dnodes, lp.first, F, V, Yw, Sg, vec,
+                         nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, lp.leaf, Li,
+                         (const int64_t*)m->dOffLi, (int)inv_used[si]);
       HSS_HIP(hipGetLastError());
     }
   }
@@ -480,45 +484,40 @@ static void solve_impl(hss_matrix_t m, const T* F, const T* V, const T* Tm, cons
 
 void solve_fp64(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld) {
   ensure_vec_ws(m, nrhs);
-  HSS_CHECK(b != x || true, HSS_ERR_INVALID_ARGUMENT, "");
-  solve_impl<double>(m, m->dF, m->dV, m->dT, m->dSg, m->dvec, b, x, nrhs, ld);
+  solve_impl<double>(m, m->dF, m->dV, m->dW, m->dSg, m->dvec, m->dLi, m->inv_used64, b, x, nrhs, ld);
 }
 
 void solve_fp32(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld) {
   ensure_vec_ws(m, nrhs);
   if (!m->fvec) m->fvec = (float*)dev_alloc(sizeof(float) * std::max<int64_t>(m->sum_n * m->ws_nrhs, 1));
-  solve_impl<float>(m, m->fF, m->fV, m->fT, m->fSg, m->fvec, b, x, nrhs, ld);
+  solve_impl<float>(m, m->fF, m->fV, m->fW, m->fSg, m->fvec, m->fLi, m->inv_used32, b, x, nrhs, ld);
 }
 
+// y = A x over the stages: up-sweep (leaves, then upward), couplings of every
+// internal node, down-sweep (downward), leaves. Roots have rank 0.
 void matvec_fp64(hss_matrix_t m, const double* x, double* y, int64_t nrhs, int64_t ld) {
   hipStream_t s = m->ctx->stream;
   ensure_vec_ws(m, nrhs);
-  const int L = m->L;
   const int64_t* perm = m->dperm;
-  if (L == 0) {
-    hipLaunchKernelGGL(k_mv_leaf, dim3(1), dim3(256), 0, s, m->dnodes, 0, (const double*)m->dD,
-                       (const double*)m->dB, x, y, ld, nrhs, perm, (const double*)m->dyt, 0);
-    HSS_HIP(hipGetLastError());
-    return;
-  }
-  const LevelPlan& leaves = m->levels[L];
+  const int ns = (int)m->stages.size();
+  const LevelPlan& leaves = m->stages[0];
   hipLaunchKernelGGL(k_mv_up_leaf, dim3(leaves.count), dim3(256), 0, s, m->dnodes, leaves.first,
                      (const double*)m->dB, x, ld, nrhs, perm, m->dxt);
   HSS_HIP(hipGetLastError());
-  for (int l = L - 1; l >= 1; --l) {
-    const LevelPlan& lp = m->levels[l];
+  for (int si = 1; si < ns; ++si) {
+    const LevelPlan& lp = m->stages[si];
     hipLaunchKernelGGL(k_mv_up, dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const double*)m->dB, nrhs,
                        m->dxt);
     HSS_HIP(hipGetLastError());
   }
-  for (int l = 0; l < L; ++l) {
-    const LevelPlan& lp = m->levels[l];
+  for (int si = 1; si < ns; ++si) {
+    const LevelPlan& lp = m->stages[si];
     hipLaunchKernelGGL(k_mv_coupling, dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const double*)m->dS,
                        nrhs, (const double*)m->dxt, m->dyt);
     HSS_HIP(hipGetLastError());
   }
-  for (int l = 1; l < L; ++l) {
-    const LevelPlan& lp = m->levels[l];
+  for (int si = ns - 1; si >= 1; --si) {
+    const LevelPlan& lp = m->stages[si];
     hipLaunchKernelGGL(k_mv_down, dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const double*)m->dB, nrhs,
                        m->dyt);
     HSS_HIP(hipGetLastError());
