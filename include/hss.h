@@ -135,12 +135,14 @@ typedef struct {
   int32_t precision;         /* precision of the last factorization */
   int32_t max_rank;          /* largest basis rank */
   int32_t failed_level;      /* on HSS_ERR_NOT_SPD: level of the failing node, else -1 */
-  int32_t failed_node;       /* heap index of the failing node, else -1 */
+  int32_t failed_node;       /* index of the failing node (heap index for a single tree), else -1 */
   int32_t failed_pivot;      /* local pivot index that failed, else -1 */
   int64_t bytes_representation;
   int64_t bytes_factor;
   double factor_ms;          /* device time of the last factorization (HIP events) */
   double solve_ms;           /* device time of the last solve */
+  int32_t systems;           /* 1, or the number of systems of a batch */
+  int32_t failed_system;     /* on HSS_ERR_NOT_SPD: system of the failing node, else -1 */
 } hss_info;
 
 /* ---- context ------------------------------------------------------------ */
@@ -237,6 +239,60 @@ hss_status hss_profile_enable(hss_ctx_t ctx, int32_t on);
  * into buf (NUL-terminated, truncated to capacity); *needed receives the full
  * size. Synchronizes. */
 hss_status hss_profile_read(hss_ctx_t ctx, char* buf, int64_t capacity, int64_t* needed);
+
+/* ---- batches of independent systems ------------------------------------ */
+/* A batch holds several HSS systems of any sizes and depths in one matrix
+ * object. Their tree nodes are regrouped by height above the leaves, so every
+ * step of the level-by-level factorization (Alg. 2) and of the solve sweeps
+ * (Eq. 17) is one launch for all systems; a system whose tree is shallower
+ * finishes at a lower height. Vectors of a batch are the systems' vectors
+ * stacked in batch order: system k owns rows [offset_k, offset_k + N_k) of b
+ * and x, in its own point order (offsets from hss_batch_query). The batch's
+ * hss_logdet is the sum over systems; hss_batch_query gives each one.
+ * hss_ulv_factor fails with NOT_SPD if any system fails (hss_info names the
+ * first failing system; hss_batch_query flags all of them). A batch cannot be
+ * exported (UNSUPPORTED). */
+
+/* Copies `count` single matrices (constructed or imported; not batches) into a
+ * new batch. The inputs stay valid and independent. */
+hss_status hss_batch_create(hss_ctx_t ctx, int32_t count, const hss_matrix_t* mats, hss_matrix_t* out);
+
+/* hss_construct of each system (arrays of `count` entries; kernels, opts and
+ * omega per system), then hss_batch_create of the results. */
+hss_status hss_construct_batched(hss_ctx_t ctx, int32_t count, const double* const* d_points, const int64_t* n,
+                                 int32_t dim, const hss_kernel* kernels, const hss_construct_opts* opts,
+                                 const double* const* d_omega, const int32_t* s, hss_matrix_t* out);
+
+/* Host outputs, each nullable: h_offsets (count + 1 entries: first row of each
+ * system, then the total N), h_failed (count: 1 where the last factorization
+ * met a non-positive pivot), h_logdet (count: per-system log-determinant of
+ * the last factorization). Synchronizes when h_failed or h_logdet is given;
+ * those require a factorization to have run (BAD_STATE otherwise). */
+hss_status hss_batch_query(hss_ctx_t ctx, hss_matrix_t m, int32_t count, int64_t* h_offsets, int32_t* h_failed,
+                           double* h_logdet);
+
+/* ---- launch recording and tuning ---------------------------------------- */
+/* When on, hss_ulv_factor records its whole launch sequence (every stage,
+ * every step) into a HIP graph on first use per precision and afterwards
+ * replays it with a single graph launch; hss_ulv_solve (and the solves inside
+ * hss_ulv_solve_refined) does the same per (precision, b, x, nrhs, ld). The
+ * recording uses a private non-blocking stream; replays go to the context
+ * stream. Ignored while profiling is enabled. Switching drops all graphs.
+ * Synchronizes. */
+hss_status hss_use_graphs(hss_ctx_t ctx, hss_matrix_t m, int32_t on);
+
+/* Autotuner of the batched GEMM tile shapes (0: 64x64, 1: 32x32, 2: 128x64,
+ * 3: 64x128): runs the factorization in `precision` once untimed, then `reps`
+ * times per tile shape, timing every batched GEMM launch with HIP events, and
+ * keeps the fastest shape for each (stage, step). h_report (nullable, 5
+ * floats) receives the GEMM milliseconds per factorization for each uniform
+ * shape and for the tuned choice. Leaves the matrix CONSTRUCTED: factor
+ * afterwards. Drops recorded graphs. Synchronizes. */
+hss_status hss_autotune(hss_ctx_t ctx, hss_matrix_t m, int32_t precision, int32_t reps, float* h_report);
+
+/* The chosen tile shape of every (stage, step) GEMM batch, in order, into
+ * h_out (nullable, up to capacity entries); *needed receives the count. */
+hss_status hss_gemm_variants(hss_matrix_t m, int32_t precision, int32_t* h_out, int64_t capacity, int64_t* needed);
 
 hss_status hss_matrix_destroy(hss_matrix_t m);
 

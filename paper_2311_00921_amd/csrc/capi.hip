@@ -217,6 +217,8 @@ void layout_representation(hss_matrix_t m) {
 
 static void destroy_matrix(hss_matrix_t m) {
   if (!m) return;
+  if (m->ctx) (void)hipStreamSynchronize(m->ctx->stream);
+  drop_graphs(m);
   free_factor(m);
   void* ptrs[] = {m->dnodes, m->dD, m->dB, m->dS, m->dperm, m->dvec, m->dxt, m->dyt, m->fvec, m->dtmp,
                   m->dOffLi, m->dOffS2};
@@ -286,6 +288,7 @@ hss_status hss_ctx_destroy(hss_ctx_t ctx) {
   for (hipEvent_t e : ctx->ev_pool) (void)hipEventDestroy(e);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
   delete ctx;
   HSS_API_END
 }
@@ -459,6 +462,7 @@ hss_status hss_construct(hss_ctx_t ctx, const double* d_points, int64_t n, int32
 hss_status hss_export_sizes(hss_matrix_t m, int64_t sizes[7]) {
   HSS_API_BEGIN
   HSS_CHECK(m && sizes, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  HSS_CHECK(m->nsys == 1, HSS_ERR_UNSUPPORTED, "a batch cannot be exported; export its systems");
   sizes[0] = (1 << m->L) + 1;
   sizes[1] = m->nnodes;
   sizes[2] = m->lenD;
@@ -474,6 +478,7 @@ hss_status hss_export_sizes(hss_matrix_t m, int64_t sizes[7]) {
 hss_status hss_export(hss_ctx_t ctx, hss_matrix_t m, hss_desc_out* o) {
   HSS_API_BEGIN
   HSS_CHECK(ctx && m && o, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  HSS_CHECK(m->nsys == 1, HSS_ERR_UNSUPPORTED, "a batch cannot be exported; export its systems");
   hipStream_t s = ctx->stream;
   const int nleaves = 1 << m->L;
   if (o->leaf_lo) {
@@ -503,12 +508,9 @@ hss_status hss_ulv_factor(hss_ctx_t ctx, hss_matrix_t m, const hss_factor_opts* 
   HSS_CHECK(prec == HSS_P_FP64 || prec == HSS_P_FP32, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
   hipStream_t s = ctx->stream;
   m->state = 0;
-  m->failed_level = m->failed_node = m->failed_pivot = -1;
+  m->failed_level = m->failed_node = m->failed_pivot = m->failed_system = -1;
   HSS_HIP(hipEventRecord(ctx->ev0, s));
-  if (prec == HSS_P_FP64)
-    factor_fp64(m);
-  else
-    factor_fp32(m);
+  factor_run(m, prec);
   HSS_HIP(hipEventRecord(ctx->ev1, s));
   int32_t info[4] = {0, 0, 0, 0};
   HSS_HIP(hipMemcpyAsync(info, m->dinfo, sizeof(info), hipMemcpyDeviceToHost, s));
@@ -520,10 +522,12 @@ hss_status hss_ulv_factor(hss_ctx_t ctx, hss_matrix_t m, const hss_factor_opts* 
   if (info[0] != 0) {
     m->state = 2;
     m->failed_node = info[1];
-    m->failed_level = level_of(info[1]);
+    m->failed_level = m->nodes[info[1]].level;
+    m->failed_system = m->nodes[info[1]].sys;
     m->failed_pivot = info[2];
     throw Error{HSS_ERR_NOT_SPD, "non-positive pivot at level " + std::to_string(m->failed_level) + ", node " +
-                                     std::to_string(info[1]) + ", pivot " + std::to_string(info[2])};
+                                     std::to_string(info[1]) + ", pivot " + std::to_string(info[2]) +
+                                     (m->nsys > 1 ? ", system " + std::to_string(m->failed_system) : "")};
   }
   m->state = 1;
   HSS_API_END
@@ -536,10 +540,7 @@ hss_status hss_ulv_solve(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, doubl
   HSS_CHECK(m->state == 1, HSS_ERR_BAD_STATE, "matrix is not factored");
   hipStream_t s = ctx->stream;
   HSS_HIP(hipEventRecord(ctx->ev0, s));
-  if (m->precision == HSS_P_FP64)
-    solve_fp64(m, d_b, d_x, nrhs, ld);
-  else
-    solve_fp32(m, d_b, d_x, nrhs, ld);
+  solve_run(m, d_b, d_x, nrhs, ld);
   HSS_HIP(hipEventRecord(ctx->ev1, s));
   HSS_API_END
 }
@@ -577,6 +578,8 @@ hss_status hss_get_info(hss_matrix_t m, hss_info* o) {
   o->bytes_factor = 8 * (m->lenF + m->lenV + m->lenT + m->lenSg);
   o->factor_ms = m->factor_ms;
   o->solve_ms = m->solve_ms;
+  o->systems = m->nsys;
+  o->failed_system = m->failed_system;
   HSS_API_END
 }
 
@@ -608,7 +611,7 @@ hss_status hss_debug_node_block(hss_ctx_t ctx, hss_matrix_t m, int32_t node, int
         h_out[i + (int64_t)j * nd.r] = sg[i] * sg[j] * F[(nd.m + a) + (int64_t)(nd.m + b) * nd.n];
       }
   } else if (what == 1) {
-    HSS_CHECK(nd.level < m->L, HSS_ERR_INVALID_ARGUMENT, "leaves have no merged block");
+    HSS_CHECK(nd.c1 >= 0, HSS_ERR_INVALID_ARGUMENT, "leaves have no merged block");
     HSS_CHECK(capacity >= (int64_t)nd.n * nd.n, HSS_ERR_INVALID_ARGUMENT, "capacity too small");
     HSS_HIP(hipMemcpyAsync(h_out, m->dM + nd.offM, sizeof(double) * nd.n * nd.n, hipMemcpyDeviceToHost, s));
     HSS_HIP(hipStreamSynchronize(s));

@@ -155,7 +155,7 @@ struct hss_matrix_s {
   int32_t nnodes = 0;
   int32_t state = 0;  // 0 constructed, 1 factored, 2 failed
   int32_t precision = 0;
-  int32_t failed_level = -1, failed_node = -1, failed_pivot = -1;
+  int32_t failed_level = -1, failed_node = -1, failed_pivot = -1, failed_system = -1;
 
   std::vector<hss::NodeDesc> nodes;  // host copy
   hss::NodeDesc* dnodes = nullptr;   // device copy

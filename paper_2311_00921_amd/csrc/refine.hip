@@ -85,10 +85,7 @@ static std::vector<double> read_dev(const double* d, int64_t k, hipStream_t s) {
 }
 
 static void lp_solve(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld) {
-  if (m->precision == HSS_P_FP64)
-    solve_fp64(m, b, x, nrhs, ld);
-  else
-    solve_fp32(m, b, x, nrhs, ld);
+  solve_run(m, b, x, nrhs, ld);
 }
 
 // returns (iterations, worst relative residual, converged)

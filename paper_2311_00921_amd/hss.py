@@ -70,7 +70,8 @@ class hss_info(C.Structure):
                 ("precision", C.c_int32), ("max_rank", C.c_int32), ("failed_level", C.c_int32),
                 ("failed_node", C.c_int32), ("failed_pivot", C.c_int32),
                 ("bytes_representation", C.c_int64), ("bytes_factor", C.c_int64),
-                ("factor_ms", C.c_double), ("solve_ms", C.c_double)]
+                ("factor_ms", C.c_double), ("solve_ms", C.c_double),
+                ("systems", C.c_int32), ("failed_system", C.c_int32)]
 
 
 # Every symbol include/hss.h declares, with its ctypes signature.
@@ -95,6 +96,15 @@ SIGNATURES = {
     "hss_debug_node_block": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
     "hss_profile_enable": (C.c_int, [_P, C.c_int32]),
     "hss_profile_read": (C.c_int, [_P, C.c_char_p, C.c_int64, C.POINTER(C.c_int64)]),
+    "hss_batch_create": (C.c_int, [_P, C.c_int32, C.POINTER(_P), C.POINTER(_P)]),
+    "hss_construct_batched": (C.c_int, [_P, C.c_int32, C.POINTER(_P), C.POINTER(C.c_int64), C.c_int32,
+                                        C.POINTER(hss_kernel), C.POINTER(hss_construct_opts), C.POINTER(_P),
+                                        C.POINTER(C.c_int32), C.POINTER(_P)]),
+    "hss_batch_query": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_int64), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_double)]),
+    "hss_use_graphs": (C.c_int, [_P, _P, C.c_int32]),
+    "hss_autotune": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_float)]),
+    "hss_gemm_variants": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_int64)]),
     "hss_matrix_destroy": (C.c_int, [_P]),
     "hss_status_string": (C.c_char_p, [C.c_int]),
     "hss_last_error": (C.c_char_p, []),
@@ -375,6 +385,80 @@ def hss_profile_read(ctx):
         name, level, cnt, ms = line.split()
         out[(name, int(level))] = (int(cnt), float(ms))
     return out
+
+
+def hss_batch_create(ctx, mats):
+    """Batch (forest) of single matrices; the inputs stay valid."""
+    arr = (C.c_void_p * len(mats))(*[C.c_void_p(m.value if isinstance(m, C.c_void_p) else m) for m in mats])
+    out = C.c_void_p()
+    _check(load().hss_batch_create(ctx, len(mats), arr, C.byref(out)), "hss_batch_create")
+    return out
+
+
+def hss_construct_batched(ctx, points_list, kernels, leafs, ranks=None, tols=None, max_ranks=None, omegas=None,
+                          lengths=None, nuggets=None, sigma2: float = 1.0, alpha: float = 1.0, eps: float = 1e-9):
+    """hss_construct of every system (per-system lists), then one batch."""
+    lib = load()
+    cnt = len(points_list)
+    ranks = ranks or [0] * cnt
+    tols = tols or [0.0] * cnt
+    max_ranks = max_ranks or [0] * cnt
+    pts = [p.contiguous() for p in points_list]
+    dim = pts[0].shape[1]
+    keep = []
+    oms, ss = [], []
+    for p, om in zip(pts, omegas):
+        n = p.shape[0]
+        oc, s, ld = _colmajor(om, n)
+        if ld != n:
+            oc = oc.t().contiguous().t()
+        keep.append(oc)
+        oms.append(_ptr(oc))
+        ss.append(s)
+    P = (C.c_void_p * cnt)(*[_ptr(p) for p in pts])
+    N = (C.c_int64 * cnt)(*[p.shape[0] for p in pts])
+    K = (hss_kernel * cnt)(*[hss_kernel(KERNELS[kernels[i]], lengths[i], sigma2, nuggets[i], alpha, eps)
+                             for i in range(cnt)])
+    O = (hss_construct_opts * cnt)(*[hss_construct_opts(leafs[i], 0, ranks[i], max_ranks[i], tols[i],
+                                                         HSS_COMPRESS_SCALED) for i in range(cnt)])
+    OM = (C.c_void_p * cnt)(*oms)
+    S = (C.c_int32 * cnt)(*ss)
+    out = C.c_void_p()
+    _check(lib.hss_construct_batched(ctx, cnt, P, N, dim, K, O, OM, S, C.byref(out)), "hss_construct_batched")
+    return out
+
+
+def hss_batch_query(ctx, m, count: int, factored: bool = True):
+    """Returns (offsets[count + 1], failed[count] or None, logdets[count] or None)."""
+    off = (C.c_int64 * (count + 1))()
+    if not factored:
+        _check(load().hss_batch_query(ctx, m, count, off, None, None), "hss_batch_query")
+        return np.array(off[:], dtype=np.int64), None, None
+    fl = (C.c_int32 * count)()
+    ld = (C.c_double * count)()
+    _check(load().hss_batch_query(ctx, m, count, off, fl, ld), "hss_batch_query")
+    return np.array(off[:], dtype=np.int64), np.array(fl[:], dtype=np.int32), np.array(ld[:])
+
+
+def hss_use_graphs(ctx, m, on: bool):
+    _check(load().hss_use_graphs(ctx, m, 1 if on else 0), "hss_use_graphs")
+
+
+def hss_autotune(ctx, m, precision: int = HSS_P_FP64, reps: int = 2):
+    """Tunes the GEMM tile shapes; returns the GEMM ms per factorization for
+    each uniform shape and for the tuned choice (5 floats)."""
+    rep = (C.c_float * 5)()
+    _check(load().hss_autotune(ctx, m, precision, reps, rep), "hss_autotune")
+    return list(rep)
+
+
+def hss_gemm_variants(m, precision: int = HSS_P_FP64):
+    lib = load()
+    need = C.c_int64(0)
+    _check(lib.hss_gemm_variants(m, precision, None, 0, C.byref(need)), "hss_gemm_variants")
+    buf = (C.c_int32 * max(1, need.value))()
+    _check(lib.hss_gemm_variants(m, precision, buf, need.value, C.byref(need)), "hss_gemm_variants")
+    return list(buf[:need.value])
 
 
 def hss_matrix_destroy(m):
