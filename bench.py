@@ -66,6 +66,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="matern32_n262144")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched leg")
+    ap.add_argument("--no-tune", action="store_true", help="skip autotuning and graph replay")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 + refinement leg")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (for scaling hardware byte counters) and exit")
     ap.add_argument("--cpu-sample-level", type=int, default=3,
                     help="oracle timed on the subtree under one node of this level")
     args = ap.parse_args()
@@ -80,6 +85,15 @@ def main():
     from paper_2311_00921_amd import hss
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        nel = args.calibrate_copy * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": nel * 8, "copy_bytes_written": nel * 8}))
+        return
     w = synth.WORKLOADS[args.workload]
     s = (w.rank if w.rank > 0 else 128) + w.oversample
     X = torch.from_numpy(w.points()).cuda()
@@ -158,9 +172,32 @@ def main():
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
     roof.update({"kernel": f"{dom_step}@level{dom_level}", "avg_launch_ms": round(avg_ms, 4),
                  "algorithmic_per_launch": flops if roof["unit"] == "TFLOP/s" else byts})
+    roof["traffic"] = measured_traffic(f"{dom_step}@level{dom_level}", w.name)
+    # library's tuned mode: autotuned GEMM tiles, factor and solve replayed from HIP graphs
+    tuned = None
+    t_best = t_fp64
+    if not args.no_tune:
+        print("# autotuning GEMM tiles (FP64)", file=sys.stderr, flush=True)
+        rep = hss.hss_autotune(ctx, m, hss.HSS_P_FP64, 2)
+        hss.hss_use_graphs(ctx, m, True)
+        for _ in range(args.warmup):
+            run_fp64(1)
+        print("# timing FP64 factor+solve (tuned, graph replay)", file=sys.stderr, flush=True)
+        t_tuned, xg, _ = run_fp64(args.steps)
+        rg = b - hss.hss_matvec(ctx, m, xg)
+        relres_g = float(torch.linalg.norm(rg) / torch.linalg.norm(b))
+        tuned = {"factor_plus_solve_s": round(t_tuned, 6), "relres": relres_g,
+                 "rel_diff_x_vs_eager": float(torch.linalg.norm(xg - x) / torch.linalg.norm(x)),
+                 "gemm_ms_per_factor_by_tile": {"64x64": rep[0], "32x32": rep[1], "128x64": rep[2],
+                                                "64x128": rep[3], "tuned": rep[4]},
+                 "tile_choice": hss.hss_gemm_variants(m, hss.HSS_P_FP64)}
+        if relres_g <= 1e-8:
+            t_best = min(t_best, t_tuned)
     # mixed form: FP32 factorization + refinement with the FP64 HSS matvec to rel. residual 1e-8
     mixed = None
     try:
+        if args.no_mixed:
+            raise RuntimeError("skipped (--no-mixed)")
         def run_mixed(steps):
             torch.cuda.synchronize()
             t = time.perf_counter()
@@ -188,8 +225,8 @@ def main():
                              for sname in ("gemm_W=MV", "gemm_two_sided_update", "gemm_small_wy",
                                            "partial_cholesky", "basis_qr"))
 
-    use_mixed = bool(mixed and mixed.get("converged"))
-    value = mixed["factor_plus_refined_solve_s"] if use_mixed else t_fp64
+    use_mixed = bool(mixed and mixed.get("converged")) and mixed["factor_plus_refined_solve_s"] < t_best
+    value = mixed["factor_plus_refined_solve_s"] if use_mixed else t_best
     result = {
         "metric": "HSS-ULV factor+solve s at N=262144; mixed+IR vs FP64 at rel. residual 1e-8",
         "value": round(value, 6),
@@ -209,6 +246,7 @@ def main():
                    "precision": "mixed fp32/fp64 + refinement" if use_mixed else "fp64"},
         "roofline": roof,
         "fp64": {"factor_plus_solve_s": round(t_fp64, 6), "relres": relres, "logdet": logdet,
+                 "tuned_graph": tuned,
                  "factor_ms_events": round(info.factor_ms, 3), "algorithmic_factor_gflop": round(total_factor_flops / 1e9, 2),
                  "factor_gflops_per_s": round(total_factor_flops / 1e9 / (info.factor_ms * 1e-3), 1),
                  "profiled_step_s": round(t_prof, 6),
@@ -218,12 +256,137 @@ def main():
         "speedup_mixed_vs_fp64": round(t_fp64 / value, 3) if use_mixed else None,
         "construct_s": round(construct_s, 3),
     }
+    hss.hss_matrix_destroy(m)
+    m = None
+    if not args.no_batched:
+        result["batched"] = batched_leg(hss, torch, np, ctx, args.steps, args.warmup)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(exp, nodes, args.cpu_sample_level, w)
-    hss.hss_matrix_destroy(m)
     hss.hss_ctx_destroy(ctx)
     print(json.dumps(result))
+
+
+def measured_traffic(label, workload):
+    """HBM bytes per launch of the profiled kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counters), or
+    None if there is none or the kernel's source changed since it was taken."""
+    import hashlib
+
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            tab = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = tab.get(f"{label}:{workload}")
+    if not ent:
+        return None
+    src = os.path.join(ROOT, ent["source"])
+    try:
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if sha != ent["source_sha256"]:
+        return None
+    return ent["hbm_bytes_per_launch"]
+
+
+def batched_leg(hss, torch, np, ctx, steps, warmup):
+    """64 independent Gaussian-kernel systems of uneven N factored and solved as
+    one batch (stages by height, autotuned tiles, graph replay), against a loop
+    over the same systems one at a time (eager launches, default tiles)."""
+    import synth
+
+    ws = synth.batch_gaussian()
+    print(f"# batched leg: {len(ws)} systems, N_total={sum(w.n for w in ws)}", file=sys.stderr, flush=True)
+    singles = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for w in ws:
+        s = w.extra["max_rank"] + w.oversample
+        X = torch.from_numpy(w.points()).cuda()
+        Om = torch.from_numpy(np.ascontiguousarray(w.omega(s).T)).cuda().t()
+        singles.append(hss.hss_construct(ctx, X, w.kernel, w.leaf, tol=w.tol, max_rank=w.extra["max_rank"],
+                                         omega=Om, length=w.length, nugget=w.nugget))
+    torch.cuda.synchronize()
+    construct_s = time.perf_counter() - t0
+    batch = hss.hss_batch_create(ctx, singles)
+    cnt = len(ws)
+    off, _, _ = hss.hss_batch_query(ctx, batch, cnt, factored=False)
+    b = torch.from_numpy(np.concatenate([w.rhs()[:, 0] for w in ws])).cuda()
+    x = torch.empty_like(b)
+    parts = [(b[off[k]:off[k + 1]], x[off[k]:off[k + 1]]) for k in range(cnt)]
+    ranks = [hss.hss_get_info(sm).max_rank for sm in singles]
+    out = {"workload": f"gaussian_batch{cnt}", "systems": cnt, "N_total": int(off[-1]),
+           "N_min": int(min(w.n for w in ws)), "N_max": int(max(w.n for w in ws)),
+           "heights": int(hss.hss_get_info(batch).levels) + 1, "max_rank_range": [min(ranks), max(ranks)],
+           "construct_s": round(construct_s, 3)}
+
+    def per_system_relres(xv):
+        r = b - hss.hss_matvec(ctx, batch, xv)
+        return max(float(torch.linalg.norm(r[off[k]:off[k + 1]]) / torch.linalg.norm(b[off[k]:off[k + 1]]))
+                   for k in range(cnt))
+
+    for prec, name in ((hss.HSS_P_FP32, "fp32"), (hss.HSS_P_FP64, "fp64")):
+        leg = {}
+        try:
+            hss.hss_use_graphs(ctx, batch, False)
+            rep = hss.hss_autotune(ctx, batch, prec, 2)
+            hss.hss_use_graphs(ctx, batch, True)
+
+            def run_batch(n):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(n):
+                    hss.hss_ulv_factor(ctx, batch, prec)
+                    hss.hss_ulv_solve(ctx, batch, b, x)
+                torch.cuda.synchronize()
+                return (time.perf_counter() - t) / n
+
+            def run_loop(n):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                for _ in range(n):
+                    for sm, (bk, xk) in zip(singles, parts):
+                        hss.hss_ulv_factor(ctx, sm, prec)
+                        hss.hss_ulv_solve(ctx, sm, bk, xk)
+                torch.cuda.synchronize()
+                return (time.perf_counter() - t) / n
+
+            for _ in range(warmup):
+                run_batch(1)
+            leg["batch_factor_plus_solve_s"] = round(run_batch(steps), 6)
+            leg["relres_max_over_systems"] = per_system_relres(x)
+            leg["gemm_ms_per_factor_uniform_64x64"] = rep[0]
+            leg["gemm_ms_per_factor_tuned"] = rep[4]
+            for _ in range(warmup):
+                run_loop(1)
+            leg["loop_factor_plus_solve_s"] = round(run_loop(steps), 6)
+            leg["speedup_batch_vs_loop"] = round(leg["loop_factor_plus_solve_s"] / leg["batch_factor_plus_solve_s"], 2)
+            if prec == hss.HSS_P_FP32:
+                hss.hss_ulv_factor(ctx, batch, prec)
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                xr, iters, rr, ok = hss.hss_ulv_solve_refined(ctx, batch, b, 1e-8, 50)
+                torch.cuda.synchronize()
+                leg["refined_solve_to_1e-8_s"] = round(time.perf_counter() - t, 6)
+                leg["refined_corrections"] = iters
+                leg["refined_converged"] = bool(ok)
+        except hss.HSSError as e:
+            leg["error"] = str(e)
+            try:
+                _, failed, _ = hss.hss_batch_query(ctx, batch, cnt)
+                leg["failed_systems"] = [int(i) for i in np.nonzero(failed)[0]]
+            except hss.HSSError:
+                pass
+        out[name] = leg
+        print(f"# batched {name}: {leg}", file=sys.stderr, flush=True)
+    hss.hss_matrix_destroy(batch)
+    for sm in singles:
+        hss.hss_matrix_destroy(sm)
+    return out
 
 
 def cpu_baseline(exp, nodes, level, w):

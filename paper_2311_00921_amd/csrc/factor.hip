@@ -502,7 +502,10 @@ __device__ __forceinline__ int pivot_block_chol(double (&a)[16], int jb, double*
 
 constexpr int PNB = 16;
 
-template <typename T, int NMAX>
+// CONSTRUCT only names the instantiation used by the construction (full
+// Cholesky of the diagonal blocks), so that profiles keep it apart from the
+// factorization's partial Cholesky; the code is the same.
+template <typename T, int NMAX, bool CONSTRUCT = false>
 __global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ nodes, int first,
                                                T* __restrict__ Fbase, int32_t* __restrict__ info,
                                                double* __restrict__ logdet) {
@@ -875,9 +878,9 @@ void launch_pchol_external(const NodeDesc* nodes, int first, int count, int nmax
                            double* logdet, hipStream_t s) {
   dim3 grid(count), block(256);
   if (nmax <= 256)
-    hipLaunchKernelGGL((k_pchol<double, 256>), grid, block, 0, s, nodes, first, F, info, logdet);
+    hipLaunchKernelGGL((k_pchol<double, 256, true>), grid, block, 0, s, nodes, first, F, info, logdet);
   else if (nmax <= 512)
-    hipLaunchKernelGGL((k_pchol<double, 512>), grid, block, 0, s, nodes, first, F, info, logdet);
+    hipLaunchKernelGGL((k_pchol<double, 512, true>), grid, block, 0, s, nodes, first, F, info, logdet);
   else
     HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "diagonal block larger than 512");
   HSS_HIP(hipGetLastError());

@@ -23,6 +23,7 @@ __all__ = [
     "test_matrix",
     "Workload",
     "WORKLOADS",
+    "batch_gaussian",
 ]
 
 
@@ -90,8 +91,8 @@ class Workload:
         return test_matrix(self.n, s, 3000 + self.seed_k)
 
 
-# The five workloads of the build's measurement plan. Sizes, kernels and
-# parameters are workload descriptions, not arithmetic.
+# Named workloads. Sizes, kernels and parameters are workload descriptions,
+# not arithmetic.
 WORKLOADS = {
     "exp2d_n2048": Workload("exp2d_n2048", 2048, 2, "exponential", 0.1, 1e-4, 128, 32,
                             mode="plain", seed_k=1),
@@ -144,3 +145,22 @@ def random_hss(n_leaves_log2: int, leaf: int, rank: int, seed: int, coupling: fl
             M *= coupling / np.linalg.norm(M, 2)
             S[l].append(np.asfortranarray(M))
     return {"n": n, "levels": L, "ranges": ranges, "rank": ranks, "D": D, "U": U, "E": E, "S": S}
+
+
+def batch_gaussian(count: int = 64, seed: int = 4) -> list:
+    """The batched workload: `count` independent systems, N ~ U{4096..32768},
+    points uniform in the unit cube, Gaussian kernel exp(-r^2/l^2) with
+    l ~ U[0.05, 0.3] plus 1e-5 on the diagonal, leaf 128 below N = 16384 and
+    256 above, adaptive truncation at 1e-6 with ranks capped at leaf/2.
+    System i draws its points, right-hand side and test matrix from seeds
+    1100+i, 2100+i and 3100+i; the sizes and lengths come from seed `seed`."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(4096, 32768, size=count, endpoint=True)
+    ls = rng.uniform(0.05, 0.3, size=count)
+    out = []
+    for i in range(count):
+        n = int(ns[i])
+        leaf = 128 if n < 16384 else 256
+        out.append(Workload(f"gaussian_batch{count}_sys{i}", n, 3, "gaussian", float(ls[i]), 1e-5, leaf, 0,
+                            tol=1e-6, seed_k=100 + i, extra={"max_rank": leaf // 2}))
+    return out
