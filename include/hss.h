@@ -35,6 +35,7 @@ extern "C" {
 
 typedef struct hss_ctx_s* hss_ctx_t;
 typedef struct hss_matrix_s* hss_matrix_t;
+typedef struct hss_rankmlp_s* hss_rankmlp_t;  /* learned rank model (see below) */
 
 typedef enum {
   HSS_OK = 0,
@@ -80,6 +81,18 @@ typedef struct {
   int32_t max_rank;    /* cap for adaptive ranks (0 = none) */
   double tol;          /* adaptive truncation: keep pivots with |R_jj| > tol*|R_00| */
   int32_t mode;        /* hss_compress_mode */
+  /* Sample sizing (adaptive ranks, tol > 0). With neither of the two below,
+   * all s columns of the test matrix are samples. Otherwise the last `probes`
+   * columns form an independent probe and the first s_b columns the samples:
+   * after the pivoted QR of each node, the judge computes
+   * |(I - Q Q^T) Y_probe|_F / |Y_probe|_F for the node's scaled probe samples
+   * and fails the node when it exceeds judge_factor * tol; any failure restarts
+   * the construction with 2 s_b samples, up to s - probes (the last attempt is
+   * kept whatever the judge says). */
+  hss_rankmlp_t rank_model;  /* trained model: s_b = (largest predicted node rank) + 8 */
+  int32_t sample_start;      /* without a model: s_b starts here (adaptive doubling) */
+  int32_t probes;            /* probe columns (0 = 8) */
+  double judge_factor;       /* 0 = 10 */
 } hss_construct_opts;
 
 typedef enum {
@@ -170,6 +183,18 @@ hss_status hss_ctx_set_stream(hss_ctx_t ctx, void* hip_stream);
 hss_status hss_construct(hss_ctx_t ctx, const double* d_points, int64_t n, int32_t dim,
                          const hss_kernel* kernel, const hss_construct_opts* opts,
                          const double* d_omega, int32_t s, hss_matrix_t* out);
+
+/* What the sample sizing did in the last hss_construct of a matrix. */
+typedef struct {
+  int32_t samples;          /* sample columns of the kept attempt (s_b) */
+  int32_t probes;           /* probe columns (0 when no judge ran) */
+  int32_t attempts;         /* constructions run (1 + restarts) */
+  int32_t judge_failures;   /* nodes failed by the judge over all attempts */
+  int32_t predicted_max;    /* largest rank the model predicted (0 without a model) */
+  int32_t max_rank;         /* largest rank kept */
+  int64_t sample_bytes;     /* device bytes of the N x (s_b + probes) sample buffers of the kept attempt */
+} hss_construct_stats;
+hss_status hss_get_construct_stats(hss_matrix_t m, hss_construct_stats* out);
 
 /* Uploads a host HSS description (see hss_desc). Copies everything. */
 hss_status hss_import(hss_ctx_t ctx, const hss_desc* desc, hss_matrix_t* out);
@@ -293,6 +318,58 @@ hss_status hss_autotune(hss_ctx_t ctx, hss_matrix_t m, int32_t precision, int32_
 /* The chosen tile shape of every (stage, step) GEMM batch, in order, into
  * h_out (nullable, up to capacity entries); *needed receives the count. */
 hss_status hss_gemm_variants(hss_matrix_t m, int32_t precision, int32_t* h_out, int64_t capacity, int64_t* needed);
+
+/* ---- learned rank model -------------------------------------------------- */
+/* A multilayer perceptron 7 -> 128 -> 128 -> 128 -> 1 (ReLU between layers)
+ * mapping the features of a tree node to y = log2(1 + rank) of the basis the
+ * adaptive pivoted QR would keep (Eq. 2 with a tolerance; the paper itself uses
+ * a fixed maximum rank). Features, per node, 7 floats: log2 of the point count
+ * (clipped at 13), the bounding-box extents sorted in decreasing order divided
+ * by the kernel length (3), the gap between the node's box and its sibling's
+ * divided by the kernel length, log10 of the kernel length, -log10 of the
+ * tolerance. Weights are FP32 on the device; training minimises the pinball
+ * loss mean(max(tau (t - y), (tau - 1)(t - y))) with Adam. Feature arrays are
+ * row-major n x 7 device memory; targets, outputs and ranks are device vectors
+ * of n entries. Packed parameters (hss_rankmlp_param_count floats): W1 (128 x
+ * 7), b1, W2 (128 x 128), b2, W3 (128 x 128), b3, W4 (1 x 128), b4, every W
+ * column-major (out x in). */
+typedef struct {
+  int32_t batch;                  /* minibatch size (1..65536) */
+  float lr, beta1, beta2, eps;    /* Adam */
+  float tau;                      /* pinball quantile in (0, 1) */
+} hss_train_opts;
+hss_status hss_rankmlp_param_count(int64_t* out);
+/* The model's features (7 floats per node, heap order: node k >= 1 at row
+ * k - 1) of the cluster tree hss_construct builds on these points with this
+ * leaf size; *needed receives the float count (h_out NULL: size query).
+ * Synchronizes. */
+hss_status hss_rank_features(hss_ctx_t ctx, const double* d_points, int64_t n, int32_t dim, int32_t leaf_size,
+                             double length, double tol, float* h_out, int64_t capacity, int64_t* needed);
+/* Creates a model with all weights zero (load them with hss_rankmlp_set_weights). */
+hss_status hss_rankmlp_create(hss_ctx_t ctx, hss_rankmlp_t* out);
+hss_status hss_rankmlp_destroy(hss_rankmlp_t mlp);
+/* Copies packed host parameters in and resets the Adam state. Synchronizes. */
+hss_status hss_rankmlp_set_weights(hss_ctx_t ctx, hss_rankmlp_t mlp, const float* h_params);
+hss_status hss_rankmlp_get_weights(hss_ctx_t ctx, hss_rankmlp_t mlp, float* h_params);
+/* d_out[j] = network output y for feature row j. */
+hss_status hss_rankmlp_forward(hss_ctx_t ctx, hss_rankmlp_t mlp, const float* d_feats, int64_t n, float* d_out);
+/* d_ranks[j] = ceil(2^y - 1 - 1e-3) clipped to [1, cap] (the slack keeps an
+ * output equal to a target on its rank despite rounding). */
+hss_status hss_rankmlp_predict(hss_ctx_t ctx, hss_rankmlp_t mlp, const float* d_feats, int64_t n, int32_t cap,
+                               int32_t* d_ranks);
+/* Gradient of the mean pinball loss over the n rows (n <= 65536) with respect
+ * to the packed parameters (h_grads, nullable) and the loss (h_loss, nullable).
+ * Synchronizes. */
+hss_status hss_rankmlp_grad(hss_ctx_t ctx, hss_rankmlp_t mlp, const float* d_feats, const float* d_targets, int64_t n,
+                            float tau, float* h_grads, float* h_loss);
+/* Minibatch Adam: the consecutive `batch`-sized chunks of d_order (indices into
+ * the n rows, each checked to lie in [0, n)) are the minibatches, a short tail
+ * being a smaller one; one Adam step per minibatch, with the bias-corrected
+ * moments of the published algorithm. h_losses (nullable) receives each
+ * step's loss before its update (ceil(order_len / batch) floats). Synchronizes. */
+hss_status hss_rankmlp_train(hss_ctx_t ctx, hss_rankmlp_t mlp, const float* d_feats, const float* d_targets,
+                             int64_t n, const int64_t* d_order, int64_t order_len, const hss_train_opts* opts,
+                             float* h_losses);
 
 hss_status hss_matrix_destroy(hss_matrix_t m);
 

@@ -441,11 +441,42 @@ hss_status hss_construct(hss_ctx_t ctx, const double* d_points, int64_t n, int32
     HSS_CHECK(L <= 20, HSS_ERR_UNSUPPORTED, "too many levels");
     HSS_CHECK(L == 0 || (d_omega && s >= 1 && s <= 512), HSS_ERR_INVALID_ARGUMENT, "need a test matrix with 1..512 columns");
     HSS_CHECK(L == 0 || opts->rank == 0 || s >= opts->rank, HSS_ERR_INVALID_ARGUMENT, "need s >= rank");
-    m = new hss_matrix_s();
-    m->ctx = ctx;
-    m->n = n;
-    m->L = L;
-    construct(m, d_points, dim, *kernel, *opts, d_omega, s);
+    const bool sized = opts->rank == 0 && (opts->rank_model != nullptr || opts->sample_start > 0);
+    HSS_CHECK(opts->sample_start >= 0 && opts->probes >= 0 && opts->probes <= 64 && opts->judge_factor >= 0.0,
+              HSS_ERR_INVALID_ARGUMENT, "bad sample sizing options");
+    SamplePlan sp;
+    if (sized && L > 0) {
+      sp.model = opts->rank_model;
+      sp.probes = opts->probes > 0 ? opts->probes : 8;
+      HSS_CHECK(s >= sp.probes + 1, HSS_ERR_INVALID_ARGUMENT, "need s > probes for the judge");
+      sp.s_basis = opts->rank_model ? 0 : std::min(opts->sample_start, s - sp.probes);
+      sp.judge_thr = (opts->judge_factor > 0.0 ? opts->judge_factor : 10.0) * opts->tol;
+    } else {
+      sp.s_basis = s;
+    }
+    hss_construct_stats st{};
+    for (;;) {
+      m = new hss_matrix_s();
+      m->ctx = ctx;
+      m->n = n;
+      m->L = L;
+      const int smax = s - sp.probes;
+      sp.abort_on_fail = sized && (sp.s_basis == 0 || sp.s_basis < smax);
+      sp.passed = true;
+      st.attempts += 1;
+      const bool ok = construct(m, d_points, dim, *kernel, *opts, d_omega, s, sp);
+      if (ok || sp.s_basis >= smax) break;
+      destroy_matrix(m);  // restart with twice the samples
+      m = nullptr;
+      sp.s_basis = std::min(2 * sp.s_basis, smax);
+    }
+    st.samples = L > 0 ? sp.s_basis : 0;
+    st.probes = sp.probes;
+    st.judge_failures = sp.judge_failures;
+    st.predicted_max = sp.predicted_max;
+    st.max_rank = m->max_rank;
+    st.sample_bytes = sp.sample_bytes;
+    m->cstats = st;
     *out = m;
     return HSS_OK;
   } catch (const hss::Error& e) {
@@ -457,6 +488,13 @@ hss_status hss_construct(hss_ctx_t ctx, const double* d_points, int64_t n, int32
     destroy_matrix(m);
     return HSS_ERR_DEVICE;
   }
+}
+
+hss_status hss_get_construct_stats(hss_matrix_t m, hss_construct_stats* out) {
+  HSS_API_BEGIN
+  HSS_CHECK(m && out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  *out = m->cstats;
+  HSS_API_END
 }
 
 hss_status hss_export_sizes(hss_matrix_t m, int64_t sizes[7]) {

@@ -377,6 +377,53 @@ __global__ void k_gather_rows(const double* __restrict__ src, int64_t lds, const
   }
 }
 
+// Judge of a node's basis: with Q (n x k, orthonormal) from the pivoted QR of
+// the first s_b sample columns, the relative residual of the probe columns
+// Y[:, s_b : s_b + p] is |(I - Q Q^T) Y_p|_F / |Y_p|_F; fail[i] = 1 when it
+// exceeds thr. One block per node.
+__global__ __launch_bounds__(256) void k_judge(const CNode* __restrict__ cn, const double* __restrict__ Yb,
+                                               const double* __restrict__ Qb, int sb, int probes, double thr,
+                                               int32_t* __restrict__ fail) {
+  const CNode c = cn[blockIdx.x];
+  const int n = c.n, k = c.k;
+  const double* Y = Yb + c.offY + (int64_t)sb * n;
+  const double* Q = Qb + c.offQ;
+  __shared__ double y[512];
+  __shared__ double cq[128];
+  __shared__ double red[2][256];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  double num = 0.0, den = 0.0;
+  for (int j = 0; j < probes; ++j) {
+    for (int i = tid; i < n; i += 256) y[i] = Y[i + (int64_t)j * n];
+    __syncthreads();
+    for (int q = wid; q < k; q += 4) {  // cq = Q^T y, one column per wave
+      double acc = 0.0;
+      for (int i = lane; i < n; i += 64) acc += Q[i + (int64_t)q * n] * y[i];
+      for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
+      if (lane == 0) cq[q] = acc;
+    }
+    __syncthreads();
+    for (int i = tid; i < n; i += 256) {
+      double r = y[i];
+      for (int q = 0; q < k; ++q) r -= Q[i + (int64_t)q * n] * cq[q];
+      num += r * r;
+      den += y[i] * y[i];
+    }
+    __syncthreads();
+  }
+  red[0][tid] = num;
+  red[1][tid] = den;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[0][tid] += red[0][tid + w];
+      red[1][tid] += red[1][tid + w];
+    }
+    __syncthreads();
+  }
+  if (tid == 0) fail[blockIdx.x] = (red[1][0] > 0.0 && sqrt(red[0][0] / red[1][0]) > thr) ? 1 : 0;
+}
+
 __global__ void k_points_soa(const double* __restrict__ pts, const int64_t* __restrict__ perm, int64_t n, int dim,
                              double* __restrict__ X) {
   for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
@@ -488,8 +535,63 @@ static void run_kgemm(const std::vector<KGemmDesc>& v, const KParams& kp, const 
 void launch_pchol_external(const NodeDesc* nodes, int first, int count, int nmax, double* F, int32_t* info,
                            double* logdet, hipStream_t s);
 
-void construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_kernel& kern,
-               const hss_construct_opts& o, const double* d_omega, int32_t s) {
+// Features of the learned rank model for every non-root node, in heap order
+// (node k >= 1): log2 of the point count clipped at 13, bounding-box extents in
+// decreasing order over the kernel length, gap to the sibling's box over the
+// kernel length, log10 of the length, -log10 of the tolerance.
+static std::vector<float> node_features(const std::vector<double>& P, const std::vector<int64_t>& perm, int dim,
+                                        int L, const std::vector<int64_t>& leaf_lo, double length, double tol) {
+  const int nn = (2 << L) - 1, nl = 1 << L;
+  std::vector<double> lo((size_t)nn * 3, 0.0), hi((size_t)nn * 3, 0.0);
+  std::vector<int64_t> np(nn, 0);
+  for (int i = 0; i < nl; ++i) {
+    const int k = nl - 1 + i;
+    for (int d = 0; d < 3; ++d) {
+      lo[3 * k + d] = 1e300;
+      hi[3 * k + d] = -1e300;
+    }
+    for (int64_t t = leaf_lo[i]; t < leaf_lo[i + 1]; ++t)
+      for (int d = 0; d < dim; ++d) {
+        const double v = P[(size_t)perm[t] * dim + d];
+        lo[3 * k + d] = std::min(lo[3 * k + d], v);
+        hi[3 * k + d] = std::max(hi[3 * k + d], v);
+      }
+    for (int d = dim; d < 3; ++d) lo[3 * k + d] = hi[3 * k + d] = 0.0;
+    np[k] = leaf_lo[i + 1] - leaf_lo[i];
+  }
+  for (int k = nl - 2; k >= 0; --k) {
+    for (int d = 0; d < 3; ++d) {
+      lo[3 * k + d] = std::min(lo[3 * (2 * k + 1) + d], lo[3 * (2 * k + 2) + d]);
+      hi[3 * k + d] = std::max(hi[3 * (2 * k + 1) + d], hi[3 * (2 * k + 2) + d]);
+    }
+    np[k] = np[2 * k + 1] + np[2 * k + 2];
+  }
+  std::vector<float> f((size_t)(nn - 1) * 7);
+  for (int k = 1; k < nn; ++k) {
+    const int sib = (k & 1) ? k + 1 : k - 1;
+    double e[3], g2 = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      e[d] = hi[3 * k + d] - lo[3 * k + d];
+      const double gap = std::max(0.0, std::max(lo[3 * sib + d] - hi[3 * k + d], lo[3 * k + d] - hi[3 * sib + d]));
+      g2 += gap * gap;
+    }
+    std::sort(e, e + 3, [](double a, double b) { return a > b; });
+    float* row = &f[(size_t)(k - 1) * 7];
+    row[0] = (float)std::min(std::log2((double)std::max<int64_t>(np[k], 1)), 13.0);
+    row[1] = (float)(e[0] / length);
+    row[2] = (float)(e[1] / length);
+    row[3] = (float)(e[2] / length);
+    row[4] = (float)(std::sqrt(g2) / length);
+    row[5] = (float)std::log10(length);
+    row[6] = (float)(-std::log10(tol));
+  }
+  return f;
+}
+
+void rankmlp_predict(hss_rankmlp_t r, const float* d_feats, int64_t n, int cap, int32_t* d_ranks);
+
+bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_kernel& kern,
+               const hss_construct_opts& o, const double* d_omega, int32_t s_avail, SamplePlan& sp) {
   hipStream_t st = m->ctx->stream;
   const int64_t N = m->n;
   const int L = m->L;
@@ -525,11 +627,37 @@ void construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
   }
   if (L == 0) {
     HSS_HIP(hipStreamSynchronize(st));
-    return;
+    return true;
   }
   const int kfix = o.rank;
   int kcap = o.rank > 0 ? o.rank : (o.max_rank > 0 ? o.max_rank : 128);
-  kcap = std::min(std::min(kcap, 128), (int)s);
+  kcap = std::min(kcap, 128);
+  if (sp.s_basis == 0) {
+    // sample count from the learned rank model: largest predicted node rank + 8
+    const std::vector<float> f = node_features(P, perm, dim, L, leaf_lo, kern.length > 0.0 ? kern.length : 1.0, o.tol);
+    const int64_t cntf = (int64_t)f.size() / 7;
+    float* dF = (float*)dev_alloc(sizeof(float) * f.size());
+    int32_t* dR = (int32_t*)dev_alloc(sizeof(int32_t) * cntf);
+    std::vector<int32_t> pr(cntf);
+    try {
+      HSS_HIP(hipMemcpyAsync(dF, f.data(), sizeof(float) * f.size(), hipMemcpyHostToDevice, st));
+      rankmlp_predict(sp.model, dF, cntf, kcap, dR);
+      HSS_HIP(hipMemcpyAsync(pr.data(), dR, sizeof(int32_t) * cntf, hipMemcpyDeviceToHost, st));
+      HSS_HIP(hipStreamSynchronize(st));
+    } catch (...) {
+      dev_free(dF);
+      dev_free(dR);
+      throw;
+    }
+    dev_free(dF);
+    dev_free(dR);
+    sp.predicted_max = *std::max_element(pr.begin(), pr.end());
+    sp.s_basis = std::max(1, std::min(s_avail - sp.probes, sp.predicted_max + 8));
+    if (sp.s_basis >= s_avail - sp.probes) sp.abort_on_fail = false;  // already the last attempt
+  }
+  const int sb = sp.s_basis;
+  const int s = sb + sp.probes;  // sample columns carried through the levels (basis samples, then the probe)
+  kcap = std::min(kcap, sb);
   HSS_CHECK(kcap >= 1, HSS_ERR_INVALID_ARGUMENT, "sample count too small");
 
   DevBuf Om, PsiN, Zfull;
@@ -537,8 +665,15 @@ void construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
   PsiN.ensure(N * s);
   Zfull.ensure(N * s);
   hipLaunchKernelGGL(k_gather_rows, dim3(2048), dim3(256), 0, st, d_omega, (int64_t)N, (const int64_t*)m->dperm, N,
-                     (int)s, Om.p, (int64_t)N);
+                     sb, Om.p, (int64_t)N);
   HSS_HIP(hipGetLastError());
+  if (sp.probes > 0) {  // the probe: the last columns of the caller's test matrix
+    hipLaunchKernelGGL(k_gather_rows, dim3(2048), dim3(256), 0, st, d_omega + (int64_t)(s_avail - sp.probes) * N,
+                       (int64_t)N, (const int64_t*)m->dperm, N, sp.probes, Om.p + (int64_t)sb * N, (int64_t)N);
+    HSS_HIP(hipGetLastError());
+  }
+  sp.sample_bytes = 3 * (int64_t)sizeof(double) * N * s;
+  DevArr<int32_t> dfail;
 
   std::vector<CNode> cur(nleaves);
   std::vector<const double*> zp(nleaves), php(nleaves);
@@ -667,9 +802,26 @@ void construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
       run_gemm(std::move(g), false, false, 1.0, 0.0, st);
     }
     dcur.upload(cur, st);
-    hipLaunchKernelGGL(k_qrcp, dim3(cnt), dim3(256), 0, st, dcur.p, Yb.p, Hb.p, Qb.p, Rb.p, (int)s, kfix, o.tol, kcap,
+    hipLaunchKernelGGL(k_qrcp, dim3(cnt), dim3(256), 0, st, dcur.p, Yb.p, Hb.p, Qb.p, Rb.p, sb, kfix, o.tol, kcap,
                        1, kcap);
     HSS_HIP(hipGetLastError());
+    if (sp.probes > 0) {
+      std::vector<int32_t> zf(cnt, 0);
+      dfail.upload(zf, st);
+      hipLaunchKernelGGL(k_judge, dim3(cnt), dim3(256), 0, st, (const CNode*)dcur.p, (const double*)Yb.p,
+                         (const double*)Qb.p, sb, sp.probes, sp.judge_thr, dfail.p);
+      HSS_HIP(hipGetLastError());
+      std::vector<int32_t> hf(cnt);
+      HSS_HIP(hipMemcpyAsync(hf.data(), dfail.p, sizeof(int32_t) * cnt, hipMemcpyDeviceToHost, st));
+      HSS_HIP(hipStreamSynchronize(st));
+      int nf = 0;
+      for (int32_t v : hf) nf += v;
+      sp.judge_failures += nf;
+      if (nf > 0 && sp.abort_on_fail) {
+        sp.passed = false;
+        return false;
+      }
+    }
     HSS_HIP(hipMemcpyAsync(cur.data(), dcur.p, sizeof(CNode) * cnt, hipMemcpyDeviceToHost, st));
     HSS_HIP(hipStreamSynchronize(st));
     // ---- K = Lc V = B R, Sigma = R R^T, W = Lc^{-T} V R^T ----
@@ -926,6 +1078,41 @@ void construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
     HSS_HIP(hipGetLastError());
     HSS_HIP(hipStreamSynchronize(st));
   }
+  return true;
 }
 
 }  // namespace hss
+
+using namespace hss;
+
+extern "C" hss_status hss_rank_features(hss_ctx_t ctx, const double* d_points, int64_t n, int32_t dim,
+                                        int32_t leaf_size, double length, double tol, float* h_out,
+                                        int64_t capacity, int64_t* needed) {
+  try {
+    HSS_CHECK(ctx && d_points && needed, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+    HSS_CHECK(n >= 1 && dim >= 1 && dim <= 3 && leaf_size >= 2, HSS_ERR_INVALID_ARGUMENT, "bad sizes");
+    HSS_CHECK(length > 0.0 && tol > 0.0, HSS_ERR_INVALID_ARGUMENT, "need length > 0 and tol > 0");
+    int L = 0;
+    while (((int64_t)leaf_size << L) < n) ++L;
+    HSS_CHECK(L <= 20, HSS_ERR_UNSUPPORTED, "too many levels");
+    const int64_t cnt = ((int64_t)2 << L) - 2;
+    *needed = cnt * 7;
+    if (!h_out) return HSS_OK;
+    HSS_CHECK(capacity >= cnt * 7, HSS_ERR_INVALID_ARGUMENT, "output too small");
+    std::vector<double> P((size_t)n * dim);
+    HSS_HIP(hipMemcpyAsync(P.data(), d_points, sizeof(double) * n * dim, hipMemcpyDeviceToHost, ctx->stream));
+    HSS_HIP(hipStreamSynchronize(ctx->stream));
+    std::vector<int64_t> leaf_lo;
+    std::vector<int64_t> perm = bisect(P, n, dim, L, leaf_lo);
+    if (L == 0) return HSS_OK;
+    const std::vector<float> f = node_features(P, perm, dim, L, leaf_lo, length, tol);
+    std::copy(f.begin(), f.end(), h_out);
+    return HSS_OK;
+  } catch (const hss::Error& e) {
+    hss::set_error(e.msg);
+    return e.st;
+  } catch (...) {
+    hss::set_error("unexpected internal exception");
+    return HSS_ERR_DEVICE;
+  }
+}

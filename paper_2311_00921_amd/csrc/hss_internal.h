@@ -223,6 +223,7 @@ struct hss_matrix_s {
 
   double factor_ms = 0.0, solve_ms = 0.0;
   int32_t max_rank = 0;
+  hss_construct_stats cstats{};
 
   // HIP graphs of the factorization (per precision) and of the last solve
   bool use_graph = false;
@@ -253,6 +254,22 @@ struct Prof {
 // allocation helpers (throw on failure)
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
+
+// Sample sizing of one construction attempt (construct.hip).
+struct SamplePlan {
+  hss_rankmlp_t model = nullptr;  // chooses s_basis when it is 0
+  int s_basis = 0;                // sample columns for the bases
+  int probes = 0;                 // probe columns for the judge (0: no judge)
+  double judge_thr = 0.0;         // fail a node when its probe residual exceeds this
+  bool abort_on_fail = false;     // stop at the first level with a failed node
+  // outputs
+  int judge_failures = 0;
+  int predicted_max = 0;
+  int64_t sample_bytes = 0;
+  bool passed = true;
+};
+bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_kernel& kern,
+               const hss_construct_opts& o, const double* d_omega, int32_t s_avail, SamplePlan& sp);
 
 // representation setup (capi.hip)
 void layout_representation(hss_matrix_t m);
@@ -285,7 +302,6 @@ void solve_fp32(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_
 void matvec_fp64(hss_matrix_t m, const double* x, double* y, int64_t nrhs, int64_t ld);
 
 // construct.hip
-void construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_kernel& kern,
-               const hss_construct_opts& opts, const double* d_omega, int32_t s);
+
 
 }  // namespace hss

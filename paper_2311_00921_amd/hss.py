@@ -43,7 +43,20 @@ class hss_kernel(C.Structure):
 
 class hss_construct_opts(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("levels", C.c_int32), ("rank", C.c_int32),
-                ("max_rank", C.c_int32), ("tol", C.c_double), ("mode", C.c_int32)]
+                ("max_rank", C.c_int32), ("tol", C.c_double), ("mode", C.c_int32),
+                ("rank_model", C.c_void_p), ("sample_start", C.c_int32), ("probes", C.c_int32),
+                ("judge_factor", C.c_double)]
+
+
+class hss_construct_stats(C.Structure):
+    _fields_ = [("samples", C.c_int32), ("probes", C.c_int32), ("attempts", C.c_int32),
+                ("judge_failures", C.c_int32), ("predicted_max", C.c_int32), ("max_rank", C.c_int32),
+                ("sample_bytes", C.c_int64)]
+
+
+class hss_train_opts(C.Structure):
+    _fields_ = [("batch", C.c_int32), ("lr", C.c_float), ("beta1", C.c_float), ("beta2", C.c_float),
+                ("eps", C.c_float), ("tau", C.c_float)]
 
 
 class hss_factor_opts(C.Structure):
@@ -105,6 +118,20 @@ SIGNATURES = {
     "hss_use_graphs": (C.c_int, [_P, _P, C.c_int32]),
     "hss_autotune": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_float)]),
     "hss_gemm_variants": (C.c_int, [_P, C.c_int32, C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_int64)]),
+    "hss_get_construct_stats": (C.c_int, [_P, C.POINTER(hss_construct_stats)]),
+    "hss_rankmlp_param_count": (C.c_int, [C.POINTER(C.c_int64)]),
+    "hss_rank_features": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                    C.POINTER(C.c_float), C.c_int64, C.POINTER(C.c_int64)]),
+    "hss_rankmlp_create": (C.c_int, [_P, C.POINTER(_P)]),
+    "hss_rankmlp_destroy": (C.c_int, [_P]),
+    "hss_rankmlp_set_weights": (C.c_int, [_P, _P, C.POINTER(C.c_float)]),
+    "hss_rankmlp_get_weights": (C.c_int, [_P, _P, C.POINTER(C.c_float)]),
+    "hss_rankmlp_forward": (C.c_int, [_P, _P, _P, C.c_int64, _P]),
+    "hss_rankmlp_predict": (C.c_int, [_P, _P, _P, C.c_int64, C.c_int32, _P]),
+    "hss_rankmlp_grad": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_float, C.POINTER(C.c_float),
+                                   C.POINTER(C.c_float)]),
+    "hss_rankmlp_train": (C.c_int, [_P, _P, _P, _P, C.c_int64, _P, C.c_int64, C.POINTER(hss_train_opts),
+                                    C.POINTER(C.c_float)]),
     "hss_matrix_destroy": (C.c_int, [_P]),
     "hss_status_string": (C.c_char_p, [C.c_int]),
     "hss_last_error": (C.c_char_p, []),
@@ -285,7 +312,8 @@ def unpack_desc(p: dict) -> dict:
 
 def hss_construct(ctx, points, kernel: str, leaf: int, rank: int = 0, tol: float = 0.0, max_rank: int = 0,
                   omega=None, length: float = 1.0, nugget: float = 0.0, sigma2: float = 1.0,
-                  alpha: float = 1.0, eps: float = 1e-9, levels: int = 0):
+                  alpha: float = 1.0, eps: float = 1e-9, levels: int = 0, rank_model=None,
+                  sample_start: int = 0, probes: int = 0, judge_factor: float = 0.0):
     """Builds the HSS approximation of the kernel matrix on device points (N x dim, row-major)."""
     lib = load()
     pts = points.contiguous()
@@ -294,7 +322,8 @@ def hss_construct(ctx, points, kernel: str, leaf: int, rank: int = 0, tol: float
     if ld != n:
         om = om.t().contiguous().t()
     k = hss_kernel(KERNELS[kernel], length, sigma2, nugget, alpha, eps)
-    o = hss_construct_opts(leaf, levels, rank, max_rank, tol, HSS_COMPRESS_SCALED)
+    o = hss_construct_opts(leaf, levels, rank, max_rank, tol, HSS_COMPRESS_SCALED, rank_model, sample_start,
+                           probes, judge_factor)
     out = C.c_void_p()
     _check(lib.hss_construct(ctx, _ptr(pts), n, dim, C.byref(k), C.byref(o), _ptr(om), s, C.byref(out)),
            "hss_construct")
@@ -420,7 +449,7 @@ def hss_construct_batched(ctx, points_list, kernels, leafs, ranks=None, tols=Non
     K = (hss_kernel * cnt)(*[hss_kernel(KERNELS[kernels[i]], lengths[i], sigma2, nuggets[i], alpha, eps)
                              for i in range(cnt)])
     O = (hss_construct_opts * cnt)(*[hss_construct_opts(leafs[i], 0, ranks[i], max_ranks[i], tols[i],
-                                                         HSS_COMPRESS_SCALED) for i in range(cnt)])
+                                                         HSS_COMPRESS_SCALED, None, 0, 0, 0.0) for i in range(cnt)])
     OM = (C.c_void_p * cnt)(*oms)
     S = (C.c_int32 * cnt)(*ss)
     out = C.c_void_p()
@@ -459,6 +488,117 @@ def hss_gemm_variants(m, precision: int = HSS_P_FP64):
     buf = (C.c_int32 * max(1, need.value))()
     _check(lib.hss_gemm_variants(m, precision, buf, need.value, C.byref(need)), "hss_gemm_variants")
     return list(buf[:need.value])
+
+
+def hss_get_construct_stats(m) -> hss_construct_stats:
+    st = hss_construct_stats()
+    _check(load().hss_get_construct_stats(m, C.byref(st)), "hss_get_construct_stats")
+    return st
+
+
+def hss_rankmlp_param_count() -> int:
+    n = C.c_int64(0)
+    _check(load().hss_rankmlp_param_count(C.byref(n)), "hss_rankmlp_param_count")
+    return int(n.value)
+
+
+def hss_rank_features(ctx, points, leaf: int, length: float, tol: float) -> np.ndarray:
+    """Features of the learned rank model for every non-root node (heap order)."""
+    lib = load()
+    pts = points.contiguous()
+    n, dim = pts.shape
+    need = C.c_int64(0)
+    _check(lib.hss_rank_features(ctx, _ptr(pts), n, dim, leaf, length, tol, None, 0, C.byref(need)),
+           "hss_rank_features")
+    out = np.zeros(max(1, need.value), dtype=np.float32)
+    _check(lib.hss_rank_features(ctx, _ptr(pts), n, dim, leaf, length, tol,
+                                 out.ctypes.data_as(C.POINTER(C.c_float)), out.size, C.byref(need)),
+           "hss_rank_features")
+    return out[:need.value].reshape(-1, 7)
+
+
+def hss_rankmlp_create(ctx):
+    out = C.c_void_p()
+    _check(load().hss_rankmlp_create(ctx, C.byref(out)), "hss_rankmlp_create")
+    return out
+
+
+def hss_rankmlp_destroy(mlp):
+    _check(load().hss_rankmlp_destroy(mlp), "hss_rankmlp_destroy")
+
+
+def pack_mlp_params(params) -> np.ndarray:
+    """[(W (out x in), b)] -> packed float32 vector (every W column-major)."""
+    parts = []
+    for W, b in params:
+        parts.append(np.asarray(W, dtype=np.float64).ravel(order="F"))
+        parts.append(np.asarray(b, dtype=np.float64).ravel())
+    return np.concatenate(parts).astype(np.float32)
+
+
+def unpack_mlp_params(vec, sizes=(7, 128, 128, 128, 1)):
+    out, o = [], 0
+    vec = np.asarray(vec)
+    for i, j in zip(sizes[:-1], sizes[1:]):
+        W = vec[o:o + i * j].reshape((j, i), order="F")
+        o += i * j
+        b = vec[o:o + j]
+        o += j
+        out.append((W, b))
+    return out
+
+
+def hss_rankmlp_set_weights(ctx, mlp, params):
+    v = pack_mlp_params(params) if isinstance(params, (list, tuple)) else np.ascontiguousarray(params, np.float32)
+    _check(load().hss_rankmlp_set_weights(ctx, mlp, v.ctypes.data_as(C.POINTER(C.c_float))), "hss_rankmlp_set_weights")
+
+
+def hss_rankmlp_get_weights(ctx, mlp) -> np.ndarray:
+    v = np.zeros(hss_rankmlp_param_count(), dtype=np.float32)
+    _check(load().hss_rankmlp_get_weights(ctx, mlp, v.ctypes.data_as(C.POINTER(C.c_float))), "hss_rankmlp_get_weights")
+    return v
+
+
+def hss_rankmlp_forward(ctx, mlp, feats):
+    import torch
+
+    f = feats.contiguous()
+    out = torch.empty(f.shape[0], dtype=torch.float32, device=f.device)
+    _check(load().hss_rankmlp_forward(ctx, mlp, _ptr(f), f.shape[0], _ptr(out)), "hss_rankmlp_forward")
+    return out
+
+
+def hss_rankmlp_predict(ctx, mlp, feats, cap: int):
+    import torch
+
+    f = feats.contiguous()
+    out = torch.empty(f.shape[0], dtype=torch.int32, device=f.device)
+    _check(load().hss_rankmlp_predict(ctx, mlp, _ptr(f), f.shape[0], cap, _ptr(out)), "hss_rankmlp_predict")
+    return out
+
+
+def hss_rankmlp_grad(ctx, mlp, feats, targets, tau: float = 0.9):
+    f = feats.contiguous()
+    t = targets.contiguous()
+    g = np.zeros(hss_rankmlp_param_count(), dtype=np.float32)
+    loss = C.c_float(0.0)
+    _check(load().hss_rankmlp_grad(ctx, mlp, _ptr(f), _ptr(t), f.shape[0], tau,
+                                   g.ctypes.data_as(C.POINTER(C.c_float)), C.byref(loss)), "hss_rankmlp_grad")
+    return float(loss.value), g
+
+
+def hss_rankmlp_train(ctx, mlp, feats, targets, order, batch: int, lr: float = 1e-3, tau: float = 0.9,
+                      beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, record_losses: bool = True):
+    f = feats.contiguous()
+    t = targets.contiguous()
+    o = order.contiguous()
+    steps = (o.shape[0] + batch - 1) // batch
+    losses = np.zeros(steps, dtype=np.float32)
+    opts = hss_train_opts(batch, lr, beta1, beta2, eps, tau)
+    _check(load().hss_rankmlp_train(ctx, mlp, _ptr(f), _ptr(t), f.shape[0], _ptr(o), o.shape[0], C.byref(opts),
+                                    losses.ctypes.data_as(C.POINTER(C.c_float)) if record_losses else None),
+           "hss_rankmlp_train")
+    return losses if record_losses else None
 
 
 def hss_matrix_destroy(m):

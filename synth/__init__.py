@@ -24,6 +24,8 @@ __all__ = [
     "Workload",
     "WORKLOADS",
     "batch_gaussian",
+    "mlp_init",
+    "minibatch_order",
 ]
 
 
@@ -164,3 +166,16 @@ def batch_gaussian(count: int = 64, seed: int = 4) -> list:
         out.append(Workload(f"gaussian_batch{count}_sys{i}", n, 3, "gaussian", float(ls[i]), 1e-5, leaf, 0,
                             tol=1e-6, seed_k=100 + i, extra={"max_rank": leaf // 2}))
     return out
+
+
+def mlp_init(sizes=(7, 128, 128, 128, 1), seed: int = 5000) -> list:
+    """Initial weights of a multilayer perceptron: W (out x in) ~ N(0, 2/in)
+    (He initialisation), b = 0; float64 [(W, b), ...]."""
+    rng = np.random.default_rng(seed)
+    return [(rng.standard_normal((o, i)) * math.sqrt(2.0 / i), np.zeros(o)) for i, o in zip(sizes[:-1], sizes[1:])]
+
+
+def minibatch_order(n: int, epochs: int, seed: int = 5100) -> np.ndarray:
+    """Concatenated random permutations of range(n), one per epoch (int64)."""
+    rng = np.random.default_rng(seed)
+    return np.concatenate([rng.permutation(n) for _ in range(epochs)]).astype(np.int64)
