@@ -69,6 +69,10 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched leg")
     ap.add_argument("--no-tune", action="store_true", help="skip autotuning and graph replay")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 + refinement leg")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-rank ablation leg")
+    ap.add_argument("--learned-workload", default="matern32_n262144",
+                    help="workload of the learned-rank ablation (matern32_n262144 with tol 1e-6 and cap 96, "
+                         "or exp3d_n1048576 with its tol 1e-8 and cap 128)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for scaling hardware byte counters) and exit")
     ap.add_argument("--cpu-sample-level", type=int, default=3,
@@ -260,6 +264,8 @@ def main():
     m = None
     if not args.no_batched:
         result["batched"] = batched_leg(hss, torch, np, ctx, args.steps, args.warmup)
+    if not args.no_learned:
+        result["learned_rank"] = learned_leg(hss, torch, np, ctx, args.learned_workload)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(exp, nodes, args.cpu_sample_level, w)
@@ -291,6 +297,104 @@ def measured_traffic(label, workload):
     if sha != ent["source_sha256"]:
         return None
     return ent["hbm_bytes_per_launch"]
+
+
+def learned_leg(hss, torch, np, ctx, workload):
+    """Learned rank model: trained on the GPU on the oracle's rank labels, then
+    three ways of sizing the randomized samples of one construction compared:
+    model-presized, fixed conservative (cap + 8 samples) and adaptive doubling
+    from 16, all with the 8-column probe judge."""
+    import synth
+
+    d = np.load(os.path.join(ROOT, "tests", "golden", "rank_labels.npz"))
+    F = torch.from_numpy(d["features"]).cuda()
+    ranks = d["ranks"]
+    T = torch.from_numpy(np.log2(1.0 + ranks).astype(np.float32)).cuda()
+    mlp = hss.hss_rankmlp_create(ctx)
+    init = synth.mlp_init((7, 128, 128, 128, 1), seed=5000)
+    hss.hss_rankmlp_set_weights(ctx, mlp, init)
+    epochs = 8
+    order = torch.from_numpy(synth.minibatch_order(len(ranks), epochs, seed=5100)).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    losses = hss.hss_rankmlp_train(ctx, mlp, F, T, order, 256, lr=1e-3, tau=0.9, record_losses=False)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    pred = hss.hss_rankmlp_predict(ctx, mlp, F, 128).cpu().numpy()
+    out = {"train": {"samples": int(len(ranks)), "epochs": epochs, "batch": 256, "steps": int(len(order) // 256 + 1),
+                     "train_s": round(train_s, 3), "coverage_pred_ge_label": float(np.mean(pred >= ranks)),
+                     "mean_abs_rank_error": float(np.mean(np.abs(pred - ranks)))}}
+    del losses
+    w = synth.WORKLOADS[workload]
+    if workload == "matern32_n262144":
+        tol, cap = 1e-6, 96
+    else:
+        tol, cap = w.tol, 128
+    s = cap + 8 + 8
+    X = torch.from_numpy(w.points()).cuda()
+    Om = torch.from_numpy(np.ascontiguousarray(w.omega(s).T)).cuda().t()
+    b = torch.from_numpy(np.ascontiguousarray(w.rhs()[:, 0])).cuda()
+    rows = torch.from_numpy(np.random.default_rng(77).choice(w.n, 256, replace=False)).cuda()
+    y_exact = None
+    modes = (("model", dict(rank_model=mlp)), ("fixed", dict(sample_start=cap + 8)),
+             ("doubling_from_16", dict(sample_start=16)))
+    out["workload"] = {"name": w.name, "N": w.n, "kernel": w.kernel, "length": w.length, "tol": tol, "cap": cap,
+                       "s_available": s}
+    for name, kw in modes:
+        print(f"# learned-rank leg: {name}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        m = hss.hss_construct(ctx, X, w.kernel, w.leaf, tol=tol, max_rank=cap, omega=Om, length=w.length,
+                              nugget=w.nugget, **kw)
+        torch.cuda.synchronize()
+        cs = time.perf_counter() - t0
+        st = hss.hss_get_construct_stats(m)
+        rec = {"construct_s": round(cs, 3), "attempts": st.attempts, "samples": st.samples, "probes": st.probes,
+               "judge_failures": st.judge_failures, "predicted_max": st.predicted_max, "max_rank": st.max_rank,
+               "sample_buffer_bytes": int(st.sample_bytes)}
+        try:
+            hss.hss_ulv_factor(ctx, m, hss.HSS_P_FP64)
+            x = hss.hss_ulv_solve(ctx, m, b)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(3):
+                hss.hss_ulv_factor(ctx, m, hss.HSS_P_FP64)
+                x = hss.hss_ulv_solve(ctx, m, b)
+            torch.cuda.synchronize()
+            rec["factor_plus_solve_s"] = round((time.perf_counter() - t0) / 3, 6)
+            r = b - hss.hss_matvec(ctx, m, x)
+            rec["relres"] = float(torch.linalg.norm(r) / torch.linalg.norm(b))
+            # compression error on 256 sampled rows of A x (Eq. 18), exact rows by direct kernel evaluation
+            if y_exact is None:
+                y_exact = exact_rows(torch, X, b, rows, w)
+            y = hss.hss_matvec(ctx, m, b)[rows]
+            rec["construction_error_rows"] = float(torch.linalg.norm(y - y_exact) / torch.linalg.norm(y_exact))
+        except hss.HSSError as e:
+            rec["error"] = str(e)
+        hss.hss_matrix_destroy(m)
+        out[name] = rec
+        print(f"# {name}: {rec}", file=sys.stderr, flush=True)
+    hss.hss_rankmlp_destroy(mlp)
+    return out
+
+
+def exact_rows(torch, X, v, rows, w):
+    """(A v)[rows] by direct evaluation of the kernel (plain torch, FP64)."""
+    out = torch.zeros(rows.shape[0], dtype=torch.float64, device=X.device)
+    Xr = X[rows]
+    step = 1 << 14
+    for c0 in range(0, X.shape[0], step):
+        Xc = X[c0:c0 + step]
+        dist = torch.sqrt(((Xr[:, None, :] - Xc[None, :, :]) ** 2).sum(-1))
+        if w.kernel == "exponential":
+            K = torch.exp(-dist / w.length)
+        elif w.kernel == "matern32":
+            a = (3.0 ** 0.5) * dist / w.length
+            K = (1.0 + a) * torch.exp(-a)
+        else:
+            K = torch.exp(-(dist / w.length) ** 2)
+        out += K @ v[c0:c0 + step]
+    return out + w.nugget * v[rows]
 
 
 def batched_leg(hss, torch, np, ctx, steps, warmup):
