@@ -44,6 +44,61 @@ struct Acc4<float> {
   typedef v4f type;
 };
 
+// Value of v held by lane l (l wave-uniform), broadcast through scalar
+// registers: no LDS round trip on the serial chains below.
+__device__ __forceinline__ double bcast_lane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// 1/sqrt(x) and 1/x for x > 0: the hardware estimates refined by two Newton
+// steps (quadratic convergence, a few ulp), much shorter on the dependency
+// chain than the correctly rounded sequences.
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  r = r * (1.5 - 0.5 * x * r * r);
+  r = r * (1.5 - 0.5 * x * r * r);
+  return r;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = r * (2.0 - x * r);
+  r = r * (2.0 - x * r);
+  return r;
+}
+
+// Stages the RM x RM frame X[i][c] (i, c < RM) from a column-major global
+// block A (leading dimension ld): entries with i < rows and c < cols come from
+// A, the others are 1 on the diagonal and 0 elsewhere. Each thread keeps SB
+// loads in flight before writing them to LDS, so that a lone workgroup is not
+// bound by one global-memory latency per element it loads.
+template <int RM, typename T>
+__device__ __forceinline__ void stage_frame(double (*X)[RM + 1], const T* __restrict__ A, int64_t ld, int rows,
+                                            int cols, bool lower_only) {
+  constexpr int TOT = RM * RM;
+  constexpr int PER = (TOT + 255) / 256;
+  constexpr int SB = 12;
+  const int tid = threadIdx.x;
+#pragma unroll 1
+  for (int q0 = 0; q0 < PER; q0 += SB) {
+    double v[SB];
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int e = (q0 + u) * 256 + tid;
+      const int i = e % RM, c = e / RM;
+      const bool in = e < TOT && i < rows && c < cols && (!lower_only || i >= c);
+      v[u] = in ? (double)A[i + (int64_t)c * ld] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int e = (q0 + u) * 256 + tid;
+      const int i = e % RM, c = e / RM;
+      if (e < TOT) X[i][c] = (i < rows && c < cols) ? v[u] : (i == c ? 1.0 : 0.0);
+    }
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Householder reconstruction of an orthonormal basis B (n x r) -> V, T, Sg.
 // With Sg chosen during the LU, B - [Sg; 0] = V U_lu where V is unit lower
@@ -215,16 +270,15 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
   __shared__ double Y[RM][RM + 1];   // upper = U_1^{-1}, strict lower = L_1^{-1} (unit diagonal implied)
   __shared__ double Pt[NB][16][17];
   __shared__ double sg[RM];
+  __shared__ double uinv[RM];  // 1 / U_ii
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int e = tid; e < RM * RM; e += 256) {
-    const int i = e % RM, c = e / RM;
-    X[i][c] = (i < r && c < r) ? (double)B[i + (int64_t)c * n] : (i == c ? 1.0 : 0.0);
-  }
+  stage_frame<RM>(X, B, n, r, r, false);
   __syncthreads();
   for (int J = 0; J < NB; ++J) {
     const int j0 = J * 16;
     if (wid == 0) {
-      // lane owns rows j0 + lane and j0 + 64 + lane of the panel (columns j0..j0+15)
+      // lane owns rows j0 + lane and j0 + 64 + lane of the panel (columns j0..j0+15);
+      // the pivot row moves between lanes through scalar registers
       double a[2][16];
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
@@ -232,24 +286,22 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
 #pragma unroll
         for (int c = 0; c < 16; ++c) a[h][c] = (row < RM) ? X[row][j0 + c] : 0.0;
       }
+      double myinv = 1.0;
 #pragma unroll
       for (int k = 0; k < 16; ++k) {
         // pivot row j0 + k is lane k's first row
-        const double u = __shfl(a[0][k], k, 64);
+        const double u = bcast_lane(a[0][k], k);
         const double sgn = (u >= 0.0) ? -1.0 : 1.0;
-        const double p = u - sgn;
-        const double pinv = 1.0 / p;
+        const double p = u - sgn;  // |p| >= 1
+        const double pinv = rcp_nr(p);
         if (lane == k) {
           a[0][k] = p;
+          myinv = pinv;
           sg[j0 + k] = sgn;
-          // publish the pivot row to LDS (columns k+1..15 of this panel)
-#pragma unroll
-          for (int c = 0; c < 16; ++c) X[j0 + k][j0 + c] = a[0][c];
         }
-        __builtin_amdgcn_wave_barrier();
         double prow[16];
 #pragma unroll
-        for (int c = 0; c < 16; ++c) prow[c] = (c > k) ? X[j0 + k][j0 + c] : 0.0;
+        for (int c = 0; c < 16; ++c) prow[c] = (c > k) ? bcast_lane(a[0][c], k) : 0.0;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int row = j0 + lane + 64 * h;
@@ -261,8 +313,8 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
               if (c > k) a[h][c] -= l * prow[c];
           }
         }
-        __builtin_amdgcn_wave_barrier();
       }
+      if (lane < 16) uinv[j0 + lane] = myinv;
 #pragma unroll
       for (int h = 0; h < 2; ++h) {
         const int row = j0 + lane + 64 * h;
@@ -313,7 +365,7 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
         double acc = 0.0;
 #pragma unroll
         for (int k = i + 1; k < 16; ++k) acc += X[o + i][o + k] * xu[k];
-        xu[i] = (i == cc) ? 1.0 / X[o + i][o + i] : (i < cc ? -acc / X[o + i][o + i] : 0.0);
+        xu[i] = (i == cc) ? uinv[o + i] : (i < cc ? -acc * uinv[o + i] : 0.0);
       }
 #pragma unroll
       for (int i = 0; i < 16; ++i) {
@@ -466,37 +518,44 @@ __global__ __launch_bounds__(256) void k_merge(const NodeDesc* __restrict__ node
 // ---------------------------------------------------------------------------
 
 // Cholesky of a 16 x 16 pivot block held by one wave: lane i < jb owns row i
-// (a[0..i]); column k of L is published through LDS (col) after each step so the
-// remaining rows read it with independent loads. Returns the first non-positive
-// pivot (or -1) and the sum of log pivots. Call from one full wave.
-__device__ __forceinline__ int pivot_block_chol(double (&a)[16], int jb, double* col, double* dsh, double& lsum) {
+// (a[0..i]). Pivots and columns of L move between lanes through scalar
+// registers; the square root and its reciprocal come from rsqrt_nr. Returns the
+// first non-positive pivot (or -1), the sum of log pivots over the wave (in
+// lsum, every lane) and, on lane i, 1 / L_ii (in rdiag). Call from one full wave.
+__device__ __forceinline__ int pivot_block_chol(double (&a)[16], int jb, double& lsum, double& rdiag) {
   const int lane = threadIdx.x & 63;
   int bad = -1;
-  lsum = 0.0;
+  double mine = 1.0;  // this lane's pivot; the logs are taken in parallel after the chain
+  rdiag = 1.0;
 #pragma unroll
   for (int k = 0; k < 16; ++k) {
     if (k < jb) {
-      if (lane == k) *dsh = a[k];
-      __builtin_amdgcn_wave_barrier();
-      double d = *dsh;
-      if (!(d > 0.0)) {
+      double x = bcast_lane(a[k], k);
+      if (!(x > 0.0)) {
         if (bad < 0) bad = k;
-        d = 1.0;
+        x = 1.0;
       }
-      d = sqrt(d);
-      lsum += log(d);
-      if (lane == k) a[k] = d;
-      else if (lane > k) a[k] /= d;
-      if (lane < 16) col[lane] = a[k];
-      __builtin_amdgcn_wave_barrier();
+      const double rs = rsqrt_nr(x);
+      if (lane == k) {
+        a[k] = x * rs;
+        mine = a[k];
+        rdiag = rs;
+      } else if (lane > k) {
+        a[k] *= rs;
+      }
 #pragma unroll
       for (int c = k + 1; c < 16; ++c) {
-        const double lc = col[c];
-        if (lane >= c && c < jb) a[c] -= a[k] * lc;
+        if (c < jb) {
+          const double lc = bcast_lane(a[k], c);  // L[c][k]
+          if (lane >= c) a[c] -= a[k] * lc;
+        }
       }
-      __builtin_amdgcn_wave_barrier();
     }
   }
+  double lg = (lane < jb) ? log(mine) : 0.0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) lg += __shfl_xor(lg, o, 64);
+  lsum = lg;
   return bad;
 }
 
@@ -514,9 +573,8 @@ __global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ node
   const int n = nd.n, m = nd.m;
   T* F = Fbase + nd.offF;
   __shared__ double Ld[PNB][PNB + 1];  // pivot blocks are always factored in FP64
+  __shared__ double Rd[PNB];           // reciprocals of the pivot block's diagonal
   __shared__ T P[PNB][NMAX + 1];
-  __shared__ double colb[16];
-  __shared__ double dshb;
   __shared__ int fail;
   __shared__ double lacc;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -533,8 +591,9 @@ __global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ node
 #pragma unroll
       for (int c = 0; c < PNB; ++c)
         a[c] = (lane < jb && c <= lane) ? (double)F[(j0 + lane) + (int64_t)(j0 + c) * n] : 0.0;
-      double lsum = 0.0;
-      const int bad = pivot_block_chol(a, jb, colb, &dshb, lsum);
+      double lsum = 0.0, rd = 1.0;
+      const int bad = pivot_block_chol(a, jb, lsum, rd);
+      if (lane < PNB) Rd[lane] = rd;
 #pragma unroll
       for (int c = 0; c < PNB; ++c) {
         if (lane < jb) Ld[lane][c] = (c <= lane) ? a[c] : 0.0;
@@ -560,7 +619,7 @@ __global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ node
           double acc = x[c];
 #pragma unroll
           for (int k = 0; k < c; ++k) acc -= x[k] * Ld[c][k];
-          x[c] = acc / Ld[c][c];
+          x[c] = acc * Rd[c];
         }
       }
 #pragma unroll
@@ -656,18 +715,11 @@ __global__ __launch_bounds__(256) void k_chol_lds(const NodeDesc* __restrict__ n
   __shared__ double X[RM][RM + 1];
   __shared__ double Y[RM][RM + 1];
   __shared__ double Pt[NB][16][17];
-  __shared__ double colb[16];
-  __shared__ double dshb;
+  __shared__ double rdg[RM];  // 1 / L_ii
   __shared__ int fail;
   __shared__ double lacc;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int e = tid; e < RM * RM; e += 256) {
-    const int i = e % RM, j = e / RM;
-    double v = 0.0;
-    if (i < m && j < m) v = (i >= j) ? (double)F[i + (int64_t)j * n] : 0.0;
-    else if (i == j) v = 1.0;
-    X[i][j] = v;
-  }
+  stage_frame<RM>(X, F, n, m, m, true);
   if (tid == 0) {
     fail = -1;
     lacc = 0.0;
@@ -679,10 +731,11 @@ __global__ __launch_bounds__(256) void k_chol_lds(const NodeDesc* __restrict__ n
       double a[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) a[c] = (lane < 16 && c <= lane) ? X[j0 + lane][j0 + c] : 0.0;
-      double lsum = 0.0;
+      double lsum = 0.0, rd = 1.0;
       const int jbl = m - j0 >= 16 ? 16 : (m - j0 > 0 ? m - j0 : 0);
-      int bad = pivot_block_chol(a, 16, colb, &dshb, lsum);
+      int bad = pivot_block_chol(a, 16, lsum, rd);
       if (bad >= jbl) bad = -1;
+      if (lane < 16) rdg[j0 + lane] = rd;
       if (lane < 16)
 #pragma unroll
         for (int c = 0; c < 16; ++c) X[j0 + lane][j0 + c] = (c <= lane) ? a[c] : 0.0;
@@ -702,7 +755,7 @@ __global__ __launch_bounds__(256) void k_chol_lds(const NodeDesc* __restrict__ n
         double acc = x[c];
 #pragma unroll
         for (int k = 0; k < c; ++k) acc -= x[k] * X[j0 + c][j0 + k];
-        x[c] = acc / X[j0 + c][j0 + c];
+        x[c] = acc * rdg[j0 + c];
       }
 #pragma unroll
       for (int c = 0; c < 16; ++c) X[i][j0 + c] = x[c];
@@ -739,7 +792,7 @@ __global__ __launch_bounds__(256) void k_chol_lds(const NodeDesc* __restrict__ n
         double acc = 0.0;
 #pragma unroll
         for (int k = 0; k < i; ++k) acc += X[o + i][o + k] * x[k];
-        x[i] = (i == cc) ? 1.0 / X[o + i][o + i] : (i > cc ? -acc / X[o + i][o + i] : 0.0);
+        x[i] = (i == cc) ? rdg[o + i] : (i > cc ? -acc * rdg[o + i] : 0.0);
       }
 #pragma unroll
       for (int i = 0; i < 16; ++i) Y[o + i][o + cc] = x[i];

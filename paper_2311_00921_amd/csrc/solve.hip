@@ -14,7 +14,9 @@
 
 namespace hss {
 
-constexpr int SW = 256;   // threads per node in the solve kernels
+// Threads per node (NT): 1024 for stages of at most 256 nodes, where a node's
+// own memory-level parallelism bounds the time, 256 for the wide stages.
+constexpr int kSolveWideNodes = 256;
 constexpr int SNB = 16;   // block size of the blocked triangular solves
 constexpr int RC = 4;     // right-hand sides per pass
 
@@ -27,12 +29,12 @@ __device__ __forceinline__ T wave_sum(T v) {
 
 // out[j, c] = sum_{i < rows} A[i + j lda] x[i + c ldx] for j < cols: one wave per
 // column (coalesced reads of the column), wave reduction. x, out in LDS.
-template <typename T>
+template <int NT, typename T>
 __device__ void col_dots(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* x, int ldx, T* out,
                          int ldo, int nc) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   constexpr int CW = 4;  // columns per wave per pass
-  for (int j0 = wid * CW; j0 < cols; j0 += (SW / 64) * CW) {
+  for (int j0 = wid * CW; j0 < cols; j0 += (NT / 64) * CW) {
     T acc[CW][RC];
 #pragma unroll
     for (int q = 0; q < CW; ++q)
@@ -61,10 +63,10 @@ __device__ void col_dots(const T* __restrict__ A, int64_t lda, int rows, int col
 }
 
 // y[i, c] (+)= sign * sum_{j < cols} A[i + j lda] u[j + c ldu] for i < rows: one thread per row.
-template <typename T>
+template <int NT, typename T>
 __device__ void row_gemv(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* u, int ldu, T* y,
                          int ldy, int nc, T sign) {
-  for (int i = threadIdx.x; i < rows; i += SW) {
+  for (int i = threadIdx.x; i < rows; i += NT) {
     T acc[RC];
 #pragma unroll
     for (int c = 0; c < RC; ++c) acc[c] = 0;
@@ -91,42 +93,19 @@ __device__ void row_gemv(const T* __restrict__ A, int64_t lda, int rows, int col
   }
 }
 
-// u = T^T t (trans) or u = T t for the upper triangular r x r T (ld r).
-template <typename T>
-__device__ void tri_mult(const T* __restrict__ Tm, int r, const T* t, T* u, int nc, bool trans) {
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int j = wid; j < r; j += SW / 64) {
-    T acc[RC];
-#pragma unroll
-    for (int c = 0; c < RC; ++c) acc[c] = 0;
-    if (trans) {  // (T^T t)_j = sum_{k <= j} T[k, j] t_k : column j, contiguous
-#pragma unroll 2
-      for (int k = lane; k <= j; k += 64) {
-        const T a = Tm[k + (int64_t)j * r];
-#pragma unroll
-        for (int c = 0; c < RC; ++c)
-          if (c < nc) acc[c] += a * t[k + c * r];
-      }
-    } else {      // (T t)_j = sum_{k >= j} T[j, k] t_k : row j
-#pragma unroll 2
-      for (int k = j + lane; k < r; k += 64) {
-        const T a = Tm[j + (int64_t)k * r];
-#pragma unroll
-        for (int c = 0; c < RC; ++c)
-          if (c < nc) acc[c] += a * t[k + c * r];
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < RC; ++c) {
-      const T v = wave_sum(acc[c]);
-      if (lane == 0 && c < nc) u[j + c * r] = v;
-    }
-  }
+// Value of v held by lane l (l wave-uniform), through scalar registers.
+__device__ __forceinline__ double bcast_lane(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float bcast_lane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
 }
 
 // In place y = L^{-1} y, L = F[0:m, 0:m] lower (ld ldf); y in LDS (ld ldy).
 // 16-row diagonal blocks are solved by one wave; the rows below are updated by all threads.
-template <typename T>
+template <int NT, typename T>
 __device__ void lower_solve(const T* __restrict__ F, int ldf, int m, T* y, int ldy, int nc) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int b0 = 0; b0 < m; b0 += SNB) {
@@ -139,14 +118,19 @@ __device__ void lower_solve(const T* __restrict__ F, int ldf, int m, T* y, int l
       T v[RC];
 #pragma unroll
       for (int c = 0; c < RC; ++c) v[c] = (lane < bb && c < nc) ? y[b0 + lane + c * ldy] : (T)0;
+      // reciprocal of this lane's diagonal entry, taken off the serial chain
+      const T rinv = (lane < bb) ? (T)1 / F[(b0 + lane) + (int64_t)(b0 + lane) * ldf] : (T)1;
 #pragma unroll
       for (int k = 0; k < SNB; ++k) {
         if (k < bb) {
+          const T rk = bcast_lane(rinv, k);
 #pragma unroll
           for (int c = 0; c < RC; ++c) {
-            T yk = __shfl(v[c] / Lrow[k], k, 64);  // lane k holds the solved value after the division
-            if (lane == k) v[c] = yk;
-            else if (lane > k) v[c] -= Lrow[k] * yk;
+            if (c < nc) {
+              const T yk = bcast_lane(v[c], k) * rk;
+              if (lane == k) v[c] = yk;
+              else if (lane > k) v[c] -= Lrow[k] * yk;
+            }
           }
         }
       }
@@ -155,20 +139,20 @@ __device__ void lower_solve(const T* __restrict__ F, int ldf, int m, T* y, int l
         if (lane < bb && c < nc) y[b0 + lane + c * ldy] = v[c];
     }
     __syncthreads();
-    row_gemv(F + (b0 + bb) + (int64_t)b0 * ldf, ldf, m - b0 - bb, bb, y + b0, ldy, y + b0 + bb, ldy, nc, (T)-1);
+    row_gemv<NT>(F + (b0 + bb) + (int64_t)b0 * ldf, ldf, m - b0 - bb, bb, y + b0, ldy, y + b0 + bb, ldy, nc, (T)-1);
     __syncthreads();
   }
 }
 
 // In place x = L^{-T} x, L = F[0:m, 0:m] lower.
-template <typename T>
+template <int NT, typename T>
 __device__ void lower_t_solve(const T* __restrict__ F, int ldf, int m, T* x, int ldx, int nc, T* scratch) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nblk = (m + SNB - 1) / SNB;
   for (int bi = nblk - 1; bi >= 0; --bi) {
     const int b0 = bi * SNB, bb = min(SNB, m - b0);
     // scratch[k] = sum_{i >= b0+bb} L[i, b0+k] x[i]
-    col_dots(F + (b0 + bb) + (int64_t)b0 * ldf, ldf, m - b0 - bb, bb, x + b0 + bb, ldx, scratch, SNB, nc);
+    col_dots<NT>(F + (b0 + bb) + (int64_t)b0 * ldf, ldf, m - b0 - bb, bb, x + b0 + bb, ldx, scratch, SNB, nc);
     __syncthreads();
     if (wid == 0) {
       // lane i < bb owns column b0 + i of the block (L^T row)
@@ -178,14 +162,18 @@ __device__ void lower_t_solve(const T* __restrict__ F, int ldf, int m, T* x, int
       T v[RC];
 #pragma unroll
       for (int c = 0; c < RC; ++c) v[c] = (lane < bb && c < nc) ? x[b0 + lane + c * ldx] - scratch[lane + c * SNB] : (T)0;
+      const T rinv = (lane < bb) ? (T)1 / F[(b0 + lane) + (int64_t)(b0 + lane) * ldf] : (T)1;
 #pragma unroll
       for (int kk = SNB - 1; kk >= 0; --kk) {
         if (kk < bb) {
+          const T rk = bcast_lane(rinv, kk);
 #pragma unroll
           for (int c = 0; c < RC; ++c) {
-            T xk = __shfl(v[c] / Lcol[kk], kk, 64);
-            if (lane == kk) v[c] = xk;
-            else if (lane < kk) v[c] -= Lcol[kk] * xk;
+            if (c < nc) {
+              const T xk = bcast_lane(v[c], kk) * rk;
+              if (lane == kk) v[c] = xk;
+              else if (lane < kk) v[c] -= Lcol[kk] * xk;
+            }
           }
         }
       }
@@ -197,8 +185,8 @@ __device__ void lower_t_solve(const T* __restrict__ F, int ldf, int m, T* x, int
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(SW) void k_solve_fwd(const NodeDesc* __restrict__ nodes, int first,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_solve_fwd(const NodeDesc* __restrict__ nodes, int first,
                                                   const T* __restrict__ Fb, const T* __restrict__ Vb,
                                                   const T* __restrict__ Yb, const T* __restrict__ Sgb,
                                                   T* __restrict__ vec, int64_t nrhs, int c0, int nc,
@@ -218,42 +206,42 @@ __global__ __launch_bounds__(SW) void k_solve_fwd(const NodeDesc* __restrict__ n
   const T* V = Vb + nd.offV;
   const T* Y = Yb + nd.offW;
   const T* Sg = Sgb + nd.offSg;
-  for (int i = threadIdx.x; i < n; i += SW)
+  for (int i = threadIdx.x; i < n; i += NT)
     for (int c = 0; c < nc; ++c)
       sb[i + c * n] = leaf ? (T)b[perm[nd.lo + i] + (int64_t)(c0 + c) * ld] : vp[i + (int64_t)(c0 + c) * n];
   __syncthreads();
   // b^ = H^T b = b - V (Y^T b) with Y = V T kept by the factorization
-  col_dots(Y, n, n, r, sb, n, st, r, nc);
+  col_dots<NT>(Y, n, n, r, sb, n, st, r, nc);
   __syncthreads();
-  row_gemv(V, n, n, r, st, r, sb, n, nc, (T)-1);
+  row_gemv<NT>(V, n, n, r, st, r, sb, n, nc, (T)-1);
   __syncthreads();
   // y_R = L_RR^{-1} b^_R  (b^_R = sb[r:n])
   if (use_inv) {
     const T* Li = Lib + offLi[p];
-    for (int i = threadIdx.x; i < m * RC; i += SW) tm[i] = 0;
+    for (int i = threadIdx.x; i < m * RC; i += NT) tm[i] = 0;
     __syncthreads();
-    row_gemv(Li, m, m, m, sb + r, n, tm, m, nc, (T)1);
+    row_gemv<NT>(Li, m, m, m, sb + r, n, tm, m, nc, (T)1);
     __syncthreads();
-    for (int i = threadIdx.x; i < m; i += SW)
+    for (int i = threadIdx.x; i < m; i += NT)
       for (int c = 0; c < nc; ++c) sb[r + i + c * n] = tm[i + c * m];
     __syncthreads();
   } else {
-    lower_solve(F, n, m, sb + r, n, nc);
+    lower_solve<NT>(F, n, m, sb + r, n, nc);
   }
   // z_S = b^_S - L_SR y_R   (L_SR = F[m:n, 0:m])
-  row_gemv(F + m, n, r, m, sb + r, n, sb, n, nc, (T)-1);
+  row_gemv<NT>(F + m, n, r, m, sb + r, n, sb, n, nc, (T)-1);
   __syncthreads();
-  for (int i = threadIdx.x; i < m; i += SW)
+  for (int i = threadIdx.x; i < m; i += NT)
     for (int c = 0; c < nc; ++c) vp[i + (int64_t)(c0 + c) * n] = sb[r + i + c * n];
   if (nd.parent < 0) return;  // a root: y = L^{-1} b is all that is left
   const NodeDesc par = nodes[nd.parent];
   T* pp = vec + par.offVec * nrhs;
-  for (int j = threadIdx.x; j < r; j += SW)
+  for (int j = threadIdx.x; j < r; j += NT)
     for (int c = 0; c < nc; ++c) pp[nd.child_row + j + (int64_t)(c0 + c) * par.n] = Sg[j] * sb[j + c * n];
 }
 
-template <typename T>
-__global__ __launch_bounds__(SW) void k_solve_bwd(const NodeDesc* __restrict__ nodes, int first,
+template <typename T, int NT>
+__global__ __launch_bounds__(NT) void k_solve_bwd(const NodeDesc* __restrict__ nodes, int first,
                                                   const T* __restrict__ Fb, const T* __restrict__ Vb,
                                                   const T* __restrict__ Yb, const T* __restrict__ Sgb,
                                                   T* __restrict__ vec, int64_t nrhs, int c0, int nc,
@@ -278,35 +266,35 @@ __global__ __launch_bounds__(SW) void k_solve_bwd(const NodeDesc* __restrict__ n
   if (nd.parent >= 0) {
     const NodeDesc par = nodes[nd.parent];
     const T* pp = vec + par.offVec * nrhs;
-    for (int j = threadIdx.x; j < r; j += SW)
+    for (int j = threadIdx.x; j < r; j += NT)
       for (int c = 0; c < nc; ++c) sx[j + c * n] = Sg[j] * pp[nd.child_row + j + (int64_t)(c0 + c) * par.n];
   }
-  for (int i = threadIdx.x; i < m; i += SW)
+  for (int i = threadIdx.x; i < m; i += NT)
     for (int c = 0; c < nc; ++c) sx[r + i + c * n] = vp[i + (int64_t)(c0 + c) * n];
   __syncthreads();
   // t = y_R - L_SR^T x_S: tm[k] = sum_j L_SR[j, k] x_S[j] (column k of L_SR is contiguous)
-  col_dots(F + m, n, r, m, sx, n, tm, n, nc);
+  col_dots<NT>(F + m, n, r, m, sx, n, tm, n, nc);
   __syncthreads();
-  for (int k = threadIdx.x; k < m; k += SW)
+  for (int k = threadIdx.x; k < m; k += NT)
     for (int c = 0; c < nc; ++c) sx[r + k + c * n] -= tm[k + c * n];
   __syncthreads();
   if (use_inv) {
     // x_R = L_RR^{-T} t: x_R[j] = sum_i Li[i, j] t_i  (columns of Li are contiguous)
     const T* Li = Lib + offLi[p];
-    col_dots(Li, m, m, m, sx + r, n, tm, n, nc);
+    col_dots<NT>(Li, m, m, m, sx + r, n, tm, n, nc);
     __syncthreads();
-    for (int i = threadIdx.x; i < m; i += SW)
+    for (int i = threadIdx.x; i < m; i += NT)
       for (int c = 0; c < nc; ++c) sx[r + i + c * n] = tm[i + c * n];
     __syncthreads();
   } else {
-    lower_t_solve(F, n, m, sx + r, n, nc, scr);
+    lower_t_solve<NT>(F, n, m, sx + r, n, nc, scr);
   }
   // x = H x^ = x^ - Y (V^T x^)
-  col_dots(V, n, n, r, sx, n, st, r, nc);
+  col_dots<NT>(V, n, n, r, sx, n, st, r, nc);
   __syncthreads();
-  row_gemv(Y, n, n, r, st, r, sx, n, nc, (T)-1);
+  row_gemv<NT>(Y, n, n, r, st, r, sx, n, nc, (T)-1);
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += SW)
+  for (int i = threadIdx.x; i < n; i += NT)
     for (int c = 0; c < nc; ++c) {
       if (leaf)
         x[perm[nd.lo + i] + (int64_t)(c0 + c) * ld] = (double)sx[i + c * n];
@@ -466,17 +454,27 @@ static void solve_impl(hss_matrix_t m, const T* F, const T* V, const T* Yw, cons
     for (int si = 0; si < ns; ++si) {
       const LevelPlan& lp = m->stages[si];
       Prof pf(m->ctx, "solve_forward", lp.level);
-      hipLaunchKernelGGL((k_solve_fwd<T>), dim3(lp.count), dim3(SW), 0, s, m->dnodes, lp.first, F, V, Yw, Sg, vec,
-                         nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, lp.leaf, Li,
-                         (const int64_t*)m->dOffLi, (int)inv_used[si]);
+      if (lp.count <= kSolveWideNodes)
+        hipLaunchKernelGGL((k_solve_fwd<T, 1024>), dim3(lp.count), dim3(1024), 0, s, m->dnodes, lp.first, F, V, Yw,
+                           Sg, vec, nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, lp.leaf, Li,
+                           (const int64_t*)m->dOffLi, (int)inv_used[si]);
+      else
+        hipLaunchKernelGGL((k_solve_fwd<T, 256>), dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, F, V, Yw,
+                           Sg, vec, nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, lp.leaf, Li,
+                           (const int64_t*)m->dOffLi, (int)inv_used[si]);
       HSS_HIP(hipGetLastError());
     }
     for (int si = ns - 1; si >= 0; --si) {
       const LevelPlan& lp = m->stages[si];
       Prof pf(m->ctx, "solve_backward", lp.level);
-      hipLaunchKernelGGL((k_solve_bwd<T>), dim3(lp.count), dim3(SW), 0, s, m->dnodes, lp.first, F, V, Yw, Sg, vec,
-                         nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, lp.leaf, Li,
-                         (const int64_t*)m->dOffLi, (int)inv_used[si]);
+      if (lp.count <= kSolveWideNodes)
+        hipLaunchKernelGGL((k_solve_bwd<T, 1024>), dim3(lp.count), dim3(1024), 0, s, m->dnodes, lp.first, F, V, Yw,
+                           Sg, vec, nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, lp.leaf, Li,
+                           (const int64_t*)m->dOffLi, (int)inv_used[si]);
+      else
+        hipLaunchKernelGGL((k_solve_bwd<T, 256>), dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, F, V, Yw,
+                           Sg, vec, nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, lp.leaf, Li,
+                           (const int64_t*)m->dOffLi, (int)inv_used[si]);
       HSS_HIP(hipGetLastError());
     }
   }
