@@ -192,8 +192,7 @@ def main():
         relres_g = float(torch.linalg.norm(rg) / torch.linalg.norm(b))
         tuned = {"factor_plus_solve_s": round(t_tuned, 6), "relres": relres_g,
                  "rel_diff_x_vs_eager": float(torch.linalg.norm(xg - x) / torch.linalg.norm(x)),
-                 "gemm_ms_per_factor_by_tile": {"64x64": rep[0], "32x32": rep[1], "128x64": rep[2],
-                                                "64x128": rep[3], "tuned": rep[4]},
+                 "gemm_ms_per_factor_by_tile": dict(zip(list(hss.GEMM_TILES) + ["tuned"], rep)),
                  "tile_choice": hss.hss_gemm_variants(m, hss.HSS_P_FP64)}
         if relres_g <= 1e-8:
             t_best = min(t_best, t_tuned)
@@ -464,7 +463,7 @@ def batched_leg(hss, torch, np, ctx, steps, warmup):
             leg["batch_factor_plus_solve_s"] = round(run_batch(steps), 6)
             leg["relres_max_over_systems"] = per_system_relres(x)
             leg["gemm_ms_per_factor_uniform_64x64"] = rep[0]
-            leg["gemm_ms_per_factor_tuned"] = rep[4]
+            leg["gemm_ms_per_factor_tuned"] = rep[-1]
             for _ in range(warmup):
                 run_loop(1)
             leg["loop_factor_plus_solve_s"] = round(run_loop(steps), 6)

@@ -564,8 +564,8 @@ constexpr int PNB = 16;
 // CONSTRUCT only names the instantiation used by the construction (full
 // Cholesky of the diagonal blocks), so that profiles keep it apart from the
 // factorization's partial Cholesky; the code is the same.
-template <typename T, int NMAX, bool CONSTRUCT = false>
-__global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ nodes, int first,
+template <typename T, int NMAX, bool CONSTRUCT = false, int NT = 256>
+__global__ __launch_bounds__(NT) void k_pchol(const NodeDesc* __restrict__ nodes, int first,
                                                T* __restrict__ Fbase, int32_t* __restrict__ info,
                                                double* __restrict__ logdet) {
   const int node = first + blockIdx.x;
@@ -608,7 +608,7 @@ __global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ node
     if (fail >= 0) break;
     // (2) panel below the pivot block: rows j0+jb .. n-1
     const int t0 = j0 + jb, nt = n - t0;
-    for (int i = tid; i < nt; i += 256) {
+    for (int i = tid; i < nt; i += NT) {
       double x[PNB];
 #pragma unroll
       for (int c = 0; c < PNB; ++c) x[c] = (c < jb) ? (double)F[(t0 + i) + (int64_t)(j0 + c) * n] : 0.0;
@@ -632,7 +632,7 @@ __global__ __launch_bounds__(256) void k_pchol(const NodeDesc* __restrict__ node
     // (3) trailing update of the lower triangle, four tiles per wave at a time
     const int nb = (nt + 15) / 16;
     const int ntiles = nb * (nb + 1) / 2;
-    for (int t4 = wid * 4; t4 < ntiles; t4 += 16) {
+    for (int t4 = wid * 4; t4 < ntiles; t4 += 4 * (NT / 64)) {
       typename Acc4<T>::type acc[4];
       int ti[4], tj[4];
 #pragma unroll
@@ -914,15 +914,25 @@ static void launch_tri_inv(const hss_matrix_t m, const LevelPlan& lp, const T* i
   HSS_HIP(hipGetLastError());
 }
 
+// Narrow launches (a few blocks, e.g. the roots) get 512 threads per block:
+// their time is the per-block chain, not the device throughput.
 template <typename T>
 static void launch_pchol(const hss_matrix_t m, int first, int count, int nmax, T* F, hipStream_t s) {
-  dim3 grid(count), block(256);
-  if (nmax <= 256)
-    hipLaunchKernelGGL((k_pchol<T, 256>), grid, block, 0, s, m->dnodes, first, F, m->dinfo, m->dlogdet);
-  else if (nmax <= 512)
-    hipLaunchKernelGGL((k_pchol<T, 512>), grid, block, 0, s, m->dnodes, first, F, m->dinfo, m->dlogdet);
+  HSS_CHECK(nmax <= 512, HSS_ERR_UNSUPPORTED, "diagonal block larger than 512");
+  dim3 grid(count);
+  const bool narrow = count <= 64;
+  if (nmax <= 256 && !narrow)
+    hipLaunchKernelGGL((k_pchol<T, 256, false, 256>), grid, dim3(256), 0, s, m->dnodes, first, F, m->dinfo,
+                       m->dlogdet);
+  else if (nmax <= 256)
+    hipLaunchKernelGGL((k_pchol<T, 256, false, 512>), grid, dim3(512), 0, s, m->dnodes, first, F, m->dinfo,
+                       m->dlogdet);
+  else if (!narrow)
+    hipLaunchKernelGGL((k_pchol<T, 512, false, 256>), grid, dim3(256), 0, s, m->dnodes, first, F, m->dinfo,
+                       m->dlogdet);
   else
-    HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "diagonal block larger than 512");
+    hipLaunchKernelGGL((k_pchol<T, 512, false, 512>), grid, dim3(512), 0, s, m->dnodes, first, F, m->dinfo,
+                       m->dlogdet);
   HSS_HIP(hipGetLastError());
 }
 
@@ -1122,7 +1132,9 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
     const int nonroot = lp.root_first - lp.first;
     if (!lp.leaf) {
       Prof pf(cx, "merge", l);
-      hipLaunchKernelGGL((k_merge<T>), dim3(lp.count, 16), dim3(256), 0, s, m->dnodes, lp.first, (const T*)b.F,
+      // narrow stages split each block's columns over more workgroups
+      hipLaunchKernelGGL((k_merge<T>), dim3(lp.count, lp.count <= 64 ? 96 : 16), dim3(256), 0, s, m->dnodes,
+                         lp.first, (const T*)b.F,
                          (const T*)b.Sg, b.S, b.M, b.F, 0);
       HSS_HIP(hipGetLastError());
     }

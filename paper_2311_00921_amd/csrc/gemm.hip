@@ -4,7 +4,7 @@
 //
 // One launch covers every node of a stage: grid.y indexes the batch entry,
 // grid.x the BM x BN output tiles of that entry. Each 256-thread workgroup
-// stages BM x 16 slices of op(A) and 16 x BN slices of op(B) in LDS; each of
+// stages BM x BK slices of op(A) and BK x BN slices of op(B) in LDS; each of
 // its four waves owns a (BM/2) x (BN/2) quadrant of the tile as a grid of
 // 16x16 MFMA accumulators. The tile shape is one of a few compiled variants,
 // picked per batch by the autotuner (default 64 x 64).
@@ -33,11 +33,12 @@ __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int BK = 16;
-
-// tile variants: {BM, BN}
-constexpr int kTileM[kGemmVariants] = {64, 32, 128, 64};
-constexpr int kTileN[kGemmVariants] = {64, 32, 64, 128};
+// tile variants: {BM, BN, BK}; the deep-K ones (BK 32 and 64) halve or quarter
+// the number of dependent global-load rounds, which is what bounds the small
+// GEMMs of the stages with few nodes
+constexpr int kTileM[kGemmVariants] = {64, 32, 128, 64, 32, 64};
+constexpr int kTileN[kGemmVariants] = {64, 32, 64, 128, 32, 64};
+constexpr int kTileK[kGemmVariants] = {16, 16, 16, 16, 64, 32};
 
 // Row of the 16x16 MFMA output held by lane `lane` in accumulator slot v.
 // FP64 16x16x4 interleaves rows across slots; FP32 16x16x4 stacks them.
@@ -48,7 +49,7 @@ __device__ __forceinline__ int perm_index(int t, int dim, int r) {
   return r > 0 ? (t < r ? t + (dim - r) : t - r) : t;
 }
 
-template <typename T, bool TA, bool TB, int BM, int BN>
+template <typename T, bool TA, bool TB, int BM, int BN, int BK>
 __device__ __forceinline__ void load_tiles(const GemmDesc& d, const T* __restrict__ A, const T* __restrict__ B,
                                            int row0, int col0, int k0, T (&ra)[BM * BK / 256],
                                            T (&rb)[BN * BK / 256]) {
@@ -87,7 +88,7 @@ __device__ __forceinline__ void load_tiles(const GemmDesc& d, const T* __restric
   }
 }
 
-template <typename T, bool TA, bool TB, int BM, int BN>
+template <typename T, bool TA, bool TB, int BM, int BN, int BK>
 __device__ __forceinline__ void store_tiles(T (&As)[BK][BM + 1], T (&Bs)[BK][BN + 1], const T (&ra)[BM * BK / 256],
                                             const T (&rb)[BN * BK / 256]) {
   const int tid = threadIdx.x;
@@ -109,7 +110,7 @@ __device__ __forceinline__ void store_tiles(T (&As)[BK][BM + 1], T (&Bs)[BK][BN 
   }
 }
 
-template <typename T, bool TA, bool TB, int BM, int BN>
+template <typename T, bool TA, bool TB, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs, T alpha, T beta) {
   constexpr int IM = BM / 32, JN = BN / 32;  // 16x16 accumulators per wave
   const GemmDesc d = descs[blockIdx.y];
@@ -135,11 +136,11 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   T ra[BM * BK / 256], rb[BN * BK / 256];
   // software pipeline: the next K slice is fetched into registers while the
   // matrix cores consume the current one from LDS
-  if (d.k > 0) load_tiles<T, TA, TB, BM, BN>(d, A, B, row0, col0, 0, ra, rb);
+  if (d.k > 0) load_tiles<T, TA, TB, BM, BN, BK>(d, A, B, row0, col0, 0, ra, rb);
   for (int k0 = 0; k0 < d.k; k0 += BK) {
-    store_tiles<T, TA, TB, BM, BN>(As, Bs, ra, rb);
+    store_tiles<T, TA, TB, BM, BN, BK>(As, Bs, ra, rb);
     __syncthreads();
-    if (k0 + BK < d.k) load_tiles<T, TA, TB, BM, BN>(d, A, B, row0, col0, k0 + BK, ra, rb);
+    if (k0 + BK < d.k) load_tiles<T, TA, TB, BM, BN, BK>(d, A, B, row0, col0, k0 + BK, ra, rb);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T a[IM], b[JN];
@@ -224,18 +225,18 @@ void gemm_free(GemmBatch& b) {
   b.dev = nullptr;
 }
 
-template <typename T, int BM, int BN>
+template <typename T, int BM, int BN, int BK>
 static void launch_tile(const GemmBatch& b, bool ta, bool tb, T alpha, T beta, hipStream_t s) {
   const int tiles = ((b.mmax + BM - 1) / BM) * ((b.nmax + BN - 1) / BN);
   dim3 grid(tiles, b.count);
   if (!ta && !tb)
-    hipLaunchKernelGGL((k_gemm<T, false, false, BM, BN>), grid, dim3(256), 0, s, b.dev, alpha, beta);
+    hipLaunchKernelGGL((k_gemm<T, false, false, BM, BN, BK>), grid, dim3(256), 0, s, b.dev, alpha, beta);
   else if (ta && !tb)
-    hipLaunchKernelGGL((k_gemm<T, true, false, BM, BN>), grid, dim3(256), 0, s, b.dev, alpha, beta);
+    hipLaunchKernelGGL((k_gemm<T, true, false, BM, BN, BK>), grid, dim3(256), 0, s, b.dev, alpha, beta);
   else if (!ta && tb)
-    hipLaunchKernelGGL((k_gemm<T, false, true, BM, BN>), grid, dim3(256), 0, s, b.dev, alpha, beta);
+    hipLaunchKernelGGL((k_gemm<T, false, true, BM, BN, BK>), grid, dim3(256), 0, s, b.dev, alpha, beta);
   else
-    hipLaunchKernelGGL((k_gemm<T, true, true, BM, BN>), grid, dim3(256), 0, s, b.dev, alpha, beta);
+    hipLaunchKernelGGL((k_gemm<T, true, true, BM, BN, BK>), grid, dim3(256), 0, s, b.dev, alpha, beta);
   HSS_HIP(hipGetLastError());
 }
 
@@ -244,12 +245,16 @@ static void launch(const GemmBatch& b, bool ta, bool tb, T alpha, T beta, hipStr
   if (b.count == 0 || b.mmax == 0 || b.nmax == 0) return;
   HSS_CHECK(b.count <= 65535, HSS_ERR_UNSUPPORTED, "too many GEMM batch entries in one launch");
   GemmTimer t(b, s);
+#define HSS_TILE(v) launch_tile<T, kTileM[v], kTileN[v], kTileK[v]>(b, ta, tb, alpha, beta, s)
   switch (b.variant) {
-    case 1: launch_tile<T, kTileM[1], kTileN[1]>(b, ta, tb, alpha, beta, s); break;
-    case 2: launch_tile<T, kTileM[2], kTileN[2]>(b, ta, tb, alpha, beta, s); break;
-    case 3: launch_tile<T, kTileM[3], kTileN[3]>(b, ta, tb, alpha, beta, s); break;
-    default: launch_tile<T, kTileM[0], kTileN[0]>(b, ta, tb, alpha, beta, s); break;
+    case 1: HSS_TILE(1); break;
+    case 2: HSS_TILE(2); break;
+    case 3: HSS_TILE(3); break;
+    case 4: HSS_TILE(4); break;
+    case 5: HSS_TILE(5); break;
+    default: HSS_TILE(0); break;
   }
+#undef HSS_TILE
 }
 
 void gemm_launch_f64(const GemmBatch& b, bool ta, bool tb, double alpha, double beta, hipStream_t s) {

@@ -91,7 +91,7 @@ struct GemmDesc {
   void* C2;        // optional second output (same values, same layout as C)
 };
 
-constexpr int kGemmVariants = 4;  // compiled tile shapes of the batched GEMM
+constexpr int kGemmVariants = 6;  // compiled tile shapes of the batched GEMM
 
 struct GemmBatch {
   std::vector<GemmDesc> host;

@@ -473,10 +473,13 @@ def hss_use_graphs(ctx, m, on: bool):
     _check(load().hss_use_graphs(ctx, m, 1 if on else 0), "hss_use_graphs")
 
 
+GEMM_TILES = ("64x64x16", "32x32x16", "128x64x16", "64x128x16", "32x32x64", "64x64x32")
+
+
 def hss_autotune(ctx, m, precision: int = HSS_P_FP64, reps: int = 2):
     """Tunes the GEMM tile shapes; returns the GEMM ms per factorization for
-    each uniform shape and for the tuned choice (5 floats)."""
-    rep = (C.c_float * 5)()
+    each uniform shape (GEMM_TILES order) and for the tuned choice (last)."""
+    rep = (C.c_float * (len(GEMM_TILES) + 1))()
     _check(load().hss_autotune(ctx, m, precision, reps, rep), "hss_autotune")
     return list(rep)
 

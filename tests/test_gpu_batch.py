@@ -218,10 +218,11 @@ def test_autotune_changes_only_rounding(env):
         hss.hss_ulv_factor(ctx, m)
         x0 = hss.hss_ulv_solve(ctx, m, bd).cpu().numpy()
         rep = hss.hss_autotune(ctx, m, hss.HSS_P_FP64, 2)
-        assert len(rep) == 5 and all(v > 0 for v in rep)
-        assert rep[4] <= min(rep[:4]) * 1.05 + 1e-3  # the per-batch choice is no worse than any uniform shape
+        nt = len(hss.GEMM_TILES)
+        assert len(rep) == nt + 1 and all(v > 0 for v in rep)
+        assert rep[-1] <= min(rep[:-1]) * 1.05 + 1e-3  # the per-batch choice is no worse than any uniform shape
         var = hss.hss_gemm_variants(m, hss.HSS_P_FP64)
-        assert len(var) > 0 and all(0 <= v < 4 for v in var)
+        assert len(var) > 0 and all(0 <= v < nt for v in var)
         with pytest.raises(hss.HSSError):
             hss.hss_ulv_solve(ctx, m, bd)  # tuning leaves the matrix unfactored
         hss.hss_ulv_factor(ctx, m)
