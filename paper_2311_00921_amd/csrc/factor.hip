@@ -478,37 +478,71 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
 template <typename T>
 __global__ __launch_bounds__(256) void k_merge(const NodeDesc* __restrict__ nodes, int first,
                                                const T* __restrict__ Fbase, const T* __restrict__ Sgbase,
-                                               const T* __restrict__ Sbase, T* __restrict__ Mbase,
-                                               T* __restrict__ Fout, int to_factor) {
+                                               const T* __restrict__ Sbase, T* __restrict__ Mbase) {
+  // one 32 x 32 tile of one parent's block per workgroup (grid.y runs over the tiles)
   const int p = first + blockIdx.x;
   const NodeDesc nd = nodes[p];
   const NodeDesc c1 = nodes[nd.c1], c2 = nodes[nd.c2];
   const int n = nd.n, r1 = c1.r;
-  T* M = Mbase + nd.offM;  // grid.y splits the columns
-  T* Fo = Fout + nd.offF;  // the root block is also written where it is factored
+  const int tpr = (n + 31) / 32;
+  if ((int)blockIdx.y >= tpr * tpr) return;
+  const int i0 = (blockIdx.y % tpr) * 32, j0 = (blockIdx.y / tpr) * 32;
+  T* M = Mbase + nd.offM;
   const T* F1 = Fbase + c1.offF;
   const T* F2 = Fbase + c2.offF;
   const T* s1 = Sgbase + c1.offSg;
   const T* s2 = Sgbase + c2.offSg;
   const T* S = Sbase + nd.offS;
-  for (int j = blockIdx.y; j < n; j += gridDim.y)
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const int64_t e = i + (int64_t)j * n;
-    T v;
-    if (i < r1 && j < r1) {
-      const int a = max(i, j), b = min(i, j);
-      v = s1[i] * s1[j] * F1[(c1.m + a) + (int64_t)(c1.m + b) * c1.n];
-    } else if (i >= r1 && j >= r1) {
-      const int ii = i - r1, jj = j - r1;
-      const int a = max(ii, jj), b = min(ii, jj);
-      v = s2[ii] * s2[jj] * F2[(c2.m + a) + (int64_t)(c2.m + b) * c2.n];
-    } else if (i < r1) {
-      v = S[i + (int64_t)(j - r1) * r1];
-    } else {
-      v = S[j + (int64_t)(i - r1) * r1];
+  __shared__ T tile[32][33];
+  const int a = threadIdx.x & 31, b = threadIdx.x >> 5;
+  // Element (i, j) of M: Sg Sigma Sg of a child (lower triangle of its trailing block), S, or S^T.
+  // "direct" sources are read with i fastest, the transposed ones with j fastest; both coalesced.
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    {  // direct: i = i0 + a, j = j0 + b + 8 rr
+      const int i = i0 + a, j = j0 + b + 8 * rr;
+      if (i < n && j < n) {
+        T v;
+        bool have = true;
+        if (i < r1 && j < r1) {
+          have = i >= j;
+          v = have ? s1[i] * s1[j] * F1[(c1.m + i) + (int64_t)(c1.m + j) * c1.n] : (T)0;
+        } else if (i >= r1 && j >= r1) {
+          have = i >= j;
+          v = have ? s2[i - r1] * s2[j - r1] * F2[(c2.m + i - r1) + (int64_t)(c2.m + j - r1) * c2.n] : (T)0;
+        } else if (i < r1) {
+          v = S[i + (int64_t)(j - r1) * r1];
+        } else {
+          have = false;
+          v = (T)0;
+        }
+        if (have) tile[a][b + 8 * rr] = v;
+      }
     }
-    M[e] = v;
-    if (to_factor) Fo[e] = v;
+    {  // transposed: i = i0 + b + 8 rr, j = j0 + a
+      const int i = i0 + b + 8 * rr, j = j0 + a;
+      if (i < n && j < n) {
+        bool have = false;
+        T v = (T)0;
+        if (i < r1 && j < r1 && i < j) {
+          have = true;
+          v = s1[i] * s1[j] * F1[(c1.m + j) + (int64_t)(c1.m + i) * c1.n];
+        } else if (i >= r1 && j >= r1 && i < j) {
+          have = true;
+          v = s2[i - r1] * s2[j - r1] * F2[(c2.m + j - r1) + (int64_t)(c2.m + i - r1) * c2.n];
+        } else if (i >= r1 && j < r1) {
+          have = true;
+          v = S[j + (int64_t)(i - r1) * r1];
+        }
+        if (have) tile[b + 8 * rr][a] = v;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int rr = 0; rr < 4; ++rr) {
+    const int i = i0 + a, j = j0 + b + 8 * rr;
+    if (i < n && j < n) M[i + (int64_t)j * n] = tile[a][b + 8 * rr];
   }
 }
 
@@ -563,8 +597,10 @@ constexpr int PNB = 16;
 
 // CONSTRUCT only names the instantiation used by the construction (full
 // Cholesky of the diagonal blocks), so that profiles keep it apart from the
-// factorization's partial Cholesky; the code is the same.
-template <typename T, int NMAX, bool CONSTRUCT = false, int NT = 256>
+// factorization's partial Cholesky; the code is the same. RR_ONLY restricts
+// the sweep to the leading m x m block (L_RR); k_sr_schur then forms L_SR and
+// Sigma without re-reading the S rows once per panel.
+template <typename T, int NMAX, bool CONSTRUCT = false, int NT = 256, bool RR_ONLY = false>
 __global__ __launch_bounds__(NT) void k_pchol(const NodeDesc* __restrict__ nodes, int first,
                                                T* __restrict__ Fbase, int32_t* __restrict__ info,
                                                double* __restrict__ logdet) {
@@ -607,7 +643,7 @@ __global__ __launch_bounds__(NT) void k_pchol(const NodeDesc* __restrict__ nodes
     __syncthreads();
     if (fail >= 0) break;
     // (2) panel below the pivot block: rows j0+jb .. n-1
-    const int t0 = j0 + jb, nt = n - t0;
+    const int t0 = j0 + jb, nt = (RR_ONLY ? m : n) - t0;
     for (int i = tid; i < nt; i += NT) {
       double x[PNB];
 #pragma unroll
@@ -690,6 +726,134 @@ __global__ __launch_bounds__(NT) void k_pchol(const NodeDesc* __restrict__ nodes
       info[4 + nd.sys] = 1;  // per-system flag
     }
     logdet[node] = 2.0 * lacc;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// L_SR and Sigma after an RR-only partial Cholesky (r <= RMAX, m <= MMAX):
+// the r x m block F_SR is held in LDS while L_SR = F_SR L_RR^{-T} is solved in
+// 16-column steps (MFMA update with the finished columns, then a 16 x 16
+// triangular solve per row), then Sigma = F_SS - L_SR L_SR^T on the matrix
+// cores from LDS. F_SR is read once and L_SR written once.
+// ---------------------------------------------------------------------------
+
+template <typename T, int RMAX, int MMAX>
+__global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ nodes, int first,
+                                                  T* __restrict__ Fbase) {
+  constexpr int NT = 512, NW = NT / 64;
+  constexpr int RT = RMAX / 16;  // row tiles of L_SR
+  const NodeDesc nd = nodes[first + blockIdx.x];
+  const int n = nd.n, r = nd.r, m = nd.m;
+  if (r == 0) return;
+  T* F = Fbase + nd.offF;
+  __shared__ T X[RMAX][MMAX + 1];  // F_SR, then L_SR
+  __shared__ T Lb[16][MMAX + 1];   // L_RR[j0:j0+16, 0:j0+16] of the current step
+  __shared__ double rd[16];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  // X = F_SR (rows m..n-1, columns 0..m-1), zero outside
+  {
+    constexpr int TOT = RMAX * MMAX, PER = (TOT + NT - 1) / NT, SB = 8;
+#pragma unroll 1
+    for (int q0 = 0; q0 < PER; q0 += SB) {
+      T v[SB];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int e = (q0 + u) * NT + tid;
+        const int i = e % RMAX, c = e / RMAX;
+        v[u] = (e < TOT && i < r && c < m) ? F[(m + i) + (int64_t)c * n] : (T)0;
+      }
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int e = (q0 + u) * NT + tid;
+        if (e < TOT) X[e % RMAX][e / RMAX] = v[u];
+      }
+    }
+  }
+  for (int j0 = 0; j0 < m; j0 += 16) {
+    const int jb = min(16, m - j0);
+    // stage rows j0..j0+jb of L_RR, columns 0..j0+jb (unit frame beyond)
+    {
+      const int cols = j0 + 16;
+      for (int e0 = tid; e0 < 16 * cols; e0 += NT * 4) {
+        T v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * NT;
+          const int q = e % 16, k = e / 16;
+          v[u] = (e < 16 * cols && q < jb && k <= j0 + q) ? F[(j0 + q) + (int64_t)k * n] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int e = e0 + u * NT;
+          const int q = e % 16, k = e / 16;
+          if (e < 16 * cols) Lb[q][k] = (q >= jb && k == j0 + q) ? (T)1 : v[u];
+        }
+      }
+    }
+    __syncthreads();
+    if (tid < 16) rd[tid] = 1.0 / (double)Lb[tid][j0 + tid];
+    // X[:, j0:j0+16] -= X[:, 0:j0] L_RR[j0:j0+16, 0:j0]^T
+    if (j0 > 0) {
+      for (int rt = wid; rt < RT; rt += NW) {
+        typename Acc4<T>::type acc;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[v] = 0;
+        for (int k0 = 0; k0 < j0; k0 += 4) {
+          const int k = k0 + (lane >> 4);
+          acc = mfma16x(X[rt * 16 + (lane & 15)][k], Lb[lane & 15][k], acc);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[rt * 16 + mfma_out_row((T)0, lane, v)][j0 + (lane & 15)] -= acc[v];
+      }
+    }
+    __syncthreads();
+    // X[i, j0:j0+16] = X[i, j0:j0+16] L_jj^{-T}: forward substitution per row
+    for (int i = tid; i < r; i += NT) {
+      double x[16];
+#pragma unroll
+      for (int c = 0; c < 16; ++c) x[c] = (c < jb) ? (double)X[i][j0 + c] : 0.0;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        double acc = x[c];
+#pragma unroll
+        for (int k = 0; k < c; ++k) acc -= x[k] * (double)Lb[c][j0 + k];
+        x[c] = acc * rd[c];
+      }
+#pragma unroll
+      for (int c = 0; c < 16; ++c)
+        if (c < jb) X[i][j0 + c] = (T)x[c];
+    }
+    __syncthreads();
+  }
+  // L_SR back to F
+  for (int e = tid; e < r * m; e += NT) {
+    const int i = e % r, c = e / r;
+    F[(m + i) + (int64_t)c * n] = X[i][c];
+  }
+  // Sigma = F_SS - L_SR L_SR^T, lower tiles
+  for (int t = wid; t < RT * (RT + 1) / 2; t += NW) {
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = t - I * (I + 1) / 2;
+    if (I * 16 >= r) continue;
+    typename Acc4<T>::type acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = 0;
+    for (int k0 = 0; k0 < m; k0 += 4) {
+      const int k = k0 + (lane >> 4);
+      acc = mfma16x(X[I * 16 + (lane & 15)][k], X[J * 16 + (lane & 15)][k], acc);
+    }
+    T cur[4];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = I * 16 + mfma_out_row((T)0, lane, v), c = J * 16 + (lane & 15);
+      cur[v] = (i < r && c < r && i >= c) ? F[(m + i) + (int64_t)(m + c) * n] : (T)0;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int i = I * 16 + mfma_out_row((T)0, lane, v), c = J * 16 + (lane & 15);
+      if (i < r && c < r && i >= c) F[(m + i) + (int64_t)(m + c) * n] = cur[v] - acc[v];
+    }
   }
 }
 
@@ -936,6 +1100,18 @@ static void launch_pchol(const hss_matrix_t m, int first, int count, int nmax, T
   HSS_HIP(hipGetLastError());
 }
 
+// Partial Cholesky of nodes with r <= 96 and 96 < m <= 160 in two kernels:
+// L_RR by the right-looking sweep restricted to the R block, then L_SR and
+// Sigma from LDS.
+template <typename T>
+static void launch_pchol_split(const hss_matrix_t m, int first, int count, T* F, hipStream_t s) {
+  hipLaunchKernelGGL((k_pchol<T, 256, false, 256, true>), dim3(count), dim3(256), 0, s, m->dnodes, first, F,
+                     m->dinfo, m->dlogdet);
+  HSS_HIP(hipGetLastError());
+  hipLaunchKernelGGL((k_sr_schur<T, 96, 160>), dim3(count), dim3(512), 0, s, m->dnodes, first, F);
+  HSS_HIP(hipGetLastError());
+}
+
 // Full Cholesky of a batch of blocks (NodeDesc n = m = block size, offF = offset).
 void launch_pchol_external(const NodeDesc* nodes, int first, int count, int nmax, double* F, int32_t* info,
                            double* logdet, hipStream_t s) {
@@ -956,6 +1132,27 @@ struct FBufs {
   const T* S;
   T *F, *M, *V, *Tm, *Sg, *W, *X, *Li, *S2;
 };
+
+// The basis QR of a node depends on its basis only, not on the factorization
+// below it: when every node above the leaves has r <= 96 (the fused kernel),
+// their QRs run in one launch on a second stream, concurrently with the leaf
+// stage. Returns the contiguous node range [lo, hi) of the stages above the leaves.
+static bool basis_hoisted(hss_matrix_t m, int& lo, int& hi) {
+  if (m->stages.size() < 2) return false;
+  const LevelPlan& l0 = m->stages[0];
+  if (l0.first == 0) {
+    lo = l0.count;
+    hi = m->nnodes;
+  } else {
+    lo = 0;
+    hi = l0.first;
+    if (l0.first + l0.count != m->nnodes) return false;
+  }
+  if (hi - lo < 1 || hi - lo > 65535) return false;
+  for (int k = lo; k < hi; ++k)
+    if (m->nodes[k].r > 96) return false;
+  return true;
+}
 
 // Builds the per-level GEMM batches of the basis QR and the diagonal product
 // (once per matrix and compute type). With Y = V T (so H = I - Y V^T):
@@ -999,6 +1196,22 @@ static std::vector<std::vector<GemmBatch>> build_gemm_plan(hss_matrix_t m, const
     }
     for (auto& g : steps) gemm_upload(g, s);
     plan[si] = std::move(steps);
+  }
+  int lo = 0, hi = 0;
+  if (basis_hoisted(m, lo, hi)) {
+    // V_2 = B_2 U_1^{-1} and Y = V T of every node above the leaves, issued once
+    std::vector<GemmBatch> hs(2);
+    for (int p = lo; p < hi; ++p) {
+      const NodeDesc& nd = m->nodes[p];
+      const int n = nd.n, r = nd.r;
+      if (r == 0) continue;
+      T* V = b.V + nd.offV;
+      hs[0].host.push_back({b.B + nd.offB + r, b.X + nd.offX + (int64_t)r * r, nullptr, V + r, n - r, r, r, n, r, 0,
+                            n, 0, 0});
+      hs[1].host.push_back({V, b.Tm + nd.offT, nullptr, b.W + nd.offW, n, r, r, n, r, 0, n, 0, 0});
+    }
+    for (auto& g : hs) gemm_upload(g, s);
+    plan.push_back(std::move(hs));
   }
   return plan;
 }
@@ -1122,34 +1335,68 @@ void root_cholesky_fp64<float>(hss_matrix_t m, const LevelPlan& lp, float* F, hi
 }
 
 template <typename T>
+static void launch_basis_top(int rmax, int first, int count, const NodeDesc* nodes, const FBufs<T>& b,
+                             hipStream_t s) {
+  dim3 grid(count), block(256);
+  if (rmax <= 32)
+    hipLaunchKernelGGL((k_basis_top<T, 32>), grid, block, 0, s, nodes, first, b.B, b.V, b.Tm, b.Sg, b.X);
+  else if (rmax <= 64)
+    hipLaunchKernelGGL((k_basis_top<T, 64>), grid, block, 0, s, nodes, first, b.B, b.V, b.Tm, b.Sg, b.X);
+  else
+    hipLaunchKernelGGL((k_basis_top<T, 96>), grid, block, 0, s, nodes, first, b.B, b.V, b.Tm, b.Sg, b.X);
+  HSS_HIP(hipGetLastError());
+}
+
+template <typename T>
 static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::vector<GemmBatch>>& plan) {
   hipStream_t s = m->ctx->stream;
   hss_ctx_t cx = m->ctx;
   const bool fp32 = sizeof(T) == 4;
+  const bool hoist = plan.size() > m->stages.size();
+  if (hoist) {
+    // basis QR of every node above the leaves, on the second stream
+    int lo = 0, hi = 0;
+    basis_hoisted(m, lo, hi);
+    int rmax = 0;
+    for (int k = lo; k < hi; ++k) rmax = std::max(rmax, m->nodes[k].r);
+    if (!cx->aux_stream) HSS_HIP(hipStreamCreateWithFlags(&cx->aux_stream, hipStreamNonBlocking));
+    if (!cx->ev_fork) HSS_HIP(hipEventCreateWithFlags(&cx->ev_fork, hipEventDisableTiming));
+    if (!cx->ev_join) HSS_HIP(hipEventCreateWithFlags(&cx->ev_join, hipEventDisableTiming));
+    hipStream_t a = cx->aux_stream;
+    HSS_HIP(hipEventRecord(cx->ev_fork, s));
+    HSS_HIP(hipStreamWaitEvent(a, cx->ev_fork, 0));
+    cx->stream = a;  // the profiling records of this section go to the second stream
+    try {
+      Prof pf(cx, "basis_qr_upper", -1);
+      launch_basis_top<T>(rmax, lo, hi - lo, m->dnodes, b, a);
+      auto& hs = plan.back();
+      gemm_run<T>(hs[0], false, false, 1.0, 0.0, a);  // V_2 = B_2 U_1^{-1}
+      gemm_run<T>(hs[1], false, false, 1.0, 0.0, a);  // Y = V T
+    } catch (...) {
+      cx->stream = s;
+      throw;
+    }
+    cx->stream = s;
+    HSS_HIP(hipEventRecord(cx->ev_join, a));
+  }
   for (size_t si = 0; si < m->stages.size(); ++si) {
     const LevelPlan& lp = m->stages[si];
     const int l = lp.level;
     const int nonroot = lp.root_first - lp.first;
+    const bool basis_done = hoist && si > 0;
+    if (hoist && si == 1) HSS_HIP(hipStreamWaitEvent(s, cx->ev_join, 0));
     if (!lp.leaf) {
       Prof pf(cx, "merge", l);
-      // narrow stages split each block's columns over more workgroups
-      hipLaunchKernelGGL((k_merge<T>), dim3(lp.count, lp.count <= 64 ? 96 : 16), dim3(256), 0, s, m->dnodes,
-                         lp.first, (const T*)b.F,
-                         (const T*)b.Sg, b.S, b.M, b.F, 0);
+      const int tpr = (lp.nmax + 31) / 32;
+      hipLaunchKernelGGL((k_merge<T>), dim3(lp.count, tpr * tpr), dim3(256), 0, s, m->dnodes, lp.first,
+                         (const T*)b.F, (const T*)b.Sg, b.S, b.M);
       HSS_HIP(hipGetLastError());
     }
     auto& st = plan[si];
-    if (lp.rmax > 0) {
+    if (lp.rmax > 0 && !basis_done) {
       Prof pf(cx, "basis_qr", l);
       if (lp.rmax <= 96) {
-        dim3 grid(lp.count), block(256);
-        if (lp.rmax <= 32)
-          hipLaunchKernelGGL((k_basis_top<T, 32>), grid, block, 0, s, m->dnodes, lp.first, b.B, b.V, b.Tm, b.Sg, b.X);
-        else if (lp.rmax <= 64)
-          hipLaunchKernelGGL((k_basis_top<T, 64>), grid, block, 0, s, m->dnodes, lp.first, b.B, b.V, b.Tm, b.Sg, b.X);
-        else
-          hipLaunchKernelGGL((k_basis_top<T, 96>), grid, block, 0, s, m->dnodes, lp.first, b.B, b.V, b.Tm, b.Sg, b.X);
-        HSS_HIP(hipGetLastError());
+        launch_basis_top<T>(lp.rmax, lp.first, lp.count, m->dnodes, b, s);
         gemm_run<T>(st[0], false, false, 1.0, 0.0, s);    // V_2 = B_2 U_1^{-1}
       } else {
         launch_lu_top<T>(m, lp, b.B, b.V, b.Tm, b.Sg, s);   // V_1, U_1 (in the T slot), Sg
@@ -1159,7 +1406,7 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
         launch_tri_inv<T>(m, lp, b.X, 1, b.Tm, 0, 1, s);    // T = (striu G + diag G / 2)^{-1}
       }
     }
-    {
+    if (!basis_done) {
       Prof pf(cx, "gemm_small_wy", l);
       gemm_run<T>(st[2], false, false, 1.0, 0.0, s);      // Y = V T
     }
@@ -1201,7 +1448,16 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
                            (const int64_t*)m->dOffS2, b.F);
         HSS_HIP(hipGetLastError());
       } else {
-        if (nonroot > 0) launch_pchol<T>(m, lp.first, nonroot, lp.nmax, b.F, s);
+        int rmax_nr = 0, mmax_nr = 0, nmax_nr = 0;
+        for (int k = lp.first; k < lp.root_first; ++k) {
+          rmax_nr = std::max(rmax_nr, m->nodes[k].r);
+          mmax_nr = std::max(mmax_nr, m->nodes[k].m);
+          nmax_nr = std::max(nmax_nr, m->nodes[k].n);
+        }
+        if (nonroot > 0 && rmax_nr <= 96 && mmax_nr <= 160 && nmax_nr <= 256)
+          launch_pchol_split<T>(m, lp.first, nonroot, b.F, s);
+        else if (nonroot > 0)
+          launch_pchol<T>(m, lp.first, nonroot, lp.nmax, b.F, s);
         if (nonroot < lp.count) {
           if (fp32)
             root_cholesky_fp64<T>(m, lp, b.F, s);

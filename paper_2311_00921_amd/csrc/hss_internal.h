@@ -146,6 +146,8 @@ struct hss_ctx_s {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   hipStream_t cap_stream = nullptr;  // non-blocking stream used only to record graphs
+  hipStream_t aux_stream = nullptr;  // second stream for work off the critical path
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 };
 
 struct hss_matrix_s {
