@@ -1184,7 +1184,8 @@ static std::vector<std::vector<GemmBatch>> build_gemm_plan(hss_matrix_t m, const
       steps[3].host.push_back({Mp, Y, nullptr, W, n, r, n, n, n, 0, n, 0, 0});            // W = M Y
       steps[4].host.push_back({Y, W, nullptr, X1, r, r, n, n, n, 0, r, 0, 0});            // C = Y^T W
       steps[5].host.push_back({V, X1, W, Zl, n, r, r, n, r, n, n, 0, 0, Zr});             // Z = W - V C / 2
-      steps[6].host.push_back({Zl, V, Mp, F, n, n, 2 * r, n, n, n, n, r, 0});             // F = P^T (M - [Z V][V Z]^T) P
+      // F = P^T (M - [Z V][V Z]^T) P, lower triangle only (nothing reads F above its diagonal)
+      steps[6].host.push_back({Zl, V, Mp, F, n, n, 2 * r, n, n, n, n, r, 0, nullptr, 1});
       if (lp.inv) {
         const int mm = nd.m;
         T* Li = b.Li + m->offLi[p];
@@ -1353,8 +1354,10 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
   hss_ctx_t cx = m->ctx;
   const bool fp32 = sizeof(T) == 4;
   const bool hoist = plan.size() > m->stages.size();
-  if (hoist) {
-    // basis QR of every node above the leaves, on the second stream
+  // basis QR of every node above the leaves, on the second stream once the
+  // leaves' own basis QR is done (so that it overlaps the leaf stage's GEMMs
+  // and partial Cholesky rather than the leaf basis QR itself)
+  auto fork_upper_basis = [&]() {
     int lo = 0, hi = 0;
     basis_hoisted(m, lo, hi);
     int rmax = 0;
@@ -1378,7 +1381,7 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
     }
     cx->stream = s;
     HSS_HIP(hipEventRecord(cx->ev_join, a));
-  }
+  };
   for (size_t si = 0; si < m->stages.size(); ++si) {
     const LevelPlan& lp = m->stages[si];
     const int l = lp.level;
@@ -1410,6 +1413,7 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
       Prof pf(cx, "gemm_small_wy", l);
       gemm_run<T>(st[2], false, false, 1.0, 0.0, s);      // Y = V T
     }
+    if (hoist && si == 0) fork_upper_basis();
     {
       Prof pf(cx, "gemm_W=MV", l);
       gemm_run<T>(st[3], false, false, 1.0, 0.0, s);      // W = M Y

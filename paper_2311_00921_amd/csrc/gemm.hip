@@ -119,6 +119,16 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   if ((int)blockIdx.x >= tilesM * tilesN) return;
   const int row0 = (blockIdx.x % tilesM) * BM;
   const int col0 = (blockIdx.x / tilesM) * BN;
+  if (d.lower_only) {
+    // output position of index t is t + (dim - r) for t < r, t - r otherwise (r = perm_r, square)
+    const int r = d.perm_r, mm = d.m - r;
+    const int r1 = min(row0 + BM, d.m) - 1, c1 = min(col0 + BN, d.n) - 1;
+    int maxp = -1;
+    if (row0 < r) maxp = max(maxp, min(r1, r - 1) + mm);
+    if (r1 >= r) maxp = max(maxp, r1 - r);
+    const int minp = (c1 >= r) ? max(col0, r) - r : col0 + mm;
+    if (maxp < minp) return;  // every element of the tile lies strictly above the diagonal
+  }
   __shared__ T As[BK][BM + 1];
   __shared__ T Bs[BK][BN + 1];
   const T* __restrict__ A = (const T*)d.A;

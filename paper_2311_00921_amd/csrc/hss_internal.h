@@ -89,6 +89,7 @@ struct GemmDesc {
   int32_t perm_r;  // 0: plain store; r > 0: index t -> (t < r ? t + (dim - r) : t - r)
   int32_t perm_in; // 1: Cin is read at the permuted position too (in-place update)
   void* C2;        // optional second output (same values, same layout as C)
+  int32_t lower_only;  // 1: square output; skip tiles lying entirely above the diagonal after the permutation
 };
 
 constexpr int kGemmVariants = 6;  // compiled tile shapes of the batched GEMM

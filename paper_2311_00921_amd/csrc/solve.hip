@@ -93,6 +93,42 @@ __device__ void row_gemv(const T* __restrict__ A, int64_t lda, int rows, int col
   }
 }
 
+// row_gemv with the columns split over NT / 256 groups of 256 threads (one
+// right-hand side, rows <= 512): a node's rows are too few to keep 1024
+// threads busy, so each group covers a slice of the columns and the partial
+// sums meet in LDS (red: (NT / 256) * 512 entries). Caller synchronizes after.
+template <int NT, typename T>
+__device__ void row_gemv_wide(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* u, int ldu, T* y,
+                              int ldy, int nc, T sign, T* red) {
+  constexpr int G = NT / 256;
+  if (G == 1 || nc != 1 || rows > 512) {
+    row_gemv<NT>(A, lda, rows, cols, u, ldu, y, ldy, nc, sign);
+    return;
+  }
+  const int g = threadIdx.x >> 8, tl = threadIdx.x & 255;
+  const int c0 = (g * cols) / G, c1 = ((g + 1) * cols) / G;
+  for (int i = tl; i < rows; i += 256) {
+    T acc = 0;
+    int j = c0;
+    for (; j + 8 <= c1; j += 8) {
+      T a[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) a[q] = A[i + (int64_t)(j + q) * lda];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc += a[q] * u[j + q];
+    }
+    for (; j < c1; ++j) acc += A[i + (int64_t)j * lda] * u[j];
+    red[g * 512 + i] = acc;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < rows; i += NT) {
+    T sum = 0;
+#pragma unroll
+    for (int q = 0; q < G; ++q) sum += red[q * 512 + i];
+    y[i] += sign * sum;
+  }
+}
+
 // Value of v held by lane l (l wave-uniform), through scalar registers.
 __device__ __forceinline__ double bcast_lane(double v, int l) {
   const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
@@ -201,6 +237,7 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(const NodeDesc* __restrict__ n
   __shared__ T st[128 * RC];
   __shared__ T su[128 * RC];
   __shared__ T tm[128 * RC];
+  __shared__ T red[(NT / 256) * 512];
   T* vp = vec + nd.offVec * nrhs;
   const T* F = Fb + nd.offF;
   const T* V = Vb + nd.offV;
@@ -213,14 +250,14 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(const NodeDesc* __restrict__ n
   // b^ = H^T b = b - V (Y^T b) with Y = V T kept by the factorization
   col_dots<NT>(Y, n, n, r, sb, n, st, r, nc);
   __syncthreads();
-  row_gemv<NT>(V, n, n, r, st, r, sb, n, nc, (T)-1);
+  row_gemv_wide<NT>(V, n, n, r, st, r, sb, n, nc, (T)-1, red);
   __syncthreads();
   // y_R = L_RR^{-1} b^_R  (b^_R = sb[r:n])
   if (use_inv) {
     const T* Li = Lib + offLi[p];
     for (int i = threadIdx.x; i < m * RC; i += NT) tm[i] = 0;
     __syncthreads();
-    row_gemv<NT>(Li, m, m, m, sb + r, n, tm, m, nc, (T)1);
+    row_gemv_wide<NT>(Li, m, m, m, sb + r, n, tm, m, nc, (T)1, red);
     __syncthreads();
     for (int i = threadIdx.x; i < m; i += NT)
       for (int c = 0; c < nc; ++c) sb[r + i + c * n] = tm[i + c * m];
@@ -229,7 +266,7 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(const NodeDesc* __restrict__ n
     lower_solve<NT>(F, n, m, sb + r, n, nc);
   }
   // z_S = b^_S - L_SR y_R   (L_SR = F[m:n, 0:m])
-  row_gemv<NT>(F + m, n, r, m, sb + r, n, sb, n, nc, (T)-1);
+  row_gemv_wide<NT>(F + m, n, r, m, sb + r, n, sb, n, nc, (T)-1, red);
   __syncthreads();
   for (int i = threadIdx.x; i < m; i += NT)
     for (int c = 0; c < nc; ++c) vp[i + (int64_t)(c0 + c) * n] = sb[r + i + c * n];
@@ -257,6 +294,7 @@ __global__ __launch_bounds__(NT) void k_solve_bwd(const NodeDesc* __restrict__ n
   __shared__ T su[128 * RC];
   __shared__ T scr[SNB * RC];
   __shared__ T tm[512 * RC];
+  __shared__ T red[(NT / 256) * 512];
   T* vp = vec + nd.offVec * nrhs;
   const T* F = Fb + nd.offF;
   const T* V = Vb + nd.offV;
@@ -292,7 +330,7 @@ __global__ __launch_bounds__(NT) void k_solve_bwd(const NodeDesc* __restrict__ n
   // x = H x^ = x^ - Y (V^T x^)
   col_dots<NT>(V, n, n, r, sx, n, st, r, nc);
   __syncthreads();
-  row_gemv<NT>(Y, n, n, r, st, r, sx, n, nc, (T)-1);
+  row_gemv_wide<NT>(Y, n, n, r, st, r, sx, n, nc, (T)-1, red);
   __syncthreads();
   for (int i = threadIdx.x; i < n; i += NT)
     for (int c = 0; c < nc; ++c) {
