@@ -28,35 +28,45 @@ HBM_PEAK_GBS = 8000.0
 
 
 def step_flops(step, n, r):
-    """Algorithmic flops of one node for the profiled step classes."""
+    """Algorithmic flops of one node for one profiled kernel launch class."""
     m = n - r
-    if step == "gemm_W=MV":
-        return 2.0 * n * n * r
-    if step == "gemm_two_sided_update":
-        return 4.0 * n * n * r
-    if step == "gemm_small_wy":
-        return 6.0 * n * r * r + 4.0 * r ** 3
-    if step == "partial_cholesky":
-        return m ** 3 / 3.0 + r * m * m + r * r * m
-    if step == "basis_qr":
-        return 2.0 * n * r * r - 2.0 / 3.0 * r ** 3
-    return 0.0
+    table = {
+        "gemm_W=MY": 2.0 * n * n * r,
+        "gemm_F_update": 2.0 * n * (n + 1) * r,  # lower triangle of M - Z V^T - V Z^T
+        "gemm_Y=VT": 2.0 * n * r * r,
+        "gemm_C=YtW": 2.0 * n * r * r,
+        "gemm_Z": 2.0 * n * r * r,
+        "gemm_V2": 2.0 * m * r * r,
+        "basis_top": 5.0 / 3.0 * r ** 3,  # LU of the top block, two triangular inverses, T
+        "pchol_RR": m ** 3 / 3.0,
+        "sr_schur": r * m * m + r * r * m,
+        "pchol": m ** 3 / 3.0 + r * m * m + r * r * m,
+        "chol_lds": 2.0 * m ** 3 / 3.0,  # Cholesky and explicit inverse
+        "gemm_LSR": 2.0 * r * m * m,
+        "gemm_Sigma": 2.0 * r * r * m,
+        "root": n ** 3 / 3.0,
+    }
+    return table.get(step, 0.0)
 
 
 def step_bytes(step, n, r):
     """Algorithmic HBM bytes of one node (each operand read once, result written once)."""
     m = n - r
-    if step == "gemm_W=MV":
-        return 8.0 * (n * n + 2 * n * r)
-    if step == "gemm_two_sided_update":
-        return 8.0 * (2 * n * n + 4 * n * r)
-    if step in ("solve_forward", "solve_backward"):
-        return 8.0 * (n * r + r * r + m * (m + 1) / 2 + r * m + 2 * n)
-    if step == "partial_cholesky":
+    if step == "merge":
         return 8.0 * 2 * n * n
+    if step in ("solve_forward", "solve_backward"):
+        return 8.0 * (2 * n * r + m * (m + 1) / 2 + r * m + 2 * n)
+    if step == "copy_lsr":
+        return 8.0 * 2 * r * m
     return 0.0
 
 
+# position of each GEMM label in a stage's list of GEMM batches (the library's plan order)
+GEMM_STEP_INDEX = {"gemm_V2": 0, "gemm_Y=VT": 2, "gemm_W=MY": 3, "gemm_C=YtW": 4, "gemm_Z": 5, "gemm_F_update": 6,
+                   "gemm_LSR": 7, "gemm_Sigma": 8}
+
+FACTOR_STEPS = ("gemm_W=MY", "gemm_F_update", "gemm_Y=VT", "gemm_C=YtW", "gemm_Z", "gemm_V2", "basis_top",
+                "pchol_RR", "sr_schur", "pchol", "chol_lds", "gemm_LSR", "gemm_Sigma", "root")
 
 
 def main():
@@ -68,6 +78,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched leg")
     ap.add_argument("--no-tune", action="store_true", help="skip autotuning and graph replay")
+    ap.add_argument("--save-tiles", default="", help="write the tuned GEMM tile choice to this JSON file")
+    ap.add_argument("--load-tiles", default="", help="use the GEMM tile choice saved in this JSON file")
+    ap.add_argument("--no-graph", action="store_true", help="time the tuned configuration with eager launches")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 + refinement leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-rank ablation leg")
     ap.add_argument("--learned-workload", default="matern32_n262144",
@@ -153,20 +166,53 @@ def main():
     relres = float(torch.linalg.norm(r) / torch.linalg.norm(b))
     logdet = hss.hss_logdet(ctx, m)
     info = hss.hss_get_info(m)
-    # per-launch events over a second timed region: the dominant kernel's average duration
+    # library's tuned mode: autotuned GEMM tiles (or a saved choice), factor and solve replayed from HIP graphs
+    tuned = None
+    t_best = t_fp64
+    tile_choice = None
+    if args.load_tiles:
+        with open(args.load_tiles) as f:
+            hss.hss_set_gemm_variants(ctx, m, json.load(f)["tile_choice"], hss.HSS_P_FP64)
+        rep = None
+    elif not args.no_tune:
+        print("# autotuning GEMM tiles (FP64)", file=sys.stderr, flush=True)
+        rep = hss.hss_autotune(ctx, m, hss.HSS_P_FP64, 2)
+    if args.load_tiles or not args.no_tune:
+        tile_choice = hss.hss_gemm_variants(m, hss.HSS_P_FP64)
+        if args.save_tiles:
+            with open(args.save_tiles, "w") as f:
+                json.dump({"workload": w.name, "tile_choice": tile_choice}, f)
+        hss.hss_use_graphs(ctx, m, not args.no_graph)
+        for _ in range(args.warmup):
+            run_fp64(1)
+        print("# timing FP64 factor+solve (tuned%s)" % ("" if args.no_graph else ", graph replay"), file=sys.stderr,
+              flush=True)
+        t_tuned, xg, _ = run_fp64(args.steps)
+        rg = b - hss.hss_matvec(ctx, m, xg)
+        relres_g = float(torch.linalg.norm(rg) / torch.linalg.norm(b))
+        tuned = {"factor_plus_solve_s": round(t_tuned, 6), "relres": relres_g,
+                 "rel_diff_x_vs_eager": float(torch.linalg.norm(xg - x) / torch.linalg.norm(x)),
+                 "gemm_ms_per_factor_by_tile": dict(zip(list(hss.GEMM_TILES) + ["tuned"], rep)) if rep else None,
+                 "tile_choice": tile_choice}
+        if relres_g <= 1e-8:
+            t_best = min(t_best, t_tuned)
+    # per-launch events over a further timed region of the same configuration (graphs are bypassed while
+    # profiling): the dominant kernel's average launch duration
     t_prof, _, prof = run_fp64(args.steps, profile=True)
     by_step = {}
     for (step, lvl), (cnt, ms) in prof.items():
         by_step.setdefault(step, 0.0)
         by_step[step] += ms
-    dom_key = max(prof.items(), key=lambda kv: kv[1][1])[0]
+    # the dominant kernel: the (kernel, level) with the largest summed event time; one launch per (kernel, level)
+    cands = {k: v for k, v in prof.items() if k[1] >= 0 and (k[0] in FACTOR_STEPS or step_bytes(k[0], 2, 1) > 0)}
+    dom_key = max(cands.items(), key=lambda kv: kv[1][1])[0]
     dom_step, dom_level = dom_key
     cnt, ms_total = prof[dom_key]
     avg_ms = ms_total / cnt
-    lvl_nodes = [nd for nd in nodes if nd[1] == dom_level]
+    lvl_nodes = [nd for nd in nodes if nd[1] == dom_level and (nd[3] > 0 or dom_step == "root")]
     flops = sum(step_flops(dom_step, n, rr) for _, _, n, rr in lvl_nodes)
     byts = sum(step_bytes(dom_step, n, rr) for _, _, n, rr in lvl_nodes)
-    if dom_step.startswith("gemm") or dom_step in ("partial_cholesky", "basis_qr"):
+    if dom_step in FACTOR_STEPS:
         ach = flops / (avg_ms * 1e-3) / 1e12
         roof = {"bound": "mfma", "achieved": round(ach, 3), "peak": MFMA_FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": round(ach / MFMA_FP64_PEAK_TFLOPS, 4), "traffic": None}
@@ -174,28 +220,14 @@ def main():
         ach = byts / (avg_ms * 1e-3) / 1e9
         roof = {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
-    roof.update({"kernel": f"{dom_step}@level{dom_level}", "avg_launch_ms": round(avg_ms, 4),
+    tile = None
+    if dom_step in GEMM_STEP_INDEX and tile_choice is not None:
+        tile = hss.GEMM_TILES[tile_choice[(L - dom_level) * 9 + GEMM_STEP_INDEX[dom_step]]]
+    elif dom_step in GEMM_STEP_INDEX:
+        tile = hss.GEMM_TILES[0]
+    roof.update({"kernel": f"{dom_step}@level{dom_level}", "tile": tile, "avg_launch_ms": round(avg_ms, 4),
                  "algorithmic_per_launch": flops if roof["unit"] == "TFLOP/s" else byts})
-    roof["traffic"] = measured_traffic(f"{dom_step}@level{dom_level}", w.name)
-    # library's tuned mode: autotuned GEMM tiles, factor and solve replayed from HIP graphs
-    tuned = None
-    t_best = t_fp64
-    if not args.no_tune:
-        print("# autotuning GEMM tiles (FP64)", file=sys.stderr, flush=True)
-        rep = hss.hss_autotune(ctx, m, hss.HSS_P_FP64, 2)
-        hss.hss_use_graphs(ctx, m, True)
-        for _ in range(args.warmup):
-            run_fp64(1)
-        print("# timing FP64 factor+solve (tuned, graph replay)", file=sys.stderr, flush=True)
-        t_tuned, xg, _ = run_fp64(args.steps)
-        rg = b - hss.hss_matvec(ctx, m, xg)
-        relres_g = float(torch.linalg.norm(rg) / torch.linalg.norm(b))
-        tuned = {"factor_plus_solve_s": round(t_tuned, 6), "relres": relres_g,
-                 "rel_diff_x_vs_eager": float(torch.linalg.norm(xg - x) / torch.linalg.norm(x)),
-                 "gemm_ms_per_factor_by_tile": dict(zip(list(hss.GEMM_TILES) + ["tuned"], rep)),
-                 "tile_choice": hss.hss_gemm_variants(m, hss.HSS_P_FP64)}
-        if relres_g <= 1e-8:
-            t_best = min(t_best, t_tuned)
+    roof["traffic"] = measured_traffic(f"{dom_step}@level{dom_level}", w.name, tile)
     # mixed form: FP32 factorization + refinement with the FP64 HSS matvec to rel. residual 1e-8
     mixed = None
     try:
@@ -225,8 +257,9 @@ def main():
     # leave the matrix factored in FP64 for anything after
     hss.hss_ulv_factor(ctx, m, hss.HSS_P_FP64)
     total_factor_flops = sum(step_flops(sname, n, rr) for _, l, n, rr in nodes if l > 0
-                             for sname in ("gemm_W=MV", "gemm_two_sided_update", "gemm_small_wy",
-                                           "partial_cholesky", "basis_qr"))
+                             for sname in ("gemm_W=MY", "gemm_F_update", "gemm_Y=VT", "gemm_C=YtW", "gemm_Z",
+                                           "gemm_V2", "basis_top", "pchol"))
+    total_factor_flops += sum(step_flops("root", n, 0) for _, l, n, rr in nodes if l == 0)
 
     use_mixed = bool(mixed and mixed.get("converged")) and mixed["factor_plus_refined_solve_s"] < t_best
     value = mixed["factor_plus_refined_solve_s"] if use_mixed else t_best
@@ -272,7 +305,7 @@ def main():
     print(json.dumps(result))
 
 
-def measured_traffic(label, workload):
+def measured_traffic(label, workload, tile):
     """HBM bytes per launch of the profiled kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counters), or
     None if there is none or the kernel's source changed since it was taken."""
@@ -293,7 +326,7 @@ def measured_traffic(label, workload):
             sha = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return None
-    if sha != ent["source_sha256"]:
+    if sha != ent["source_sha256"] or ent.get("tile") != tile:
         return None
     return ent["hbm_bytes_per_launch"]
 

@@ -320,6 +320,12 @@ hss_status hss_autotune(hss_ctx_t ctx, hss_matrix_t m, int32_t precision, int32_
  * h_out (nullable, up to capacity entries); *needed receives the count. */
 hss_status hss_gemm_variants(hss_matrix_t m, int32_t precision, int32_t* h_out, int64_t capacity, int64_t* needed);
 
+/* Sets the tile shape of every (stage, step) GEMM batch (the order of
+ * hss_gemm_variants; count must match), e.g. to replay a saved tuning.
+ * Drops recorded graphs. Synchronizes. */
+hss_status hss_set_gemm_variants(hss_ctx_t ctx, hss_matrix_t m, int32_t precision, const int32_t* h_variants,
+                                 int64_t count);
+
 /* ---- learned rank model -------------------------------------------------- */
 /* A multilayer perceptron 7 -> 128 -> 128 -> 128 -> 1 (ReLU between layers)
  * mapping the features of a tree node to y = log2(1 + rank) of the basis the

@@ -427,4 +427,24 @@ hss_status hss_gemm_variants(hss_matrix_t m, int32_t precision, int32_t* h_out, 
   HSS_API_END
 }
 
+hss_status hss_set_gemm_variants(hss_ctx_t ctx, hss_matrix_t m, int32_t precision, const int32_t* h_variants,
+                                 int64_t count) {
+  HSS_API_BEGIN
+  HSS_CHECK(ctx && m && h_variants, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  HSS_CHECK(precision == HSS_P_FP64 || precision == HSS_P_FP32, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
+  prepare_factor(m, precision);
+  auto& plan = precision == HSS_P_FP64 ? m->gemm_plan : m->gemm_plan32;
+  int64_t k = 0;
+  for (auto& st : plan) k += (int64_t)st.size();
+  HSS_CHECK(count == k, HSS_ERR_INVALID_ARGUMENT, "count must equal the number of GEMM batches");
+  for (int64_t i = 0; i < count; ++i)
+    HSS_CHECK(h_variants[i] >= 0 && h_variants[i] < kGemmVariants, HSS_ERR_INVALID_ARGUMENT, "unknown tile shape");
+  HSS_HIP(hipStreamSynchronize(ctx->stream));
+  drop_graphs(m);
+  k = 0;
+  for (auto& st : plan)
+    for (auto& g : st) g.variant = h_variants[k++];
+  HSS_API_END
+}
+
 }  // extern "C"

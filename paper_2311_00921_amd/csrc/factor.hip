@@ -1104,10 +1104,15 @@ static void launch_pchol(const hss_matrix_t m, int first, int count, int nmax, T
 // L_RR by the right-looking sweep restricted to the R block, then L_SR and
 // Sigma from LDS.
 template <typename T>
-static void launch_pchol_split(const hss_matrix_t m, int first, int count, T* F, hipStream_t s) {
-  hipLaunchKernelGGL((k_pchol<T, 256, false, 256, true>), dim3(count), dim3(256), 0, s, m->dnodes, first, F,
-                     m->dinfo, m->dlogdet);
-  HSS_HIP(hipGetLastError());
+static void launch_pchol_split(const hss_matrix_t m, int first, int count, T* F, hipStream_t s, hss_ctx_t cx,
+                               int level) {
+  {
+    Prof pf(cx, "pchol_RR", level);
+    hipLaunchKernelGGL((k_pchol<T, 256, false, 256, true>), dim3(count), dim3(256), 0, s, m->dnodes, first, F,
+                       m->dinfo, m->dlogdet);
+    HSS_HIP(hipGetLastError());
+  }
+  Prof pf(cx, "sr_schur", level);
   hipLaunchKernelGGL((k_sr_schur<T, 96, 160>), dim3(count), dim3(512), 0, s, m->dnodes, first, F);
   HSS_HIP(hipGetLastError());
 }
@@ -1397,11 +1402,15 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
     }
     auto& st = plan[si];
     if (lp.rmax > 0 && !basis_done) {
-      Prof pf(cx, "basis_qr", l);
       if (lp.rmax <= 96) {
-        launch_basis_top<T>(lp.rmax, lp.first, lp.count, m->dnodes, b, s);
+        {
+          Prof pf(cx, "basis_top", l);
+          launch_basis_top<T>(lp.rmax, lp.first, lp.count, m->dnodes, b, s);
+        }
+        Prof pf(cx, "gemm_V2", l);
         gemm_run<T>(st[0], false, false, 1.0, 0.0, s);    // V_2 = B_2 U_1^{-1}
       } else {
+        Prof pf(cx, "basis_qr", l);
         launch_lu_top<T>(m, lp, b.B, b.V, b.Tm, b.Sg, s);   // V_1, U_1 (in the T slot), Sg
         launch_tri_inv<T>(m, lp, b.Tm, 0, b.X, 2, 0, s);    // U_1^{-1} -> second half of X
         gemm_run<T>(st[0], false, false, 1.0, 0.0, s);      // V_2 = B_2 U_1^{-1}
@@ -1410,21 +1419,24 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
       }
     }
     if (!basis_done) {
-      Prof pf(cx, "gemm_small_wy", l);
+      Prof pf(cx, "gemm_Y=VT", l);
       gemm_run<T>(st[2], false, false, 1.0, 0.0, s);      // Y = V T
     }
     if (hoist && si == 0) fork_upper_basis();
     {
-      Prof pf(cx, "gemm_W=MV", l);
+      Prof pf(cx, "gemm_W=MY", l);
       gemm_run<T>(st[3], false, false, 1.0, 0.0, s);      // W = M Y
     }
     {
-      Prof pf(cx, "gemm_small_wy", l);
+      Prof pf(cx, "gemm_C=YtW", l);
       gemm_run<T>(st[4], true, false, 1.0, 0.0, s);       // C = Y^T W
+    }
+    {
+      Prof pf(cx, "gemm_Z", l);
       gemm_run<T>(st[5], false, false, -0.5, 1.0, s);     // Z = W - V C / 2 (both copies)
     }
     {
-      Prof pf(cx, "gemm_two_sided_update", l);
+      Prof pf(cx, "gemm_F_update", l);
       gemm_run<T>(st[6], false, true, -1.0, 1.0, s);      // F = P^T (M - Z V^T - V Z^T) P
     }
     // With FP32 compute a stage that holds roots is factored by the blocked
@@ -1432,22 +1444,31 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
     const bool use_inv = lp.inv && !(fp32 && nonroot < lp.count);
     (fp32 ? m->inv_used32 : m->inv_used64)[si] = use_inv ? 1 : 0;
     {
-      Prof pf(cx, nonroot == 0 ? "root" : "partial_cholesky", l);
       if (use_inv) {
         const int mm = lp.mmax;
         dim3 grid(lp.count), block(256);
-        if (mm <= 32)
-          hipLaunchKernelGGL((k_chol_lds<T, 32>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet);
-        else if (mm <= 64)
-          hipLaunchKernelGGL((k_chol_lds<T, 64>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet);
-        else
-          hipLaunchKernelGGL((k_chol_lds<T, 96>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet);
-        HSS_HIP(hipGetLastError());
-        gemm_run<T>(st[7], false, true, 1.0, 0.0, s);
-        gemm_run<T>(st[8], false, true, -1.0, 1.0, s);
+        {
+          Prof pf(cx, nonroot == 0 ? "root" : "chol_lds", l);
+          if (mm <= 32)
+            hipLaunchKernelGGL((k_chol_lds<T, 32>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
+                               (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet);
+          else if (mm <= 64)
+            hipLaunchKernelGGL((k_chol_lds<T, 64>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
+                               (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet);
+          else
+            hipLaunchKernelGGL((k_chol_lds<T, 96>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
+                               (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet);
+          HSS_HIP(hipGetLastError());
+        }
+        {
+          Prof pf(cx, "gemm_LSR", l);
+          gemm_run<T>(st[7], false, true, 1.0, 0.0, s);  // L_SR = F_SR L_RR^{-T}
+        }
+        {
+          Prof pf(cx, "gemm_Sigma", l);
+          gemm_run<T>(st[8], false, true, -1.0, 1.0, s);  // Sigma = F_SS - L_SR L_SR^T
+        }
+        Prof pf(cx, "copy_lsr", l);
         hipLaunchKernelGGL((k_copy_lsr<T>), dim3(16, lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const T*)b.S2,
                            (const int64_t*)m->dOffS2, b.F);
         HSS_HIP(hipGetLastError());
@@ -1458,11 +1479,14 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
           mmax_nr = std::max(mmax_nr, m->nodes[k].m);
           nmax_nr = std::max(nmax_nr, m->nodes[k].n);
         }
-        if (nonroot > 0 && rmax_nr <= 96 && mmax_nr <= 160 && nmax_nr <= 256)
-          launch_pchol_split<T>(m, lp.first, nonroot, b.F, s);
-        else if (nonroot > 0)
+        if (nonroot > 0 && rmax_nr <= 96 && mmax_nr <= 160 && nmax_nr <= 256) {
+          launch_pchol_split<T>(m, lp.first, nonroot, b.F, s, cx, l);
+        } else if (nonroot > 0) {
+          Prof pf(cx, "pchol", l);
           launch_pchol<T>(m, lp.first, nonroot, lp.nmax, b.F, s);
+        }
         if (nonroot < lp.count) {
+          Prof pf(cx, "root", l);
           if (fp32)
             root_cholesky_fp64<T>(m, lp, b.F, s);
           else

@@ -33,6 +33,9 @@ __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
+// Row padding of the LDS tiles (one element; measured best among 1 and 16).
+constexpr int LPAD = 1;
+
 // tile variants: {BM, BN, BK}; the deep-K ones (BK 32 and 64) halve or quarter
 // the number of dependent global-load rounds, which is what bounds the small
 // GEMMs of the stages with few nodes
@@ -89,7 +92,7 @@ __device__ __forceinline__ void load_tiles(const GemmDesc& d, const T* __restric
 }
 
 template <typename T, bool TA, bool TB, int BM, int BN, int BK>
-__device__ __forceinline__ void store_tiles(T (&As)[BK][BM + 1], T (&Bs)[BK][BN + 1], const T (&ra)[BM * BK / 256],
+__device__ __forceinline__ void store_tiles(T (&As)[BK][BM + LPAD], T (&Bs)[BK][BN + LPAD], const T (&ra)[BM * BK / 256],
                                             const T (&rb)[BN * BK / 256]) {
   const int tid = threadIdx.x;
 #pragma unroll
@@ -110,15 +113,31 @@ __device__ __forceinline__ void store_tiles(T (&As)[BK][BM + 1], T (&Bs)[BK][BN 
   }
 }
 
+// Workgroups are dealt to the 8 XCDs round-robin by linear id, and each XCD
+// has its own L2. The logical (tile, entry) of a workgroup is chosen so that
+// consecutive workgroups of one XCD take consecutive tiles of the same batch
+// entry: the panels that the tiles of an entry share are then read from that
+// XCD's L2 instead of once per tile from HBM.
+__device__ __forceinline__ void xcd_tile(int& tile, int& entry) {
+  const int gx = gridDim.x;
+  const int total = gx * gridDim.y;
+  const int lin = blockIdx.x + blockIdx.y * gx;
+  const int q = (total % 8 == 0) ? (lin % 8) * (total / 8) + lin / 8 : lin;
+  tile = q % gx;
+  entry = q / gx;
+}
+
 template <typename T, bool TA, bool TB, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs, T alpha, T beta) {
   constexpr int IM = BM / 32, JN = BN / 32;  // 16x16 accumulators per wave
-  const GemmDesc d = descs[blockIdx.y];
+  int tile, entry;
+  xcd_tile(tile, entry);
+  const GemmDesc d = descs[entry];
   const int tilesM = (d.m + BM - 1) / BM;
   const int tilesN = (d.n + BN - 1) / BN;
-  if ((int)blockIdx.x >= tilesM * tilesN) return;
-  const int row0 = (blockIdx.x % tilesM) * BM;
-  const int col0 = (blockIdx.x / tilesM) * BN;
+  if (tile >= tilesM * tilesN) return;
+  const int row0 = (tile % tilesM) * BM;
+  const int col0 = (tile / tilesM) * BN;
   if (d.lower_only) {
     // output position of index t is t + (dim - r) for t < r, t - r otherwise (r = perm_r, square)
     const int r = d.perm_r, mm = d.m - r;
@@ -129,8 +148,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
     const int minp = (c1 >= r) ? max(col0, r) - r : col0 + mm;
     if (maxp < minp) return;  // every element of the tile lies strictly above the diagonal
   }
-  __shared__ T As[BK][BM + 1];
-  __shared__ T Bs[BK][BN + 1];
+  __shared__ T As[BK][BM + LPAD];
+  __shared__ T Bs[BK][BN + LPAD];
   const T* __restrict__ A = (const T*)d.A;
   const T* __restrict__ B = (const T*)d.B;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;

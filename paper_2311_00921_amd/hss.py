@@ -132,6 +132,7 @@ SIGNATURES = {
                                    C.POINTER(C.c_float)]),
     "hss_rankmlp_train": (C.c_int, [_P, _P, _P, _P, C.c_int64, _P, C.c_int64, C.POINTER(hss_train_opts),
                                     C.POINTER(C.c_float)]),
+    "hss_set_gemm_variants": (C.c_int, [_P, _P, C.c_int32, C.POINTER(C.c_int32), C.c_int64]),
     "hss_matrix_destroy": (C.c_int, [_P]),
     "hss_status_string": (C.c_char_p, [C.c_int]),
     "hss_last_error": (C.c_char_p, []),
@@ -491,6 +492,11 @@ def hss_gemm_variants(m, precision: int = HSS_P_FP64):
     buf = (C.c_int32 * max(1, need.value))()
     _check(lib.hss_gemm_variants(m, precision, buf, need.value, C.byref(need)), "hss_gemm_variants")
     return list(buf[:need.value])
+
+
+def hss_set_gemm_variants(ctx, m, variants, precision: int = HSS_P_FP64):
+    arr = (C.c_int32 * len(variants))(*variants)
+    _check(load().hss_set_gemm_variants(ctx, m, precision, arr, len(variants)), "hss_set_gemm_variants")
 
 
 def hss_get_construct_stats(m) -> hss_construct_stats:
