@@ -601,7 +601,7 @@ constexpr int PNB = 16;
 // the sweep to the leading m x m block (L_RR); k_sr_schur then forms L_SR and
 // Sigma without re-reading the S rows once per panel.
 template <typename T, int NMAX, bool CONSTRUCT = false, int NT = 256, bool RR_ONLY = false>
-__global__ __launch_bounds__(NT) void k_pchol(const NodeDesc* __restrict__ nodes, int first,
+__global__ __launch_bounds__(NT, 1024 / NT) void k_pchol(const NodeDesc* __restrict__ nodes, int first,
                                                T* __restrict__ Fbase, int32_t* __restrict__ info,
                                                double* __restrict__ logdet) {
   const int node = first + blockIdx.x;

@@ -222,7 +222,7 @@ __device__ void lower_t_solve(const T* __restrict__ F, int ldf, int m, T* x, int
 }
 
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_solve_fwd(const NodeDesc* __restrict__ nodes, int first,
+__global__ __launch_bounds__(NT, 1024 / NT) void k_solve_fwd(const NodeDesc* __restrict__ nodes, int first,
                                                   const T* __restrict__ Fb, const T* __restrict__ Vb,
                                                   const T* __restrict__ Yb, const T* __restrict__ Sgb,
                                                   T* __restrict__ vec, int64_t nrhs, int c0, int nc,
@@ -278,7 +278,7 @@ __global__ __launch_bounds__(NT) void k_solve_fwd(const NodeDesc* __restrict__ n
 }
 
 template <typename T, int NT>
-__global__ __launch_bounds__(NT) void k_solve_bwd(const NodeDesc* __restrict__ nodes, int first,
+__global__ __launch_bounds__(NT, 1024 / NT) void k_solve_bwd(const NodeDesc* __restrict__ nodes, int first,
                                                   const T* __restrict__ Fb, const T* __restrict__ Vb,
                                                   const T* __restrict__ Yb, const T* __restrict__ Sgb,
                                                   T* __restrict__ vec, int64_t nrhs, int c0, int nc,
