@@ -39,9 +39,10 @@ constexpr int LPAD = 1;
 // tile variants: {BM, BN, BK}; the deep-K ones (BK 32 and 64) halve or quarter
 // the number of dependent global-load rounds, which is what bounds the small
 // GEMMs of the stages with few nodes
-constexpr int kTileM[kGemmVariants] = {64, 32, 128, 64, 32, 64};
-constexpr int kTileN[kGemmVariants] = {64, 32, 64, 128, 32, 64};
-constexpr int kTileK[kGemmVariants] = {16, 16, 16, 16, 64, 32};
+// 64x96 and 96x96 fit the r = 96 panels of the workloads without ragged tiles
+constexpr int kTileM[kGemmVariants] = {64, 32, 128, 64, 32, 64, 64, 96};
+constexpr int kTileN[kGemmVariants] = {64, 32, 64, 128, 32, 64, 96, 96};
+constexpr int kTileK[kGemmVariants] = {16, 16, 16, 16, 64, 32, 16, 16};
 
 // Row of the 16x16 MFMA output held by lane `lane` in accumulator slot v.
 // FP64 16x16x4 interleaves rows across slots; FP32 16x16x4 stacks them.
@@ -281,6 +282,8 @@ static void launch(const GemmBatch& b, bool ta, bool tb, T alpha, T beta, hipStr
     case 3: HSS_TILE(3); break;
     case 4: HSS_TILE(4); break;
     case 5: HSS_TILE(5); break;
+    case 6: HSS_TILE(6); break;
+    case 7: HSS_TILE(7); break;
     default: HSS_TILE(0); break;
   }
 #undef HSS_TILE

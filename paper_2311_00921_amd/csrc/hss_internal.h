@@ -92,7 +92,7 @@ struct GemmDesc {
   int32_t lower_only;  // 1: square output; skip tiles lying entirely above the diagonal after the permutation
 };
 
-constexpr int kGemmVariants = 6;  // compiled tile shapes of the batched GEMM
+constexpr int kGemmVariants = 8;  // compiled tile shapes of the batched GEMM
 
 struct GemmBatch {
   std::vector<GemmDesc> host;

@@ -474,7 +474,7 @@ def hss_use_graphs(ctx, m, on: bool):
     _check(load().hss_use_graphs(ctx, m, 1 if on else 0), "hss_use_graphs")
 
 
-GEMM_TILES = ("64x64x16", "32x32x16", "128x64x16", "64x128x16", "32x32x64", "64x64x32")
+GEMM_TILES = ("64x64x16", "32x32x16", "128x64x16", "64x128x16", "32x32x64", "64x64x32", "64x96x16", "96x96x16")
 
 
 def hss_autotune(ctx, m, precision: int = HSS_P_FP64, reps: int = 2):
