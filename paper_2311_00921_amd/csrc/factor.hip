@@ -551,12 +551,18 @@ __global__ __launch_bounds__(256) void k_merge(const NodeDesc* __restrict__ node
 // 16-column panels; the trailing lower triangle is updated with MFMA tiles.
 // ---------------------------------------------------------------------------
 
-// Cholesky of a 16 x 16 pivot block held by one wave: lane i < jb owns row i
-// (a[0..i]). Pivots and columns of L move between lanes through scalar
-// registers; the square root and its reciprocal come from rsqrt_nr. Returns the
-// first non-positive pivot (or -1), the sum of log pivots over the wave (in
-// lsum, every lane) and, on lane i, 1 / L_ii (in rdiag). Call from one full wave.
-__device__ __forceinline__ int pivot_block_chol(double (&a)[16], int jb, double& lsum, double& rdiag) {
+// Cholesky of a 16-column panel on one wave. Lanes 0..15 hold rows 0..15 of
+// the 16 x 16 pivot block (a[c], c <= lane); lanes 16..63 may hold further
+// rows of the panel below it. Step k scales column k by the reciprocal square
+// root of the pivot (read from lane k through scalar registers) and updates
+// the later columns with L[c][k] read from lane c. On the rows below the pivot
+// block these are exactly the steps of the triangular solve with L^T, so the
+// whole panel is finished in one chain. Entries above the diagonal of the
+// pivot block are left undefined (callers keep c <= lane only). Only steps
+// k < jb run (jb wave-uniform). Returns the first non-positive pivot (or -1),
+// the sum of the log pivots over the wave (in lsum, every lane) and, on lane
+// i < 16, 1 / L_ii (in rdiag). Call from one full wave.
+__device__ __forceinline__ int panel_chol16(double (&a)[16], int jb, double& lsum, double& rdiag) {
   const int lane = threadIdx.x & 63;
   int bad = -1;
   double mine = 1.0;  // this lane's pivot; the logs are taken in parallel after the chain
@@ -570,20 +576,14 @@ __device__ __forceinline__ int pivot_block_chol(double (&a)[16], int jb, double&
         x = 1.0;
       }
       const double rs = rsqrt_nr(x);
-      if (lane == k) {
-        a[k] = x * rs;
-        mine = a[k];
-        rdiag = rs;
-      } else if (lane > k) {
-        a[k] *= rs;
-      }
+      const double piv = x * rs;
+      const bool me = lane == k;
+      a[k] = me ? piv : a[k] * rs;
+      mine = me ? piv : mine;
+      rdiag = me ? rs : rdiag;
 #pragma unroll
-      for (int c = k + 1; c < 16; ++c) {
-        if (c < jb) {
-          const double lc = bcast_lane(a[k], c);  // L[c][k]
-          if (lane >= c) a[c] -= a[k] * lc;
-        }
-      }
+      for (int c = k + 1; c < 16; ++c)
+        if (c < jb) a[c] -= a[k] * bcast_lane(a[k], c);  // L[c][k] from lane c
     }
   }
   double lg = (lane < jb) ? log(mine) : 0.0;
@@ -621,14 +621,16 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_pchol(const NodeDesc* __restr
   __syncthreads();
   for (int j0 = 0; j0 < m; j0 += PNB) {
     const int jb = min(PNB, m - j0);
-    // (1) pivot block: lane i < jb of wave 0 holds row j0+i, factored with shuffles
+    // (1) pivot block: lane i < jb of wave 0 holds row j0+i (many workgroups share
+    // a compute unit here, so the rows below are solved from LDS by all threads
+    // rather than on more register chains)
     if (wid == 0) {
       double a[PNB];
 #pragma unroll
       for (int c = 0; c < PNB; ++c)
         a[c] = (lane < jb && c <= lane) ? (double)F[(j0 + lane) + (int64_t)(j0 + c) * n] : 0.0;
       double lsum = 0.0, rd = 1.0;
-      const int bad = pivot_block_chol(a, jb, lsum, rd);
+      const int bad = panel_chol16(a, jb, lsum, rd);
       if (lane < PNB) Rd[lane] = rd;
 #pragma unroll
       for (int c = 0; c < PNB; ++c) {
@@ -742,6 +744,7 @@ __global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ n
                                                   T* __restrict__ Fbase) {
   constexpr int NT = 512, NW = NT / 64;
   constexpr int RT = RMAX / 16;  // row tiles of L_SR
+  static_assert(RMAX <= 2 * 64 && RMAX % 16 == 0 && MMAX % 16 == 0, "rows of L_SR on two waves, 16-wide tiles");
   const NodeDesc nd = nodes[first + blockIdx.x];
   const int n = nd.n, r = nd.r, m = nd.m;
   if (r == 0) return;
@@ -750,9 +753,9 @@ __global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ n
   __shared__ T Lb[16][MMAX + 1];   // L_RR[j0:j0+16, 0:j0+16] of the current step
   __shared__ double rd[16];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  // X = F_SR (rows m..n-1, columns 0..m-1), zero outside
+  // X = F_SR (rows m..n-1, columns 0..m-1), zero outside; 15 loads in flight per thread
   {
-    constexpr int TOT = RMAX * MMAX, PER = (TOT + NT - 1) / NT, SB = 8;
+    constexpr int TOT = RMAX * MMAX, PER = (TOT + NT - 1) / NT, SB = 15;
 #pragma unroll 1
     for (int q0 = 0; q0 < PER; q0 += SB) {
       T v[SB];
@@ -760,12 +763,12 @@ __global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ n
       for (int u = 0; u < SB; ++u) {
         const int e = (q0 + u) * NT + tid;
         const int i = e % RMAX, c = e / RMAX;
-        v[u] = (e < TOT && i < r && c < m) ? F[(m + i) + (int64_t)c * n] : (T)0;
+        v[u] = (q0 + u < PER && e < TOT && i < r && c < m) ? F[(m + i) + (int64_t)c * n] : (T)0;
       }
 #pragma unroll
       for (int u = 0; u < SB; ++u) {
         const int e = (q0 + u) * NT + tid;
-        if (e < TOT) X[e % RMAX][e / RMAX] = v[u];
+        if (q0 + u < PER && e < TOT) X[e % RMAX][e / RMAX] = v[u];
       }
     }
   }
@@ -792,43 +795,56 @@ __global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ n
     }
     __syncthreads();
     if (tid < 16) rd[tid] = 1.0 / (double)Lb[tid][j0 + tid];
-    // X[:, j0:j0+16] -= X[:, 0:j0] L_RR[j0:j0+16, 0:j0]^T
+    // X[:, j0:j0+16] -= X[:, 0:j0] L_RR[j0:j0+16, 0:j0]^T, four MFMA steps per
+    // iteration so that their LDS reads are in flight together
     if (j0 > 0) {
       for (int rt = wid; rt < RT; rt += NW) {
         typename Acc4<T>::type acc;
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] = 0;
-        for (int k0 = 0; k0 < j0; k0 += 4) {
-          const int k = k0 + (lane >> 4);
-          acc = mfma16x(X[rt * 16 + (lane & 15)][k], Lb[lane & 15][k], acc);
+        for (int k0 = 0; k0 < j0; k0 += 16) {
+#pragma unroll
+          for (int u = 0; u < 16; u += 4) {
+            const int k = k0 + u + (lane >> 4);
+            acc = mfma16x(X[rt * 16 + (lane & 15)][k], Lb[lane & 15][k], acc);
+          }
         }
 #pragma unroll
         for (int v = 0; v < 4; ++v) X[rt * 16 + mfma_out_row((T)0, lane, v)][j0 + (lane & 15)] -= acc[v];
       }
     }
     __syncthreads();
-    // X[i, j0:j0+16] = X[i, j0:j0+16] L_jj^{-T}: forward substitution per row
-    for (int i = tid; i < r; i += NT) {
-      double x[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) x[c] = (c < jb) ? (double)X[i][j0 + c] : 0.0;
+    // X[i, j0:j0+16] = X[i, j0:j0+16] L_jj^{-T}: forward substitution with row i
+    // on lane i % 64 of wave i / 64 and row q of L_jj on lane q, read through
+    // scalar registers
+    if (wid * 64 < r) {
+      const int i = wid * 64 + lane;
+      const bool own = i < r;
+      double l[16], x[16];
 #pragma unroll
       for (int c = 0; c < 16; ++c) {
-        double acc = x[c];
-#pragma unroll
-        for (int k = 0; k < c; ++k) acc -= x[k] * (double)Lb[c][j0 + k];
-        x[c] = acc * rd[c];
+        l[c] = (lane < 16) ? (double)Lb[lane][j0 + c] : 0.0;
+        x[c] = (own && c < jb) ? (double)X[own ? i : 0][j0 + c] : 0.0;
       }
+      const double rl = (lane < 16) ? rd[lane] : 1.0;
 #pragma unroll
-      for (int c = 0; c < 16; ++c)
-        if (c < jb) X[i][j0 + c] = (T)x[c];
+      for (int k = 0; k < 16; ++k) {
+        x[k] *= bcast_lane(rl, k);
+#pragma unroll
+        for (int c = k + 1; c < 16; ++c) x[c] -= x[k] * bcast_lane(l[k], c);
+      }
+      if (own)
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c < jb) X[i][j0 + c] = (T)x[c];
     }
     __syncthreads();
   }
-  // L_SR back to F
-  for (int e = tid; e < r * m; e += NT) {
-    const int i = e % r, c = e / r;
-    F[(m + i) + (int64_t)c * n] = X[i][c];
+  // L_SR back to F: thread t writes row t % RMAX of columns t / RMAX, t / RMAX + NT / RMAX, ...
+  if (tid < (NT / RMAX) * RMAX) {
+    const int i = tid % RMAX;
+    if (i < r)
+      for (int c = tid / RMAX; c < m; c += NT / RMAX) F[(m + i) + (int64_t)c * n] = X[i][c];
   }
   // Sigma = F_SS - L_SR L_SR^T, lower tiles
   for (int t = wid; t < RT * (RT + 1) / 2; t += NW) {
@@ -839,9 +855,13 @@ __global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ n
     typename Acc4<T>::type acc;
 #pragma unroll
     for (int v = 0; v < 4; ++v) acc[v] = 0;
-    for (int k0 = 0; k0 < m; k0 += 4) {
-      const int k = k0 + (lane >> 4);
-      acc = mfma16x(X[I * 16 + (lane & 15)][k], X[J * 16 + (lane & 15)][k], acc);
+    // columns m..MMAX-1 of X are zero, so the K loop may run to a multiple of 16
+    for (int k0 = 0; k0 < m; k0 += 16) {
+#pragma unroll
+      for (int u = 0; u < 16; u += 4) {
+        const int k = k0 + u + (lane >> 4);
+        acc = mfma16x(X[I * 16 + (lane & 15)][k], X[J * 16 + (lane & 15)][k], acc);
+      }
     }
     T cur[4];
 #pragma unroll
@@ -859,8 +879,9 @@ __global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ n
 
 // ---------------------------------------------------------------------------
 // partial Cholesky of a level whose redundant blocks are small (m <= RM <= 96):
-// L_RR = chol(F_RR) entirely in LDS (16-column panels, pivot blocks in FP64 by
-// one wave, trailing updates on the matrix cores from LDS), and the explicit
+// L_RR = chol(F_RR) entirely in LDS (16-column panels factored in registers,
+// pivot block and the rows below it in one chain, trailing updates on the
+// matrix cores from LDS), and the explicit
 // inverse L_RR^{-1} (blocked, bottom-up MFMA recurrence). L_RR goes back to F,
 // L_RR^{-1} to Li (m x m, lower). L_SR and Sigma follow by batched GEMMs.
 // ---------------------------------------------------------------------------
@@ -891,40 +912,41 @@ __global__ __launch_bounds__(256) void k_chol_lds(const NodeDesc* __restrict__ n
   __syncthreads();
   for (int J = 0; J < NB; ++J) {
     const int j0 = J * 16;
-    if (wid == 0) {
-      double a[16];
+    // panel: the pivot block on lanes 0..15 of each wave taking part, the rows
+    // below it on lanes 16..63 (48 per wave); wave 0 keeps L of the pivot block
+    // in registers until every wave has read the block
+    double dk[16];
+    {
+      constexpr int kMaxBelow = 48 * 4;
+      static_assert(RM - 16 <= kMaxBelow, "panel rows exceed the waves");
+      const int below = RM - j0 - 16;
+      const int nwp = below > 0 ? (below + 47) / 48 : 1;
+      if (wid < nwp) {
+        const int prow = lane < 16 ? j0 + lane : j0 + 16 + 48 * wid + (lane - 16);
+        const bool valid = prow < RM;
+        double a[16];
 #pragma unroll
-      for (int c = 0; c < 16; ++c) a[c] = (lane < 16 && c <= lane) ? X[j0 + lane][j0 + c] : 0.0;
-      double lsum = 0.0, rd = 1.0;
-      const int jbl = m - j0 >= 16 ? 16 : (m - j0 > 0 ? m - j0 : 0);
-      int bad = pivot_block_chol(a, 16, lsum, rd);
-      if (bad >= jbl) bad = -1;
-      if (lane < 16) rdg[j0 + lane] = rd;
-      if (lane < 16)
+        for (int c = 0; c < 16; ++c) a[c] = valid ? X[valid ? prow : 0][j0 + c] : 0.0;
+        double lsum = 0.0, rd = 1.0;
+        const int jbl = m - j0 >= 16 ? 16 : (m - j0 > 0 ? m - j0 : 0);
+        int bad = panel_chol16(a, 16, lsum, rd);
+        if (bad >= jbl) bad = -1;
+        if (lane >= 16 && valid)
 #pragma unroll
-        for (int c = 0; c < 16; ++c) X[j0 + lane][j0 + c] = (c <= lane) ? a[c] : 0.0;
-      if (lane == 0) {
-        lacc += lsum;
-        if (bad >= 0 && fail < 0) fail = j0 + bad;
+          for (int c = 0; c < 16; ++c) X[prow][j0 + c] = a[c];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) dk[c] = a[c];
+        if (wid == 0 && lane < 16) rdg[j0 + lane] = rd;
+        if (wid == 0 && lane == 0) {
+          lacc += lsum;
+          if (bad >= 0 && fail < 0) fail = j0 + bad;
+        }
       }
     }
     __syncthreads();
-    // panel rows below the pivot block
-    for (int i = j0 + 16 + tid; i < RM; i += 256) {
-      double x[16];
+    if (wid == 0 && lane < 16)
 #pragma unroll
-      for (int c = 0; c < 16; ++c) x[c] = X[i][j0 + c];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        double acc = x[c];
-#pragma unroll
-        for (int k = 0; k < c; ++k) acc -= x[k] * X[j0 + c][j0 + k];
-        x[c] = acc * rdg[j0 + c];
-      }
-#pragma unroll
-      for (int c = 0; c < 16; ++c) X[i][j0 + c] = x[c];
-    }
-    __syncthreads();
+      for (int c = 0; c < 16; ++c) X[j0 + lane][j0 + c] = (c <= lane) ? dk[c] : 0.0;
     // trailing update: tiles (I2 >= J2 > J) -= P_I2 P_J2^T with P = X[:, j0:j0+16]
     const int rem = NB - J - 1;
     const int ntl = rem * (rem + 1) / 2;
