@@ -73,11 +73,11 @@ __device__ __forceinline__ double rcp_nr(double x) {
 // A, the others are 1 on the diagonal and 0 elsewhere. Each thread keeps SB
 // loads in flight before writing them to LDS, so that a lone workgroup is not
 // bound by one global-memory latency per element it loads.
-template <int RM, typename T>
+template <int RM, int NT = 256, typename T>
 __device__ __forceinline__ void stage_frame(double (*X)[RM + 1], const T* __restrict__ A, int64_t ld, int rows,
                                             int cols, bool lower_only) {
   constexpr int TOT = RM * RM;
-  constexpr int PER = (TOT + 255) / 256;
+  constexpr int PER = (TOT + NT - 1) / NT;
   constexpr int SB = 12;
   const int tid = threadIdx.x;
 #pragma unroll 1
@@ -85,14 +85,14 @@ __device__ __forceinline__ void stage_frame(double (*X)[RM + 1], const T* __rest
     double v[SB];
 #pragma unroll
     for (int u = 0; u < SB; ++u) {
-      const int e = (q0 + u) * 256 + tid;
+      const int e = (q0 + u) * NT + tid;
       const int i = e % RM, c = e / RM;
       const bool in = e < TOT && i < rows && c < cols && (!lower_only || i >= c);
       v[u] = in ? (double)A[i + (int64_t)c * ld] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < SB; ++u) {
-      const int e = (q0 + u) * 256 + tid;
+      const int e = (q0 + u) * NT + tid;
       const int i = e % RM, c = e / RM;
       if (e < TOT) X[i][c] = (i < rows && c < cols) ? v[u] : (i == c ? 1.0 : 0.0);
     }
@@ -883,15 +883,17 @@ __global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ n
 // pivot block and the rows below it in one chain, trailing updates on the
 // matrix cores from LDS), and the explicit
 // inverse L_RR^{-1} (blocked, bottom-up MFMA recurrence). L_RR goes back to F,
-// L_RR^{-1} to Li (m x m, lower). L_SR and Sigma follow by batched GEMMs.
+// L_RR^{-1} to Li (m x m, lower). With FUSE (r <= RM) the kernel goes on to
+// L_SR = F_SR L_RR^{-T} and Sigma = F_SS - L_SR L_SR^T from LDS; otherwise
+// batched GEMMs follow.
 // ---------------------------------------------------------------------------
 
-template <typename T, int RM>
-__global__ __launch_bounds__(256) void k_chol_lds(const NodeDesc* __restrict__ nodes, int first,
+template <typename T, int RM, bool FUSE, int NT = 512>
+__global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ nodes, int first,
                                                   T* __restrict__ Fbase, T* __restrict__ Libase,
                                                   const int64_t* __restrict__ offLi, int32_t* __restrict__ info,
                                                   double* __restrict__ logdet) {
-  constexpr int NB = RM / 16;
+  constexpr int NB = RM / 16, NW = NT / 64;
   const int node = first + blockIdx.x;
   const NodeDesc nd = nodes[node];
   const int n = nd.n, m = nd.m;
@@ -904,7 +906,7 @@ __global__ __launch_bounds__(256) void k_chol_lds(const NodeDesc* __restrict__ n
   __shared__ int fail;
   __shared__ double lacc;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  stage_frame<RM>(X, F, n, m, m, true);
+  stage_frame<RM, NT>(X, F, n, m, m, true);
   if (tid == 0) {
     fail = -1;
     lacc = 0.0;
@@ -917,7 +919,7 @@ __global__ __launch_bounds__(256) void k_chol_lds(const NodeDesc* __restrict__ n
     // in registers until every wave has read the block
     double dk[16];
     {
-      constexpr int kMaxBelow = 48 * 4;
+      constexpr int kMaxBelow = 48 * NW;
       static_assert(RM - 16 <= kMaxBelow, "panel rows exceed the waves");
       const int below = RM - j0 - 16;
       const int nwp = below > 0 ? (below + 47) / 48 : 1;
@@ -950,7 +952,7 @@ __global__ __launch_bounds__(256) void k_chol_lds(const NodeDesc* __restrict__ n
     // trailing update: tiles (I2 >= J2 > J) -= P_I2 P_J2^T with P = X[:, j0:j0+16]
     const int rem = NB - J - 1;
     const int ntl = rem * (rem + 1) / 2;
-    for (int t = wid; t < ntl; t += 4) {
+    for (int t = wid; t < ntl; t += NW) {
       int a = 0;
       while ((a + 1) * (a + 2) / 2 <= t) ++a;
       const int b = t - a * (a + 1) / 2;
@@ -986,7 +988,7 @@ __global__ __launch_bounds__(256) void k_chol_lds(const NodeDesc* __restrict__ n
   }
   __syncthreads();
   for (int I = 1; I < NB; ++I) {
-    for (int J = wid; J < I; J += 4) {
+    for (int J = wid; J < I; J += NW) {
       v4d acc = {0.0, 0.0, 0.0, 0.0};
       for (int K = J; K < I; ++K) {
 #pragma unroll
@@ -1000,7 +1002,7 @@ __global__ __launch_bounds__(256) void k_chol_lds(const NodeDesc* __restrict__ n
       for (int v = 0; v < 4; ++v) Pt[J][mfma_out_row(0.0, lane, v)][lane & 15] = acc[v];
     }
     __syncthreads();
-    for (int J = wid; J < I; J += 4) {
+    for (int J = wid; J < I; J += NW) {
       v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int kk = 0; kk < 16; kk += 4) {
@@ -1013,10 +1015,97 @@ __global__ __launch_bounds__(256) void k_chol_lds(const NodeDesc* __restrict__ n
     }
     __syncthreads();
   }
-  for (int e = tid; e < m * m; e += 256) {
+  for (int e = tid; e < m * m; e += NT) {
     const int i = e % m, j = e / m;
     if (i >= j) F[i + (int64_t)j * n] = (T)X[i][j];
     Li[e] = (T)(i >= j ? Y[i][j] : 0.0);
+  }
+  const int r = nd.r;
+  if (FUSE && r > 0) {
+    // L_SR = F_SR L_RR^{-T} and Sigma = F_SS - L_SR L_SR^T from LDS (r <= RM):
+    // F_SR replaces L_RR in X (zero outside r x m), Y still holds L_RR^{-1}
+    __syncthreads();
+    {
+      constexpr int TOT = RM * RM, PER = (TOT + NT - 1) / NT, SB = 12;
+#pragma unroll 1
+      for (int q0 = 0; q0 < PER; q0 += SB) {
+        double v[SB];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+          const int e = (q0 + u) * NT + tid;
+          const int i = e % RM, c = e / RM;
+          v[u] = (q0 + u < PER && e < TOT && i < r && c < m) ? (double)F[(m + i) + (int64_t)c * n] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+          const int e = (q0 + u) * NT + tid;
+          if (q0 + u < PER && e < TOT) X[e % RM][e / RM] = v[u];
+        }
+      }
+    }
+    __syncthreads();
+    // output tile (I, J) of L_SR: sum over the column blocks K <= J of
+    // F_SR[I, K] (L_RR^{-1}[J, K])^T; up to NB * NB / 4 tiles per wave, kept in
+    // registers until every wave has read F_SR
+    const int RT = (r + 15) / 16, CT = (m + 15) / 16;
+    constexpr int MQ = (NB * NB + NW - 1) / NW;
+    v4d acc[MQ];
+#pragma unroll
+    for (int q = 0; q < MQ; ++q) {
+      acc[q] = (v4d){0.0, 0.0, 0.0, 0.0};
+      const int t = wid + NW * q;
+      if (t < RT * CT) {
+        const int I = t % RT, J = t / RT;
+        for (int K = 0; K <= J; ++K) {
+#pragma unroll
+          for (int kk = 0; kk < 16; kk += 4) {
+            const double av = X[I * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
+            const double bv = Y[J * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
+            acc[q] = mfma16x(av, bv, acc[q]);
+          }
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MQ; ++q) {
+      const int t = wid + NW * q;
+      if (t < RT * CT) {
+        const int I = t % RT, J = t / RT;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[I * 16 + mfma_out_row(0.0, lane, v)][J * 16 + (lane & 15)] = acc[q][v];
+      }
+    }
+    __syncthreads();
+    for (int e = tid; e < r * m; e += NT) {
+      const int i = e % r, c = e / r;
+      F[(m + i) + (int64_t)c * n] = (T)X[i][c];
+    }
+    // Sigma: lower tiles of the r x r block at (m, m)
+    for (int t = wid; t < RT * (RT + 1) / 2; t += NW) {
+      int I = 0;
+      while ((I + 1) * (I + 2) / 2 <= t) ++I;
+      const int J = t - I * (I + 1) / 2;
+      v4d sacc = {0.0, 0.0, 0.0, 0.0};
+      for (int k0 = 0; k0 < m; k0 += 16) {
+#pragma unroll
+        for (int kk = 0; kk < 16; kk += 4) {
+          const int k = k0 + kk + (lane >> 4);
+          sacc = mfma16x(X[I * 16 + (lane & 15)][k], X[J * 16 + (lane & 15)][k], sacc);
+        }
+      }
+      T cur[4];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = I * 16 + mfma_out_row(0.0, lane, v), c = J * 16 + (lane & 15);
+        cur[v] = (i < r && c < r && i >= c) ? F[(m + i) + (int64_t)(m + c) * n] : (T)0;
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int i = I * 16 + mfma_out_row(0.0, lane, v), c = J * 16 + (lane & 15);
+        if (i < r && c < r && i >= c) F[(m + i) + (int64_t)(m + c) * n] = (T)((double)cur[v] - sacc[v]);
+      }
+    }
   }
   if (tid == 0) {
     if (fail >= 0) {
@@ -1468,32 +1557,39 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
     {
       if (use_inv) {
         const int mm = lp.mmax;
-        dim3 grid(lp.count), block(256);
+        const int rm = mm <= 32 ? 32 : (mm <= 64 ? 64 : 96);
+        // L_SR and Sigma inside the Cholesky kernel when the S rows fit its frame
+        const bool fuse = lp.rmax <= rm;
+        dim3 grid(lp.count), block(512);
         {
           Prof pf(cx, nonroot == 0 ? "root" : "chol_lds", l);
-          if (mm <= 32)
-            hipLaunchKernelGGL((k_chol_lds<T, 32>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                               (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet);
-          else if (mm <= 64)
-            hipLaunchKernelGGL((k_chol_lds<T, 64>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                               (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet);
-          else
-            hipLaunchKernelGGL((k_chol_lds<T, 96>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                               (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet);
+#define CHOL_LDS(RM, FU)                                                                                      \
+  hipLaunchKernelGGL((k_chol_lds<T, RM, FU>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,              \
+                     (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet)
+          if (rm == 32) {
+            if (fuse) CHOL_LDS(32, true); else CHOL_LDS(32, false);
+          } else if (rm == 64) {
+            if (fuse) CHOL_LDS(64, true); else CHOL_LDS(64, false);
+          } else {
+            if (fuse) CHOL_LDS(96, true); else CHOL_LDS(96, false);
+          }
+#undef CHOL_LDS
           HSS_HIP(hipGetLastError());
         }
-        {
-          Prof pf(cx, "gemm_LSR", l);
-          gemm_run<T>(st[7], false, true, 1.0, 0.0, s);  // L_SR = F_SR L_RR^{-T}
+        if (!fuse) {
+          {
+            Prof pf(cx, "gemm_LSR", l);
+            gemm_run<T>(st[7], false, true, 1.0, 0.0, s);  // L_SR = F_SR L_RR^{-T}
+          }
+          {
+            Prof pf(cx, "gemm_Sigma", l);
+            gemm_run<T>(st[8], false, true, -1.0, 1.0, s);  // Sigma = F_SS - L_SR L_SR^T
+          }
+          Prof pf(cx, "copy_lsr", l);
+          hipLaunchKernelGGL((k_copy_lsr<T>), dim3(16, lp.count), dim3(256), 0, s, m->dnodes, lp.first,
+                             (const T*)b.S2, (const int64_t*)m->dOffS2, b.F);
+          HSS_HIP(hipGetLastError());
         }
-        {
-          Prof pf(cx, "gemm_Sigma", l);
-          gemm_run<T>(st[8], false, true, -1.0, 1.0, s);  // Sigma = F_SS - L_SR L_SR^T
-        }
-        Prof pf(cx, "copy_lsr", l);
-        hipLaunchKernelGGL((k_copy_lsr<T>), dim3(16, lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const T*)b.S2,
-                           (const int64_t*)m->dOffS2, b.F);
-        HSS_HIP(hipGetLastError());
       } else {
         int rmax_nr = 0, mmax_nr = 0, nmax_nr = 0;
         for (int k = lp.first; k < lp.root_first; ++k) {
