@@ -151,6 +151,16 @@ void finish_stages(hss_matrix_t m) {
     }
     lp.leaf = (nd[lp.first].c1 < 0) ? 1 : 0;
     lp.inv = (lp.mmax <= 96 && lp.mmax >= 1) ? 1 : 0;
+    lp.root_split = (!lp.inv && lp.root_first == lp.first && lp.nmax > 96 && lp.nmax <= 192) ? 1 : 0;
+    if (lp.root_split) {
+      // inverses of the two diagonal blocks, h x h then (n - h) x (n - h)
+      for (int k = lp.first; k < lp.first + lp.count; ++k) {
+        const int h = root_split_h(nd[k].n), h2 = nd[k].n - h;
+        m->offLi[k] = oLi;
+        oLi += (int64_t)h * h + (int64_t)h2 * h2;
+      }
+      continue;
+    }
     if (!lp.inv) continue;
     for (int k = lp.first; k < lp.first + lp.count; ++k) {
       m->offLi[k] = oLi;

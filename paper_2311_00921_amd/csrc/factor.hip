@@ -892,13 +892,20 @@ template <typename T, int RM, bool FUSE, int NT = 512>
 __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ nodes, int first,
                                                   T* __restrict__ Fbase, T* __restrict__ Libase,
                                                   const int64_t* __restrict__ offLi, int32_t* __restrict__ info,
-                                                  double* __restrict__ logdet) {
+                                                  double* __restrict__ logdet, int part) {
   constexpr int NB = RM / 16, NW = NT / 64;
   const int node = first + blockIdx.x;
   const NodeDesc nd = nodes[node];
-  const int n = nd.n, m = nd.m;
-  T* F = Fbase + nd.offF;
-  T* Li = Libase + offLi[node];
+  // part 0: the node's partial Cholesky. Parts 1 and 2 split a root (r = 0) of
+  // order n at h: part 1 is the partial Cholesky of the leading h x h block
+  // with the n - h rows below as its S rows, part 2 the Cholesky of the
+  // remaining Schur complement; together they are the root's Cholesky factor.
+  const int n = nd.n, h = root_split_h(n);
+  const int m = part == 0 ? nd.m : (part == 1 ? h : n - h);
+  const int r = part == 0 ? nd.r : (part == 1 ? n - h : 0);
+  const int piv0 = part == 2 ? h : 0;
+  T* F = Fbase + nd.offF + (part == 2 ? (int64_t)h * (n + 1) : 0);
+  T* Li = Libase + offLi[node] + (part == 2 ? (int64_t)h * h : 0);
   __shared__ double X[RM][RM + 1];
   __shared__ double Y[RM][RM + 1];
   __shared__ double Pt[NB][16][17];
@@ -1020,7 +1027,6 @@ __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ no
     if (i >= j) F[i + (int64_t)j * n] = (T)X[i][j];
     Li[e] = (T)(i >= j ? Y[i][j] : 0.0);
   }
-  const int r = nd.r;
   if (FUSE && r > 0) {
     // L_SR = F_SR L_RR^{-T} and Sigma = F_SS - L_SR L_SR^T from LDS (r <= RM):
     // F_SR replaces L_RR in X (zero outside r x m), Y still holds L_RR^{-1}
@@ -1111,11 +1117,14 @@ __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ no
     if (fail >= 0) {
       if (atomicCAS(&info[0], 0, 1) == 0) {
         info[1] = node;
-        info[2] = fail;
+        info[2] = piv0 + fail;
       }
       info[4 + nd.sys] = 1;  // per-system flag
     }
-    logdet[node] = 2.0 * lacc;
+    if (part == 2)
+      logdet[node] += 2.0 * lacc;
+    else
+      logdet[node] = 2.0 * lacc;
   }
 }
 
@@ -1553,9 +1562,28 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
     // With FP32 compute a stage that holds roots is factored by the blocked
     // kernel, so that the roots can be done in FP64.
     const bool use_inv = lp.inv && !(fp32 && nonroot < lp.count);
-    (fp32 ? m->inv_used32 : m->inv_used64)[si] = use_inv ? 1 : 0;
+    const bool split = !fp32 && lp.root_split;
+    (fp32 ? m->inv_used32 : m->inv_used64)[si] = use_inv ? 1 : (split ? 2 : 0);
     {
-      if (use_inv) {
+      if (split) {
+        // every node is a root of order 96 < n <= 192: two LDS Cholesky passes
+        Prof pf(cx, "root", l);
+        int hmax = 0;
+        for (int k = lp.first; k < lp.first + lp.count; ++k) hmax = std::max(hmax, root_split_h(m->nodes[k].n));
+        dim3 grid(lp.count), block(512);
+        if (hmax <= 64) {
+          hipLaunchKernelGGL((k_chol_lds<T, 64, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
+                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 1);
+          hipLaunchKernelGGL((k_chol_lds<T, 64, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
+                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 2);
+        } else {
+          hipLaunchKernelGGL((k_chol_lds<T, 96, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
+                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 1);
+          hipLaunchKernelGGL((k_chol_lds<T, 96, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
+                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 2);
+        }
+        HSS_HIP(hipGetLastError());
+      } else if (use_inv) {
         const int mm = lp.mmax;
         const int rm = mm <= 32 ? 32 : (mm <= 64 ? 64 : 96);
         // L_SR and Sigma inside the Cholesky kernel when the S rows fit its frame
@@ -1565,7 +1593,7 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
           Prof pf(cx, nonroot == 0 ? "root" : "chol_lds", l);
 #define CHOL_LDS(RM, FU)                                                                                      \
   hipLaunchKernelGGL((k_chol_lds<T, RM, FU>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,              \
-                     (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet)
+                     (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 0)
           if (rm == 32) {
             if (fuse) CHOL_LDS(32, true); else CHOL_LDS(32, false);
           } else if (rm == 64) {

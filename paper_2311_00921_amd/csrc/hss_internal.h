@@ -75,7 +75,14 @@ struct LevelPlan {
   int32_t leaf;        // 1 for the stage of the leaves
   int32_t inv;         // 1 if the LDS Cholesky + explicit inverse path is used
   int32_t root_first;  // first root of the stage (first + count if none)
+  int32_t root_split;  // 1 if the stage holds only roots with 96 < n <= 192: each is
+                       // factored as two LDS blocks of h = (n + 1) / 2 and n - h
+                       // (leading block with its S rows, then the trailing Schur
+                       // complement), both with explicit inverses
 };
+
+// Split point of a root factored in two LDS blocks (LevelPlan::root_split).
+__host__ __device__ inline int root_split_h(int n) { return (n + 1) / 2; }
 
 // Batched GEMM entry: C = alpha * op(A) op(B) + beta * Cin, optional symmetric
 // permutation of the output from [S;R] to [R;S] order (perm_r = r > 0).

@@ -253,7 +253,28 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_fwd(const NodeDesc* __r
   row_gemv_wide<NT>(V, n, n, r, st, r, sb, n, nc, (T)-1, red);
   __syncthreads();
   // y_R = L_RR^{-1} b^_R  (b^_R = sb[r:n])
-  if (use_inv) {
+  if (use_inv == 2) {
+    // a root factored in two blocks at h: y1 = L11^{-1} b1, y2 = L22^{-1} (b2 - L21 y1)
+    const int h = root_split_h(n), h2 = n - h;
+    const T* Li1 = Lib + offLi[p];
+    const T* Li2 = Li1 + (int64_t)h * h;
+    for (int i = threadIdx.x; i < h * RC; i += NT) tm[i] = 0;
+    __syncthreads();
+    row_gemv_wide<NT>(Li1, h, h, h, sb, n, tm, h, nc, (T)1, red);
+    __syncthreads();
+    for (int i = threadIdx.x; i < h; i += NT)
+      for (int c = 0; c < nc; ++c) sb[i + c * n] = tm[i + c * h];
+    __syncthreads();
+    row_gemv_wide<NT>(F + h, n, h2, h, sb, n, sb + h, n, nc, (T)-1, red);
+    __syncthreads();
+    for (int i = threadIdx.x; i < h2 * RC; i += NT) tm[i] = 0;
+    __syncthreads();
+    row_gemv_wide<NT>(Li2, h2, h2, h2, sb + h, n, tm, h2, nc, (T)1, red);
+    __syncthreads();
+    for (int i = threadIdx.x; i < h2; i += NT)
+      for (int c = 0; c < nc; ++c) sb[h + i + c * n] = tm[i + c * h2];
+    __syncthreads();
+  } else if (use_inv) {
     const T* Li = Lib + offLi[p];
     for (int i = threadIdx.x; i < m * RC; i += NT) tm[i] = 0;
     __syncthreads();
@@ -316,7 +337,27 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_bwd(const NodeDesc* __r
   for (int k = threadIdx.x; k < m; k += NT)
     for (int c = 0; c < nc; ++c) sx[r + k + c * n] -= tm[k + c * n];
   __syncthreads();
-  if (use_inv) {
+  if (use_inv == 2) {
+    // a root factored in two blocks at h: x2 = L22^{-T} y2, x1 = L11^{-T} (y1 - L21^T x2)
+    const int h = root_split_h(n), h2 = n - h;
+    const T* Li1 = Lib + offLi[p];
+    const T* Li2 = Li1 + (int64_t)h * h;
+    col_dots<NT>(Li2, h2, h2, h2, sx + h, n, tm, n, nc);
+    __syncthreads();
+    for (int i = threadIdx.x; i < h2; i += NT)
+      for (int c = 0; c < nc; ++c) sx[h + i + c * n] = tm[i + c * n];
+    __syncthreads();
+    col_dots<NT>(F + h, n, h2, h, sx + h, n, tm, n, nc);
+    __syncthreads();
+    for (int k = threadIdx.x; k < h; k += NT)
+      for (int c = 0; c < nc; ++c) sx[k + c * n] -= tm[k + c * n];
+    __syncthreads();
+    col_dots<NT>(Li1, h, h, h, sx, n, tm, n, nc);
+    __syncthreads();
+    for (int i = threadIdx.x; i < h; i += NT)
+      for (int c = 0; c < nc; ++c) sx[i + c * n] = tm[i + c * n];
+    __syncthreads();
+  } else if (use_inv) {
     // x_R = L_RR^{-T} t: x_R[j] = sum_i Li[i, j] t_i  (columns of Li are contiguous)
     const T* Li = Lib + offLi[p];
     col_dots<NT>(Li, m, m, m, sx + r, n, tm, n, nc);
