@@ -448,20 +448,40 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
   }
   for (int c = tid; c < r; c += 256) Sg[c] = (T)sg[c];
   // T = -U_1 Sg L_1^{-T}: tile (I, J), I <= J: -sum_{K=I..J} U_IK Sg_K (Yl_JK)^T
+  // (tiles below the block diagonal are zero; the tile list is the upper
+  // triangle in row-major order, so the waves get similar K ranges)
   for (int t = wid; t < NB * NB; t += 4) {
-    const int I = t % NB, J = t / NB;
+    int I = 0, J = 0;
+    if (t < NB * (NB + 1) / 2) {
+      int rem = t;
+      while (rem >= NB - I) {
+        rem -= NB - I;
+        ++I;
+      }
+      J = I + rem;
+    } else {
+      const int z = t - NB * (NB + 1) / 2;  // strictly lower tiles, written as zeros
+      int a = 1;
+      while (a * (a + 1) / 2 <= z) ++a;
+      I = a;
+      J = z - (a - 1) * a / 2;
+    }
     v4d acc = {0.0, 0.0, 0.0, 0.0};
     if (I <= J) {
-      for (int K = I; K <= J; ++K)
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-          const int ar = I * 16 + (lane & 15), ac = K * 16 + kk + (lane >> 4);
-          const double av = (ar <= ac) ? X[ar][ac] * sg[ac] : 0.0;  // U_1 Sg
-          const int br = K * 16 + kk + (lane >> 4), bc = J * 16 + (lane & 15);
-          // (L_1^{-1})^T[br][bc] = Yl[bc][br]: nonzero for bc >= br, unit on the diagonal
-          const double bv = (bc == br) ? 1.0 : (bc > br ? Y[bc][br] : 0.0);
-          acc = mfma16x(av, bv, acc);
+      for (int K = 0; K < NB; ++K) {
+        if (K >= I && K <= J) {
+#pragma unroll
+          for (int kk = 0; kk < 16; kk += 4) {
+            const int ar = I * 16 + (lane & 15), ac = K * 16 + kk + (lane >> 4);
+            const double av = (ar <= ac) ? X[ar][ac] * sg[ac] : 0.0;  // U_1 Sg
+            const int br = K * 16 + kk + (lane >> 4), bc = J * 16 + (lane & 15);
+            // (L_1^{-1})^T[br][bc] = Yl[bc][br]: nonzero for bc >= br, unit on the diagonal
+            const double bv = (bc == br) ? 1.0 : (bc > br ? Y[bc][br] : 0.0);
+            acc = mfma16x(av, bv, acc);
+          }
         }
+      }
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -802,11 +822,14 @@ __global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ n
         typename Acc4<T>::type acc;
 #pragma unroll
         for (int v = 0; v < 4; ++v) acc[v] = 0;
-        for (int k0 = 0; k0 < j0; k0 += 16) {
 #pragma unroll
-          for (int u = 0; u < 16; u += 4) {
-            const int k = k0 + u + (lane >> 4);
-            acc = mfma16x(X[rt * 16 + (lane & 15)][k], Lb[lane & 15][k], acc);
+        for (int k0 = 0; k0 < MMAX - 16; k0 += 16) {
+          if (k0 < j0) {
+#pragma unroll
+            for (int u = 0; u < 16; u += 4) {
+              const int k = k0 + u + (lane >> 4);
+              acc = mfma16x(X[rt * 16 + (lane & 15)][k], Lb[lane & 15][k], acc);
+            }
           }
         }
 #pragma unroll
@@ -852,22 +875,20 @@ __global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ n
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
     const int J = t - I * (I + 1) / 2;
     if (I * 16 >= r) continue;
-    typename Acc4<T>::type acc;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) acc[v] = 0;
-    // columns m..MMAX-1 of X are zero, so the K loop may run to a multiple of 16
-    for (int k0 = 0; k0 < m; k0 += 16) {
-#pragma unroll
-      for (int u = 0; u < 16; u += 4) {
-        const int k = k0 + u + (lane >> 4);
-        acc = mfma16x(X[I * 16 + (lane & 15)][k], X[J * 16 + (lane & 15)][k], acc);
-      }
-    }
-    T cur[4];
+    T cur[4];  // F_SS, fetched before the products
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = I * 16 + mfma_out_row((T)0, lane, v), c = J * 16 + (lane & 15);
       cur[v] = (i < r && c < r && i >= c) ? F[(m + i) + (int64_t)(m + c) * n] : (T)0;
+    }
+    typename Acc4<T>::type acc;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] = 0;
+    // columns m..MMAX-1 of X are zero: the K loop runs over MMAX and unrolls
+#pragma unroll
+    for (int k0 = 0; k0 < MMAX; k0 += 4) {
+      const int k = k0 + (lane >> 4);
+      acc = mfma16x(X[I * 16 + (lane & 15)][k], X[J * 16 + (lane & 15)][k], acc);
     }
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
@@ -1062,12 +1083,15 @@ __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ no
       const int t = wid + NW * q;
       if (t < RT * CT) {
         const int I = t % RT, J = t / RT;
-        for (int K = 0; K <= J; ++K) {
 #pragma unroll
-          for (int kk = 0; kk < 16; kk += 4) {
-            const double av = X[I * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
-            const double bv = Y[J * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
-            acc[q] = mfma16x(av, bv, acc[q]);
+        for (int K = 0; K < NB; ++K) {
+          if (K <= J) {
+#pragma unroll
+            for (int kk = 0; kk < 16; kk += 4) {
+              const double av = X[I * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
+              const double bv = Y[J * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
+              acc[q] = mfma16x(av, bv, acc[q]);
+            }
           }
         }
       }
@@ -1087,24 +1111,24 @@ __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ no
       const int i = e % r, c = e / r;
       F[(m + i) + (int64_t)c * n] = (T)X[i][c];
     }
-    // Sigma: lower tiles of the r x r block at (m, m)
+    // Sigma: lower tiles of the r x r block at (m, m); the K loop runs over the
+    // whole frame (columns m..RM-1 of X are zero) so that it unrolls, and F_SS
+    // is fetched before the products
     for (int t = wid; t < RT * (RT + 1) / 2; t += NW) {
       int I = 0;
       while ((I + 1) * (I + 2) / 2 <= t) ++I;
       const int J = t - I * (I + 1) / 2;
-      v4d sacc = {0.0, 0.0, 0.0, 0.0};
-      for (int k0 = 0; k0 < m; k0 += 16) {
-#pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-          const int k = k0 + kk + (lane >> 4);
-          sacc = mfma16x(X[I * 16 + (lane & 15)][k], X[J * 16 + (lane & 15)][k], sacc);
-        }
-      }
       T cur[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = I * 16 + mfma_out_row(0.0, lane, v), c = J * 16 + (lane & 15);
         cur[v] = (i < r && c < r && i >= c) ? F[(m + i) + (int64_t)(m + c) * n] : (T)0;
+      }
+      v4d sacc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k0 = 0; k0 < RM; k0 += 4) {
+        const int k = k0 + (lane >> 4);
+        sacc = mfma16x(X[I * 16 + (lane & 15)][k], X[J * 16 + (lane & 15)][k], sacc);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
