@@ -68,13 +68,18 @@ __device__ __forceinline__ double rcp_nr(double x) {
   return r;
 }
 
+// Row padding of the FP64 LDS frames: a row stride of 2 (mod 32) eight-byte
+// banks lets the 16 rows x 4 k-steps of an MFMA operand read spread over the
+// banks two-way (a stride of 1 (mod 32) collides four-way).
+constexpr int kLdsPad = 2;
+
 // Stages the RM x RM frame X[i][c] (i, c < RM) from a column-major global
 // block A (leading dimension ld): entries with i < rows and c < cols come from
 // A, the others are 1 on the diagonal and 0 elsewhere. Each thread keeps SB
 // loads in flight before writing them to LDS, so that a lone workgroup is not
 // bound by one global-memory latency per element it loads.
 template <int RM, int NT = 256, typename T>
-__device__ __forceinline__ void stage_frame(double (*X)[RM + 1], const T* __restrict__ A, int64_t ld, int rows,
+__device__ __forceinline__ void stage_frame(double (*X)[RM + kLdsPad], const T* __restrict__ A, int64_t ld, int rows,
                                             int cols, bool lower_only) {
   constexpr int TOT = RM * RM;
   constexpr int PER = (TOT + NT - 1) / NT;
@@ -266,9 +271,8 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
   T* Tm = Tbase + nd.offT;
   T* Sg = Sgbase + nd.offSg;
   T* U1i = Xbase + nd.offX + (int64_t)r * r;
-  __shared__ double X[RM][RM + 1];   // LU in place: strict lower = L_1, upper = U_1
-  __shared__ double Y[RM][RM + 1];   // upper = U_1^{-1}, strict lower = L_1^{-1} (unit diagonal implied)
-  __shared__ double Pt[NB][16][17];
+  __shared__ double X[RM][RM + kLdsPad];  // LU in place: strict lower = L_1, upper = U_1
+  __shared__ double Y[RM][RM + kLdsPad];  // upper = U_1^{-1}, strict lower = L_1^{-1} (unit diagonal implied)
   __shared__ double sg[RM];
   __shared__ double uinv[RM];  // 1 / U_ii
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -381,28 +385,25 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
   __syncthreads();
   // off-diagonal tiles of U_1^{-1}, block rows bottom-up: Yu_IJ = -Yu_II sum_{K=I+1..J} U_IK Yu_KJ
   for (int Iu = NB - 2; Iu >= 0; --Iu) {
+    // (block row Iu of Y is neither read nor written by another wave in this step)
     for (int J = Iu + 1 + wid; J < NB; J += 4) {
-      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      v4d pp = {0.0, 0.0, 0.0, 0.0};
       for (int K = Iu + 1; K <= J; ++K)
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
           const double av = X[Iu * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
           const int kr = K * 16 + kk + (lane >> 4), jc = J * 16 + (lane & 15);
           const double bv = (K == J && kr > jc) ? 0.0 : Y[kr][jc];  // upper part of the diagonal tile
-          acc = mfma16x(av, bv, acc);
+          pp = mfma16x(av, bv, pp);
         }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Pt[J][mfma_out_row(0.0, lane, v)][lane & 15] = acc[v];
-    }
-    __syncthreads();
-    for (int J = Iu + 1 + wid; J < NB; J += 4) {
+      // the accumulator of a 16x16x4 FP64 product holds, in slot v, the rows
+      // 4v..4v+3 of the B operand of the next product's step v: no LDS round trip
       v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) {
-        const int ar = Iu * 16 + (lane & 15), ac = Iu * 16 + kk + (lane >> 4);
+      for (int v = 0; v < 4; ++v) {
+        const int ar = Iu * 16 + (lane & 15), ac = Iu * 16 + 4 * v + (lane >> 4);
         const double av = (ar <= ac) ? Y[ar][ac] : 0.0;
-        const double bv = Pt[J][kk + (lane >> 4)][lane & 15];
-        acc = mfma16x(av, bv, acc);
+        acc = mfma16x(av, pp[v], acc);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) Y[Iu * 16 + mfma_out_row(0.0, lane, v)][J * 16 + (lane & 15)] = -acc[v];
@@ -413,27 +414,21 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
   // Yl_IJ = -Yl_II sum_{K=J..I-1} L_IK Yl_KJ
   for (int Il = 1; Il < NB; ++Il) {
     for (int J = wid; J < Il; J += 4) {
-      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      v4d pp = {0.0, 0.0, 0.0, 0.0};
       for (int K = J; K < Il; ++K)
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
           const double av = X[Il * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
           const int kr = K * 16 + kk + (lane >> 4), jc = J * 16 + (lane & 15);
           const double bv = (K == J) ? (kr == jc ? 1.0 : (kr > jc ? Y[kr][jc] : 0.0)) : Y[kr][jc];
-          acc = mfma16x(av, bv, acc);
+          pp = mfma16x(av, bv, pp);
         }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Pt[J][mfma_out_row(0.0, lane, v)][lane & 15] = -acc[v];
-    }
-    __syncthreads();
-    for (int J = wid; J < Il; J += 4) {
       v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) {
-        const int ar = Il * 16 + (lane & 15), ac = Il * 16 + kk + (lane >> 4);
+      for (int v = 0; v < 4; ++v) {
+        const int ar = Il * 16 + (lane & 15), ac = Il * 16 + 4 * v + (lane >> 4);
         const double av = (ar == ac) ? 1.0 : (ar > ac ? Y[ar][ac] : 0.0);
-        const double bv = Pt[J][kk + (lane >> 4)][lane & 15];
-        acc = mfma16x(av, bv, acc);
+        acc = mfma16x(av, -pp[v], acc);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) Y[Il * 16 + mfma_out_row(0.0, lane, v)][J * 16 + (lane & 15)] = acc[v];
@@ -769,8 +764,8 @@ __global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ n
   const int n = nd.n, r = nd.r, m = nd.m;
   if (r == 0) return;
   T* F = Fbase + nd.offF;
-  __shared__ T X[RMAX][MMAX + 1];  // F_SR, then L_SR
-  __shared__ T Lb[16][MMAX + 1];   // L_RR[j0:j0+16, 0:j0+16] of the current step
+  __shared__ T X[RMAX][MMAX + kLdsPad];  // F_SR, then L_SR
+  __shared__ T Lb[16][MMAX + kLdsPad];   // L_RR[j0:j0+16, 0:j0+16] of the current step
   __shared__ double rd[16];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   // X = F_SR (rows m..n-1, columns 0..m-1), zero outside; 15 loads in flight per thread
@@ -927,9 +922,8 @@ __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ no
   const int piv0 = part == 2 ? h : 0;
   T* F = Fbase + nd.offF + (part == 2 ? (int64_t)h * (n + 1) : 0);
   T* Li = Libase + offLi[node] + (part == 2 ? (int64_t)h * h : 0);
-  __shared__ double X[RM][RM + 1];
-  __shared__ double Y[RM][RM + 1];
-  __shared__ double Pt[NB][16][17];
+  __shared__ double X[RM][RM + kLdsPad];
+  __shared__ double Y[RM][RM + kLdsPad];
   __shared__ double rdg[RM];  // 1 / L_ii
   __shared__ int fail;
   __shared__ double lacc;
@@ -1016,27 +1010,23 @@ __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ no
   }
   __syncthreads();
   for (int I = 1; I < NB; ++I) {
+    // block row I of Y is neither read nor written by another wave in this step
     for (int J = wid; J < I; J += NW) {
-      v4d acc = {0.0, 0.0, 0.0, 0.0};
+      v4d pp = {0.0, 0.0, 0.0, 0.0};
       for (int K = J; K < I; ++K) {
 #pragma unroll
         for (int kk = 0; kk < 16; kk += 4) {
           const double av = X[I * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
           const double bv = Y[K * 16 + kk + (lane >> 4)][J * 16 + (lane & 15)];
-          acc = mfma16x(av, bv, acc);
+          pp = mfma16x(av, bv, pp);
         }
       }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Pt[J][mfma_out_row(0.0, lane, v)][lane & 15] = acc[v];
-    }
-    __syncthreads();
-    for (int J = wid; J < I; J += NW) {
+      // slot v of the accumulator is the B operand of step v of the next product
       v4d acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) {
-        const double av = Y[I * 16 + (lane & 15)][I * 16 + kk + (lane >> 4)];
-        const double bv = Pt[J][kk + (lane >> 4)][lane & 15];
-        acc = mfma16x(av, bv, acc);
+      for (int v = 0; v < 4; ++v) {
+        const double av = Y[I * 16 + (lane & 15)][I * 16 + 4 * v + (lane >> 4)];
+        acc = mfma16x(av, pp[v], acc);
       }
 #pragma unroll
       for (int v = 0; v < 4; ++v) Y[I * 16 + mfma_out_row(0.0, lane, v)][J * 16 + (lane & 15)] = -acc[v];
