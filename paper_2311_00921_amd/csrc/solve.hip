@@ -62,6 +62,67 @@ __device__ void col_dots(const T* __restrict__ A, int64_t lda, int rows, int col
   }
 }
 
+// The same product for wide blocks (NT >= 1024, few nodes per launch): thread
+// t sums a contiguous chunk of rows of column t % cols (chunk t / cols), so no
+// wave reduction is needed; the partial sums meet in LDS (red: NT * RC
+// entries). Ends with a barrier.
+template <int NT, typename T>
+__device__ void col_dots_split(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* x, int ldx,
+                               T* out, int ldo, int nc, T* red) {
+  const int t = threadIdx.x;
+  for (int jb = 0; jb < cols; jb += NT) {
+    const int cw = min(cols - jb, NT);
+    const int G = NT / cw;                  // row chunks per column
+    const int chunk = (rows + G - 1) / G;
+    const int g = t / cw, jl = t % cw;
+    if (g < G) {
+      T acc[RC];
+#pragma unroll
+      for (int c = 0; c < RC; ++c) acc[c] = 0;
+      const int i0 = g * chunk, i1 = min(rows, i0 + chunk);
+      const T* __restrict__ a = A + (int64_t)(jb + jl) * lda;
+      int i = i0;
+      for (; i + 4 <= i1; i += 4) {
+        T v[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] = a[i + q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+#pragma unroll
+          for (int c = 0; c < RC; ++c)
+            if (c < nc) acc[c] += v[q] * x[i + q + c * ldx];
+      }
+      for (; i < i1; ++i) {
+        const T v = a[i];
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+          if (c < nc) acc[c] += v * x[i + c * ldx];
+      }
+#pragma unroll
+      for (int c = 0; c < RC; ++c)
+        if (c < nc) red[g * cw + jl + c * NT] = acc[c];
+    }
+    __syncthreads();
+    for (int q = t; q < cw; q += NT)
+      for (int c = 0; c < nc; ++c) {
+        T sum = 0;
+        for (int g2 = 0; g2 < G; ++g2) sum += red[g2 * cw + q + c * NT];
+        out[jb + q + c * ldo] = sum;
+      }
+    __syncthreads();
+  }
+}
+
+// col_dots for the solve kernels: the chunked form when a node has 1024 threads.
+template <int NT, typename T>
+__device__ __forceinline__ void col_dots_node(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* x,
+                                              int ldx, T* out, int ldo, int nc, T* red) {
+  if constexpr (NT >= 1024)
+    col_dots_split<NT>(A, lda, rows, cols, x, ldx, out, ldo, nc, red);
+  else
+    col_dots<NT>(A, lda, rows, cols, x, ldx, out, ldo, nc);
+}
+
 // y[i, c] (+)= sign * sum_{j < cols} A[i + j lda] u[j + c ldu] for i < rows: one thread per row.
 template <int NT, typename T>
 __device__ void row_gemv(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* u, int ldu, T* y,
@@ -237,7 +298,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_fwd(const NodeDesc* __r
   __shared__ T st[128 * RC];
   __shared__ T su[128 * RC];
   __shared__ T tm[128 * RC];
-  __shared__ T red[(NT / 256) * 512];
+  __shared__ T red[NT * RC];  // row_gemv_wide needs (NT / 256) * 512, col_dots_split NT * RC
   T* vp = vec + nd.offVec * nrhs;
   const T* F = Fb + nd.offF;
   const T* V = Vb + nd.offV;
@@ -248,7 +309,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_fwd(const NodeDesc* __r
       sb[i + c * n] = leaf ? (T)b[perm[nd.lo + i] + (int64_t)(c0 + c) * ld] : vp[i + (int64_t)(c0 + c) * n];
   __syncthreads();
   // b^ = H^T b = b - V (Y^T b) with Y = V T kept by the factorization
-  col_dots<NT>(Y, n, n, r, sb, n, st, r, nc);
+  col_dots_node<NT>(Y, n, n, r, sb, n, st, r, nc, red);
   __syncthreads();
   row_gemv_wide<NT>(V, n, n, r, st, r, sb, n, nc, (T)-1, red);
   __syncthreads();
@@ -315,7 +376,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_bwd(const NodeDesc* __r
   __shared__ T su[128 * RC];
   __shared__ T scr[SNB * RC];
   __shared__ T tm[512 * RC];
-  __shared__ T red[(NT / 256) * 512];
+  __shared__ T red[NT * RC];  // row_gemv_wide needs (NT / 256) * 512, col_dots_split NT * RC
   T* vp = vec + nd.offVec * nrhs;
   const T* F = Fb + nd.offF;
   const T* V = Vb + nd.offV;
@@ -332,7 +393,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_bwd(const NodeDesc* __r
     for (int c = 0; c < nc; ++c) sx[r + i + c * n] = vp[i + (int64_t)(c0 + c) * n];
   __syncthreads();
   // t = y_R - L_SR^T x_S: tm[k] = sum_j L_SR[j, k] x_S[j] (column k of L_SR is contiguous)
-  col_dots<NT>(F + m, n, r, m, sx, n, tm, n, nc);
+  col_dots_node<NT>(F + m, n, r, m, sx, n, tm, n, nc, red);
   __syncthreads();
   for (int k = threadIdx.x; k < m; k += NT)
     for (int c = 0; c < nc; ++c) sx[r + k + c * n] -= tm[k + c * n];
@@ -342,17 +403,17 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_bwd(const NodeDesc* __r
     const int h = root_split_h(n), h2 = n - h;
     const T* Li1 = Lib + offLi[p];
     const T* Li2 = Li1 + (int64_t)h * h;
-    col_dots<NT>(Li2, h2, h2, h2, sx + h, n, tm, n, nc);
+    col_dots_node<NT>(Li2, h2, h2, h2, sx + h, n, tm, n, nc, red);
     __syncthreads();
     for (int i = threadIdx.x; i < h2; i += NT)
       for (int c = 0; c < nc; ++c) sx[h + i + c * n] = tm[i + c * n];
     __syncthreads();
-    col_dots<NT>(F + h, n, h2, h, sx + h, n, tm, n, nc);
+    col_dots_node<NT>(F + h, n, h2, h, sx + h, n, tm, n, nc, red);
     __syncthreads();
     for (int k = threadIdx.x; k < h; k += NT)
       for (int c = 0; c < nc; ++c) sx[k + c * n] -= tm[k + c * n];
     __syncthreads();
-    col_dots<NT>(Li1, h, h, h, sx, n, tm, n, nc);
+    col_dots_node<NT>(Li1, h, h, h, sx, n, tm, n, nc, red);
     __syncthreads();
     for (int i = threadIdx.x; i < h; i += NT)
       for (int c = 0; c < nc; ++c) sx[i + c * n] = tm[i + c * n];
@@ -360,7 +421,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_bwd(const NodeDesc* __r
   } else if (use_inv) {
     // x_R = L_RR^{-T} t: x_R[j] = sum_i Li[i, j] t_i  (columns of Li are contiguous)
     const T* Li = Lib + offLi[p];
-    col_dots<NT>(Li, m, m, m, sx + r, n, tm, n, nc);
+    col_dots_node<NT>(Li, m, m, m, sx + r, n, tm, n, nc, red);
     __syncthreads();
     for (int i = threadIdx.x; i < m; i += NT)
       for (int c = 0; c < nc; ++c) sx[r + i + c * n] = tm[i + c * n];
@@ -369,7 +430,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_bwd(const NodeDesc* __r
     lower_t_solve<NT>(F, n, m, sx + r, n, nc, scr);
   }
   // x = H x^ = x^ - Y (V^T x^)
-  col_dots<NT>(V, n, n, r, sx, n, st, r, nc);
+  col_dots_node<NT>(V, n, n, r, sx, n, st, r, nc, red);
   __syncthreads();
   row_gemv_wide<NT>(Y, n, n, r, st, r, sx, n, nc, (T)-1, red);
   __syncthreads();
