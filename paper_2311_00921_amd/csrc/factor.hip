@@ -271,8 +271,8 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
   T* Tm = Tbase + nd.offT;
   T* Sg = Sgbase + nd.offSg;
   T* U1i = Xbase + nd.offX + (int64_t)r * r;
-  __shared__ double X[RM][RM + kLdsPad];  // LU in place: strict lower = L_1, upper = U_1
-  __shared__ double Y[RM][RM + kLdsPad];  // upper = U_1^{-1}, strict lower = L_1^{-1} (unit diagonal implied)
+  // LU in place (strict lower = L_1, upper = U_1), later L_1^{-1} and U_1^{-1} in place
+  __shared__ double X[RM][RM + kLdsPad];
   __shared__ double sg[RM];
   __shared__ double uinv[RM];  // 1 / U_ii
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -358,90 +358,82 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
     }
     __syncthreads();
   }
-  // diagonal tiles of U_1^{-1} (upper) and L_1^{-1} (unit lower) into Y
-  {
-    const int b = tid >> 4, cc = tid & 15;
-    if (b < NB) {
-      const int o = b * 16;
-      double xu[16], xl[16];
-#pragma unroll
-      for (int i = 15; i >= 0; --i) {
-        double acc = 0.0;
-#pragma unroll
-        for (int k = i + 1; k < 16; ++k) acc += X[o + i][o + k] * xu[k];
-        xu[i] = (i == cc) ? uinv[o + i] : (i < cc ? -acc * uinv[o + i] : 0.0);
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) {
-        double acc = 0.0;
-#pragma unroll
-        for (int k = 0; k < i; ++k) acc += X[o + i][o + k] * xl[k];
-        xl[i] = (i == cc) ? 1.0 : (i > cc ? -acc : 0.0);
-      }
-#pragma unroll
-      for (int i = 0; i < 16; ++i) Y[o + i][o + cc] = (i <= cc) ? xu[i] : xl[i];
-    }
-  }
-  __syncthreads();
-  // off-diagonal tiles of U_1^{-1}, block rows bottom-up: Yu_IJ = -Yu_II sum_{K=I+1..J} U_IK Yu_KJ
-  for (int Iu = NB - 2; Iu >= 0; --Iu) {
-    // (block row Iu of Y is neither read nor written by another wave in this step)
-    for (int J = Iu + 1 + wid; J < NB; J += 4) {
-      v4d pp = {0.0, 0.0, 0.0, 0.0};
-      for (int K = Iu + 1; K <= J; ++K)
-#pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-          const double av = X[Iu * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
-          const int kr = K * 16 + kk + (lane >> 4), jc = J * 16 + (lane & 15);
-          const double bv = (K == J && kr > jc) ? 0.0 : Y[kr][jc];  // upper part of the diagonal tile
-          pp = mfma16x(av, bv, pp);
-        }
-      // the accumulator of a 16x16x4 FP64 product holds, in slot v, the rows
-      // 4v..4v+3 of the B operand of the next product's step v: no LDS round trip
-      v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int ar = Iu * 16 + (lane & 15), ac = Iu * 16 + 4 * v + (lane >> 4);
-        const double av = (ar <= ac) ? Y[ar][ac] : 0.0;
-        acc = mfma16x(av, pp[v], acc);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Y[Iu * 16 + mfma_out_row(0.0, lane, v)][J * 16 + (lane & 15)] = -acc[v];
-    }
-    __syncthreads();
-  }
-  // off-diagonal tiles of L_1^{-1} (unit lower), block rows top-down:
-  // Yl_IJ = -Yl_II sum_{K=J..I-1} L_IK Yl_KJ
-  for (int Il = 1; Il < NB; ++Il) {
-    for (int J = wid; J < Il; J += 4) {
-      v4d pp = {0.0, 0.0, 0.0, 0.0};
-      for (int K = J; K < Il; ++K)
-#pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-          const double av = X[Il * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
-          const int kr = K * 16 + kk + (lane >> 4), jc = J * 16 + (lane & 15);
-          const double bv = (K == J) ? (kr == jc ? 1.0 : (kr > jc ? Y[kr][jc] : 0.0)) : Y[kr][jc];
-          pp = mfma16x(av, bv, pp);
-        }
-      v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int ar = Il * 16 + (lane & 15), ac = Il * 16 + 4 * v + (lane >> 4);
-        const double av = (ar == ac) ? 1.0 : (ar > ac ? Y[ar][ac] : 0.0);
-        acc = mfma16x(av, -pp[v], acc);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) Y[Il * 16 + mfma_out_row(0.0, lane, v)][J * 16 + (lane & 15)] = acc[v];
-    }
-    __syncthreads();
-  }
-  // outputs: V_1, Sg, U_1^{-1}
+  // V_1 = L_1 (unit lower) and Sg go out before L_1 is replaced by its inverse
   for (int e = tid; e < r * r; e += 256) {
     const int i = e % r, c = e / r;
     V[i + (int64_t)c * n] = (T)(c < i ? X[i][c] : (c == i ? 1.0 : 0.0));
-    U1i[e] = (T)(i <= c ? Y[i][c] : 0.0);
   }
   for (int c = tid; c < r; c += 256) Sg[c] = (T)sg[c];
+  // Inverses in place in X: L_1^{-1} (unit lower, strict lower part) first,
+  // then T = -U_1 Sg L_1^{-T}, then U_1^{-1} (upper part). Diagonal 16 x 16
+  // blocks by one thread per column (both kept in registers until their
+  // block may be overwritten), off-diagonal block rows on the matrix cores.
+  const int b = tid >> 4, cc = tid & 15;
+  double xu[16], xl[16];
+  if (b < NB) {
+    const int o = b * 16;
+#pragma unroll
+    for (int i = 15; i >= 0; --i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = i + 1; k < 16; ++k) acc += X[o + i][o + k] * xu[k];
+      xu[i] = (i == cc) ? uinv[o + i] : (i < cc ? -acc * uinv[o + i] : 0.0);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+      double acc = 0.0;
+#pragma unroll
+      for (int k = 0; k < i; ++k) acc += X[o + i][o + k] * xl[k];
+      xl[i] = (i == cc) ? 1.0 : (i > cc ? -acc : 0.0);
+    }
+  }
+  __syncthreads();
+  if (b < NB) {
+    const int o = b * 16;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (i > cc) X[o + i][o + cc] = xl[i];
+  }
+  __syncthreads();
+  // off-diagonal tiles of L_1^{-1}, block rows top-down:
+  // Yl_IJ = -Yl_II sum_{K=J..I-1} L_IK Yl_KJ (rows above I already inverted, row I
+  // still original until every wave has read it)
+  constexpr int MQ = (NB + 3) / 4;  // tiles of one block row per wave
+  for (int Il = 1; Il < NB; ++Il) {
+    v4d res[MQ];
+#pragma unroll
+    for (int q = 0; q < MQ; ++q) {
+      res[q] = (v4d){0.0, 0.0, 0.0, 0.0};
+      const int J = wid + 4 * q;
+      if (J < Il) {
+        v4d pp = {0.0, 0.0, 0.0, 0.0};
+        for (int K = J; K < Il; ++K)
+#pragma unroll
+          for (int kk = 0; kk < 16; kk += 4) {
+            const double av = X[Il * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
+            const int kr = K * 16 + kk + (lane >> 4), jc = J * 16 + (lane & 15);
+            const double bv = (K == J) ? (kr == jc ? 1.0 : (kr > jc ? X[kr][jc] : 0.0)) : X[kr][jc];
+            pp = mfma16x(av, bv, pp);
+          }
+        // slot v of the accumulator is the B operand of step v of the next product
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ar = Il * 16 + (lane & 15), ac = Il * 16 + 4 * v + (lane >> 4);
+          const double av = (ar == ac) ? 1.0 : (ar > ac ? X[ar][ac] : 0.0);
+          res[q] = mfma16x(av, -pp[v], res[q]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MQ; ++q) {
+      const int J = wid + 4 * q;
+      if (J < Il)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[Il * 16 + mfma_out_row(0.0, lane, v)][J * 16 + (lane & 15)] = res[q][v];
+    }
+    __syncthreads();
+  }
   // T = -U_1 Sg L_1^{-T}: tile (I, J), I <= J: -sum_{K=I..J} U_IK Sg_K (Yl_JK)^T
   // (tiles below the block diagonal are zero; the tile list is the upper
   // triangle in row-major order, so the waves get similar K ranges)
@@ -472,7 +464,7 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
             const double av = (ar <= ac) ? X[ar][ac] * sg[ac] : 0.0;  // U_1 Sg
             const int br = K * 16 + kk + (lane >> 4), bc = J * 16 + (lane & 15);
             // (L_1^{-1})^T[br][bc] = Yl[bc][br]: nonzero for bc >= br, unit on the diagonal
-            const double bv = (bc == br) ? 1.0 : (bc > br ? Y[bc][br] : 0.0);
+            const double bv = (bc == br) ? 1.0 : (bc > br ? X[bc][br] : 0.0);
             acc = mfma16x(av, bv, acc);
           }
         }
@@ -483,6 +475,54 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
       const int i = I * 16 + mfma_out_row(0.0, lane, v), c = J * 16 + (lane & 15);
       if (i < r && c < r) Tm[i + (int64_t)c * r] = (T)(i <= c ? -acc[v] : 0.0);
     }
+  }
+  __syncthreads();
+  // U_1^{-1}: diagonal blocks from the registers, then block rows bottom-up:
+  // Yu_IJ = -Yu_II sum_{K=I+1..J} U_IK Yu_KJ (rows below I already inverted)
+  if (b < NB) {
+    const int o = b * 16;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (i <= cc) X[o + i][o + cc] = xu[i];
+  }
+  __syncthreads();
+  for (int Iu = NB - 2; Iu >= 0; --Iu) {
+    v4d res[MQ];
+#pragma unroll
+    for (int q = 0; q < MQ; ++q) {
+      res[q] = (v4d){0.0, 0.0, 0.0, 0.0};
+      const int J = Iu + 1 + wid + 4 * q;
+      if (J < NB) {
+        v4d pp = {0.0, 0.0, 0.0, 0.0};
+        for (int K = Iu + 1; K <= J; ++K)
+#pragma unroll
+          for (int kk = 0; kk < 16; kk += 4) {
+            const double av = X[Iu * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
+            const int kr = K * 16 + kk + (lane >> 4), jc = J * 16 + (lane & 15);
+            const double bv = (K == J && kr > jc) ? 0.0 : X[kr][jc];  // upper part of the diagonal block
+            pp = mfma16x(av, bv, pp);
+          }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int ar = Iu * 16 + (lane & 15), ac = Iu * 16 + 4 * v + (lane >> 4);
+          const double av = (ar <= ac) ? X[ar][ac] : 0.0;
+          res[q] = mfma16x(av, pp[v], res[q]);
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MQ; ++q) {
+      const int J = Iu + 1 + wid + 4 * q;
+      if (J < NB)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) X[Iu * 16 + mfma_out_row(0.0, lane, v)][J * 16 + (lane & 15)] = -res[q][v];
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < r * r; e += 256) {
+    const int i = e % r, c = e / r;
+    U1i[e] = (T)(i <= c ? X[i][c] : 0.0);
   }
 }
 
