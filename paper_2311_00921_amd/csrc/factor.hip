@@ -1596,6 +1596,7 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
       Prof pf(cx, "gemm_Y=VT", l);
       gemm_run<T>(st[2], false, false, 1.0, 0.0, s);      // Y = V T
     }
+    if (hoist && si == 0) fork_upper_basis();
     {
       Prof pf(cx, "gemm_W=MY", l);
       gemm_run<T>(st[3], false, false, 1.0, 0.0, s);      // W = M Y
@@ -1612,7 +1613,6 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
       Prof pf(cx, "gemm_F_update", l);
       gemm_run<T>(st[6], false, true, -1.0, 1.0, s);      // F = P^T (M - Z V^T - V Z^T) P
     }
-    if (hoist && si == 0) fork_upper_basis();
     // With FP32 compute a stage that holds roots is factored by the blocked
     // kernel, so that the roots can be done in FP64.
     const bool use_inv = lp.inv && !(fp32 && nonroot < lp.count);
