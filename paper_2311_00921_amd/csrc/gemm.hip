@@ -6,7 +6,8 @@
 // grid.x the BM x BN output tiles of that entry. Each 256-thread workgroup
 // stages BM x BK slices of op(A) and BK x BN slices of op(B) in LDS; each of
 // its four waves owns a (BM/2) x (BN/2) quadrant of the tile as a grid of
-// 16x16 MFMA accumulators. The tile shape is one of a few compiled variants,
+// 16x16 MFMA accumulators, computed transposed so that the stores of the
+// column-major output coalesce. The tile shape is one of a few compiled variants,
 // picked per batch by the autotuner (default 64 x 64).
 #include "hss_internal.h"
 
@@ -53,67 +54,6 @@ __device__ __forceinline__ int perm_index(int t, int dim, int r) {
   return r > 0 ? (t < r ? t + (dim - r) : t - r) : t;
 }
 
-template <typename T, bool TA, bool TB, int BM, int BN, int BK>
-__device__ __forceinline__ void load_tiles(const GemmDesc& d, const T* __restrict__ A, const T* __restrict__ B,
-                                           int row0, int col0, int k0, T (&ra)[BM * BK / 256],
-                                           T (&rb)[BN * BK / 256]) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int q = 0; q < BM * BK / 256; ++q) {
-    const int e = q * 256 + tid;
-    int r, kk;
-    if (!TA) {
-      r = e % BM;
-      kk = e / BM;
-    } else {
-      kk = e % BK;
-      r = e / BK;
-    }
-    const int gr = row0 + r, gk = k0 + kk;
-    T v = 0;
-    if (gr < d.m && gk < d.k) v = TA ? A[gk + (int64_t)gr * d.lda] : A[gr + (int64_t)gk * d.lda];
-    ra[q] = v;
-  }
-#pragma unroll
-  for (int q = 0; q < BN * BK / 256; ++q) {
-    const int e = q * 256 + tid;
-    int c, kk;
-    if (!TB) {
-      kk = e % BK;
-      c = e / BK;
-    } else {
-      c = e % BN;
-      kk = e / BN;
-    }
-    const int gc = col0 + c, gk = k0 + kk;
-    T v = 0;
-    if (gc < d.n && gk < d.k) v = TB ? B[gc + (int64_t)gk * d.ldb] : B[gk + (int64_t)gc * d.ldb];
-    rb[q] = v;
-  }
-}
-
-template <typename T, bool TA, bool TB, int BM, int BN, int BK>
-__device__ __forceinline__ void store_tiles(T (&As)[BK][BM + LPAD], T (&Bs)[BK][BN + LPAD], const T (&ra)[BM * BK / 256],
-                                            const T (&rb)[BN * BK / 256]) {
-  const int tid = threadIdx.x;
-#pragma unroll
-  for (int q = 0; q < BM * BK / 256; ++q) {
-    const int e = q * 256 + tid;
-    if (!TA)
-      As[e / BM][e % BM] = ra[q];
-    else
-      As[e % BK][e / BK] = ra[q];
-  }
-#pragma unroll
-  for (int q = 0; q < BN * BK / 256; ++q) {
-    const int e = q * 256 + tid;
-    if (!TB)
-      Bs[e % BK][e / BK] = rb[q];
-    else
-      Bs[e / BN][e % BN] = rb[q];
-  }
-}
-
 // Workgroups are dealt to the 8 XCDs round-robin by linear id, and each XCD
 // has its own L2. The logical (tile, entry) of a workgroup is chosen so that
 // consecutive workgroups of one XCD take consecutive tiles of the same batch
@@ -151,11 +91,44 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   }
   __shared__ T As[BK][BM + LPAD];
   __shared__ T Bs[BK][BN + LPAD];
+  constexpr int QA = BM * BK / 256, QB = BN * BK / 256;  // elements per thread and K slice
   const T* __restrict__ A = (const T*)d.A;
   const T* __restrict__ B = (const T*)d.B;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   const int wm = (wid >> 1) * (BM / 2), wn = (wid & 1) * (BN / 2);
   const int lr = lane & 15, lk = lane >> 4;
+  // interior tiles (the whole tile inside the output and no partial K slice)
+  // load without bounds checks, by pointers stepped once per K slice
+  const bool interior = row0 + BM <= d.m && col0 + BN <= d.n && d.k % BK == 0;
+  int ar[QA], ak[QA], bc[QB], bk[QB];
+  const T* pa[QA];
+  const T* pb[QB];
+#pragma unroll
+  for (int q = 0; q < QA; ++q) {
+    const int e = q * 256 + tid;
+    if (!TA) {
+      ar[q] = e % BM;
+      ak[q] = e / BM;
+    } else {
+      ak[q] = e % BK;
+      ar[q] = e / BK;
+    }
+    pa[q] = TA ? A + ak[q] + (int64_t)(row0 + ar[q]) * d.lda : A + (row0 + ar[q]) + (int64_t)ak[q] * d.lda;
+  }
+#pragma unroll
+  for (int q = 0; q < QB; ++q) {
+    const int e = q * 256 + tid;
+    if (!TB) {
+      bk[q] = e % BK;
+      bc[q] = e / BK;
+    } else {
+      bc[q] = e % BN;
+      bk[q] = e / BN;
+    }
+    pb[q] = TB ? B + (col0 + bc[q]) + (int64_t)bk[q] * d.ldb : B + bk[q] + (int64_t)(col0 + bc[q]) * d.ldb;
+  }
+  const int64_t sa = TA ? BK : (int64_t)BK * d.lda;
+  const int64_t sb = TB ? (int64_t)BK * d.ldb : BK;
   typename AccT<T>::type acc[IM][JN];
 #pragma unroll
   for (int i = 0; i < IM; ++i)
@@ -163,14 +136,42 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
     for (int j = 0; j < JN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
-  T ra[BM * BK / 256], rb[BN * BK / 256];
+  T ra[QA], rb[QB];
+  auto load = [&](int k0) {
+    if (interior) {
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        ra[q] = *pa[q];
+        pa[q] += sa;
+      }
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        rb[q] = *pb[q];
+        pb[q] += sb;
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < QA; ++q) {
+        ra[q] = (row0 + ar[q] < d.m && k0 + ak[q] < d.k) ? *pa[q] : (T)0;
+        pa[q] += sa;
+      }
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        rb[q] = (col0 + bc[q] < d.n && k0 + bk[q] < d.k) ? *pb[q] : (T)0;
+        pb[q] += sb;
+      }
+    }
+  };
   // software pipeline: the next K slice is fetched into registers while the
   // matrix cores consume the current one from LDS
-  if (d.k > 0) load_tiles<T, TA, TB, BM, BN, BK>(d, A, B, row0, col0, 0, ra, rb);
+  if (d.k > 0) load(0);
   for (int k0 = 0; k0 < d.k; k0 += BK) {
-    store_tiles<T, TA, TB, BM, BN, BK>(As, Bs, ra, rb);
+#pragma unroll
+    for (int q = 0; q < QA; ++q) As[ak[q]][ar[q]] = ra[q];
+#pragma unroll
+    for (int q = 0; q < QB; ++q) Bs[bk[q]][bc[q]] = rb[q];
     __syncthreads();
-    if (k0 + BK < d.k) load_tiles<T, TA, TB, BM, BN, BK>(d, A, B, row0, col0, k0 + BK, ra, rb);
+    if (k0 + BK < d.k) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       T a[IM], b[JN];
@@ -178,10 +179,12 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
       for (int i = 0; i < IM; ++i) a[i] = As[kk + lk][wm + 16 * i + lr];
 #pragma unroll
       for (int j = 0; j < JN; ++j) b[j] = Bs[kk + lk][wn + 16 * j + lr];
+      // operands swapped: the accumulator holds the transposed 16 x 16 tile,
+      // so that lanes run along the output's rows (column-major stores coalesce)
 #pragma unroll
       for (int i = 0; i < IM; ++i)
 #pragma unroll
-        for (int j = 0; j < JN; ++j) acc[i][j] = mfma16(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < JN; ++j) acc[i][j] = mfma16(b[j], a[i], acc[i][j]);
     }
     __syncthreads();
   }
@@ -194,8 +197,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
     for (int j = 0; j < JN; ++j)
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int row = row0 + wm + 16 * i + mfma_row((T)0, lane, v);
-        const int col = col0 + wn + 16 * j + lr;
+        const int row = row0 + wm + 16 * i + lr;
+        const int col = col0 + wn + 16 * j + mfma_row((T)0, lane, v);
         if (row < d.m && col < d.n) {
           const int prow = perm_index(row, d.m, d.perm_r);
           const int pcol = perm_index(col, d.n, d.perm_r);
