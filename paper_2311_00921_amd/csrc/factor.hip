@@ -530,10 +530,13 @@ __global__ __launch_bounds__(256) void k_basis_top(const NodeDesc* __restrict__ 
 // merge: parent block from the children's Schur complements and the coupling
 // ---------------------------------------------------------------------------
 
+// With coupling_only, only the S and S^T blocks are written (the children's
+// kernels then write Sg Sigma Sg into the diagonal blocks themselves).
 template <typename T>
 __global__ __launch_bounds__(256) void k_merge(const NodeDesc* __restrict__ nodes, int first,
                                                const T* __restrict__ Fbase, const T* __restrict__ Sgbase,
-                                               const T* __restrict__ Sbase, T* __restrict__ Mbase) {
+                                               const T* __restrict__ Sbase, T* __restrict__ Mbase,
+                                               int coupling_only) {
   // one 32 x 32 tile of one parent's block per workgroup (grid.y runs over the tiles)
   const int p = first + blockIdx.x;
   const NodeDesc nd = nodes[p];
@@ -597,7 +600,7 @@ __global__ __launch_bounds__(256) void k_merge(const NodeDesc* __restrict__ node
 #pragma unroll
   for (int rr = 0; rr < 4; ++rr) {
     const int i = i0 + a, j = j0 + b + 8 * rr;
-    if (i < n && j < n) M[i + (int64_t)j * n] = tile[a][b + 8 * rr];
+    if (i < n && j < n && (!coupling_only || ((i < r1) != (j < r1)))) M[i + (int64_t)j * n] = tile[a][b + 8 * rr];
   }
 }
 
@@ -605,6 +608,17 @@ __global__ __launch_bounds__(256) void k_merge(const NodeDesc* __restrict__ node
 // partial Cholesky: first m columns of a right-looking Cholesky of F (n x n)
 // 16-column panels; the trailing lower triangle is updated with MFMA tiles.
 // ---------------------------------------------------------------------------
+
+// Writes an entry of a child's Schur complement straight into its parent's
+// merged block: M_p[ro + i, ro + c] = M_p[ro + c, ro + i] = Sg_i Sg_c Sigma_ic,
+// with ro the child's row offset in the parent (what the merge would copy).
+template <typename T>
+__device__ __forceinline__ void sigma_to_parent(T* __restrict__ Mp, int pn, int ro, const T* __restrict__ sg, int i,
+                                                int c, T val) {
+  const T v = sg[i] * sg[c] * val;
+  Mp[(ro + i) + (int64_t)(ro + c) * pn] = v;
+  Mp[(ro + c) + (int64_t)(ro + i) * pn] = v;
+}
 
 // Cholesky of a 16-column panel on one wave. Lanes 0..15 hold rows 0..15 of
 // the 16 x 16 pivot block (a[c], c <= lane); lanes 16..63 may hold further
@@ -796,7 +810,8 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_pchol(const NodeDesc* __restr
 
 template <typename T, int RMAX, int MMAX>
 __global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ nodes, int first,
-                                                  T* __restrict__ Fbase) {
+                                                  T* __restrict__ Fbase, T* __restrict__ Mbase,
+                                                  const T* __restrict__ Sgbase) {
   constexpr int NT = 512, NW = NT / 64;
   constexpr int RT = RMAX / 16;  // row tiles of L_SR
   static_assert(RMAX <= 2 * 64 && RMAX % 16 == 0 && MMAX % 16 == 0, "rows of L_SR on two waves, 16-wide tiles");
@@ -904,7 +919,11 @@ __global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ n
     if (i < r)
       for (int c = tid / RMAX; c < m; c += NT / RMAX) F[(m + i) + (int64_t)c * n] = X[i][c];
   }
-  // Sigma = F_SS - L_SR L_SR^T, lower tiles
+  // Sigma = F_SS - L_SR L_SR^T, lower tiles (also into the parent's merged
+  // block when Mbase is given)
+  T* Mp = (Mbase && nd.parent >= 0) ? Mbase + nodes[nd.parent].offM : nullptr;
+  const int pn = nd.parent >= 0 ? nodes[nd.parent].n : 0;
+  const T* sg = Sgbase + nd.offSg;
   for (int t = wid; t < RT * (RT + 1) / 2; t += NW) {
     int I = 0;
     while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -928,7 +947,11 @@ __global__ __launch_bounds__(512) void k_sr_schur(const NodeDesc* __restrict__ n
 #pragma unroll
     for (int v = 0; v < 4; ++v) {
       const int i = I * 16 + mfma_out_row((T)0, lane, v), c = J * 16 + (lane & 15);
-      if (i < r && c < r && i >= c) F[(m + i) + (int64_t)(m + c) * n] = cur[v] - acc[v];
+      if (i < r && c < r && i >= c) {
+        const T val = cur[v] - acc[v];
+        F[(m + i) + (int64_t)(m + c) * n] = val;
+        if (Mp) sigma_to_parent(Mp, pn, nd.child_row, sg, i, c, val);
+      }
     }
   }
 }
@@ -948,7 +971,8 @@ template <typename T, int RM, bool FUSE, int NT = 512>
 __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ nodes, int first,
                                                   T* __restrict__ Fbase, T* __restrict__ Libase,
                                                   const int64_t* __restrict__ offLi, int32_t* __restrict__ info,
-                                                  double* __restrict__ logdet, int part) {
+                                                  double* __restrict__ logdet, int part, T* __restrict__ Mbase,
+                                                  const T* __restrict__ Sgbase) {
   constexpr int NB = RM / 16, NW = NT / 64;
   const int node = first + blockIdx.x;
   const NodeDesc nd = nodes[node];
@@ -1143,7 +1167,11 @@ __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ no
     }
     // Sigma: lower tiles of the r x r block at (m, m); the K loop runs over the
     // whole frame (columns m..RM-1 of X are zero) so that it unrolls, and F_SS
-    // is fetched before the products
+    // is fetched before the products. With Mbase (part 0, not a root) it also
+    // goes straight into the parent's merged block.
+    T* Mp = (Mbase && part == 0 && nd.parent >= 0) ? Mbase + nodes[nd.parent].offM : nullptr;
+    const int pn = nd.parent >= 0 ? nodes[nd.parent].n : 0;
+    const T* sg = Sgbase + nd.offSg;
     for (int t = wid; t < RT * (RT + 1) / 2; t += NW) {
       int I = 0;
       while ((I + 1) * (I + 2) / 2 <= t) ++I;
@@ -1163,7 +1191,11 @@ __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ no
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int i = I * 16 + mfma_out_row(0.0, lane, v), c = J * 16 + (lane & 15);
-        if (i < r && c < r && i >= c) F[(m + i) + (int64_t)(m + c) * n] = (T)((double)cur[v] - sacc[v]);
+        if (i < r && c < r && i >= c) {
+          const T val = (T)((double)cur[v] - sacc[v]);
+          F[(m + i) + (int64_t)(m + c) * n] = val;
+          if (Mp) sigma_to_parent(Mp, pn, nd.child_row, sg, i, c, val);
+        }
       }
     }
   }
@@ -1278,8 +1310,8 @@ static void launch_pchol(const hss_matrix_t m, int first, int count, int nmax, T
 // L_RR by the right-looking sweep restricted to the R block, then L_SR and
 // Sigma from LDS.
 template <typename T>
-static void launch_pchol_split(const hss_matrix_t m, int first, int count, T* F, hipStream_t s, hss_ctx_t cx,
-                               int level) {
+static void launch_pchol_split(const hss_matrix_t m, int first, int count, T* F, T* Msink, const T* Sg,
+                               hipStream_t s, hss_ctx_t cx, int level) {
   {
     Prof pf(cx, "pchol_RR", level);
     hipLaunchKernelGGL((k_pchol<T, 256, false, 256, true>), dim3(count), dim3(256), 0, s, m->dnodes, first, F,
@@ -1287,7 +1319,7 @@ static void launch_pchol_split(const hss_matrix_t m, int first, int count, T* F,
     HSS_HIP(hipGetLastError());
   }
   Prof pf(cx, "sr_schur", level);
-  hipLaunchKernelGGL((k_sr_schur<T, 96, 160>), dim3(count), dim3(512), 0, s, m->dnodes, first, F);
+  hipLaunchKernelGGL((k_sr_schur<T, 96, 160>), dim3(count), dim3(512), 0, s, m->dnodes, first, F, Msink, Sg);
   HSS_HIP(hipGetLastError());
 }
 
@@ -1533,6 +1565,28 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
   hss_ctx_t cx = m->ctx;
   const bool fp32 = sizeof(T) == 4;
   const bool hoist = plan.size() > m->stages.size();
+  // When every stage's Schur complements come from k_sr_schur or the fused
+  // LDS Cholesky, those kernels write Sg Sigma Sg straight into the parents'
+  // merged blocks, the coupling blocks are written once on the second stream,
+  // and the per-stage merge launches disappear.
+  bool direct = hoist;
+  for (const LevelPlan& lp : m->stages) {
+    const int nonroot = lp.root_first - lp.first;
+    if (nonroot == 0) continue;
+    if (lp.inv && !(fp32 && nonroot < lp.count)) {
+      const int rm = lp.mmax <= 32 ? 32 : (lp.mmax <= 64 ? 64 : 96);
+      direct = direct && lp.rmax <= rm;
+    } else {
+      int rmax_nr = 0, mmax_nr = 0, nmax_nr = 0;
+      for (int k = lp.first; k < lp.root_first; ++k) {
+        rmax_nr = std::max(rmax_nr, m->nodes[k].r);
+        mmax_nr = std::max(mmax_nr, m->nodes[k].m);
+        nmax_nr = std::max(nmax_nr, m->nodes[k].n);
+      }
+      direct = direct && rmax_nr <= 96 && mmax_nr <= 160 && nmax_nr <= 256;
+    }
+  }
+  T* msink = direct ? b.M : nullptr;
   // basis QR of every node above the leaves, on the second stream once the
   // leaves' own basis QR is done (so that it overlaps the leaf stage's GEMMs
   // and partial Cholesky rather than the leaf basis QR itself)
@@ -1550,6 +1604,16 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
     cx->stream = a;  // the profiling records of this section go to the second stream
     try {
       Prof pf(cx, "basis_qr_upper", -1);
+      if (direct) {
+        // the S and S^T blocks of every merged block; the diagonal blocks come
+        // from the children's Schur complement kernels
+        int nmax = 0;
+        for (int k = lo; k < hi; ++k) nmax = std::max(nmax, m->nodes[k].n);
+        const int tpr = (nmax + 31) / 32;
+        hipLaunchKernelGGL((k_merge<T>), dim3(hi - lo, tpr * tpr), dim3(256), 0, a, m->dnodes, lo, (const T*)b.F,
+                           (const T*)b.Sg, b.S, b.M, 1);
+        HSS_HIP(hipGetLastError());
+      }
       launch_basis_top<T>(rmax, lo, hi - lo, m->dnodes, b, a);
       auto& hs = plan.back();
       gemm_run<T>(hs[0], false, false, 1.0, 0.0, a);  // V_2 = B_2 U_1^{-1}
@@ -1567,11 +1631,11 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
     const int nonroot = lp.root_first - lp.first;
     const bool basis_done = hoist && si > 0;
     if (hoist && si == 1) HSS_HIP(hipStreamWaitEvent(s, cx->ev_join, 0));
-    if (!lp.leaf) {
+    if (!lp.leaf && !direct) {
       Prof pf(cx, "merge", l);
       const int tpr = (lp.nmax + 31) / 32;
       hipLaunchKernelGGL((k_merge<T>), dim3(lp.count, tpr * tpr), dim3(256), 0, s, m->dnodes, lp.first,
-                         (const T*)b.F, (const T*)b.Sg, b.S, b.M);
+                         (const T*)b.F, (const T*)b.Sg, b.S, b.M, 0);
       HSS_HIP(hipGetLastError());
     }
     auto& st = plan[si];
@@ -1627,14 +1691,14 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
         dim3 grid(lp.count), block(512);
         if (hmax <= 64) {
           hipLaunchKernelGGL((k_chol_lds<T, 64, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 1);
+                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 1, (T*)nullptr, (const T*)b.Sg);
           hipLaunchKernelGGL((k_chol_lds<T, 64, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 2);
+                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 2, (T*)nullptr, (const T*)b.Sg);
         } else {
           hipLaunchKernelGGL((k_chol_lds<T, 96, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 1);
+                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 1, (T*)nullptr, (const T*)b.Sg);
           hipLaunchKernelGGL((k_chol_lds<T, 96, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 2);
+                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 2, (T*)nullptr, (const T*)b.Sg);
         }
         HSS_HIP(hipGetLastError());
       } else if (use_inv) {
@@ -1647,7 +1711,7 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
           Prof pf(cx, nonroot == 0 ? "root" : "chol_lds", l);
 #define CHOL_LDS(RM, FU)                                                                                      \
   hipLaunchKernelGGL((k_chol_lds<T, RM, FU>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,              \
-                     (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 0)
+                     (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 0, msink, (const T*)b.Sg)
           if (rm == 32) {
             if (fuse) CHOL_LDS(32, true); else CHOL_LDS(32, false);
           } else if (rm == 64) {
@@ -1680,7 +1744,7 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
           nmax_nr = std::max(nmax_nr, m->nodes[k].n);
         }
         if (nonroot > 0 && rmax_nr <= 96 && mmax_nr <= 160 && nmax_nr <= 256) {
-          launch_pchol_split<T>(m, lp.first, nonroot, b.F, s, cx, l);
+          launch_pchol_split<T>(m, lp.first, nonroot, b.F, msink, (const T*)b.Sg, s, cx, l);
         } else if (nonroot > 0) {
           Prof pf(cx, "pchol", l);
           launch_pchol<T>(m, lp.first, nonroot, lp.nmax, b.F, s);
