@@ -801,6 +801,130 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_pchol(const NodeDesc* __restr
 }
 
 // ---------------------------------------------------------------------------
+// Cholesky of the R block (m <= 16 NBT) entirely in LDS, for the nodes whose
+// R block is too large for a square frame: the lower triangle is kept as
+// packed 16 x 16 tiles (tile (I, J), I >= J, at I (I + 1) / 2 + J; element
+// (r, c) of a tile at c * 16 + r), beyond m a unit frame. Panels are factored
+// in registers (pivot block on lanes 0..15 of each wave taking part, the rows
+// below it on lanes 16..63, as in k_chol_lds); the trailing lower tiles are
+// updated on the matrix cores, computed transposed so that the tile stores
+// run along rows. F is read once and L_RR written once.
+// ---------------------------------------------------------------------------
+
+template <typename T, int NBT>
+__global__ __launch_bounds__(512) void k_pchol_rr_lds(const NodeDesc* __restrict__ nodes, int first,
+                                                      T* __restrict__ Fbase, int32_t* __restrict__ info,
+                                                      double* __restrict__ logdet) {
+  constexpr int NT = 512, NW = NT / 64, RM = 16 * NBT, NTILE = NBT * (NBT + 1) / 2;
+  static_assert(RM - 16 <= 48 * NW, "panel rows exceed the waves");
+  const int node = first + blockIdx.x;
+  const NodeDesc nd = nodes[node];
+  const int n = nd.n, m = nd.m;
+  T* F = Fbase + nd.offF;
+  __shared__ double Xt[NTILE][256];
+  __shared__ int fail;
+  __shared__ double lacc;
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  // stage: each wave loads whole tiles (4 elements per lane, columns of 16 rows coalesced)
+  for (int t = wid; t < NTILE; t += NW) {
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = t - I * (I + 1) / 2;
+    double v[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int w = q * 64 + lane, r = w & 15, c = w >> 4;
+      const int gi = I * 16 + r, gj = J * 16 + c;
+      v[q] = (gi < m && gj < m && gi >= gj) ? (double)F[gi + (int64_t)gj * n] : (gi == gj ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) Xt[t][q * 64 + lane] = v[q];
+  }
+  if (tid == 0) {
+    fail = -1;
+    lacc = 0.0;
+  }
+  __syncthreads();
+  for (int J = 0; J < NBT; ++J) {
+    const int j0 = J * 16;
+    const int dtile = J * (J + 1) / 2 + J;
+    double dk[16];
+    {
+      const int below = RM - j0 - 16;
+      const int nwp = below > 0 ? (below + 47) / 48 : 1;
+      if (wid < nwp) {
+        const int row = lane < 16 ? j0 + lane : j0 + 16 + 48 * wid + (lane - 16);
+        const bool valid = row < RM;
+        const int I = valid ? row >> 4 : J;
+        const int tt = I * (I + 1) / 2 + J, rr = valid ? row & 15 : 0;
+        double a[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) a[c] = valid ? Xt[tt][c * 16 + rr] : 0.0;
+        double lsum = 0.0, rd = 1.0;
+        const int jbl = m - j0 >= 16 ? 16 : (m - j0 > 0 ? m - j0 : 0);
+        int bad = panel_chol16(a, 16, lsum, rd);
+        if (bad >= jbl) bad = -1;
+        if (lane >= 16 && valid)
+#pragma unroll
+          for (int c = 0; c < 16; ++c) Xt[tt][c * 16 + rr] = a[c];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) dk[c] = a[c];
+        if (wid == 0 && lane == 0) {
+          lacc += lsum;
+          if (bad >= 0 && fail < 0) fail = j0 + bad;
+        }
+      }
+    }
+    __syncthreads();
+    if (wid == 0 && lane < 16)
+#pragma unroll
+      for (int c = 0; c < 16; ++c) Xt[dtile][c * 16 + lane] = (c <= lane) ? dk[c] : 0.0;
+    // trailing update: tiles (I2, J2), J < J2 <= I2, minus P_I2 P_J2^T with P the panel tiles
+    const int rem = NBT - J - 1;
+    const int ntl = rem * (rem + 1) / 2;
+    for (int t = wid; t < ntl; t += NW) {
+      int a = 0;
+      while ((a + 1) * (a + 2) / 2 <= t) ++a;
+      const int b = t - a * (a + 1) / 2;
+      const int I2 = J + 1 + a, J2 = J + 1 + b;
+      const int pI = I2 * (I2 + 1) / 2 + J, pJ = J2 * (J2 + 1) / 2 + J, o = I2 * (I2 + 1) / 2 + J2;
+      v4d acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int kk = 0; kk < 16; kk += 4) {
+        const int kq = (kk + (lane >> 4)) * 16 + (lane & 15);
+        acc = mfma16x(Xt[pJ][kq], Xt[pI][kq], acc);  // (P_I2 P_J2^T)^T
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) Xt[o][(mfma_out_row(0.0, lane, v)) * 16 + (lane & 15)] -= acc[v];
+    }
+    __syncthreads();
+    if (fail >= 0) break;
+  }
+  // L_RR back to F (lower triangle, rows and columns below m)
+  for (int t = wid; t < NTILE; t += NW) {
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= t) ++I;
+    const int J = t - I * (I + 1) / 2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int w = q * 64 + lane, r = w & 15, c = w >> 4;
+      const int gi = I * 16 + r, gj = J * 16 + c;
+      if (gi < m && gj < m && gi >= gj) F[gi + (int64_t)gj * n] = (T)Xt[t][w];
+    }
+  }
+  if (tid == 0) {
+    if (fail >= 0) {
+      if (atomicCAS(&info[0], 0, 1) == 0) {
+        info[1] = node;
+        info[2] = fail;
+      }
+      info[4 + nd.sys] = 1;  // per-system flag
+    }
+    logdet[node] = 2.0 * lacc;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // L_SR and Sigma after an RR-only partial Cholesky (r <= RMAX, m <= MMAX):
 // the r x m block F_SR is held in LDS while L_SR = F_SR L_RR^{-T} is solved in
 // 16-column steps (MFMA update with the finished columns, then a 16 x 16
@@ -1314,8 +1438,8 @@ static void launch_pchol_split(const hss_matrix_t m, int first, int count, T* F,
                                hipStream_t s, hss_ctx_t cx, int level) {
   {
     Prof pf(cx, "pchol_RR", level);
-    hipLaunchKernelGGL((k_pchol<T, 256, false, 256, true>), dim3(count), dim3(256), 0, s, m->dnodes, first, F,
-                       m->dinfo, m->dlogdet);
+    hipLaunchKernelGGL((k_pchol_rr_lds<T, 10>), dim3(count), dim3(512), 0, s, m->dnodes, first, F, m->dinfo,
+                       m->dlogdet);
     HSS_HIP(hipGetLastError());
   }
   Prof pf(cx, "sr_schur", level);
