@@ -15,8 +15,8 @@
 namespace hss {
 
 // Threads per node (NT): 1024 for stages of at most 512 nodes (two per compute
-// unit), where a node's
-// own memory-level parallelism bounds the time, 256 for the wide stages.
+// unit), where a node's own memory-level parallelism bounds the time, 256 for
+// the wide stages.
 constexpr int kSolveWideNodes = 512;
 constexpr int SNB = 16;   // block size of the blocked triangular solves
 constexpr int RC = 4;     // right-hand sides per pass
