@@ -545,6 +545,8 @@ __global__ __launch_bounds__(256) void k_merge(const NodeDesc* __restrict__ node
   const int tpr = (n + 31) / 32;
   if ((int)blockIdx.y >= tpr * tpr) return;
   const int i0 = (blockIdx.y % tpr) * 32, j0 = (blockIdx.y / tpr) * 32;
+  // tiles that lie inside one child's diagonal block hold nothing to write then
+  if (coupling_only && ((i0 + 32 <= r1 && j0 + 32 <= r1) || (i0 >= r1 && j0 >= r1))) return;
   T* M = Mbase + nd.offM;
   const T* F1 = Fbase + c1.offF;
   const T* F2 = Fbase + c2.offF;
@@ -563,10 +565,10 @@ __global__ __launch_bounds__(256) void k_merge(const NodeDesc* __restrict__ node
         T v;
         bool have = true;
         if (i < r1 && j < r1) {
-          have = i >= j;
+          have = !coupling_only && i >= j;
           v = have ? s1[i] * s1[j] * F1[(c1.m + i) + (int64_t)(c1.m + j) * c1.n] : (T)0;
         } else if (i >= r1 && j >= r1) {
-          have = i >= j;
+          have = !coupling_only && i >= j;
           v = have ? s2[i - r1] * s2[j - r1] * F2[(c2.m + i - r1) + (int64_t)(c2.m + j - r1) * c2.n] : (T)0;
         } else if (i < r1) {
           v = S[i + (int64_t)(j - r1) * r1];
@@ -582,7 +584,12 @@ __global__ __launch_bounds__(256) void k_merge(const NodeDesc* __restrict__ node
       if (i < n && j < n) {
         bool have = false;
         T v = (T)0;
-        if (i < r1 && j < r1 && i < j) {
+        if (coupling_only) {
+          if (i >= r1 && j < r1) {
+            have = true;
+            v = S[j + (int64_t)(i - r1) * r1];
+          }
+        } else if (i < r1 && j < r1 && i < j) {
           have = true;
           v = s1[i] * s1[j] * F1[(c1.m + j) + (int64_t)(c1.m + i) * c1.n];
         } else if (i >= r1 && j >= r1 && i < j) {
