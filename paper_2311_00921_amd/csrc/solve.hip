@@ -31,8 +31,8 @@ __device__ __forceinline__ T wave_sum(T v) {
 // out[j, c] = sum_{i < rows} A[i + j lda] x[i + c ldx] for j < cols: one wave per
 // column (coalesced reads of the column), wave reduction. x, out in LDS.
 template <int NT, typename T>
-__device__ void col_dots(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* x, int ldx, T* out,
-                         int ldo, int nc) {
+__device__ __forceinline__ void col_dots(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* x,
+                                         int ldx, T* out, int ldo, int nc) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   constexpr int CW = 4;  // columns per wave per pass
   for (int j0 = wid * CW; j0 < cols; j0 += (NT / 64) * CW) {
@@ -68,8 +68,8 @@ __device__ void col_dots(const T* __restrict__ A, int64_t lda, int rows, int col
 // wave reduction is needed; the partial sums meet in LDS (red: NT * RC
 // entries). Ends with a barrier.
 template <int NT, typename T>
-__device__ void col_dots_split(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* x, int ldx,
-                               T* out, int ldo, int nc, T* red) {
+__device__ __forceinline__ void col_dots_split(const T* __restrict__ A, int64_t lda, int rows, int cols,
+                                               const T* x, int ldx, T* out, int ldo, int nc, T* red) {
   const int t = threadIdx.x;
   for (int jb = 0; jb < cols; jb += NT) {
     const int cw = min(cols - jb, NT);
@@ -126,8 +126,8 @@ __device__ __forceinline__ void col_dots_node(const T* __restrict__ A, int64_t l
 
 // y[i, c] (+)= sign * sum_{j < cols} A[i + j lda] u[j + c ldu] for i < rows: one thread per row.
 template <int NT, typename T>
-__device__ void row_gemv(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* u, int ldu, T* y,
-                         int ldy, int nc, T sign) {
+__device__ __forceinline__ void row_gemv(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* u,
+                                         int ldu, T* y, int ldy, int nc, T sign) {
   for (int i = threadIdx.x; i < rows; i += NT) {
     T acc[RC];
 #pragma unroll
@@ -160,8 +160,8 @@ __device__ void row_gemv(const T* __restrict__ A, int64_t lda, int rows, int col
 // threads busy, so each group covers a slice of the columns and the partial
 // sums meet in LDS (red: (NT / 256) * 512 entries). Caller synchronizes after.
 template <int NT, typename T>
-__device__ void row_gemv_wide(const T* __restrict__ A, int64_t lda, int rows, int cols, const T* u, int ldu, T* y,
-                              int ldy, int nc, T sign, T* red) {
+__device__ __forceinline__ void row_gemv_wide(const T* __restrict__ A, int64_t lda, int rows, int cols,
+                                              const T* u, int ldu, T* y, int ldy, int nc, T sign, T* red) {
   constexpr int G = NT / 256;
   if (G == 1 || nc != 1 || rows > 512) {
     row_gemv<NT>(A, lda, rows, cols, u, ldu, y, ldy, nc, sign);
@@ -204,7 +204,7 @@ __device__ __forceinline__ float bcast_lane(float v, int l) {
 // In place y = L^{-1} y, L = F[0:m, 0:m] lower (ld ldf); y in LDS (ld ldy).
 // 16-row diagonal blocks are solved by one wave; the rows below are updated by all threads.
 template <int NT, typename T>
-__device__ void lower_solve(const T* __restrict__ F, int ldf, int m, T* y, int ldy, int nc) {
+__device__ __forceinline__ void lower_solve(const T* __restrict__ F, int ldf, int m, T* y, int ldy, int nc) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int b0 = 0; b0 < m; b0 += SNB) {
     const int bb = min(SNB, m - b0);
@@ -244,7 +244,8 @@ __device__ void lower_solve(const T* __restrict__ F, int ldf, int m, T* y, int l
 
 // In place x = L^{-T} x, L = F[0:m, 0:m] lower.
 template <int NT, typename T>
-__device__ void lower_t_solve(const T* __restrict__ F, int ldf, int m, T* x, int ldx, int nc, T* scratch) {
+__device__ __forceinline__ void lower_t_solve(const T* __restrict__ F, int ldf, int m, T* x, int ldx, int nc,
+                                              T* scratch) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int nblk = (m + SNB - 1) / SNB;
   for (int bi = nblk - 1; bi >= 0; --bi) {
@@ -280,6 +281,168 @@ __device__ void lower_t_solve(const T* __restrict__ F, int ldf, int m, T* x, int
         if (lane < bb && c < nc) x[b0 + lane + c * ldx] = v[c];
     }
     __syncthreads();
+  }
+}
+
+// Forward substitution with the first m columns of F (n x n, lower, ld ldf)
+// over all n rows at once (n <= NT): rows i < m end as y_R = L_RR^{-1} b_R,
+// rows m..n-1 as b_S - L_SR y_R. Thread t owns row t, kept at y[pos(t)] with
+// pos(t) = rS + t for t < m and t - m after. Each 16-column block is solved on
+// the wave holding its rows (readlane chain; that wave's rows below the block
+// take the block's update in the same chain); the other waves below apply the
+// update with the block's solution from LDS (ys: 2 * SNB * RC entries, double
+// buffered, so one barrier per block). A row's entries of the next block are
+// loaded while the current one is solved, all loads coalesced along the rows.
+template <int NT, typename T>
+__device__ __forceinline__ void lower_solve_rows(const T* __restrict__ F, int ldf, int m, int n, T* y, int ldy,
+                                                 int rS, int nc, T* ys) {
+  const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+  const bool act = t < n;
+  const int pos = t < m ? rS + t : t - m;
+  T v[RC];
+#pragma unroll
+  for (int c = 0; c < RC; ++c) v[c] = (act && c < nc) ? y[pos + c * ldy] : (T)0;
+  const T rinv = (t < m) ? (T)1 / F[t + (int64_t)t * ldf] : (T)1;
+  const T* __restrict__ Frow = F + t;
+  T cur[SNB], nxt[SNB];
+  auto fetch = [&](int b0, T(&d)[SNB]) {
+#pragma unroll
+    for (int q = 0; q < SNB; ++q) {
+      const int c = b0 + q;
+      d[q] = (act && c < m && c <= t) ? Frow[(int64_t)c * ldf] : (T)0;
+    }
+  };
+  fetch(0, cur);
+  const int nblk = (m + SNB - 1) / SNB;
+  for (int j = 0; j < nblk; ++j) {
+    const int b0 = j * SNB, bb = min(SNB, m - b0);
+    if (j + 1 < nblk) fetch(b0 + SNB, nxt);
+    T* yb = ys + (j & 1) * SNB * RC;
+    const int cw = b0 >> 6;  // blocks start at multiples of 16, so one wave holds all rows of a block
+    if (wid == cw) {
+      const int base = b0 & 63;
+#pragma unroll
+      for (int k = 0; k < SNB; ++k) {
+        if (k < bb) {
+          const T rk = bcast_lane(rinv, base + k);
+#pragma unroll
+          for (int c = 0; c < RC; ++c) {
+            if (c < nc) {
+              const T yk = bcast_lane(v[c], base + k) * rk;
+              if (lane == base + k) v[c] = yk;
+              else if (lane > base + k) v[c] -= cur[k] * yk;
+            }
+          }
+        }
+      }
+      if (lane >= base && lane < base + bb)
+#pragma unroll
+        for (int c = 0; c < RC; ++c)
+          if (c < nc) yb[(lane - base) + c * SNB] = v[c];
+    }
+    __syncthreads();
+    if (wid > cw && act) {
+#pragma unroll
+      for (int q = 0; q < SNB; ++q)
+        if (q < bb)
+#pragma unroll
+          for (int c = 0; c < RC; ++c)
+            if (c < nc) v[c] -= cur[q] * yb[q + c * SNB];
+    }
+#pragma unroll
+    for (int q = 0; q < SNB; ++q) cur[q] = nxt[q];
+  }
+  if (act)
+#pragma unroll
+    for (int c = 0; c < RC; ++c)
+      if (c < nc) y[pos + c * ldy] = v[c];
+}
+
+// Columns per lane group in lower_t_solve_cols: L_RR of at most 16 * kTBlocks
+// columns.
+constexpr int kTBlocks = 10;
+
+// x_R = L_RR^{-T} (y_R - L_SR^T x_S), L = the first m columns of F (n x n,
+// lower, ld ldf), one right-hand side, four waves, m <= 16 * kTBlocks. x holds
+// x_S at 0..r-1 and y_R at r..r+m-1 on entry, x_R there on exit. Lane (p, g)
+// of wave w (p = lane & 15, g = lane >> 4) keeps in acc[k] its products of the
+// rows = p (mod 16) already solved with column 16 k + 4 w + g; the 16 sums of a
+// block are reduced over the lanes of each 16-lane group only when the
+// backward sweep reaches that block. So every entry of L is loaded once, each
+// load covering 16 consecutive rows of one column per 16 lanes, and a block's
+// rows are loaded while the previous block is solved. The 16 x 16 diagonal
+// block goes through LDS to wave 0, which solves it with a readlane chain
+// (sh: 16 * 17 + 32 entries). Two barriers per block.
+template <typename T>
+__device__ __forceinline__ void lower_t_solve_cols(const T* __restrict__ F, int ldf, int m, int r, T* x, T* sh) {
+  constexpr int KB = kTBlocks;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int p = lane & 15, cl = 4 * w + (lane >> 4);  // row within a block, column within a block
+  T* dg = sh;             // dg[i * 17 + c]: entry (i, c) of the diagonal block
+  T* sums = sh + 16 * 17;  // the block's reduced column sums
+  T* rdg = sums + 16;      // reciprocals of its diagonal entries
+  const int nblk = (m + 15) / 16;
+  T acc[KB];
+#pragma unroll
+  for (int k = 0; k < KB; ++k) acc[k] = 0;
+  // the S rows m..m+r-1, whose x_S is known
+  for (int s0 = 0; s0 < r; s0 += 16) {
+    const bool ok = s0 + p < r;
+    const T xs = ok ? x[s0 + p] : (T)0;
+    const T* __restrict__ Fr = F + (m + s0 + p);
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int c = 16 * k + cl;
+      if (ok && c < m) acc[k] += Fr[(int64_t)c * ldf] * xs;
+    }
+  }
+  T cur[KB], nxt[KB];
+  auto fetch = [&](int jj, T(&d)[KB]) {
+    const int row = 16 * jj + p;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int c = 16 * k + cl;
+      d[k] = (k <= jj && row < m && c <= row) ? F[row + (int64_t)c * ldf] : (T)0;
+    }
+  };
+  if (nblk > 0) fetch(nblk - 1, cur);
+  for (int jj = nblk - 1; jj >= 0; --jj) {
+    const int R0 = 16 * jj, bb = min(16, m - R0);
+    if (jj > 0) fetch(jj - 1, nxt);
+    T a = 0, d = 0;
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+      if (k == jj) {
+        a = acc[k];
+        d = cur[k];
+      }
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) a += __shfl_xor(a, o, 64);
+    if (p == 0) sums[cl] = a;
+    dg[p * 17 + cl] = d;
+    if (p == cl) rdg[cl] = (p < bb) ? (T)1 / d : (T)1;
+    __syncthreads();
+    if (w == 0) {
+      // lane q < 16 owns column R0 + q
+      T v = (lane < bb) ? x[r + R0 + lane] - sums[lane] : (T)0;
+      const T rq = (lane < 16) ? rdg[lane] : (T)1;
+#pragma unroll
+      for (int kk = 15; kk >= 0; --kk) {
+        if (kk < bb) {
+          const T xk = bcast_lane(v, kk) * bcast_lane(rq, kk);
+          if (lane == kk) v = xk;
+          else if (lane < kk) v -= dg[kk * 17 + lane] * xk;
+        }
+      }
+      if (lane < bb) x[r + R0 + lane] = v;
+    }
+    __syncthreads();
+    const T xp = (p < bb) ? x[r + R0 + p] : (T)0;
+#pragma unroll
+    for (int k = 0; k < KB; ++k)
+      if (k < jj) acc[k] += cur[k] * xp;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) cur[k] = nxt[k];
   }
 }
 
@@ -345,12 +508,18 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_fwd(const NodeDesc* __r
     for (int i = threadIdx.x; i < m; i += NT)
       for (int c = 0; c < nc; ++c) sb[r + i + c * n] = tm[i + c * m];
     __syncthreads();
+  } else if (n <= NT) {
+    // y_R and z_S = b^_S - L_SR y_R in one sweep over the first m columns of F
+    lower_solve_rows<NT>(F, n, m, n, sb, n, r, nc, tm);
+    __syncthreads();
   } else {
     lower_solve<NT>(F, n, m, sb + r, n, nc);
   }
-  // z_S = b^_S - L_SR y_R   (L_SR = F[m:n, 0:m])
-  row_gemv_wide<NT>(F + m, n, r, m, sb + r, n, sb, n, nc, (T)-1, red);
-  __syncthreads();
+  if (use_inv || n > NT) {
+    // z_S = b^_S - L_SR y_R   (L_SR = F[m:n, 0:m])
+    row_gemv_wide<NT>(F + m, n, r, m, sb + r, n, sb, n, nc, (T)-1, red);
+    __syncthreads();
+  }
   for (int i = threadIdx.x; i < m; i += NT)
     for (int c = 0; c < nc; ++c) vp[i + (int64_t)(c0 + c) * n] = sb[r + i + c * n];
   if (nd.parent < 0) return;  // a root: y = L^{-1} b is all that is left
@@ -393,13 +562,20 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_bwd(const NodeDesc* __r
   for (int i = threadIdx.x; i < m; i += NT)
     for (int c = 0; c < nc; ++c) sx[r + i + c * n] = vp[i + (int64_t)(c0 + c) * n];
   __syncthreads();
-  // t = y_R - L_SR^T x_S: tm[k] = sum_j L_SR[j, k] x_S[j] (column k of L_SR is contiguous)
-  col_dots_node<NT>(F + m, n, r, m, sx, n, tm, n, nc, red);
-  __syncthreads();
-  for (int k = threadIdx.x; k < m; k += NT)
-    for (int c = 0; c < nc; ++c) sx[r + k + c * n] -= tm[k + c * n];
-  __syncthreads();
-  if (use_inv == 2) {
+  // L_RR^{-T} (y_R - L_SR^T x_S) in one backward sweep over the first m columns of F
+  const bool by_cols = NT == 256 && !use_inv && nc == 1 && m <= 16 * kTBlocks;
+  if (!by_cols) {
+    // t = y_R - L_SR^T x_S: tm[k] = sum_j L_SR[j, k] x_S[j] (column k of L_SR is contiguous)
+    col_dots_node<NT>(F + m, n, r, m, sx, n, tm, n, nc, red);
+    __syncthreads();
+    for (int k = threadIdx.x; k < m; k += NT)
+      for (int c = 0; c < nc; ++c) sx[r + k + c * n] -= tm[k + c * n];
+    __syncthreads();
+  }
+  if (by_cols) {
+    if constexpr (NT == 256) lower_t_solve_cols(F, n, m, r, sx, tm);
+    __syncthreads();
+  } else if (use_inv == 2) {
     // a root factored in two blocks at h: x2 = L22^{-T} y2, x1 = L11^{-T} (y1 - L21^T x2)
     const int h = root_split_h(n), h2 = n - h;
     const T* Li1 = Lib + offLi[p];
