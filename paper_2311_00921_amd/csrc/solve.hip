@@ -63,55 +63,66 @@ __device__ __forceinline__ void col_dots(const T* __restrict__ A, int64_t lda, i
   }
 }
 
-// The same product for wide blocks (NT >= 1024, few nodes per launch): thread
-// t sums a contiguous chunk of rows of column t % cols (chunk t / cols), so no
-// wave reduction is needed; the partial sums meet in LDS (red: NT * RC
-// entries). Ends with a barrier.
+// The same product for wide blocks (NT >= 1024, few nodes per launch), in
+// 16-lane groups: lane p of a group reads rows p, p + 16, ... of the group's
+// columns, so that each load of a group is one 128-byte line, and a column's
+// 16 partial sums meet by shuffles within the group. Group q takes columns q
+// and q + NT / 16 of each pass; up to 16 * kColSegs rows of both columns are
+// loaded before any product (one memory latency per pass). Ends with a
+// barrier (red is not needed).
+constexpr int kColSegs = 12;
 template <int NT, typename T>
 __device__ __forceinline__ void col_dots_split(const T* __restrict__ A, int64_t lda, int rows, int cols,
                                                const T* x, int ldx, T* out, int ldo, int nc, T* red) {
-  const int t = threadIdx.x;
-  for (int jb = 0; jb < cols; jb += NT) {
-    const int cw = min(cols - jb, NT);
-    const int G = NT / cw;                  // row chunks per column
-    const int chunk = (rows + G - 1) / G;
-    const int g = t / cw, jl = t % cw;
-    if (g < G) {
-      T acc[RC];
+  constexpr int NG = NT / 16;
+  const int p = threadIdx.x & 15, grp = threadIdx.x >> 4;
+  for (int j0 = 0; j0 < cols; j0 += 2 * NG) {
+    int jc[2];
+    bool ok[2];
+    const T* __restrict__ a[2];
 #pragma unroll
-      for (int c = 0; c < RC; ++c) acc[c] = 0;
-      const int i0 = g * chunk, i1 = min(rows, i0 + chunk);
-      const T* __restrict__ a = A + (int64_t)(jb + jl) * lda;
-      int i = i0;
-      for (; i + 4 <= i1; i += 4) {
-        T v[4];
+    for (int h = 0; h < 2; ++h) {
+      jc[h] = j0 + grp + h * NG;
+      ok[h] = jc[h] < cols;
+      a[h] = A + (int64_t)min(jc[h], cols - 1) * lda;
+    }
+    T acc[2][RC];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) v[q] = a[i + q];
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+      for (int c = 0; c < RC; ++c) acc[h][c] = 0;
+    for (int s0 = 0; s0 < rows; s0 += 16 * kColSegs) {
+      T v[2][kColSegs];
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < kColSegs; ++q) {
+          const int i = s0 + 16 * q + p;
+          v[h][q] = (ok[h] && i < rows) ? a[h][i] : (T)0;
+        }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int q = 0; q < kColSegs; ++q) {
+          const int i = min(s0 + 16 * q + p, rows - 1);
 #pragma unroll
           for (int c = 0; c < RC; ++c)
-            if (c < nc) acc[c] += v[q] * x[i + q + c * ldx];
-      }
-      for (; i < i1; ++i) {
-        const T v = a[i];
-#pragma unroll
-        for (int c = 0; c < RC; ++c)
-          if (c < nc) acc[c] += v * x[i + c * ldx];
-      }
-#pragma unroll
-      for (int c = 0; c < RC; ++c)
-        if (c < nc) red[g * cw + jl + c * NT] = acc[c];
+            if (c < nc) acc[h][c] += v[h][q] * x[i + c * ldx];
+        }
     }
-    __syncthreads();
-    for (int q = t; q < cw; q += NT)
-      for (int c = 0; c < nc; ++c) {
-        T sum = 0;
-        for (int g2 = 0; g2 < G; ++g2) sum += red[g2 * cw + q + c * NT];
-        out[jb + q + c * ldo] = sum;
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int c = 0; c < RC; ++c) {
+        if (c < nc) {
+          T sum = acc[h][c];
+#pragma unroll
+          for (int o = 1; o < 16; o <<= 1) sum += __shfl_xor(sum, o, 64);
+          if (p == 0 && ok[h]) out[jc[h] + c * ldo] = sum;
+        }
       }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // col_dots for the solve kernels: the chunked form when a node has 1024 threads.
