@@ -222,6 +222,17 @@ hss_status hss_ulv_factor(hss_ctx_t ctx, hss_matrix_t m, const hss_factor_opts* 
 hss_status hss_ulv_solve(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, double* d_x,
                          int64_t nrhs, int64_t ld);
 
+/* FP64 factorization and solve in one call (Alg. 2, then Eq. 17): the same
+ * results as hss_ulv_factor (FP64) followed by hss_ulv_solve, for callers that
+ * hold the right-hand sides at factorization time. A stage's forward sweep
+ * needs only that stage's factors, so it runs on a second stream while the
+ * stages above it are factored; the backward sweep follows the root. Leaves
+ * the matrix FACTORED (or FAILED, with NOT_SPD as hss_ulv_factor; d_x is then
+ * undefined). Arguments as hss_ulv_solve; d_x may equal d_b. hss_info's
+ * factor_ms receives the time of the whole call. Synchronizes. */
+hss_status hss_ulv_factor_solve(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, double* d_x,
+                                int64_t nrhs, int64_t ld);
+
 /* Solve with iterative refinement: x_{k+1} = x_k + solve(b - A x_k), the
  * residual by the FP64 HSS matvec, until |b - A x|_2 <= tol |b|_2 for every
  * column, or max_iters corrections. If the residual stalls, switches to

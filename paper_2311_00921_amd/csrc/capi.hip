@@ -302,6 +302,7 @@ hss_status hss_ctx_destroy(hss_ctx_t ctx) {
   if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
   if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
   if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->ev_trail) (void)hipEventDestroy(ctx->ev_trail);
   delete ctx;
   HSS_API_END
 }
@@ -552,16 +553,14 @@ hss_status hss_export(hss_ctx_t ctx, hss_matrix_t m, hss_desc_out* o) {
   HSS_API_END
 }
 
-hss_status hss_ulv_factor(hss_ctx_t ctx, hss_matrix_t m, const hss_factor_opts* opts) {
-  HSS_API_BEGIN
-  HSS_CHECK(ctx && m, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
-  const int prec = opts ? opts->precision : HSS_P_FP64;
-  HSS_CHECK(prec == HSS_P_FP64 || prec == HSS_P_FP32, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
+// Runs a factorization (run() enqueues it on the context stream), then reads
+// the pivot status: FACTORED, or FAILED with the failing node and NOT_SPD.
+static void factor_checked(hss_ctx_t ctx, hss_matrix_t m, int prec, const std::function<void()>& run) {
   hipStream_t s = ctx->stream;
   m->state = 0;
   m->failed_level = m->failed_node = m->failed_pivot = m->failed_system = -1;
   HSS_HIP(hipEventRecord(ctx->ev0, s));
-  factor_run(m, prec);
+  run();
   HSS_HIP(hipEventRecord(ctx->ev1, s));
   int32_t info[4] = {0, 0, 0, 0};
   HSS_HIP(hipMemcpyAsync(info, m->dinfo, sizeof(info), hipMemcpyDeviceToHost, s));
@@ -581,6 +580,31 @@ hss_status hss_ulv_factor(hss_ctx_t ctx, hss_matrix_t m, const hss_factor_opts* 
                                      (m->nsys > 1 ? ", system " + std::to_string(m->failed_system) : "")};
   }
   m->state = 1;
+}
+
+hss_status hss_ulv_factor(hss_ctx_t ctx, hss_matrix_t m, const hss_factor_opts* opts) {
+  HSS_API_BEGIN
+  HSS_CHECK(ctx && m, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  const int prec = opts ? opts->precision : HSS_P_FP64;
+  HSS_CHECK(prec == HSS_P_FP64 || prec == HSS_P_FP32, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
+  factor_checked(ctx, m, prec, [&] { factor_run(m, prec); });
+  HSS_API_END
+}
+
+hss_status hss_ulv_factor_solve(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, double* d_x, int64_t nrhs,
+                                int64_t ld) {
+  HSS_API_BEGIN
+  HSS_CHECK(ctx && m && d_b && d_x, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  HSS_CHECK(nrhs >= 1 && ld >= m->n, HSS_ERR_INVALID_ARGUMENT, "need nrhs >= 1 and ld >= n");
+  factor_checked(ctx, m, HSS_P_FP64, [&] {
+    if (ctx->prof) {
+      // per-launch profiling times every launch on the context stream: no overlap
+      factor_fp64(m);
+      solve_fp64(m, d_b, d_x, nrhs, ld);
+    } else {
+      factor_solve_fp64(m, d_b, d_x, nrhs, ld);
+    }
+  });
   HSS_API_END
 }
 

@@ -1889,6 +1889,7 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
         }
       }
     }
+    if (m->after_stage) m->after_stage((int)si);
   }
 }
 

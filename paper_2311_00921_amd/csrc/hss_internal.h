@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -156,6 +157,7 @@ struct hss_ctx_s {
   hipStream_t cap_stream = nullptr;  // non-blocking stream used only to record graphs
   hipStream_t aux_stream = nullptr;  // second stream for work off the critical path
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_trail = nullptr;  // fused factor + solve: a stage factored / the forward sweep done
 };
 
 struct hss_matrix_s {
@@ -205,6 +207,8 @@ struct hss_matrix_s {
   bool factor_ready = false;
   std::vector<std::vector<hss::GemmBatch>> gemm_plan;  // per stage, per step
   std::vector<char> inv_used64, inv_used32;  // per stage: explicit inverse factor present
+  // called once the kernels of factor stage si are enqueued (fused factor + solve)
+  std::function<void(int)> after_stage;
 
   // FP32 factor (mixed precision)
   float* fF = nullptr;
@@ -299,6 +303,7 @@ double read_logdet(hss_matrix_t m);
 void free_factor(hss_matrix_t m);
 
 void prepare_factor(hss_matrix_t m, int precision);
+void factor_solve_fp64(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld);
 
 // batch.hip: forest layout, graph replay, autotuning
 void factor_run(hss_matrix_t m, int precision);

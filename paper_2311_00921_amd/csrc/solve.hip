@@ -770,40 +770,55 @@ void ensure_vec_ws(hss_matrix_t m, int64_t nrhs) {
   m->ws_nrhs = nrhs;
 }
 
-// Forward sweep over the stages leaves-first (roots finish with y = L^{-1} b),
-// then the backward sweep in the reverse order, RC right-hand sides at a time.
+// One stage of the forward sweep (roots finish with y = L^{-1} b) and of the
+// backward sweep, for right-hand sides c0 .. c0 + nc - 1, on stream s.
+template <typename T>
+static void launch_fwd(hss_matrix_t m, int si, const T* F, const T* V, const T* Yw, const T* Sg, T* vec, const T* Li,
+                       int inv, const double* b, int64_t nrhs, int64_t c0, int nc, int64_t ld, hipStream_t s) {
+  const LevelPlan& lp = m->stages[si];
+  if (lp.count <= kSolveWideNodes)
+    hipLaunchKernelGGL((k_solve_fwd<T, 1024>), dim3(lp.count), dim3(1024), 0, s, m->dnodes, lp.first, F, V, Yw, Sg,
+                       vec, nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, lp.leaf, Li,
+                       (const int64_t*)m->dOffLi, inv);
+  else
+    hipLaunchKernelGGL((k_solve_fwd<T, 256>), dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, F, V, Yw, Sg,
+                       vec, nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, lp.leaf, Li,
+                       (const int64_t*)m->dOffLi, inv);
+  HSS_HIP(hipGetLastError());
+}
+
+template <typename T>
+static void launch_bwd(hss_matrix_t m, int si, const T* F, const T* V, const T* Yw, const T* Sg, T* vec, const T* Li,
+                       int inv, double* x, int64_t nrhs, int64_t c0, int nc, int64_t ld, hipStream_t s) {
+  const LevelPlan& lp = m->stages[si];
+  if (lp.count <= kSolveWideNodes)
+    hipLaunchKernelGGL((k_solve_bwd<T, 1024>), dim3(lp.count), dim3(1024), 0, s, m->dnodes, lp.first, F, V, Yw, Sg,
+                       vec, nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, lp.leaf, Li,
+                       (const int64_t*)m->dOffLi, inv);
+  else
+    hipLaunchKernelGGL((k_solve_bwd<T, 256>), dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, F, V, Yw, Sg,
+                       vec, nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, lp.leaf, Li,
+                       (const int64_t*)m->dOffLi, inv);
+  HSS_HIP(hipGetLastError());
+}
+
+// Forward sweep over the stages leaves-first, then the backward sweep in the
+// reverse order, RC right-hand sides at a time (from column c_begin on).
 template <typename T>
 static void solve_impl(hss_matrix_t m, const T* F, const T* V, const T* Yw, const T* Sg, T* vec, const T* Li,
-                       const std::vector<char>& inv_used, const double* b, double* x, int64_t nrhs, int64_t ld) {
+                       const std::vector<char>& inv_used, const double* b, double* x, int64_t nrhs, int64_t ld,
+                       int64_t c_begin = 0) {
   hipStream_t s = m->ctx->stream;
   const int ns = (int)m->stages.size();
-  for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
+  for (int64_t c0 = c_begin; c0 < nrhs; c0 += RC) {
     const int nc = (int)std::min<int64_t>(RC, nrhs - c0);
     for (int si = 0; si < ns; ++si) {
-      const LevelPlan& lp = m->stages[si];
-      Prof pf(m->ctx, "solve_forward", lp.level);
-      if (lp.count <= kSolveWideNodes)
-        hipLaunchKernelGGL((k_solve_fwd<T, 1024>), dim3(lp.count), dim3(1024), 0, s, m->dnodes, lp.first, F, V, Yw,
-                           Sg, vec, nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, lp.leaf, Li,
-                           (const int64_t*)m->dOffLi, (int)inv_used[si]);
-      else
-        hipLaunchKernelGGL((k_solve_fwd<T, 256>), dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, F, V, Yw,
-                           Sg, vec, nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, lp.leaf, Li,
-                           (const int64_t*)m->dOffLi, (int)inv_used[si]);
-      HSS_HIP(hipGetLastError());
+      Prof pf(m->ctx, "solve_forward", m->stages[si].level);
+      launch_fwd<T>(m, si, F, V, Yw, Sg, vec, Li, inv_used[si], b, nrhs, c0, nc, ld, s);
     }
     for (int si = ns - 1; si >= 0; --si) {
-      const LevelPlan& lp = m->stages[si];
-      Prof pf(m->ctx, "solve_backward", lp.level);
-      if (lp.count <= kSolveWideNodes)
-        hipLaunchKernelGGL((k_solve_bwd<T, 1024>), dim3(lp.count), dim3(1024), 0, s, m->dnodes, lp.first, F, V, Yw,
-                           Sg, vec, nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, lp.leaf, Li,
-                           (const int64_t*)m->dOffLi, (int)inv_used[si]);
-      else
-        hipLaunchKernelGGL((k_solve_bwd<T, 256>), dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, F, V, Yw,
-                           Sg, vec, nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, lp.leaf, Li,
-                           (const int64_t*)m->dOffLi, (int)inv_used[si]);
-      HSS_HIP(hipGetLastError());
+      Prof pf(m->ctx, "solve_backward", m->stages[si].level);
+      launch_bwd<T>(m, si, F, V, Yw, Sg, vec, Li, inv_used[si], x, nrhs, c0, nc, ld, s);
     }
   }
 }
@@ -817,6 +832,43 @@ void solve_fp32(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_
   ensure_vec_ws(m, nrhs);
   if (!m->fvec) m->fvec = (float*)dev_alloc(sizeof(float) * std::max<int64_t>(m->sum_n * m->ws_nrhs, 1));
   solve_impl<float>(m, m->fF, m->fV, m->fW, m->fSg, m->fvec, m->fLi, m->inv_used32, b, x, nrhs, ld);
+}
+
+// FP64 factorization and solve in one pass. The forward sweep of a stage
+// needs only that stage's factors and its children's forward results, so it
+// is enqueued on the second stream as soon as the stage's factorization
+// kernels are, and runs while the stages above are factored (their kernels
+// are few and latency-bound and leave most compute units idle). The main
+// stream joins the second one after the root, then runs the backward sweep.
+// The first RC right-hand sides ride along; any further ones follow.
+void factor_solve_fp64(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld) {
+  hss_ctx_t cx = m->ctx;
+  hipStream_t s = cx->stream;
+  ensure_vec_ws(m, nrhs);
+  if (!cx->aux_stream) HSS_HIP(hipStreamCreateWithFlags(&cx->aux_stream, hipStreamNonBlocking));
+  if (!cx->ev_trail) HSS_HIP(hipEventCreateWithFlags(&cx->ev_trail, hipEventDisableTiming));
+  hipStream_t a = cx->aux_stream;
+  const int nc = (int)std::min<int64_t>(RC, nrhs);
+  m->after_stage = [&](int si) {
+    HSS_HIP(hipEventRecord(cx->ev_trail, s));
+    HSS_HIP(hipStreamWaitEvent(a, cx->ev_trail, 0));
+    launch_fwd<double>(m, si, m->dF, m->dV, m->dW, m->dSg, m->dvec, m->dLi, m->inv_used64[si], b, nrhs, 0, nc, ld,
+                       a);
+  };
+  try {
+    factor_fp64(m);
+  } catch (...) {
+    m->after_stage = nullptr;
+    throw;
+  }
+  m->after_stage = nullptr;
+  HSS_HIP(hipEventRecord(cx->ev_trail, a));
+  HSS_HIP(hipStreamWaitEvent(s, cx->ev_trail, 0));
+  for (int si = (int)m->stages.size() - 1; si >= 0; --si)
+    launch_bwd<double>(m, si, m->dF, m->dV, m->dW, m->dSg, m->dvec, m->dLi, m->inv_used64[si], x, nrhs, 0, nc, ld,
+                       s);
+  if (nrhs > RC)
+    solve_impl<double>(m, m->dF, m->dV, m->dW, m->dSg, m->dvec, m->dLi, m->inv_used64, b, x, nrhs, ld, RC);
 }
 
 // y = A x over the stages: up-sweep (leaves, then upward), couplings of every

@@ -100,6 +100,7 @@ SIGNATURES = {
     "hss_export": (C.c_int, [_P, _P, C.POINTER(hss_desc_out)]),
     "hss_ulv_factor": (C.c_int, [_P, _P, C.POINTER(hss_factor_opts)]),
     "hss_ulv_solve": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64]),
+    "hss_ulv_factor_solve": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64]),
     "hss_ulv_solve_refined": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64, C.c_double, C.c_int32,
                                         C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "hss_matvec": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64]),
@@ -345,6 +346,19 @@ def hss_ulv_solve(ctx, m, b, x=None):
     if x is None:
         x = torch.empty_strided(bc.shape, bc.stride(), dtype=torch.float64, device=b.device)
     _check(load().hss_ulv_solve(ctx, m, _ptr(bc), _ptr(x), k, ld), "hss_ulv_solve")
+    return x
+
+
+def hss_ulv_factor_solve(ctx, m, b, x=None):
+    """FP64 factorization and x = A^{-1} b in one call (forward sweep overlapped
+    with the factorization); b is a (N,) or (N, nrhs) float64 device tensor."""
+    import torch
+
+    n = b.shape[0]
+    bc, k, ld = _colmajor(b, n)
+    if x is None:
+        x = torch.empty_strided(bc.shape, bc.stride(), dtype=torch.float64, device=b.device)
+    _check(load().hss_ulv_factor_solve(ctx, m, _ptr(bc), _ptr(x), k, ld), "hss_ulv_factor_solve")
     return x
 
 

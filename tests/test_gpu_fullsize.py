@@ -8,8 +8,8 @@ second stream, root factored in two halves).
 The oracle cannot factor the whole matrix in test time, so the checks are
   (a) properties that hold at any size: the relative residual of the solve
       against the FP64 HSS matvec (itself pinned to the oracle on small
-      matrices), for one and for three right-hand sides, and graph replay
-      equal to eager launches;
+      matrices), for one and for three right-hand sides, graph replay equal
+      to eager launches, and the fused factor + solve equal to the two calls;
   (b) sampled outputs that the oracle computes one by one: the Schur
       complement Sigma of every node of a few subtrees, and the merged block
       at each subtree's root, from the oracle's factorization of that subtree
@@ -114,6 +114,20 @@ def test_fullsize_graph_replay_equals_eager(full):
             assert hss.hss_logdet(ctx, m) == ld0
     finally:
         hss.hss_use_graphs(ctx, m, False)
+
+
+def test_fullsize_fused_factor_solve_equals_separate(full):
+    torch, hss, ctx, m = full
+    b = torch.from_numpy(np.ascontiguousarray(synth.rhs_normal(W.n, 1, 31)[:, 0])).cuda()
+    hss.hss_ulv_factor(ctx, m)
+    x0 = hss.hss_ulv_solve(ctx, m, b).clone()
+    ld0 = hss.hss_logdet(ctx, m)
+    for rep in range(2):
+        print(f"case {W.name}: fused factor+solve {rep}", flush=True)
+        x1 = hss.hss_ulv_factor_solve(ctx, m, b)
+        torch.cuda.synchronize()
+        assert float(torch.abs(x1 - x0).max()) == 0.0
+        assert hss.hss_logdet(ctx, m) == ld0
 
 
 @pytest.fixture(scope="module")

@@ -170,3 +170,58 @@ def test_export_roundtrip(ctx, torch_dev):
                 np.testing.assert_array_equal(a, b)
     finally:
         hss.hss_matrix_destroy(m)
+
+
+@pytest.mark.parametrize("levels,leaf,rank,nrhs", [(3, 64, 16, 1), (2, 256, 96, 1), (5, 32, 12, 3), (3, 250, 90, 6),
+                                                   (1, 200, 40, 1)])
+def test_fused_factor_solve_equals_separate_calls(ctx, torch_dev, levels, leaf, rank, nrhs):
+    # the fused call reorders independent launches across two streams only:
+    # the same kernels on the same data, so the results are bit-identical
+    from paper_2311_00921_amd import hss
+
+    d = synth.random_hss(levels, leaf, rank, seed=levels * 100 + rank)
+    h = O.HSS(d["n"], d["levels"], d["ranges"], d["rank"], d["D"], d["U"], d["E"], d["S"])
+    print(f"case fused n={h.n} levels={levels} nrhs={nrhs}", flush=True)
+    m = hss.hss_import(ctx, oracle_to_dict(h))
+    try:
+        b = torch_dev.from_numpy(np.ascontiguousarray(synth.rhs_normal(h.n, nrhs, 5).T)).cuda().t()
+        hss.hss_ulv_factor(ctx, m)
+        x0 = hss.hss_ulv_solve(ctx, m, b).clone()
+        ld0 = hss.hss_logdet(ctx, m)
+        x1 = hss.hss_ulv_factor_solve(ctx, m, b)
+        torch_dev.cuda.synchronize()
+        assert float(torch_dev.abs(x1 - x0).max()) == 0.0
+        assert hss.hss_logdet(ctx, m) == ld0
+        assert hss.hss_get_info(m).factored == 1
+        # in place (x aliasing b)
+        bb = b.clone()
+        hss.hss_ulv_factor_solve(ctx, m, bb, x=bb)
+        torch_dev.cuda.synchronize()
+        assert float(torch_dev.abs(bb - x0).max()) == 0.0
+        F = O.ulv_factor(h)
+        x_or = O.ulv_solve(h, F, synth.rhs_normal(h.n, nrhs, 5))
+        assert rel(x1.cpu().numpy(), x_or) <= 1e-10
+    finally:
+        hss.hss_matrix_destroy(m)
+
+
+def test_fused_factor_solve_reports_not_spd(ctx, torch_dev):
+    from paper_2311_00921_amd import hss
+
+    X = synth.points_uniform(1024, 3, 1002)
+    kern = O.Kernel("matern32", 0.2, 1e-6)
+    t = O.build_tree(X, 64)
+    h = O.construct_plain(X, t, kern, rank=16)
+    m = hss.hss_import(ctx, oracle_to_dict(h))
+    try:
+        b = torch_dev.ones(1024, dtype=torch_dev.float64, device="cuda")
+        with pytest.raises(hss.HSSError) as eg:
+            hss.hss_ulv_factor_solve(ctx, m, b)
+        assert eg.value.status == hss.HSS_ERR_NOT_SPD
+        info = hss.hss_get_info(m)
+        assert info.factored == 0 and info.failed_level >= 0 and info.failed_node >= 0
+        with pytest.raises(hss.HSSError) as es:
+            hss.hss_ulv_solve(ctx, m, b)
+        assert es.value.status == hss.HSS_ERR_BAD_STATE
+    finally:
+        hss.hss_matrix_destroy(m)
