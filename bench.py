@@ -177,7 +177,7 @@ def main():
         rep = None
     elif not args.no_tune:
         print("# autotuning GEMM tiles (FP64)", file=sys.stderr, flush=True)
-        rep = hss.hss_autotune(ctx, m, hss.HSS_P_FP64, 2)
+        rep = hss.hss_autotune(ctx, m, hss.HSS_P_FP64, 4)
     if args.load_tiles or not args.no_tune:
         tile_choice = hss.hss_gemm_variants(m, hss.HSS_P_FP64)
         if args.save_tiles:

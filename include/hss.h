@@ -320,10 +320,12 @@ hss_status hss_use_graphs(hss_ctx_t ctx, hss_matrix_t m, int32_t on);
 /* Autotuner of the batched GEMM tile shapes (M x N x K per workgroup: 0:
  * 64x64x16, 1: 32x32x16, 2: 128x64x16, 3: 64x128x16, 4: 32x32x64, 5:
  * 64x64x32, 6: 64x96x16, 7: 96x96x16): runs the factorization in `precision`
- * once untimed, then `reps` times per tile shape, timing every batched GEMM
- * launch with HIP events, and keeps the fastest shape for each (stage, step).
+ * once untimed, then `reps` rounds of one factorization per tile shape (the
+ * shapes take turns), timing every batched GEMM launch with HIP events, and
+ * keeps for each (stage, step) the shape with the best time over the rounds.
  * h_report (nullable, 9 floats) receives the GEMM milliseconds per
- * factorization for each uniform shape and for the tuned choice. Leaves the matrix CONSTRUCTED: factor
+ * factorization (best over the rounds) for each uniform shape and for the
+ * tuned choice. Leaves the matrix CONSTRUCTED: factor
  * afterwards. Drops recorded graphs. Synchronizes. */
 hss_status hss_autotune(hss_ctx_t ctx, hss_matrix_t m, int32_t precision, int32_t reps, float* h_report);
 

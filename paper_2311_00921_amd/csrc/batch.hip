@@ -266,18 +266,28 @@ static void autotune(hss_matrix_t m, int precision, int reps, std::vector<float>
   } guard{&rec, m->ctx, prof};
   factor_direct(m, precision);  // warm-up
   g_tune = &rec;
-  for (int v = 0; v < kGemmVariants; ++v) {
-    for (auto& st : plan)
-      for (auto& g : st) g.variant = v;
-    for (int it = 0; it < reps; ++it) {
+  // the shapes take turns within each repetition, and each batch keeps its
+  // best time over the repetitions: drift and interference from the second
+  // stream then bias no shape
+  for (int it = 0; it < reps; ++it) {
+    for (int v = 0; v < kGemmVariants; ++v) {
+      for (auto& st : plan)
+        for (auto& g : st) g.variant = v;
       rec.recs.clear();
       rec.used = 0;
       factor_direct(m, precision);
       HSS_HIP(hipStreamSynchronize(s));
+      std::map<const GemmBatch*, double> once;  // per factorization (a batch may launch more than once)
       for (auto& r : rec.recs) {
         float ms = 0.f;
         HSS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
-        tm[r.batch][v] += ms;
+        once[r.batch] += ms;
+      }
+      for (auto& kv : once) {
+        auto ins = tm.try_emplace(kv.first);
+        if (ins.second) ins.first->second.fill(1e30);
+        double& slot = ins.first->second[v];
+        slot = std::min(slot, kv.second);
       }
     }
   }
@@ -292,10 +302,10 @@ static void autotune(hss_matrix_t m, int precision, int reps, std::vector<float>
       }
       int best = 0;
       for (int v = 0; v < kGemmVariants; ++v) {
-        total[v] += (float)(it->second[v] / reps);
+        total[v] += (float)it->second[v];
         if (it->second[v] < it->second[best]) best = v;
       }
-      total[kGemmVariants] += (float)(it->second[best] / reps);
+      total[kGemmVariants] += (float)it->second[best];
       g.variant = best;
     }
   if (report) report->assign(total, total + kGemmVariants + 1);
