@@ -1729,9 +1729,14 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
     if (!cx->aux_stream) HSS_HIP(hipStreamCreateWithFlags(&cx->aux_stream, hipStreamNonBlocking));
     if (!cx->ev_fork) HSS_HIP(hipEventCreateWithFlags(&cx->ev_fork, hipEventDisableTiming));
     if (!cx->ev_join) HSS_HIP(hipEventCreateWithFlags(&cx->ev_join, hipEventDisableTiming));
-    hipStream_t a = cx->aux_stream;
-    HSS_HIP(hipEventRecord(cx->ev_fork, s));
-    HSS_HIP(hipStreamWaitEvent(a, cx->ev_fork, 0));
+    // while the GEMM tiles are tuned the section stays on the main stream, so
+    // that every GEMM is timed without the other stream's work beside it
+    const bool serial = g_tune != nullptr;
+    hipStream_t a = serial ? s : cx->aux_stream;
+    if (!serial) {
+      HSS_HIP(hipEventRecord(cx->ev_fork, s));
+      HSS_HIP(hipStreamWaitEvent(a, cx->ev_fork, 0));
+    }
     cx->stream = a;  // the profiling records of this section go to the second stream
     try {
       Prof pf(cx, "basis_qr_upper", -1);
@@ -1754,14 +1759,14 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
       throw;
     }
     cx->stream = s;
-    HSS_HIP(hipEventRecord(cx->ev_join, a));
+    if (!serial) HSS_HIP(hipEventRecord(cx->ev_join, a));
   };
   for (size_t si = 0; si < m->stages.size(); ++si) {
     const LevelPlan& lp = m->stages[si];
     const int l = lp.level;
     const int nonroot = lp.root_first - lp.first;
     const bool basis_done = hoist && si > 0;
-    if (hoist && si == 1) HSS_HIP(hipStreamWaitEvent(s, cx->ev_join, 0));
+    if (hoist && si == 1 && !g_tune) HSS_HIP(hipStreamWaitEvent(s, cx->ev_join, 0));
     if (!lp.leaf && !direct) {
       Prof pf(cx, "merge", l);
       const int tpr = (lp.nmax + 31) / 32;
