@@ -91,6 +91,8 @@ def main():
                     help="only run a plain device copy of MIB MiB (for scaling hardware byte counters) and exit")
     ap.add_argument("--cpu-sample-level", type=int, default=3,
                     help="oracle timed on the subtree under one node of this level")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only run the one-GPU scaling sweeps (N and leaf size) and print them as one JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -111,6 +113,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": nel * 8, "copy_bytes_written": nel * 8}))
+        return
+    if args.sweep:
+        ctx = hss.hss_ctx_create(0)
+        print(json.dumps({"sweep": sweep_leg(hss, torch, np, ctx, args.steps, args.warmup)}))
+        hss.hss_ctx_destroy(ctx)
         return
     w = synth.WORKLOADS[args.workload]
     s = (w.rank if w.rank > 0 else 128) + w.oversample
@@ -335,6 +342,50 @@ def main():
         result["cpu_baseline"] = cpu_baseline(exp, nodes, args.cpu_sample_level, w)
     hss.hss_ctx_destroy(ctx)
     print(json.dumps(result))
+
+
+def sweep_leg(hss, torch, np, ctx, steps, warmup):
+    """One-GPU scaling sweeps for the paper's linear-complexity and leaf-size
+    claims (Sec. 5.4-5.5): the FP64 one-call factor + solve (autotuned tiles)
+    of the Matern-3/2 workload (3-D uniform points, length 0.2, nugget 1e-6,
+    scaled construction, rank 96) for N = 4096 .. 262144 at leaf 256, and for
+    leaf 128 and 512 at N = 262144."""
+    import dataclasses
+
+    import synth
+
+    base = synth.WORKLOADS["matern32_n262144"]
+    configs = [dataclasses.replace(base, name=f"matern32_n{n}", n=n) for n in
+               (4096, 8192, 16384, 32768, 65536, 131072, 262144)]
+    configs += [dataclasses.replace(base, name=f"matern32_n262144_leaf{lf}", leaf=lf) for lf in (128, 512)]
+    out = []
+    for w in configs:
+        print(f"# sweep: {w.name} N={w.n} leaf={w.leaf}", file=sys.stderr, flush=True)
+        s = w.rank + w.oversample
+        X = torch.from_numpy(w.points()).cuda()
+        Om = torch.from_numpy(np.ascontiguousarray(w.omega(s).T)).cuda().t()
+        b = torch.from_numpy(np.ascontiguousarray(w.rhs()[:, 0])).cuda()
+        m = hss.hss_construct(ctx, X, w.kernel, w.leaf, rank=w.rank, omega=Om, length=w.length, nugget=w.nugget)
+        del X, Om
+        try:
+            hss.hss_autotune(ctx, m, hss.HSS_P_FP64, 3)
+            for _ in range(warmup):
+                hss.hss_ulv_factor_solve(ctx, m, b)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            x = None
+            for _ in range(steps):
+                x = hss.hss_ulv_factor_solve(ctx, m, b)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t) / steps
+            rr = float(torch.linalg.norm(b - hss.hss_matvec(ctx, m, x)) / torch.linalg.norm(b))
+            info = hss.hss_get_info(m)
+            out.append({"workload": w.name, "N": w.n, "leaf": w.leaf, "levels": int(info.levels), "rank": w.rank,
+                        "factor_plus_solve_ms": round(dt * 1e3, 4), "ns_per_unknown": round(dt / w.n * 1e9, 3),
+                        "relres": rr})
+        finally:
+            hss.hss_matrix_destroy(m)
+    return out
 
 
 def measured_traffic(label, workload, tile):
