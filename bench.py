@@ -93,6 +93,8 @@ def main():
                     help="oracle timed on the subtree under one node of this level")
     ap.add_argument("--sweep", action="store_true",
                     help="only run the one-GPU scaling sweeps (N and leaf size) and print them as one JSON line")
+    ap.add_argument("--table2", action="store_true",
+                    help="only run the Table 2 accuracy leg (Eq. 18-19 on the 256 x 256 grid) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -117,6 +119,11 @@ def main():
     if args.sweep:
         ctx = hss.hss_ctx_create(0)
         print(json.dumps({"sweep": sweep_leg(hss, torch, np, ctx, args.steps, args.warmup)}))
+        hss.hss_ctx_destroy(ctx)
+        return
+    if args.table2:
+        ctx = hss.hss_ctx_create(0)
+        print(json.dumps({"table2": table2_leg(hss, torch, np, ctx)}))
         hss.hss_ctx_destroy(ctx)
         return
     w = synth.WORKLOADS[args.workload]
@@ -388,6 +395,58 @@ def sweep_leg(hss, torch, np, ctx, steps, warmup):
     return out
 
 
+def table2_leg(hss, torch, np, ctx):
+    """Accuracy on the paper's Table 2 setting (Sec. 5.1): N = 65536 points on
+    the uniform 256 x 256 grid, the three kernels of Table 3 (Laplace-2D,
+    Yukawa, and Matern with rho = 1/2, i.e. exp(-d / 0.03)), max rank 100,
+    leaf 256. Eq. 18 (construction error) on 256 sampled rows of A b with the
+    exact rows by direct kernel evaluation; Eq. 19 (solve error) in full. The
+    construction here is the scaled randomized one (the paper's is a pivoted
+    QR of dense blocks), so the construction errors are not expected to match;
+    the solve error measures the factorization alone. Table 2's other
+    (rank, leaf) rows need ranks above this library's 128."""
+    import dataclasses
+    import csv
+
+    import synth
+
+    with open(os.path.join(ROOT, "tests", "golden", "table2_hatrix.csv")) as f:
+        rows = [r for r in csv.reader(line for line in f if not line.startswith("#"))]
+    printed = {(int(r[0]), int(r[1])): [float(v) for v in r[2:]] for r in rows}[(100, 256)]
+    base = synth.Workload("table2_grid_n65536", 65536, 2, "exponential", 0.03, 0.0, 256, 100, geometry="grid2d",
+                          seed_k=5)
+    kernels = (("laplace2d", dict(kernel="laplace2d", extra={"eps": 1e-9, "alpha": 1.0}), 0),
+               ("yukawa", dict(kernel="yukawa", extra={"eps": 1e-9, "alpha": 1.0}), 2),
+               ("matern_rho_half_mu_0.03", dict(kernel="exponential"), 4))
+    out = []
+    for name, kw, col in kernels:
+        w = dataclasses.replace(base, name=f"table2_{name}", **kw)
+        print(f"# table2 leg: {name}", file=sys.stderr, flush=True)
+        s = w.rank + w.oversample
+        X = torch.from_numpy(w.points()).cuda()
+        Om = torch.from_numpy(np.ascontiguousarray(w.omega(s).T)).cuda().t()
+        b = torch.from_numpy(np.ascontiguousarray(w.rhs()[:, 0])).cuda()
+        extra = w.extra or {}
+        m = hss.hss_construct(ctx, X, w.kernel, w.leaf, rank=w.rank, omega=Om, length=w.length, nugget=w.nugget,
+                              alpha=extra.get("alpha", 1.0), eps=extra.get("eps", 1e-9))
+        rec = {"kernel": name, "N": w.n, "max_rank": w.rank, "leaf": w.leaf,
+               "paper_construct_error": printed[col], "paper_solve_error": printed[col + 1]}
+        try:
+            sel = torch.from_numpy(np.random.default_rng(78).choice(w.n, 256, replace=False)).cuda()
+            ab = hss.hss_matvec(ctx, m, b)
+            y_exact = exact_rows(torch, X, b, sel, w)
+            rec["construct_error_eq18_rows"] = float(torch.linalg.norm(ab[sel] - y_exact) / torch.linalg.norm(y_exact))
+            hss.hss_ulv_factor(ctx, m, hss.HSS_P_FP64)
+            x = hss.hss_ulv_solve(ctx, m, ab)
+            rec["solve_error_eq19"] = float(torch.linalg.norm(b - x) / torch.linalg.norm(b))
+        except hss.HSSError as e:
+            rec["error"] = str(e)
+        finally:
+            hss.hss_matrix_destroy(m)
+        out.append(rec)
+    return out
+
+
 def measured_traffic(label, workload, tile):
     """HBM bytes per launch of the profiled kernel from the committed counter
     summary (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's counters), or
@@ -503,6 +562,10 @@ def exact_rows(torch, X, v, rows, w):
         dist = torch.sqrt(((Xr[:, None, :] - Xc[None, :, :]) ** 2).sum(-1))
         if w.kernel == "exponential":
             K = torch.exp(-dist / w.length)
+        elif w.kernel == "laplace2d":
+            K = -torch.log(w.extra["eps"] + dist)
+        elif w.kernel == "yukawa":
+            K = torch.exp(-w.extra["alpha"] * (w.extra["eps"] + dist)) / (w.extra["eps"] + dist)
         elif w.kernel == "matern32":
             a = (3.0 ** 0.5) * dist / w.length
             K = (1.0 + a) * torch.exp(-a)
