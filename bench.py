@@ -97,7 +97,7 @@ def main():
                     help="only run the Table 2 accuracy leg (Eq. 18-19 on the 256 x 256 grid) and print it")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
