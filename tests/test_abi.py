@@ -56,3 +56,20 @@ def test_pack_unpack_roundtrip():
     for l in range(3):
         for a, b in zip(d["S"][l], q["S"][l]):
             np.testing.assert_array_equal(a, b)
+
+
+def test_header_declares_the_one_call_factor_solve():
+    assert "hss_ulv_factor_solve" in declared_symbols()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    # the benchmark is a one-GPU program: --gpus above 1 exits with a message
+    # before anything touches a device
+    import json
+    import subprocess
+    import sys
+
+    p = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in json.loads(p.stdout.strip().splitlines()[-1])["error"]
