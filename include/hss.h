@@ -196,7 +196,14 @@ typedef struct {
 } hss_construct_stats;
 hss_status hss_get_construct_stats(hss_matrix_t m, hss_construct_stats* out);
 
-/* Uploads a host HSS description (see hss_desc). Copies everything. */
+/* Uploads a host HSS matrix in the paper's format (Sec. 2): leaf dense blocks
+ * D, leaf shared bases U, the transfer matrices E of the nested bases (Eq. 6:
+ * the basis of a parent is blkdiag(children's bases) times E), and the
+ * skeleton couplings S of sibling pairs; layout in hss_desc. Copies everything
+ * (the host buffers may be freed on return) and synchronizes. Leaves the
+ * matrix CONSTRUCTED. Errors: INVALID_ARGUMENT for NULL or inconsistent sizes
+ * or a perm that is not a permutation; UNSUPPORTED for blocks above 512 rows
+ * or ranks above 128. */
 hss_status hss_import(hss_ctx_t ctx, const hss_desc* desc, hss_matrix_t* out);
 
 /* Sizes (in elements) of the arrays hss_export writes: leaf_lo, rank, D, U, E, S, perm. */
@@ -243,8 +250,14 @@ hss_status hss_ulv_solve_refined(hss_ctx_t ctx, hss_matrix_t m, const double* d_
                                  int64_t nrhs, int64_t ld, double tol, int32_t max_iters,
                                  int32_t* iters_out, double* relres_out);
 
-/* FP64 HSS matrix-vector product y = A x (up-sweep, couplings, down-sweep,
- * leaf blocks). Allowed in any state after construction/import. */
+/* FP64 HSS matrix-vector product y = A x with the nested-basis form of Sec. 2
+ * (Eq. 6): up-sweep x~ = U^T x at the leaves and E^T [x~_c1; x~_c2] above,
+ * sibling couplings y~_c1 = S x~_c2 and y~_c2 = S^T x~_c1, down-sweep
+ * [y~_c1; y~_c2] += E y~, and y = D x + U y~ at the leaves. This is the product
+ * A b of the construction error (Eq. 18) and the residual of the refinement.
+ * d_x, d_y: N x nrhs device memory, column-major with ld >= N, caller's point
+ * order; they must not alias. Allowed in any state after construction/import.
+ * Errors: INVALID_ARGUMENT for NULL, aliasing or bad sizes. */
 hss_status hss_matvec(hss_ctx_t ctx, hss_matrix_t m, const double* d_x, double* d_y,
                       int64_t nrhs, int64_t ld);
 

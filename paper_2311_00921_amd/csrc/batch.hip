@@ -229,6 +229,7 @@ void solve_run(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t
   key.x = x;
   key.nrhs = nrhs;
   key.ld = ld;
+  key.ws = m->precision == HSS_P_FP64 ? (const void*)m->dvec : (const void*)m->fvec;
   if (!m->gexec_solve || !(m->solve_key == key)) {
     if (m->gexec_solve) (void)hipGraphExecDestroy(m->gexec_solve);
     m->gexec_solve = nullptr;

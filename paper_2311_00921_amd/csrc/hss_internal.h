@@ -248,8 +248,9 @@ struct hss_matrix_s {
     const double* b = nullptr;
     double* x = nullptr;
     int64_t nrhs = 0, ld = 0;
+    const void* ws = nullptr;  // the per-node vector workspace the recording used
     bool operator==(const SolveKey& o) const {
-      return prec == o.prec && b == o.b && x == o.x && nrhs == o.nrhs && ld == o.ld;
+      return prec == o.prec && b == o.b && x == o.x && nrhs == o.nrhs && ld == o.ld && ws == o.ws;
     }
   } solve_key;
 };

@@ -759,6 +759,12 @@ __global__ __launch_bounds__(256) void k_mv_leaf(const NodeDesc* __restrict__ no
 
 void ensure_vec_ws(hss_matrix_t m, int64_t nrhs) {
   if (m->ws_nrhs >= nrhs) return;
+  // a recorded solve graph holds the addresses of the buffers freed below
+  if (m->gexec_solve) {
+    (void)hipGraphExecDestroy(m->gexec_solve);
+    m->gexec_solve = nullptr;
+    m->solve_key = hss_matrix_s::SolveKey{};
+  }
   if (m->dvec) dev_free(m->dvec);
   if (m->dxt) dev_free(m->dxt);
   if (m->dyt) dev_free(m->dyt);

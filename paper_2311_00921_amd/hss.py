@@ -186,6 +186,50 @@ def _colmajor(t, n):
     return tc, t.shape[1], n
 
 
+def _require(t, name: str, dtype, dims=(1, 2), rows=None, cols=None):
+    """Checks that t is a tensor on a GPU with the given dtype, rank and sizes
+    before its address goes to the library (a host pointer or a buffer of the
+    wrong element size would be read out of bounds by the kernels)."""
+    import torch
+
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device (cuda) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.dim() not in dims:
+        raise ValueError(f"{name} must have {' or '.join(map(str, dims))} dimensions, got {t.dim()}")
+    if rows is not None and t.shape[0] != rows:
+        raise ValueError(f"{name} must have {rows} rows, got {t.shape[0]}")
+    if cols is not None and t.dim() == 2 and t.shape[1] != cols:
+        raise ValueError(f"{name} must have {cols} columns, got {t.shape[1]}")
+    if t.numel() == 0:
+        raise ValueError(f"{name} is empty")
+
+
+def _matrix_n(m) -> int:
+    return int(hss_get_info(m).n)
+
+
+def _vec_args(m, b, x, bname="b", xname="x"):
+    """Validates a right-hand side block and an optional output of the same
+    shape for a matrix of order N; returns (b column-major, nrhs, ld, x)."""
+    import torch
+
+    n = _matrix_n(m)
+    _require(b, bname, torch.float64, rows=n)
+    bc, k, ld = _colmajor(b, n)
+    if x is None:
+        x = torch.empty_strided(bc.shape, bc.stride(), dtype=torch.float64, device=b.device)
+    else:
+        _require(x, xname, torch.float64, rows=n)
+        if tuple(x.shape) != tuple(bc.shape) or tuple(x.stride()) != tuple(bc.stride()):
+            raise ValueError(f"{xname} must have the shape and strides of {bname} "
+                             f"({tuple(bc.shape)}, {tuple(bc.stride())})")
+    return bc, k, ld, x
+
+
 # --------------------------------------------------------------------------
 # entry points
 # --------------------------------------------------------------------------
@@ -317,9 +361,15 @@ def hss_construct(ctx, points, kernel: str, leaf: int, rank: int = 0, tol: float
                   alpha: float = 1.0, eps: float = 1e-9, levels: int = 0, rank_model=None,
                   sample_start: int = 0, probes: int = 0, judge_factor: float = 0.0):
     """Builds the HSS approximation of the kernel matrix on device points (N x dim, row-major)."""
+    import torch
+
     lib = load()
+    _require(points, "points", torch.float64, dims=(2,))
     pts = points.contiguous()
     n, dim = pts.shape
+    if not 1 <= dim <= 3:
+        raise ValueError(f"points must have 1, 2 or 3 columns, got {dim}")
+    _require(omega, "omega", torch.float64, rows=n)
     om, s, ld = _colmajor(omega, n)
     if ld != n:
         om = om.t().contiguous().t()
@@ -339,12 +389,7 @@ def hss_ulv_factor(ctx, m, precision: int = HSS_P_FP64):
 
 def hss_ulv_solve(ctx, m, b, x=None):
     """x = A^{-1} b for a (N,) or (N, nrhs) float64 device tensor b."""
-    import torch
-
-    n = b.shape[0]
-    bc, k, ld = _colmajor(b, n)
-    if x is None:
-        x = torch.empty_strided(bc.shape, bc.stride(), dtype=torch.float64, device=b.device)
+    bc, k, ld, x = _vec_args(m, b, x)
     _check(load().hss_ulv_solve(ctx, m, _ptr(bc), _ptr(x), k, ld), "hss_ulv_solve")
     return x
 
@@ -352,23 +397,13 @@ def hss_ulv_solve(ctx, m, b, x=None):
 def hss_ulv_factor_solve(ctx, m, b, x=None):
     """FP64 factorization and x = A^{-1} b in one call (forward sweep overlapped
     with the factorization); b is a (N,) or (N, nrhs) float64 device tensor."""
-    import torch
-
-    n = b.shape[0]
-    bc, k, ld = _colmajor(b, n)
-    if x is None:
-        x = torch.empty_strided(bc.shape, bc.stride(), dtype=torch.float64, device=b.device)
+    bc, k, ld, x = _vec_args(m, b, x)
     _check(load().hss_ulv_factor_solve(ctx, m, _ptr(bc), _ptr(x), k, ld), "hss_ulv_factor_solve")
     return x
 
 
 def hss_ulv_solve_refined(ctx, m, b, tol: float, max_iters: int = 50, x=None):
-    import torch
-
-    n = b.shape[0]
-    bc, k, ld = _colmajor(b, n)
-    if x is None:
-        x = torch.empty_strided(bc.shape, bc.stride(), dtype=torch.float64, device=b.device)
+    bc, k, ld, x = _vec_args(m, b, x)
     iters = C.c_int32(0)
     rr = C.c_double(0.0)
     st = load().hss_ulv_solve_refined(ctx, m, _ptr(bc), _ptr(x), k, ld, tol, max_iters, C.byref(iters),
@@ -379,12 +414,7 @@ def hss_ulv_solve_refined(ctx, m, b, tol: float, max_iters: int = 50, x=None):
 
 
 def hss_matvec(ctx, m, x, y=None):
-    import torch
-
-    n = x.shape[0]
-    xc, k, ld = _colmajor(x, n)
-    if y is None:
-        y = torch.empty_strided(xc.shape, xc.stride(), dtype=torch.float64, device=x.device)
+    xc, k, ld, y = _vec_args(m, x, y, "x", "y")
     _check(load().hss_matvec(ctx, m, _ptr(xc), _ptr(y), k, ld), "hss_matvec")
     return y
 
@@ -402,6 +432,9 @@ def hss_get_info(m) -> hss_info:
 
 
 def hss_get_permutation(ctx, m, out):
+    import torch
+
+    _require(out, "out", torch.int64, dims=(1,), rows=_matrix_n(m))
     _check(load().hss_get_permutation(ctx, m, _ptr(out)), "hss_get_permutation")
     return out
 
@@ -447,6 +480,15 @@ def hss_construct_batched(ctx, points_list, kernels, leafs, ranks=None, tols=Non
     ranks = ranks or [0] * cnt
     tols = tols or [0.0] * cnt
     max_ranks = max_ranks or [0] * cnt
+    import torch
+
+    if len(omegas) != cnt:
+        raise ValueError("one omega per system is required")
+    for i, (p, om) in enumerate(zip(points_list, omegas)):
+        _require(p, f"points[{i}]", torch.float64, dims=(2,))
+        _require(om, f"omegas[{i}]", torch.float64, rows=p.shape[0])
+        if p.shape[1] != points_list[0].shape[1]:
+            raise ValueError("every system must have the same point dimension")
     pts = [p.contiguous() for p in points_list]
     dim = pts[0].shape[1]
     keep = []
@@ -527,7 +569,10 @@ def hss_rankmlp_param_count() -> int:
 
 def hss_rank_features(ctx, points, leaf: int, length: float, tol: float) -> np.ndarray:
     """Features of the learned rank model for every non-root node (heap order)."""
+    import torch
+
     lib = load()
+    _require(points, "points", torch.float64, dims=(2,))
     pts = points.contiguous()
     n, dim = pts.shape
     need = C.c_int64(0)
@@ -585,6 +630,7 @@ def hss_rankmlp_get_weights(ctx, mlp) -> np.ndarray:
 def hss_rankmlp_forward(ctx, mlp, feats):
     import torch
 
+    _require(feats, "feats", torch.float32, dims=(2,), cols=7)
     f = feats.contiguous()
     out = torch.empty(f.shape[0], dtype=torch.float32, device=f.device)
     _check(load().hss_rankmlp_forward(ctx, mlp, _ptr(f), f.shape[0], _ptr(out)), "hss_rankmlp_forward")
@@ -594,6 +640,7 @@ def hss_rankmlp_forward(ctx, mlp, feats):
 def hss_rankmlp_predict(ctx, mlp, feats, cap: int):
     import torch
 
+    _require(feats, "feats", torch.float32, dims=(2,), cols=7)
     f = feats.contiguous()
     out = torch.empty(f.shape[0], dtype=torch.int32, device=f.device)
     _check(load().hss_rankmlp_predict(ctx, mlp, _ptr(f), f.shape[0], cap, _ptr(out)), "hss_rankmlp_predict")
@@ -601,6 +648,10 @@ def hss_rankmlp_predict(ctx, mlp, feats, cap: int):
 
 
 def hss_rankmlp_grad(ctx, mlp, feats, targets, tau: float = 0.9):
+    import torch
+
+    _require(feats, "feats", torch.float32, dims=(2,), cols=7)
+    _require(targets, "targets", torch.float32, dims=(1,), rows=feats.shape[0])
     f = feats.contiguous()
     t = targets.contiguous()
     g = np.zeros(hss_rankmlp_param_count(), dtype=np.float32)
@@ -612,6 +663,11 @@ def hss_rankmlp_grad(ctx, mlp, feats, targets, tau: float = 0.9):
 
 def hss_rankmlp_train(ctx, mlp, feats, targets, order, batch: int, lr: float = 1e-3, tau: float = 0.9,
                       beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, record_losses: bool = True):
+    import torch
+
+    _require(feats, "feats", torch.float32, dims=(2,), cols=7)
+    _require(targets, "targets", torch.float32, dims=(1,), rows=feats.shape[0])
+    _require(order, "order", torch.int64, dims=(1,))
     f = feats.contiguous()
     t = targets.contiguous()
     o = order.contiguous()

@@ -76,6 +76,80 @@ def test_nugget_only_on_diagonal():
     np.testing.assert_allclose(K - K0, 0.5 * np.eye(20), atol=1e-15)
 
 
+def test_gaussian_kernel_closed_form_values():
+    # exp(-d^2/l^2) without a factor 1/2 (the workload's literal form): the value at
+    # d = l is 1/e (exp(-d^2/(2 l^2)) would give e^-1/2 there), the value at 0 is
+    # sigma2, and squaring the kernel doubles d^2 (f(d)^2 = f(sqrt2 d)), which no
+    # other power of d in the exponent satisfies.
+    for ell in (0.05, 0.3, 1.7):
+        k = O.Kernel("gaussian", ell, sigma2=1.0)
+        assert abs(k.f(np.array([ell]))[0] - math.e ** -1) < 1e-15
+        d = np.linspace(0.0, 3 * ell, 31)
+        np.testing.assert_allclose(k.f(d) ** 2, k.f(math.sqrt(2.0) * d), rtol=1e-13, atol=1e-300)
+    assert O.Kernel("gaussian", 0.3, sigma2=2.5).f(np.array([0.0]))[0] == 2.5
+    # a known value: d = l/2 gives exp(-1/4) = 0.77880078307...
+    assert abs(O.Kernel("gaussian", 0.2).f(np.array([0.1]))[0] - 0.7788007830714049) < 1e-15
+
+
+def test_yukawa_known_values_and_helmholtz_equation():
+    # Table 3's Yukawa potential exp(-alpha t)/t with t = theta + d: at t = 1 it is
+    # e^-alpha, and for d > 0 it solves the radial modified Helmholtz equation
+    # f'' + (2/t) f' - alpha^2 f = 0 (the screened Coulomb Green's function in 3-D),
+    # checked by central differences; a dropped 1/t or a wrong sign fails it.
+    k = O.Kernel("yukawa")
+    assert abs(k.f(np.array([1.0 - 1e-9]))[0] - math.e ** -1) < 1e-15
+    k2 = O.Kernel("yukawa", alpha=2.0, eps=0.0)
+    assert abs(k2.f(np.array([0.5]))[0] - 2.0 * math.e ** -1) < 1e-14
+    for alpha in (1.0, 3.0):
+        kk = O.Kernel("yukawa", alpha=alpha, eps=1e-9)
+        t = np.linspace(0.2, 2.0, 10)
+        h = 1e-4
+        f0, fp, fm = kk.f(t), kk.f(t + h), kk.f(t - h)
+        d2 = (fp - 2 * f0 + fm) / h ** 2
+        d1 = (fp - fm) / (2 * h)
+        res = d2 + 2.0 / (t + 1e-9) * d1 - alpha ** 2 * f0
+        assert np.max(np.abs(res) / (alpha ** 2 * np.abs(f0))) < 1e-5
+
+
+def test_pairwise_dist_matches_scipy_cdist():
+    import scipy.spatial.distance as ssd
+
+    for dim, seed in ((1, 1), (2, 2), (3, 3)):
+        X = synth.points_uniform(37, dim, seed)
+        Y = synth.points_uniform(23, dim, seed + 10)
+        np.testing.assert_allclose(O.pairwise_dist(X, Y), ssd.cdist(X, Y), rtol=1e-14, atol=1e-15)
+        np.testing.assert_allclose(np.diag(O.pairwise_dist(X, X)), 0.0, atol=0.0)
+
+
+def _r_with_diag(d):
+    R = np.triu(np.full((len(d), len(d) + 3), 0.25))
+    R[np.arange(len(d)), np.arange(len(d))] = d
+    return R
+
+
+def test_choose_rank_tolerance_rule():
+    # the adaptive rule keeps the leading pivots with |R_jj| > tol |R_00| and stops
+    # at the first one that is not (k = min{j : |R_jj| <= tol |R_00|}): hand-built
+    # diagonals with a known k, exact ties (powers of two), a non-monotone diagonal,
+    # the max_rank cap, a zero R and the fixed-rank path
+    R = _r_with_diag([10.0, 5.0, 1.0, 0.1, 0.01, 0.001])
+    assert O.choose_rank(R, 0, 0.05, 0, 64) == 3        # 10, 5, 1 > 0.5
+    assert O.choose_rank(R, 0, 0.2, 0, 64) == 2         # 1 > 2 fails
+    assert O.choose_rank(-R, 0, 0.05, 0, 64) == 3       # magnitudes, not signed values
+    Rt = _r_with_diag([8.0, 4.0, 2.0, 1.0])
+    assert O.choose_rank(Rt, 0, 0.25, 0, 64) == 2       # 2 == 0.25 * 8 is not kept (strict)
+    assert O.choose_rank(Rt, 0, 0.25 - 2 ** -20, 0, 64) == 3
+    Rn = _r_with_diag([8.0, 1.0, 4.0, 4.0])
+    assert O.choose_rank(Rn, 0, 0.25, 0, 64) == 1       # stops at the first failing pivot
+    assert O.choose_rank(R, 0, 1e-12, 0, 64) == 6       # every pivot kept
+    assert O.choose_rank(R, 0, 1e-12, 4, 64) == 4       # cap
+    assert O.choose_rank(R, 0, 1e-12, 0, 5) == 5        # never above the block size
+    assert O.choose_rank(R, 0, 0.99, 0, 64) == 1        # at least one column
+    assert O.choose_rank(np.zeros((4, 6)), 0, 0.1, 0, 64) == 1
+    assert O.choose_rank(R, 4, 0.5, 2, 64) == 4         # a fixed rank ignores tol and cap
+    assert O.choose_rank(R, 9, 0.0, 0, 64) == 6         # ... but not the columns there are
+
+
 # --------------------------------------------------------------------------
 # tree (brute force on tiny inputs)
 # --------------------------------------------------------------------------
