@@ -95,9 +95,31 @@ typedef struct {
   double judge_factor;       /* 0 = 10 */
 } hss_construct_opts;
 
+/* Precision of the factorization (the north-star "precision" form; the paper
+ * itself is FP64). Both leave FP64 factors, applied by the same FP64 solve.
+ *  FP64: every step in FP64.
+ *  FP32: the leaf stage's four contractions of the diagonal product (Eq. 7:
+ *        W = M Y, C = Y^T W, Z = W - V C / 2 and the rank-2r update of M) run
+ *        on FP32 matrix cores, operands rounded to FP32, FP32 accumulation,
+ *        the FP64 block M added to the product in FP64. The basis QR (the
+ *        orthogonal transform itself), every pivot block and partial
+ *        Cholesky, triangular solve and Schur complement (Eq. 10-12), and the
+ *        stages above the leaves (whose blocks carry the growing norms of the
+ *        merged Schur complements) stay FP64. Accuracy guard, in the same
+ *        call: a leaf whose FP64 pivot fails after the FP32 products, or whose
+ *        smallest pivot is below 2^-18 trace(D) (where the FP32 rounding of its
+ *        products, about u32 |D|, would be an O(1) relative error), is redone
+ *        in FP64 before the stage above; a node above the leaves whose pivot
+ *        fails (its block made indefinite by the perturbation below it) has
+ *        its whole subtree and its ancestors redone in FP64. When at least half
+ *        of the leaves are redone, later FP32 factorizations of the same matrix
+ *        run FP64 from the start. hss_info.promoted_nodes counts the leaves
+ *        factored in FP64. The result factors the HSS matrix with its other
+ *        leaf blocks perturbed by the FP32 rounding: refine with
+ *        hss_ulv_solve_refined. */
 typedef enum {
-  HSS_P_FP64 = 0, /* every step in FP64 */
-  HSS_P_FP32 = 1  /* basis transforms, TRSM and Schur GEMMs in FP32; pivots and root FP64 */
+  HSS_P_FP64 = 0,
+  HSS_P_FP32 = 1
 } hss_precision;
 
 typedef struct {
@@ -156,6 +178,7 @@ typedef struct {
   double solve_ms;           /* device time of the last solve */
   int32_t systems;           /* 1, or the number of systems of a batch */
   int32_t failed_system;     /* on HSS_ERR_NOT_SPD: system of the failing node, else -1 */
+  int32_t promoted_nodes;    /* FP32 factorization: leaves factored in FP64 (accuracy guard) */
 } hss_info;
 
 /* ---- context ------------------------------------------------------------ */

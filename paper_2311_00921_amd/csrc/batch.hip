@@ -194,11 +194,13 @@ static void factor_direct(hss_matrix_t m, int precision) {
   if (precision == HSS_P_FP64)
     factor_fp64(m);
   else
-    factor_fp32(m);
+    factor_mixed(m);
 }
 
 void factor_run(hss_matrix_t m, int precision) {
-  if (!m->use_graph || m->ctx->prof || g_tune) {
+  // the mixed factorization reads a failure count back between stages, so it
+  // is never recorded into a graph
+  if (!m->use_graph || m->ctx->prof || g_tune || precision != HSS_P_FP64) {
     factor_direct(m, precision);
     return;
   }
@@ -208,11 +210,9 @@ void factor_run(hss_matrix_t m, int precision) {
   HSS_HIP(hipGraphLaunch(ex, m->ctx->stream));
 }
 
+// Both precisions leave FP64 factors: the solve is the same.
 static void solve_direct(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld) {
-  if (m->precision == HSS_P_FP64)
-    solve_fp64(m, b, x, nrhs, ld);
-  else
-    solve_fp32(m, b, x, nrhs, ld);
+  solve_fp64(m, b, x, nrhs, ld);
 }
 
 void solve_run(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld) {
@@ -221,15 +221,13 @@ void solve_run(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t
     return;
   }
   ensure_vec_ws(m, nrhs);
-  if (m->precision != HSS_P_FP64 && !m->fvec)
-    m->fvec = (float*)dev_alloc(sizeof(float) * std::max<int64_t>(m->sum_n * m->ws_nrhs, 1));
   hss_matrix_s::SolveKey key;
   key.prec = m->precision;
   key.b = b;
   key.x = x;
   key.nrhs = nrhs;
   key.ld = ld;
-  key.ws = m->precision == HSS_P_FP64 ? (const void*)m->dvec : (const void*)m->fvec;
+  key.ws = m->dvec;
   if (!m->gexec_solve || !(m->solve_key == key)) {
     if (m->gexec_solve) (void)hipGraphExecDestroy(m->gexec_solve);
     m->gexec_solve = nullptr;

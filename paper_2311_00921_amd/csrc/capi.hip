@@ -172,7 +172,6 @@ void finish_stages(hss_matrix_t m) {
   m->lenLi = oLi;
   m->lenS2 = oS2;
   m->inv_used64.assign(m->stages.size(), 0);
-  m->inv_used32.assign(m->stages.size(), 0);
   if (m->dOffLi) dev_free(m->dOffLi);
   if (m->dOffS2) dev_free(m->dOffS2);
   m->dOffLi = (int64_t*)dev_alloc(sizeof(int64_t) * nn);
@@ -230,7 +229,7 @@ static void destroy_matrix(hss_matrix_t m) {
   if (m->ctx) (void)hipStreamSynchronize(m->ctx->stream);
   drop_graphs(m);
   free_factor(m);
-  void* ptrs[] = {m->dnodes, m->dD, m->dB, m->dS, m->dperm, m->dvec, m->dxt, m->dyt, m->fvec, m->dtmp,
+  void* ptrs[] = {m->dnodes, m->dD, m->dB, m->dS, m->dperm, m->dvec, m->dxt, m->dyt, m->dtmp,
                   m->dOffLi, m->dOffS2};
   for (void* p : ptrs)
     if (p) dev_free(p);
@@ -655,6 +654,7 @@ hss_status hss_get_info(hss_matrix_t m, hss_info* o) {
   o->solve_ms = m->solve_ms;
   o->systems = m->nsys;
   o->failed_system = m->failed_system;
+  o->promoted_nodes = m->promoted;
   HSS_API_END
 }
 
@@ -670,7 +670,7 @@ hss_status hss_debug_node_block(hss_ctx_t ctx, hss_matrix_t m, int32_t node, int
   HSS_API_BEGIN
   HSS_CHECK(ctx && m && h_out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(node >= 0 && node < m->nnodes, HSS_ERR_INVALID_ARGUMENT, "node out of range");
-  HSS_CHECK(m->state == 1 && m->precision == HSS_P_FP64, HSS_ERR_BAD_STATE, "needs an FP64 factorization");
+  HSS_CHECK(m->state == 1, HSS_ERR_BAD_STATE, "matrix is not factored");
   const NodeDesc& nd = m->nodes[node];
   hipStream_t s = ctx->stream;
   if (what == 0) {

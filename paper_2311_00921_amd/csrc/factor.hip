@@ -637,8 +637,11 @@ __device__ __forceinline__ void sigma_to_parent(T* __restrict__ Mp, int pn, int 
 // pivot block are left undefined (callers keep c <= lane only). Only steps
 // k < jb run (jb wave-uniform). Returns the first non-positive pivot (or -1),
 // the sum of the log pivots over the wave (in lsum, every lane) and, on lane
-// i < 16, 1 / L_ii (in rdiag). Call from one full wave.
-__device__ __forceinline__ int panel_chol16(double (&a)[16], int jb, double& lsum, double& rdiag) {
+// i < 16, 1 / L_ii (in rdiag), and the smallest pivot (a diagonal entry before
+// its square root) over the first jvalid steps (in pmin, every lane). Call
+// from one full wave.
+__device__ __forceinline__ int panel_chol16(double (&a)[16], int jb, double& lsum, double& rdiag, int jvalid,
+                                            double& pmin) {
   const int lane = threadIdx.x & 63;
   int bad = -1;
   double mine = 1.0;  // this lane's pivot; the logs are taken in parallel after the chain
@@ -663,9 +666,14 @@ __device__ __forceinline__ int panel_chol16(double (&a)[16], int jb, double& lsu
     }
   }
   double lg = (lane < jb) ? log(mine) : 0.0;
+  double mn = (lane < jb && lane < jvalid) ? mine * mine : __builtin_huge_val();
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) lg += __shfl_xor(lg, o, 64);
+  for (int o = 32; o > 0; o >>= 1) {
+    lg += __shfl_xor(lg, o, 64);
+    mn = fmin(mn, __shfl_xor(mn, o, 64));
+  }
   lsum = lg;
+  pmin = mn;
   return bad;
 }
 
@@ -679,11 +687,12 @@ constexpr int PNB = 16;
 template <typename T, int NMAX, bool CONSTRUCT = false, int NT = 256, bool RR_ONLY = false>
 __global__ __launch_bounds__(NT, 1024 / NT) void k_pchol(const NodeDesc* __restrict__ nodes, int first,
                                                T* __restrict__ Fbase, int32_t* __restrict__ info,
-                                               double* __restrict__ logdet) {
+                                               double* __restrict__ logdet, double* __restrict__ pminv) {
   const int node = first + blockIdx.x;
   const NodeDesc nd = nodes[node];
   const int n = nd.n, m = nd.m;
   T* F = Fbase + nd.offF;
+  __shared__ double pmn;
   __shared__ double Ld[PNB][PNB + 1];  // pivot blocks are always factored in FP64
   __shared__ double Rd[PNB];           // reciprocals of the pivot block's diagonal
   __shared__ T P[PNB][NMAX + 1];
@@ -693,6 +702,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_pchol(const NodeDesc* __restr
   if (tid == 0) {
     fail = -1;
     lacc = 0.0;
+    pmn = __builtin_huge_val();
   }
   __syncthreads();
   for (int j0 = 0; j0 < m; j0 += PNB) {
@@ -705,8 +715,8 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_pchol(const NodeDesc* __restr
 #pragma unroll
       for (int c = 0; c < PNB; ++c)
         a[c] = (lane < jb && c <= lane) ? (double)F[(j0 + lane) + (int64_t)(j0 + c) * n] : 0.0;
-      double lsum = 0.0, rd = 1.0;
-      const int bad = panel_chol16(a, jb, lsum, rd);
+      double lsum = 0.0, rd = 1.0, pm = 0.0;
+      const int bad = panel_chol16(a, jb, lsum, rd, jb, pm);
       if (lane < PNB) Rd[lane] = rd;
 #pragma unroll
       for (int c = 0; c < PNB; ++c) {
@@ -715,6 +725,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_pchol(const NodeDesc* __restr
       }
       if (lane == 0) {
         lacc += lsum;
+        pmn = fmin(pmn, pm);
         if (bad >= 0) fail = j0 + bad;
       }
     }
@@ -801,9 +812,11 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_pchol(const NodeDesc* __restr
         info[1] = node;
         info[2] = fail;
       }
-      info[4 + nd.sys] = 1;  // per-system flag
+      atomicAdd(&info[3], 1);  // failed nodes
+      info[4 + nd.sys] = 1;    // per-system flag
     }
-    logdet[node] = 2.0 * lacc;
+    logdet[node] = fail >= 0 ? __builtin_nan("") : 2.0 * lacc;  // NaN marks the failed node
+    if (pminv) pminv[node] = pmn;
   }
 }
 
@@ -821,7 +834,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_pchol(const NodeDesc* __restr
 template <typename T, int NBT>
 __global__ __launch_bounds__(512) void k_pchol_rr_lds(const NodeDesc* __restrict__ nodes, int first,
                                                       T* __restrict__ Fbase, int32_t* __restrict__ info,
-                                                      double* __restrict__ logdet) {
+                                                      double* __restrict__ logdet, double* __restrict__ pminv) {
   constexpr int NT = 512, NW = NT / 64, RM = 16 * NBT, NTILE = NBT * (NBT + 1) / 2;
   static_assert(RM - 16 <= 48 * NW, "panel rows exceed the waves");
   const int node = first + blockIdx.x;
@@ -830,7 +843,7 @@ __global__ __launch_bounds__(512) void k_pchol_rr_lds(const NodeDesc* __restrict
   T* F = Fbase + nd.offF;
   __shared__ double Xt[NTILE][256];
   __shared__ int fail;
-  __shared__ double lacc;
+  __shared__ double lacc, pmn;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   // stage: each wave loads whole tiles (4 elements per lane, columns of 16 rows coalesced)
   for (int t = wid; t < NTILE; t += NW) {
@@ -850,6 +863,7 @@ __global__ __launch_bounds__(512) void k_pchol_rr_lds(const NodeDesc* __restrict
   if (tid == 0) {
     fail = -1;
     lacc = 0.0;
+    pmn = __builtin_huge_val();
   }
   __syncthreads();
   for (int J = 0; J < NBT; ++J) {
@@ -867,9 +881,9 @@ __global__ __launch_bounds__(512) void k_pchol_rr_lds(const NodeDesc* __restrict
         double a[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) a[c] = valid ? Xt[tt][c * 16 + rr] : 0.0;
-        double lsum = 0.0, rd = 1.0;
+        double lsum = 0.0, rd = 1.0, pm = 0.0;
         const int jbl = m - j0 >= 16 ? 16 : (m - j0 > 0 ? m - j0 : 0);
-        int bad = panel_chol16(a, 16, lsum, rd);
+        int bad = panel_chol16(a, 16, lsum, rd, jbl, pm);
         if (bad >= jbl) bad = -1;
         if (lane >= 16 && valid)
 #pragma unroll
@@ -878,6 +892,7 @@ __global__ __launch_bounds__(512) void k_pchol_rr_lds(const NodeDesc* __restrict
         for (int c = 0; c < 16; ++c) dk[c] = a[c];
         if (wid == 0 && lane == 0) {
           lacc += lsum;
+          pmn = fmin(pmn, pm);
           if (bad >= 0 && fail < 0) fail = j0 + bad;
         }
       }
@@ -925,9 +940,11 @@ __global__ __launch_bounds__(512) void k_pchol_rr_lds(const NodeDesc* __restrict
         info[1] = node;
         info[2] = fail;
       }
-      info[4 + nd.sys] = 1;  // per-system flag
+      atomicAdd(&info[3], 1);  // failed nodes
+      info[4 + nd.sys] = 1;    // per-system flag
     }
-    logdet[node] = 2.0 * lacc;
+    logdet[node] = fail >= 0 ? __builtin_nan("") : 2.0 * lacc;  // NaN marks the failed node
+    if (pminv) pminv[node] = pmn;
   }
 }
 
@@ -1103,7 +1120,7 @@ __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ no
                                                   T* __restrict__ Fbase, T* __restrict__ Libase,
                                                   const int64_t* __restrict__ offLi, int32_t* __restrict__ info,
                                                   double* __restrict__ logdet, int part, T* __restrict__ Mbase,
-                                                  const T* __restrict__ Sgbase) {
+                                                  const T* __restrict__ Sgbase, double* __restrict__ pminv) {
   constexpr int NB = RM / 16, NW = NT / 64;
   const int node = first + blockIdx.x;
   const NodeDesc nd = nodes[node];
@@ -1121,12 +1138,13 @@ __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ no
   __shared__ double Y[RM][RM + kLdsPad];
   __shared__ double rdg[RM];  // 1 / L_ii
   __shared__ int fail;
-  __shared__ double lacc;
+  __shared__ double lacc, pmn;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   stage_frame<RM, NT>(X, F, n, m, m, true);
   if (tid == 0) {
     fail = -1;
     lacc = 0.0;
+    pmn = __builtin_huge_val();
   }
   __syncthreads();
   for (int J = 0; J < NB; ++J) {
@@ -1146,9 +1164,9 @@ __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ no
         double a[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c) a[c] = valid ? X[valid ? prow : 0][j0 + c] : 0.0;
-        double lsum = 0.0, rd = 1.0;
+        double lsum = 0.0, rd = 1.0, pm = 0.0;
         const int jbl = m - j0 >= 16 ? 16 : (m - j0 > 0 ? m - j0 : 0);
-        int bad = panel_chol16(a, 16, lsum, rd);
+        int bad = panel_chol16(a, 16, lsum, rd, jbl, pm);
         if (bad >= jbl) bad = -1;
         if (lane >= 16 && valid)
 #pragma unroll
@@ -1158,6 +1176,7 @@ __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ no
         if (wid == 0 && lane < 16) rdg[j0 + lane] = rd;
         if (wid == 0 && lane == 0) {
           lacc += lsum;
+          pmn = fmin(pmn, pm);
           if (bad >= 0 && fail < 0) fail = j0 + bad;
         }
       }
@@ -1336,12 +1355,16 @@ __global__ __launch_bounds__(NT) void k_chol_lds(const NodeDesc* __restrict__ no
         info[1] = node;
         info[2] = piv0 + fail;
       }
-      info[4 + nd.sys] = 1;  // per-system flag
+      atomicAdd(&info[3], 1);  // failed nodes
+      info[4 + nd.sys] = 1;    // per-system flag
     }
+    // NaN marks the failed node (and stays NaN through part 2 of a split root)
+    const double part_sum = fail >= 0 ? __builtin_nan("") : 2.0 * lacc;
     if (part == 2)
-      logdet[node] += 2.0 * lacc;
+      logdet[node] += part_sum;
     else
-      logdet[node] = 2.0 * lacc;
+      logdet[node] = part_sum;
+    if (pminv) pminv[node] = part == 2 ? fmin(pminv[node], pmn) : pmn;
   }
 }
 
@@ -1424,16 +1447,16 @@ static void launch_pchol(const hss_matrix_t m, int first, int count, int nmax, T
   const bool narrow = count <= 64;
   if (nmax <= 256 && !narrow)
     hipLaunchKernelGGL((k_pchol<T, 256, false, 256>), grid, dim3(256), 0, s, m->dnodes, first, F, m->dinfo,
-                       m->dlogdet);
+                       m->dlogdet, m->dpmin);
   else if (nmax <= 256)
     hipLaunchKernelGGL((k_pchol<T, 256, false, 512>), grid, dim3(512), 0, s, m->dnodes, first, F, m->dinfo,
-                       m->dlogdet);
+                       m->dlogdet, m->dpmin);
   else if (!narrow)
     hipLaunchKernelGGL((k_pchol<T, 512, false, 256>), grid, dim3(256), 0, s, m->dnodes, first, F, m->dinfo,
-                       m->dlogdet);
+                       m->dlogdet, m->dpmin);
   else
     hipLaunchKernelGGL((k_pchol<T, 512, false, 512>), grid, dim3(512), 0, s, m->dnodes, first, F, m->dinfo,
-                       m->dlogdet);
+                       m->dlogdet, m->dpmin);
   HSS_HIP(hipGetLastError());
 }
 
@@ -1446,7 +1469,7 @@ static void launch_pchol_split(const hss_matrix_t m, int first, int count, T* F,
   {
     Prof pf(cx, "pchol_RR", level);
     hipLaunchKernelGGL((k_pchol_rr_lds<T, 10>), dim3(count), dim3(512), 0, s, m->dnodes, first, F, m->dinfo,
-                       m->dlogdet);
+                       m->dlogdet, m->dpmin);
     HSS_HIP(hipGetLastError());
   }
   Prof pf(cx, "sr_schur", level);
@@ -1459,9 +1482,11 @@ void launch_pchol_external(const NodeDesc* nodes, int first, int count, int nmax
                            double* logdet, hipStream_t s) {
   dim3 grid(count), block(256);
   if (nmax <= 256)
-    hipLaunchKernelGGL((k_pchol<double, 256, true>), grid, block, 0, s, nodes, first, F, info, logdet);
+    hipLaunchKernelGGL((k_pchol<double, 256, true>), grid, block, 0, s, nodes, first, F, info, logdet,
+                       (double*)nullptr);
   else if (nmax <= 512)
-    hipLaunchKernelGGL((k_pchol<double, 512, true>), grid, block, 0, s, nodes, first, F, info, logdet);
+    hipLaunchKernelGGL((k_pchol<double, 512, true>), grid, block, 0, s, nodes, first, F, info, logdet,
+                       (double*)nullptr);
   else
     HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "diagonal block larger than 512");
   HSS_HIP(hipGetLastError());
@@ -1560,33 +1585,18 @@ static std::vector<std::vector<GemmBatch>> build_gemm_plan(hss_matrix_t m, const
 }
 
 template <typename T>
-static void gemm_run(const GemmBatch& g, bool ta, bool tb, double alpha, double beta, hipStream_t s);
-template <>
-void gemm_run<double>(const GemmBatch& g, bool ta, bool tb, double alpha, double beta, hipStream_t s) {
+static void gemm_run(const GemmBatch& g, bool ta, bool tb, double alpha, double beta, hipStream_t s) {
   gemm_launch_f64(g, ta, tb, alpha, beta, s);
-}
-template <>
-void gemm_run<float>(const GemmBatch& g, bool ta, bool tb, double alpha, double beta, hipStream_t s) {
-  gemm_launch_f32(g, ta, tb, (float)alpha, (float)beta, s);
-}
-
-template <typename A, typename B>
-__global__ void k_cast(const A* __restrict__ src, B* __restrict__ dst, int64_t n) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    dst[i] = (B)src[i];
-}
-
-template <typename A, typename B>
-static void cast(const A* src, B* dst, int64_t n, hipStream_t s) {
-  if (n <= 0) return;
-  const int blocks = (int)std::min<int64_t>((n + 255) / 256, 8192);
-  hipLaunchKernelGGL((k_cast<A, B>), dim3(blocks), dim3(256), 0, s, src, dst, n);
-  HSS_HIP(hipGetLastError());
 }
 
 static void alloc_common(hss_matrix_t m) {
   if (!m->dinfo) m->dinfo = (int32_t*)dev_alloc(sizeof(int32_t) * (4 + m->nsys));
   if (!m->dlogdet) m->dlogdet = (double*)dev_alloc(sizeof(double) * (m->nnodes + 1));
+  if (!m->dpmin) m->dpmin = (double*)dev_alloc(sizeof(double) * m->nnodes);
+}
+
+static FBufs<double> fbufs(hss_matrix_t m) {
+  return FBufs<double>{m->dD, m->dB, m->dS, m->dF, m->dM, m->dV, m->dT, m->dSg, m->dW, m->dX, m->dLi, m->dS2};
 }
 
 static void alloc_factor(hss_matrix_t m) {
@@ -1601,32 +1611,59 @@ static void alloc_factor(hss_matrix_t m) {
   m->dX = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenX, 1));
   m->dLi = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenLi, 1));
   m->dS2 = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenS2, 1));
-  FBufs<double> b{m->dD, m->dB, m->dS, m->dF, m->dM, m->dV, m->dT, m->dSg, m->dW, m->dX, m->dLi, m->dS2};
-  m->gemm_plan = build_gemm_plan<double>(m, b);
+  m->gemm_plan = build_gemm_plan<double>(m, fbufs(m));
   m->factor_ready = true;
 }
 
-static void alloc_factor32(hss_matrix_t m) {
-  alloc_common(m);
-  if (m->factor32_ready) return;
-  auto fa = [](int64_t n) { return (float*)dev_alloc(sizeof(float) * std::max<int64_t>(n, 1)); };
-  m->fD = fa(m->lenD);
-  m->fB = fa(m->lenB);
-  m->fS = fa(m->lenS);
-  m->fF = fa(m->lenF);
-  m->fM = fa(m->lenM);
-  m->fV = fa(m->lenV);
-  m->fT = fa(m->lenT);
-  m->fSg = fa(m->lenSg);
-  m->fW = fa(m->lenW);
-  m->fX = fa(m->lenX);
-  m->fLi = fa(m->lenLi);
-  m->fS2 = fa(m->lenS2);
-  // FP64 scratch for the root blocks (same offsets as F)
-  m->dRoot = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->lenF, 1));
-  FBufs<float> b{m->fD, m->fB, m->fS, m->fF, m->fM, m->fV, m->fT, m->fSg, m->fW, m->fX, m->fLi, m->fS2};
-  m->gemm_plan32 = build_gemm_plan<float>(m, b);
-  m->factor32_ready = true;
+// The GEMM steps of a stage that the mixed factorization runs on FP32 matrix
+// cores: W = M Y, C = Y^T W, Z = W - V C / 2 and the rank-2r update of the
+// leaf stage (the bulk of the flops, and the smallest block norms). The basis
+// QR and Y = V T stay FP64: they define the orthogonal transform itself, which
+// the solve applies again and whose exactness keeps the redundant rows of the
+// off-diagonal blocks zero (Eq. 8).
+static bool mixed_step(const LevelPlan& lp, int step) { return lp.leaf && step >= 3 && step <= 6; }
+
+// trace(D) of every leaf (one workgroup per leaf)
+__global__ void k_leaf_trace(const NodeDesc* __restrict__ nodes, int first, const double* __restrict__ Db,
+                             double* __restrict__ out) {
+  const NodeDesc nd = nodes[first + blockIdx.x];
+  __shared__ double part[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < nd.n; i += blockDim.x) acc += Db[nd.offD + i + (int64_t)i * nd.n];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[blockIdx.x] = part[0];
+}
+
+static void alloc_mixed(hss_matrix_t m) {
+  alloc_factor(m);
+  if (m->mixed_ready) return;
+  {
+    // the scale of the FP32 rounding of each leaf's products, once per matrix
+    const LevelPlan& lp = m->stages[0];
+    hipStream_t s = m->ctx->stream;
+    double* tr = (double*)dev_alloc(sizeof(double) * lp.count);
+    hipLaunchKernelGGL(k_leaf_trace, dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const double*)m->dD, tr);
+    std::vector<double> h(lp.count);
+    const hipError_t e1 = hipGetLastError();
+    const hipError_t e2 = hipMemcpyAsync(h.data(), tr, sizeof(double) * lp.count, hipMemcpyDeviceToHost, s);
+    const hipError_t e3 = hipStreamSynchronize(s);
+    dev_free(tr);
+    HSS_HIP(e1);
+    HSS_HIP(e2);
+    HSS_HIP(e3);
+    m->leaf_trace.assign(m->nnodes, 0.0);
+    for (int k = 0; k < lp.count; ++k) m->leaf_trace[lp.first + k] = h[k];
+  }
+  m->gemm_plan32 = build_gemm_plan<double>(m, fbufs(m));
+  for (size_t si = 0; si < m->stages.size(); ++si)
+    for (int st = 0; st < (int)m->gemm_plan32[si].size(); ++st)
+      m->gemm_plan32[si][st].fp32_compute = mixed_step(m->stages[si], st);
+  m->mixed_ready = true;
 }
 
 void free_factor(hss_matrix_t m) {
@@ -1636,45 +1673,13 @@ void free_factor(hss_matrix_t m) {
     for (auto& b : lv) gemm_free(b);
   m->gemm_plan.clear();
   m->gemm_plan32.clear();
-  void* ptrs[] = {m->dF, m->dM, m->dV, m->dT, m->dSg, m->dW, m->dX, m->dinfo, m->dlogdet, m->dRoot,
-                  m->fF, m->fM, m->fV, m->fT, m->fSg, m->fW, m->fX, m->fD, m->fB, m->fS,
-                  m->dLi, m->dS2, m->fLi, m->fS2};
+  void* ptrs[] = {m->dF, m->dM, m->dV, m->dT, m->dSg, m->dW, m->dX, m->dinfo, m->dlogdet, m->dLi, m->dS2, m->dpmin};
   for (void* p : ptrs)
     if (p) dev_free(p);
-  m->dF = m->dM = m->dV = m->dT = m->dSg = m->dW = m->dX = m->dRoot = m->dLi = m->dS2 = nullptr;
-  m->fLi = m->fS2 = nullptr;
+  m->dF = m->dM = m->dV = m->dT = m->dSg = m->dW = m->dX = m->dLi = m->dS2 = m->dpmin = nullptr;
   m->dinfo = nullptr;
   m->dlogdet = nullptr;
-  m->fF = m->fM = m->fV = m->fT = m->fSg = m->fW = m->fX = m->fD = m->fB = m->fS = nullptr;
-  m->factor_ready = m->factor32_ready = false;
-}
-
-// One sweep of Alg. 2 over the stages (leaves first, roots included) in
-// compute type T. A root has rank 0: its transform is the identity and its
-// "partial" Cholesky is complete. With FP32 compute, the roots of a stage are
-// factored in FP64 (their blocks are cast to FP64 and back).
-template <typename T>
-static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::vector<GemmBatch>>& plan);
-
-template <typename T>
-static void root_cholesky_fp64(hss_matrix_t m, const LevelPlan& lp, T* F, hipStream_t s);
-
-template <>
-void root_cholesky_fp64<double>(hss_matrix_t m, const LevelPlan& lp, double* F, hipStream_t s) {
-  launch_pchol<double>(m, lp.root_first, lp.first + lp.count - lp.root_first, lp.nmax, F, s);
-}
-
-template <>
-void root_cholesky_fp64<float>(hss_matrix_t m, const LevelPlan& lp, float* F, hipStream_t s) {
-  for (int k = lp.root_first; k < lp.first + lp.count; ++k) {
-    const NodeDesc& nd = m->nodes[k];
-    cast<float, double>(F + nd.offF, m->dRoot + nd.offF, (int64_t)nd.n * nd.n, s);
-  }
-  launch_pchol<double>(m, lp.root_first, lp.first + lp.count - lp.root_first, lp.nmax, m->dRoot, s);
-  for (int k = lp.root_first; k < lp.first + lp.count; ++k) {
-    const NodeDesc& nd = m->nodes[k];
-    cast<double, float>(m->dRoot + nd.offF, F + nd.offF, (int64_t)nd.n * nd.n, s);
-  }
+  m->factor_ready = m->mixed_ready = false;
 }
 
 template <typename T>
@@ -1690,11 +1695,294 @@ static void launch_basis_top(int rmax, int first, int count, const NodeDesc* nod
   HSS_HIP(hipGetLastError());
 }
 
+// Largest rank, redundant size and block size over the non-root nodes of a stage.
+static void nonroot_extent(const hss_matrix_t m, const LevelPlan& lp, int& rmax, int& mmax, int& nmax) {
+  rmax = mmax = nmax = 0;
+  for (int k = lp.first; k < lp.root_first; ++k) {
+    rmax = std::max(rmax, m->nodes[k].r);
+    mmax = std::max(mmax, m->nodes[k].m);
+    nmax = std::max(nmax, m->nodes[k].n);
+  }
+}
+
+static int lds_frame(int mmax) { return mmax <= 32 ? 32 : (mmax <= 64 ? 64 : 96); }
+
+// The partial Cholesky of a stage (Eq. 10-12) and the Cholesky of its roots,
+// for the nodes [lp.first, lp.first + lp.count) with the kernel choice of the
+// stage they belong to (lp carries the stage's extents). Returns the choice for
+// the solve: 1 explicit inverse factors, 2 split roots, 0 neither.
 template <typename T>
-static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::vector<GemmBatch>>& plan) {
+static int stage_cholesky(hss_matrix_t m, const LevelPlan& lp, const FBufs<T>& b, std::vector<GemmBatch>& st,
+                          T* msink, hipStream_t s) {
+  hss_ctx_t cx = m->ctx;
+  const int l = lp.level;
+  const int nonroot = lp.root_first - lp.first;
+  if (lp.root_split) {
+    // every node is a root of order 96 < n <= 192: two LDS Cholesky passes
+    Prof pf(cx, "root", l);
+    int hmax = 0;
+    for (int k = lp.first; k < lp.first + lp.count; ++k) hmax = std::max(hmax, root_split_h(m->nodes[k].n));
+    dim3 grid(lp.count), block(512);
+    for (int part = 1; part <= 2; ++part) {
+      if (hmax <= 64)
+        hipLaunchKernelGGL((k_chol_lds<T, 64, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
+                           (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, part, (T*)nullptr, (const T*)b.Sg,
+                           m->dpmin);
+      else
+        hipLaunchKernelGGL((k_chol_lds<T, 96, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
+                           (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, part, (T*)nullptr, (const T*)b.Sg,
+                           m->dpmin);
+      HSS_HIP(hipGetLastError());
+    }
+    return 2;
+  }
+  if (lp.inv) {
+    const int rm = lds_frame(lp.mmax);
+    // L_SR and Sigma inside the Cholesky kernel when the S rows fit its frame
+    const bool fuse = lp.rmax <= rm;
+    dim3 grid(lp.count), block(512);
+    {
+      Prof pf(cx, nonroot == 0 ? "root" : "chol_lds", l);
+#define CHOL_LDS(RM, FU)                                                                                      \
+  hipLaunchKernelGGL((k_chol_lds<T, RM, FU>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,              \
+                     (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 0, msink, (const T*)b.Sg, m->dpmin)
+      if (rm == 32) {
+        if (fuse) CHOL_LDS(32, true); else CHOL_LDS(32, false);
+      } else if (rm == 64) {
+        if (fuse) CHOL_LDS(64, true); else CHOL_LDS(64, false);
+      } else {
+        if (fuse) CHOL_LDS(96, true); else CHOL_LDS(96, false);
+      }
+#undef CHOL_LDS
+      HSS_HIP(hipGetLastError());
+    }
+    if (!fuse) {
+      {
+        Prof pf(cx, "gemm_LSR", l);
+        gemm_run<T>(st[7], false, true, 1.0, 0.0, s);  // L_SR = F_SR L_RR^{-T}
+      }
+      {
+        Prof pf(cx, "gemm_Sigma", l);
+        gemm_run<T>(st[8], false, true, -1.0, 1.0, s);  // Sigma = F_SS - L_SR L_SR^T
+      }
+      Prof pf(cx, "copy_lsr", l);
+      hipLaunchKernelGGL((k_copy_lsr<T>), dim3(16, lp.count), dim3(256), 0, s, m->dnodes, lp.first,
+                         (const T*)b.S2, (const int64_t*)m->dOffS2, b.F);
+      HSS_HIP(hipGetLastError());
+    }
+    return 1;
+  }
+  int rmax_nr = 0, mmax_nr = 0, nmax_nr = 0;
+  nonroot_extent(m, lp, rmax_nr, mmax_nr, nmax_nr);
+  if (nonroot > 0 && rmax_nr <= 96 && mmax_nr <= 160 && nmax_nr <= 256) {
+    launch_pchol_split<T>(m, lp.first, nonroot, b.F, msink, (const T*)b.Sg, s, cx, l);
+  } else if (nonroot > 0) {
+    Prof pf(cx, "pchol", l);
+    launch_pchol<T>(m, lp.first, nonroot, lp.nmax, b.F, s);
+  }
+  if (nonroot < lp.count) {
+    Prof pf(cx, "root", l);
+    launch_pchol<T>(m, lp.root_first, lp.count - nonroot, lp.nmax, b.F, s);
+  }
+  return 0;
+}
+
+// Clears the status words (and, with clear_logdet, the per-node
+// log-determinant sums) with a kernel, not a memset node, so that the
+// sequence can be recorded into a HIP graph.
+__global__ void k_clear_status(int32_t* __restrict__ info, int ninfo, double* __restrict__ logdet, int nld) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ninfo + nld; i += gridDim.x * blockDim.x) {
+    if (i < ninfo)
+      info[i] = 0;
+    else
+      logdet[i - ninfo] = 0.0;
+  }
+}
+
+static void clear_status(hss_matrix_t m, hipStream_t s, bool clear_logdet = true) {
+  const int nld = clear_logdet ? m->nnodes + 1 : 0;
+  const int tot = 4 + m->nsys + nld;
+  hipLaunchKernelGGL(k_clear_status, dim3(std::min((tot + 255) / 256, 1024)), dim3(256), 0, s, m->dinfo,
+                     4 + m->nsys, m->dlogdet, nld);
+  HSS_HIP(hipGetLastError());
+}
+
+// Nodes redone one by one below this count; above it the whole stage is redone.
+constexpr int kPromoteEach = 64;
+
+// Redoes the nodes `list` of stage si in FP64 from their current blocks: the
+// merge (when the children do not write into it), the four products, then the
+// partial Cholesky, which writes the node's Schur complement into its parent.
+// The basis QR depends on the representation only and is kept.
+template <typename T>
+static void redo_nodes_fp64(hss_matrix_t m, int si, const std::vector<int>& list, const FBufs<T>& b, T* msink,
+                            std::vector<char>& done) {
+  hipStream_t s = m->ctx->stream;
+  const LevelPlan& lp = m->stages[si];
+  auto& full = m->gemm_plan[si];  // the FP64 batches of the stage
+  const bool whole = (int)list.size() > kPromoteEach || (lp.inv && lp.rmax > lds_frame(lp.mmax));
+  auto merge = [&](int first, int count) {
+    if (lp.leaf || msink) return;
+    const int tpr = (lp.nmax + 31) / 32;
+    hipLaunchKernelGGL((k_merge<T>), dim3(count, tpr * tpr), dim3(256), 0, s, m->dnodes, first, (const T*)b.F,
+                       (const T*)b.Sg, b.S, b.M, 0);
+    HSS_HIP(hipGetLastError());
+  };
+  if (whole) {
+    for (int k = lp.first; k < lp.first + lp.count; ++k) done[k] = 1;
+    merge(lp.first, lp.count);
+    gemm_run<T>(full[3], false, false, 1.0, 0.0, s);   // W = M Y
+    gemm_run<T>(full[4], true, false, 1.0, 0.0, s);    // C = Y^T W
+    gemm_run<T>(full[5], false, false, -0.5, 1.0, s);  // Z = W - V C / 2
+    gemm_run<T>(full[6], false, true, -1.0, 1.0, s);   // F = P^T (M - Z V^T - V Z^T) P
+    stage_cholesky<T>(m, lp, b, full, msink, s);
+    return;
+  }
+  for (int p : list) done[p] = 1;
+  for (int p : list) merge(p, 1);
+  std::vector<GemmBatch> sub(4);
+  for (int q = 0; q < 4; ++q) {
+    for (int p : list) sub[q].host.push_back(full[3 + q].host[p - lp.first]);
+    sub[q].variant = full[3 + q].variant;
+    gemm_upload(sub[q], s);
+  }
+  gemm_run<T>(sub[0], false, false, 1.0, 0.0, s);
+  gemm_run<T>(sub[1], true, false, 1.0, 0.0, s);
+  gemm_run<T>(sub[2], false, false, -0.5, 1.0, s);
+  gemm_run<T>(sub[3], false, true, -1.0, 1.0, s);
+  for (int p : list) {
+    LevelPlan one = lp;
+    one.first = p;
+    one.count = 1;
+    one.root_first = p >= lp.root_first ? p : p + 1;
+    stage_cholesky<T>(m, one, b, full, msink, s);
+  }
+  HSS_HIP(hipStreamSynchronize(s));  // the uploaded descriptors stay alive until the launches ran
+  for (auto& g : sub) gemm_free(g);
+}
+
+// Accuracy test of the FP32 leaf products. Rounding the products of a leaf to
+// FP32 perturbs its transformed block by about u32 * |D| (absolute: the
+// redundant block is formed from D by cancellation), and a redundant block
+// whose smallest pivot is not well above that is then factored with an O(1)
+// relative error, which refinement cannot remove in a few steps. Such leaves,
+// and those whose pivot failed outright, are redone in FP64 before the stage
+// above starts. Threshold: smallest pivot < 2^6 u32 trace(D) (trace(D) >= |D|_2;
+// the rounding measured on the benchmark's leaves is about 3 u32 trace(D)).
+constexpr double kMixedPivotRatio = 64.0 * 0x1p-24;
+
+template <typename T>
+static int promote_leaves(hss_matrix_t m, int si, const FBufs<T>& b, T* msink) {
+  hipStream_t s = m->ctx->stream;
+  const LevelPlan& lp = m->stages[si];
+  std::vector<double> ld(lp.count), pm(lp.count);
+  HSS_HIP(hipMemcpyAsync(ld.data(), m->dlogdet + lp.first, sizeof(double) * lp.count, hipMemcpyDeviceToHost, s));
+  HSS_HIP(hipMemcpyAsync(pm.data(), m->dpmin + lp.first, sizeof(double) * lp.count, hipMemcpyDeviceToHost, s));
+  HSS_HIP(hipStreamSynchronize(s));
+  std::vector<int> list;
+  for (int k = 0; k < lp.count; ++k) {
+    const int p = lp.first + k;
+    if (p >= lp.root_first) continue;  // roots have no FP32 products
+    if (std::isnan(ld[k]) || !(pm[k] >= kMixedPivotRatio * m->leaf_trace[p])) list.push_back(p);
+  }
+  if (list.empty()) return 0;
+  clear_status(m, s, false);
+  Prof pf(m->ctx, "promote_fp64", lp.level);
+  std::vector<char> done(m->nnodes, 0);
+  redo_nodes_fp64<T>(m, si, list, b, msink, done);
+  int cnt = 0;
+  for (int k = lp.first; k < lp.root_first; ++k)
+    if (done[k]) {
+      m->fp64_leaf[k] = 1;
+      ++cnt;
+    }
+  return cnt;
+}
+
+// Mixed precision: after the sweep, the nodes whose FP64 pivots failed are
+// found (the kernels mark a failed node with a NaN log-determinant and count it
+// in info[3]). A failure anywhere -- at a leaf, or above it where the FP32
+// perturbation of the leaves below has made a merged block indefinite -- is
+// repaired by redoing the failed node's whole subtree in FP64 and then every
+// ancestor of it (their blocks were formed from the failed values), stage by
+// stage from the leaves. The status words are cleared first; if a node fails
+// again although its whole subtree is FP64 the matrix is not SPD, and that
+// failure is reported. Reads the counter back (synchronizes); returns the
+// number of leaves redone.
+template <typename T>
+static int promote_failed(hss_matrix_t m, const FBufs<T>& b, T* msink) {
+  hipStream_t s = m->ctx->stream;
+  const int nn = m->nnodes;
+  // subtree FP64 through and through: its leaves were redone (or are roots)
+  std::vector<char> fp64(nn, 0);
+  auto propagate = [&]() {
+    for (const LevelPlan& lp : m->stages)
+      for (int k = lp.first; k < lp.first + lp.count; ++k) {
+        const NodeDesc& d = m->nodes[k];
+        fp64[k] = d.c1 < 0 ? (char)(m->fp64_leaf[k] || d.parent < 0) : (char)(fp64[d.c1] && fp64[d.c2]);
+      }
+  };
+  propagate();
+  for (int round = 0;; ++round) {
+    int32_t cnt = 0;
+    HSS_HIP(hipMemcpyAsync(&cnt, m->dinfo + 3, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HSS_HIP(hipStreamSynchronize(s));
+    if (cnt == 0) break;
+    std::vector<double> ld(nn);
+    HSS_HIP(hipMemcpyAsync(ld.data(), m->dlogdet, sizeof(double) * nn, hipMemcpyDeviceToHost, s));
+    HSS_HIP(hipStreamSynchronize(s));
+    std::vector<char> bad(nn, 0), redo(nn, 0);
+    for (int k = 0; k < nn; ++k) bad[k] = std::isnan(ld[k]) ? 1 : 0;
+    bool genuine = false;
+    for (int k = 0; k < nn; ++k) {
+      const NodeDesc& d = m->nodes[k];
+      if (!bad[k] || (d.c1 >= 0 && (bad[d.c1] || bad[d.c2]))) continue;  // not a lowest failure
+      if (fp64[k]) {
+        genuine = true;  // its subtree is FP64 already
+        continue;
+      }
+      std::vector<int> stack{k};
+      while (!stack.empty()) {
+        const int q = stack.back();
+        stack.pop_back();
+        redo[q] = 1;
+        if (m->nodes[q].c1 >= 0) {
+          stack.push_back(m->nodes[q].c1);
+          stack.push_back(m->nodes[q].c2);
+        }
+      }
+      for (int q = d.parent; q >= 0; q = m->nodes[q].parent) redo[q] = 1;
+    }
+    if (genuine || round >= 8) break;  // leave the failure in the status words
+    clear_status(m, s, false);
+    Prof pf(m->ctx, "promote_fp64", -1);
+    for (size_t si = 0; si < m->stages.size(); ++si) {
+      const LevelPlan& lp = m->stages[si];
+      std::vector<int> list;
+      for (int k = lp.first; k < lp.first + lp.count; ++k)
+        if (redo[k]) list.push_back(k);
+      if (list.empty()) continue;
+      std::vector<char> done(nn, 0);
+      redo_nodes_fp64<T>(m, (int)si, list, b, msink, done);
+      for (int k = 0; k < nn; ++k)
+        if (done[k] && m->nodes[k].c1 < 0) m->fp64_leaf[k] = 1;
+    }
+    propagate();  // the stages above the leaves never use FP32
+  }
+  int leaves = 0;
+  for (int k = 0; k < nn; ++k) leaves += (m->fp64_leaf[k] && m->nodes[k].c1 < 0 && m->nodes[k].parent >= 0) ? 1 : 0;
+  return leaves;
+}
+
+// One sweep of Alg. 2 over the stages (leaves first, roots included). A root
+// has rank 0: its transform is the identity and its "partial" Cholesky is
+// complete. `mixed`: the plan runs some products on FP32 matrix cores, and the
+// nodes of those stages whose pivots fail are promoted to FP64.
+template <typename T>
+static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::vector<GemmBatch>>& plan,
+                          bool mixed) {
   hipStream_t s = m->ctx->stream;
   hss_ctx_t cx = m->ctx;
-  const bool fp32 = sizeof(T) == 4;
   const bool hoist = plan.size() > m->stages.size();
   // When every stage's Schur complements come from k_sr_schur or the fused
   // LDS Cholesky, those kernels write Sg Sigma Sg straight into the parents'
@@ -1704,16 +1992,11 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
   for (const LevelPlan& lp : m->stages) {
     const int nonroot = lp.root_first - lp.first;
     if (nonroot == 0) continue;
-    if (lp.inv && !(fp32 && nonroot < lp.count)) {
-      const int rm = lp.mmax <= 32 ? 32 : (lp.mmax <= 64 ? 64 : 96);
-      direct = direct && lp.rmax <= rm;
+    if (lp.inv) {
+      direct = direct && lp.rmax <= lds_frame(lp.mmax);
     } else {
       int rmax_nr = 0, mmax_nr = 0, nmax_nr = 0;
-      for (int k = lp.first; k < lp.root_first; ++k) {
-        rmax_nr = std::max(rmax_nr, m->nodes[k].r);
-        mmax_nr = std::max(mmax_nr, m->nodes[k].m);
-        nmax_nr = std::max(nmax_nr, m->nodes[k].n);
-      }
+      nonroot_extent(m, lp, rmax_nr, mmax_nr, nmax_nr);
       direct = direct && rmax_nr <= 96 && mmax_nr <= 160 && nmax_nr <= 256;
     }
   }
@@ -1764,7 +2047,6 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
   for (size_t si = 0; si < m->stages.size(); ++si) {
     const LevelPlan& lp = m->stages[si];
     const int l = lp.level;
-    const int nonroot = lp.root_first - lp.first;
     const bool basis_done = hoist && si > 0;
     if (hoist && si == 1 && !g_tune) HSS_HIP(hipStreamWaitEvent(s, cx->ev_join, 0));
     if (!lp.leaf && !direct) {
@@ -1813,143 +2095,57 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
       Prof pf(cx, "gemm_F_update", l);
       gemm_run<T>(st[6], false, true, -1.0, 1.0, s);      // F = P^T (M - Z V^T - V Z^T) P
     }
-    // With FP32 compute a stage that holds roots is factored by the blocked
-    // kernel, so that the roots can be done in FP64.
-    const bool use_inv = lp.inv && !(fp32 && nonroot < lp.count);
-    const bool split = !fp32 && lp.root_split;
-    (fp32 ? m->inv_used32 : m->inv_used64)[si] = use_inv ? 1 : (split ? 2 : 0);
-    {
-      if (split) {
-        // every node is a root of order 96 < n <= 192: two LDS Cholesky passes
-        Prof pf(cx, "root", l);
-        int hmax = 0;
-        for (int k = lp.first; k < lp.first + lp.count; ++k) hmax = std::max(hmax, root_split_h(m->nodes[k].n));
-        dim3 grid(lp.count), block(512);
-        if (hmax <= 64) {
-          hipLaunchKernelGGL((k_chol_lds<T, 64, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 1, (T*)nullptr, (const T*)b.Sg);
-          hipLaunchKernelGGL((k_chol_lds<T, 64, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 2, (T*)nullptr, (const T*)b.Sg);
-        } else {
-          hipLaunchKernelGGL((k_chol_lds<T, 96, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 1, (T*)nullptr, (const T*)b.Sg);
-          hipLaunchKernelGGL((k_chol_lds<T, 96, true>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,
-                             (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 2, (T*)nullptr, (const T*)b.Sg);
-        }
-        HSS_HIP(hipGetLastError());
-      } else if (use_inv) {
-        const int mm = lp.mmax;
-        const int rm = mm <= 32 ? 32 : (mm <= 64 ? 64 : 96);
-        // L_SR and Sigma inside the Cholesky kernel when the S rows fit its frame
-        const bool fuse = lp.rmax <= rm;
-        dim3 grid(lp.count), block(512);
-        {
-          Prof pf(cx, nonroot == 0 ? "root" : "chol_lds", l);
-#define CHOL_LDS(RM, FU)                                                                                      \
-  hipLaunchKernelGGL((k_chol_lds<T, RM, FU>), grid, block, 0, s, m->dnodes, lp.first, b.F, b.Li,              \
-                     (const int64_t*)m->dOffLi, m->dinfo, m->dlogdet, 0, msink, (const T*)b.Sg)
-          if (rm == 32) {
-            if (fuse) CHOL_LDS(32, true); else CHOL_LDS(32, false);
-          } else if (rm == 64) {
-            if (fuse) CHOL_LDS(64, true); else CHOL_LDS(64, false);
-          } else {
-            if (fuse) CHOL_LDS(96, true); else CHOL_LDS(96, false);
-          }
-#undef CHOL_LDS
-          HSS_HIP(hipGetLastError());
-        }
-        if (!fuse) {
-          {
-            Prof pf(cx, "gemm_LSR", l);
-            gemm_run<T>(st[7], false, true, 1.0, 0.0, s);  // L_SR = F_SR L_RR^{-T}
-          }
-          {
-            Prof pf(cx, "gemm_Sigma", l);
-            gemm_run<T>(st[8], false, true, -1.0, 1.0, s);  // Sigma = F_SS - L_SR L_SR^T
-          }
-          Prof pf(cx, "copy_lsr", l);
-          hipLaunchKernelGGL((k_copy_lsr<T>), dim3(16, lp.count), dim3(256), 0, s, m->dnodes, lp.first,
-                             (const T*)b.S2, (const int64_t*)m->dOffS2, b.F);
-          HSS_HIP(hipGetLastError());
-        }
-      } else {
-        int rmax_nr = 0, mmax_nr = 0, nmax_nr = 0;
-        for (int k = lp.first; k < lp.root_first; ++k) {
-          rmax_nr = std::max(rmax_nr, m->nodes[k].r);
-          mmax_nr = std::max(mmax_nr, m->nodes[k].m);
-          nmax_nr = std::max(nmax_nr, m->nodes[k].n);
-        }
-        if (nonroot > 0 && rmax_nr <= 96 && mmax_nr <= 160 && nmax_nr <= 256) {
-          launch_pchol_split<T>(m, lp.first, nonroot, b.F, msink, (const T*)b.Sg, s, cx, l);
-        } else if (nonroot > 0) {
-          Prof pf(cx, "pchol", l);
-          launch_pchol<T>(m, lp.first, nonroot, lp.nmax, b.F, s);
-        }
-        if (nonroot < lp.count) {
-          Prof pf(cx, "root", l);
-          if (fp32)
-            root_cholesky_fp64<T>(m, lp, b.F, s);
-          else
-            launch_pchol<T>(m, lp.root_first, lp.count - nonroot, lp.nmax, b.F, s);
-        }
-      }
-    }
+    m->inv_used64[si] = (char)stage_cholesky<T>(m, lp, b, st, msink, s);
+    if (mixed && st.size() > 6 && st[6].fp32_compute) promote_leaves<T>(m, (int)si, b, msink);
     if (m->after_stage) m->after_stage((int)si);
   }
-}
-
-// Clears the status words and the per-node log-determinant sums with a kernel
-// (not a memset node), so that the sequence can be recorded into a HIP graph.
-__global__ void k_clear_status(int32_t* __restrict__ info, int ninfo, double* __restrict__ logdet, int nld) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < ninfo + nld; i += gridDim.x * blockDim.x) {
-    if (i < ninfo)
-      info[i] = 0;
-    else
-      logdet[i - ninfo] = 0.0;
-  }
-}
-
-static void clear_status(hss_matrix_t m, hipStream_t s) {
-  const int tot = 4 + m->nsys + m->nnodes + 1;
-  hipLaunchKernelGGL(k_clear_status, dim3(std::min((tot + 255) / 256, 1024)), dim3(256), 0, s, m->dinfo,
-                     4 + m->nsys, m->dlogdet, m->nnodes + 1);
-  HSS_HIP(hipGetLastError());
+  if (mixed) m->promoted = promote_failed<T>(m, b, msink);
 }
 
 void prepare_factor(hss_matrix_t m, int precision) {
   if (precision == HSS_P_FP64)
     alloc_factor(m);
   else
-    alloc_factor32(m);
+    alloc_mixed(m);
 }
 
 void factor_fp64(hss_matrix_t m) {
   hipStream_t s = m->ctx->stream;
   alloc_factor(m);
   clear_status(m, s);
-  FBufs<double> b{m->dD, m->dB, m->dS, m->dF, m->dM, m->dV, m->dT, m->dSg, m->dW, m->dX, m->dLi, m->dS2};
-  factor_stages<double>(m, b, m->gemm_plan);
+  m->promoted = 0;
+  factor_stages<double>(m, fbufs(m), m->gemm_plan, false);
   hipLaunchKernelGGL(k_sum_logdet, dim3(1), dim3(256), 0, s, (const double*)m->dlogdet, m->nnodes,
                      m->dlogdet + m->nnodes);
   HSS_HIP(hipGetLastError());
 }
 
-// Mixed precision: the representation is rounded to FP32; the basis QR, the
-// diagonal product, the panel TRSM and the Schur updates run in FP32 (FP32
-// MFMA, FP32 accumulation); the 16x16 pivot blocks of every partial Cholesky
-// and the whole Cholesky of every root run in FP64.
-void factor_fp32(hss_matrix_t m) {
+// Mixed precision (hss_precision FP32): the same FP64 buffers and launch
+// sequence as factor_fp64, with the products W, C, Z and F of the leaf stage on
+// FP32 matrix cores (operands rounded to FP32, FP32 accumulation, the FP64 block
+// M added to the product in FP64); every pivot, Cholesky, triangular solve and
+// Schur complement, the basis QR and the stages above stay FP64, and a leaf
+// whose pivot fails is redone in FP64 (promote_failed). The result is the exact
+// factorization of the HSS matrix with its leaf blocks perturbed by the FP32
+// rounding of those products; the FP64 solve applies it, and refinement with
+// the FP64 matvec removes the perturbation.
+void factor_mixed(hss_matrix_t m) {
   hipStream_t s = m->ctx->stream;
-  alloc_factor32(m);
+  alloc_mixed(m);
   clear_status(m, s);
-  {
-    Prof pf(m->ctx, "convert_fp32", m->L);
-    cast<double, float>(m->dD, m->fD, m->lenD, s);
-    cast<double, float>(m->dB, m->fB, m->lenB, s);
-    cast<double, float>(m->dS, m->fS, m->lenS, s);
+  m->fp64_leaf.assign(m->nnodes, 0);
+  if (m->mixed_all64) {
+    // an earlier mixed factorization of this matrix redid at least half of its
+    // leaves in FP64: the FP32 products are skipped altogether
+    factor_stages<double>(m, fbufs(m), m->gemm_plan, false);
+    m->promoted = 0;
+    for (const NodeDesc& d : m->nodes) m->promoted += (d.c1 < 0 && d.parent >= 0) ? 1 : 0;
+  } else {
+    factor_stages<double>(m, fbufs(m), m->gemm_plan32, true);
+    int leaves = 0;
+    for (const NodeDesc& d : m->nodes) leaves += (d.c1 < 0 && d.parent >= 0) ? 1 : 0;
+    m->mixed_all64 = leaves > 0 && 2 * m->promoted >= leaves;
   }
-  FBufs<float> b{m->fD, m->fB, m->fS, m->fF, m->fM, m->fV, m->fT, m->fSg, m->fW, m->fX, m->fLi, m->fS2};
-  factor_stages<float>(m, b, m->gemm_plan32);
   hipLaunchKernelGGL(k_sum_logdet, dim3(1), dim3(256), 0, s, (const double*)m->dlogdet, m->nnodes,
                      m->dlogdet + m->nnodes);
   HSS_HIP(hipGetLastError());

@@ -68,7 +68,10 @@ __device__ __forceinline__ void xcd_tile(int& tile, int& entry) {
   entry = q / gx;
 }
 
-template <typename T, bool TA, bool TB, int BM, int BN, int BK>
+// T is the storage type of A, B, Cin and C; TC the compute type: the operands
+// are rounded to TC as they are staged into LDS, the matrix cores multiply and
+// accumulate in TC, and alpha * (product) + beta * Cin is formed in T.
+template <typename T, typename TC, bool TA, bool TB, int BM, int BN, int BK>
 __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs, T alpha, T beta) {
   constexpr int IM = BM / 32, JN = BN / 32;  // 16x16 accumulators per wave
   int tile, entry;
@@ -89,8 +92,8 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
     const int minp = (c1 >= r) ? max(col0, r) - r : col0 + mm;
     if (maxp < minp) return;  // every element of the tile lies strictly above the diagonal
   }
-  __shared__ T As[BK][BM + LPAD];
-  __shared__ T Bs[BK][BN + LPAD];
+  __shared__ TC As[BK][BM + LPAD];
+  __shared__ TC Bs[BK][BN + LPAD];
   constexpr int QA = BM * BK / 256, QB = BN * BK / 256;  // elements per thread and K slice
   const T* __restrict__ A = (const T*)d.A;
   const T* __restrict__ B = (const T*)d.B;
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   }
   const int64_t sa = TA ? BK : (int64_t)BK * d.lda;
   const int64_t sb = TB ? (int64_t)BK * d.ldb : BK;
-  typename AccT<T>::type acc[IM][JN];
+  typename AccT<TC>::type acc[IM][JN];
 #pragma unroll
   for (int i = 0; i < IM; ++i)
 #pragma unroll
@@ -167,14 +170,14 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   if (d.k > 0) load(0);
   for (int k0 = 0; k0 < d.k; k0 += BK) {
 #pragma unroll
-    for (int q = 0; q < QA; ++q) As[ak[q]][ar[q]] = ra[q];
+    for (int q = 0; q < QA; ++q) As[ak[q]][ar[q]] = (TC)ra[q];
 #pragma unroll
-    for (int q = 0; q < QB; ++q) Bs[bk[q]][bc[q]] = rb[q];
+    for (int q = 0; q < QB; ++q) Bs[bk[q]][bc[q]] = (TC)rb[q];
     __syncthreads();
     if (k0 + BK < d.k) load(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      T a[IM], b[JN];
+      TC a[IM], b[JN];
 #pragma unroll
       for (int i = 0; i < IM; ++i) a[i] = As[kk + lk][wm + 16 * i + lr];
 #pragma unroll
@@ -198,11 +201,11 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + wm + 16 * i + lr;
-        const int col = col0 + wn + 16 * j + mfma_row((T)0, lane, v);
+        const int col = col0 + wn + 16 * j + mfma_row((TC)0, lane, v);
         if (row < d.m && col < d.n) {
           const int prow = perm_index(row, d.m, d.perm_r);
           const int pcol = perm_index(col, d.n, d.perm_r);
-          T val = alpha * acc[i][j][v];
+          T val = alpha * (T)acc[i][j][v];
           if (beta != (T)0) {
             const int irow = d.perm_in ? prow : row;
             const int icol = d.perm_in ? pcol : col;
@@ -258,27 +261,27 @@ void gemm_free(GemmBatch& b) {
   b.dev = nullptr;
 }
 
-template <typename T, int BM, int BN, int BK>
+template <typename T, typename TC, int BM, int BN, int BK>
 static void launch_tile(const GemmBatch& b, bool ta, bool tb, T alpha, T beta, hipStream_t s) {
   const int tiles = ((b.mmax + BM - 1) / BM) * ((b.nmax + BN - 1) / BN);
   dim3 grid(tiles, b.count);
   if (!ta && !tb)
-    hipLaunchKernelGGL((k_gemm<T, false, false, BM, BN, BK>), grid, dim3(256), 0, s, b.dev, alpha, beta);
+    hipLaunchKernelGGL((k_gemm<T, TC, false, false, BM, BN, BK>), grid, dim3(256), 0, s, b.dev, alpha, beta);
   else if (ta && !tb)
-    hipLaunchKernelGGL((k_gemm<T, true, false, BM, BN, BK>), grid, dim3(256), 0, s, b.dev, alpha, beta);
+    hipLaunchKernelGGL((k_gemm<T, TC, true, false, BM, BN, BK>), grid, dim3(256), 0, s, b.dev, alpha, beta);
   else if (!ta && tb)
-    hipLaunchKernelGGL((k_gemm<T, false, true, BM, BN, BK>), grid, dim3(256), 0, s, b.dev, alpha, beta);
+    hipLaunchKernelGGL((k_gemm<T, TC, false, true, BM, BN, BK>), grid, dim3(256), 0, s, b.dev, alpha, beta);
   else
-    hipLaunchKernelGGL((k_gemm<T, true, true, BM, BN, BK>), grid, dim3(256), 0, s, b.dev, alpha, beta);
+    hipLaunchKernelGGL((k_gemm<T, TC, true, true, BM, BN, BK>), grid, dim3(256), 0, s, b.dev, alpha, beta);
   HSS_HIP(hipGetLastError());
 }
 
-template <typename T>
+template <typename T, typename TC>
 static void launch(const GemmBatch& b, bool ta, bool tb, T alpha, T beta, hipStream_t s) {
   if (b.count == 0 || b.mmax == 0 || b.nmax == 0) return;
   HSS_CHECK(b.count <= 65535, HSS_ERR_UNSUPPORTED, "too many GEMM batch entries in one launch");
   GemmTimer t(b, s);
-#define HSS_TILE(v) launch_tile<T, kTileM[v], kTileN[v], kTileK[v]>(b, ta, tb, alpha, beta, s)
+#define HSS_TILE(v) launch_tile<T, TC, kTileM[v], kTileN[v], kTileK[v]>(b, ta, tb, alpha, beta, s)
   switch (b.variant) {
     case 1: HSS_TILE(1); break;
     case 2: HSS_TILE(2); break;
@@ -293,10 +296,13 @@ static void launch(const GemmBatch& b, bool ta, bool tb, T alpha, T beta, hipStr
 }
 
 void gemm_launch_f64(const GemmBatch& b, bool ta, bool tb, double alpha, double beta, hipStream_t s) {
-  launch<double>(b, ta, tb, alpha, beta, s);
+  if (b.fp32_compute)
+    launch<double, float>(b, ta, tb, alpha, beta, s);
+  else
+    launch<double, double>(b, ta, tb, alpha, beta, s);
 }
 void gemm_launch_f32(const GemmBatch& b, bool ta, bool tb, float alpha, float beta, hipStream_t s) {
-  launch<float>(b, ta, tb, alpha, beta, s);
+  launch<float, float>(b, ta, tb, alpha, beta, s);
 }
 
 }  // namespace hss

@@ -108,6 +108,7 @@ struct GemmBatch {
   int32_t count = 0;
   int32_t mmax = 0, nmax = 0;
   int32_t variant = 0;  // tile shape, set by the autotuner
+  bool fp32_compute = false;  // FP64 storage, operands rounded to FP32 for FP32 MFMA
 };
 
 // Autotuning: while a recorder is installed on the calling thread, every
@@ -198,38 +199,30 @@ struct hss_matrix_s {
   int64_t* dOffS2 = nullptr;
   double* dLi = nullptr;
   double* dS2 = nullptr;
-  float* fLi = nullptr;
-  float* fS2 = nullptr;
   int64_t lenLi = 0, lenS2 = 0;
   int32_t* dinfo = nullptr;  // [0] status, [1] node, [2] pivot
   double* dlogdet = nullptr; // per node partial sums
   int64_t lenF = 0, lenM = 0, lenV = 0, lenT = 0, lenSg = 0, lenW = 0, lenX = 0;
   bool factor_ready = false;
   std::vector<std::vector<hss::GemmBatch>> gemm_plan;  // per stage, per step
-  std::vector<char> inv_used64, inv_used32;  // per stage: explicit inverse factor present
+  std::vector<char> inv_used64;  // per stage: 1 explicit inverse factor, 2 split root, 0 neither
   // called once the kernels of factor stage si are enqueued (fused factor + solve)
   std::function<void(int)> after_stage;
 
-  // FP32 factor (mixed precision)
-  float* fF = nullptr;
-  float* fM = nullptr;
-  float* fV = nullptr;
-  float* fT = nullptr;
-  float* fW = nullptr;
-  float* fX = nullptr;
-  float* fD = nullptr;
-  float* fB = nullptr;
-  float* fS = nullptr;
-  float* fSg = nullptr;
-  double* dRoot = nullptr;          // FP64 root blocks of the mixed factorization (F offsets)
-  bool factor32_ready = false;
+  // mixed precision: the same FP64 buffers and GEMM batches, with the leaf
+  // stage's products computed on FP32 matrix cores (own tile choices)
+  bool mixed_ready = false;
+  int32_t promoted = 0;  // leaves of the last mixed factorization redone in FP64
+  bool mixed_all64 = false;  // FP32 found unsuitable for this matrix: mixed runs FP64
+  double* dpmin = nullptr;   // per node: smallest pivot of its last partial Cholesky
+  std::vector<double> leaf_trace;  // per node (leaves): trace of D, the FP32 error scale
+  std::vector<char> fp64_leaf;     // per node: leaf redone in FP64 by the last mixed factorization
   std::vector<std::vector<hss::GemmBatch>> gemm_plan32;
 
   // solve / matvec workspaces (device), sized for ws_nrhs columns
   double* dvec = nullptr;   // per-node vectors, sum(n) x nrhs
   double* dxt = nullptr;    // matvec up-sweep, sum(r) x nrhs
   double* dyt = nullptr;    // matvec down-sweep, sum(r) x nrhs
-  float* fvec = nullptr;
   int64_t ws_nrhs = 0;
   int64_t sum_n = 0, sum_r = 0;
   double* dtmp = nullptr;   // refinement temporaries (4 x N x nrhs)
@@ -299,7 +292,7 @@ void gemm_launch_f32(const GemmBatch& b, bool ta, bool tb, float alpha, float be
 
 // factor.hip
 void factor_fp64(hss_matrix_t m);
-void factor_fp32(hss_matrix_t m);
+void factor_mixed(hss_matrix_t m);
 double read_logdet(hss_matrix_t m);
 void free_factor(hss_matrix_t m);
 
@@ -314,7 +307,6 @@ void drop_graphs(hss_matrix_t m);
 // solve.hip
 void ensure_vec_ws(hss_matrix_t m, int64_t nrhs);
 void solve_fp64(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld);
-void solve_fp32(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld);
 void matvec_fp64(hss_matrix_t m, const double* x, double* y, int64_t nrhs, int64_t ld);
 
 // construct.hip

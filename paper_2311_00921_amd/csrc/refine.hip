@@ -191,8 +191,6 @@ void refine(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld
   *converged = worst <= tol;
 }
 
-void solve_fp32(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld);
-
 }  // namespace hss
 
 using namespace hss;

@@ -768,8 +768,6 @@ void ensure_vec_ws(hss_matrix_t m, int64_t nrhs) {
   if (m->dvec) dev_free(m->dvec);
   if (m->dxt) dev_free(m->dxt);
   if (m->dyt) dev_free(m->dyt);
-  if (m->fvec) dev_free(m->fvec);
-  m->fvec = nullptr;
   m->dvec = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->sum_n * nrhs, 1));
   m->dxt = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->sum_r * nrhs, 1));
   m->dyt = (double*)dev_alloc(sizeof(double) * std::max<int64_t>(m->sum_r * nrhs, 1));
@@ -834,11 +832,6 @@ void solve_fp64(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_
   solve_impl<double>(m, m->dF, m->dV, m->dW, m->dSg, m->dvec, m->dLi, m->inv_used64, b, x, nrhs, ld);
 }
 
-void solve_fp32(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld) {
-  ensure_vec_ws(m, nrhs);
-  if (!m->fvec) m->fvec = (float*)dev_alloc(sizeof(float) * std::max<int64_t>(m->sum_n * m->ws_nrhs, 1));
-  solve_impl<float>(m, m->fF, m->fV, m->fW, m->fSg, m->fvec, m->fLi, m->inv_used32, b, x, nrhs, ld);
-}
 
 // FP64 factorization and solve in one pass. The forward sweep of a stage
 // needs only that stage's factors and its children's forward results, so it

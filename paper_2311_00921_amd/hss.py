@@ -84,7 +84,7 @@ class hss_info(C.Structure):
                 ("failed_node", C.c_int32), ("failed_pivot", C.c_int32),
                 ("bytes_representation", C.c_int64), ("bytes_factor", C.c_int64),
                 ("factor_ms", C.c_double), ("solve_ms", C.c_double),
-                ("systems", C.c_int32), ("failed_system", C.c_int32)]
+                ("systems", C.c_int32), ("failed_system", C.c_int32), ("promoted_nodes", C.c_int32)]
 
 
 # Every symbol include/hss.h declares, with its ctypes signature.
@@ -439,11 +439,14 @@ def hss_get_permutation(ctx, m, out):
     return out
 
 
-def hss_debug_node_block(ctx, m, node: int, what: int, rows: int) -> np.ndarray:
-    buf = np.zeros(rows * rows)
+def hss_debug_node_block(ctx, m, node: int, what: int, rows: int, cols: int | None = None) -> np.ndarray:
+    """One intermediate block of the factorization as a rows x cols (default
+    square) column-major host array; `what` as in include/hss.h."""
+    cols = rows if cols is None else cols
+    buf = np.zeros(max(rows * cols, 1))
     _check(load().hss_debug_node_block(ctx, m, node, what, buf.ctypes.data_as(C.POINTER(C.c_double)), buf.size),
            "hss_debug_node_block")
-    return buf.reshape((rows, rows), order="F")
+    return buf[:rows * cols].reshape((rows, cols), order="F")
 
 
 def hss_profile_enable(ctx, on: bool):

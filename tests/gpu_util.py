@@ -10,3 +10,11 @@ def rel(a, b):
     a = np.asarray(a)
     b = np.asarray(b)
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def maxrel(a, b):
+    """Elementwise gate: max |a - b| / max |b| (a few wrong entries cannot hide
+    under a normwise difference)."""
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
