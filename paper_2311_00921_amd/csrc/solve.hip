@@ -632,128 +632,6 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_bwd(const NodeDesc* __r
 }
 
 // ---------------------------------------------------------------------------
-// FP64 HSS matvec
-// ---------------------------------------------------------------------------
-
-// leaves: xt_i = U_i^T x_i (x gathered through perm)
-__global__ __launch_bounds__(256) void k_mv_up_leaf(const NodeDesc* __restrict__ nodes, int first,
-                                                    const double* __restrict__ Bb, const double* __restrict__ x,
-                                                    int64_t ld, int64_t nrhs, const int64_t* __restrict__ perm,
-                                                    double* __restrict__ xt) {
-  const NodeDesc nd = nodes[first + blockIdx.x];
-  const int n = nd.n, r = nd.r;
-  __shared__ double sx[512];
-  const double* U = Bb + nd.offB;
-  for (int64_t c = 0; c < nrhs; ++c) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) sx[i] = x[perm[nd.lo + i] + c * ld];
-    __syncthreads();
-    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int j = wid; j < r; j += blockDim.x >> 6) {
-      double acc = 0.0;
-      for (int i = lane; i < n; i += 64) acc += U[i + (int64_t)j * n] * sx[i];
-      acc = wave_sum(acc);
-      if (lane == 0) xt[nd.offR * nrhs + j + c * r] = acc;
-    }
-    __syncthreads();
-  }
-}
-
-// upper: xt_p = E_p^T [xt_c1; xt_c2]
-__global__ __launch_bounds__(256) void k_mv_up(const NodeDesc* __restrict__ nodes, int first,
-                                               const double* __restrict__ Bb, int64_t nrhs,
-                                               double* __restrict__ xt) {
-  const int p = first + blockIdx.x;
-  const NodeDesc nd = nodes[p];
-  const NodeDesc c1 = nodes[nd.c1], c2 = nodes[nd.c2];
-  const int n = nd.n, r = nd.r;
-  const double* E = Bb + nd.offB;
-  const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  for (int64_t c = 0; c < nrhs; ++c) {
-    for (int j = wid; j < r; j += blockDim.x >> 6) {
-      double acc = 0.0;
-      for (int i = lane; i < n; i += 64) {
-        const double v = (i < c1.r) ? xt[c1.offR * nrhs + i + c * c1.r] : xt[c2.offR * nrhs + (i - c1.r) + c * c2.r];
-        acc += E[i + (int64_t)j * n] * v;
-      }
-      acc = wave_sum(acc);
-      if (lane == 0) xt[nd.offR * nrhs + j + c * r] = acc;
-    }
-  }
-}
-
-// couplings of the children of each node on a level: yt_c1 = S xt_c2, yt_c2 = S^T xt_c1
-__global__ __launch_bounds__(256) void k_mv_coupling(const NodeDesc* __restrict__ nodes, int first,
-                                                     const double* __restrict__ Sb, int64_t nrhs,
-                                                     const double* __restrict__ xt, double* __restrict__ yt) {
-  const int p = first + blockIdx.x;
-  const NodeDesc nd = nodes[p];
-  const NodeDesc c1 = nodes[nd.c1], c2 = nodes[nd.c2];
-  const int r1 = c1.r, r2 = c2.r;
-  const double* S = Sb + nd.offS;
-  for (int64_t c = 0; c < nrhs; ++c) {
-    for (int i = threadIdx.x; i < r1; i += blockDim.x) {
-      double acc = 0.0;
-      for (int j = 0; j < r2; ++j) acc += S[i + (int64_t)j * r1] * xt[c2.offR * nrhs + j + c * r2];
-      yt[c1.offR * nrhs + i + c * r1] = acc;
-    }
-    for (int j = threadIdx.x; j < r2; j += blockDim.x) {
-      double acc = 0.0;
-      for (int i = 0; i < r1; ++i) acc += S[i + (int64_t)j * r1] * xt[c1.offR * nrhs + i + c * r1];
-      yt[c2.offR * nrhs + j + c * r2] = acc;
-    }
-  }
-}
-
-// down-sweep: [yt_c1; yt_c2] += E_p yt_p
-__global__ __launch_bounds__(256) void k_mv_down(const NodeDesc* __restrict__ nodes, int first,
-                                                 const double* __restrict__ Bb, int64_t nrhs,
-                                                 double* __restrict__ yt) {
-  const int p = first + blockIdx.x;
-  const NodeDesc nd = nodes[p];
-  const NodeDesc c1 = nodes[nd.c1], c2 = nodes[nd.c2];
-  const int n = nd.n, r = nd.r;
-  const double* E = Bb + nd.offB;
-  for (int64_t c = 0; c < nrhs; ++c) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      double acc = 0.0;
-      for (int j = 0; j < r; ++j) acc += E[i + (int64_t)j * n] * yt[nd.offR * nrhs + j + c * r];
-      if (i < c1.r)
-        yt[c1.offR * nrhs + i + c * c1.r] += acc;
-      else
-        yt[c2.offR * nrhs + (i - c1.r) + c * c2.r] += acc;
-    }
-  }
-}
-
-// leaves: y_i = D_i x_i + U_i yt_i, scattered through perm
-__global__ __launch_bounds__(256) void k_mv_leaf(const NodeDesc* __restrict__ nodes, int first,
-                                                 const double* __restrict__ Db, const double* __restrict__ Bb,
-                                                 const double* __restrict__ x, double* __restrict__ y, int64_t ld,
-                                                 int64_t nrhs, const int64_t* __restrict__ perm,
-                                                 const double* __restrict__ yt, int has_yt) {
-  const NodeDesc nd = nodes[first + blockIdx.x];
-  const int n = nd.n, r = nd.r;
-  __shared__ double sx[512];
-  __shared__ double sy[128];
-  const double* D = Db + nd.offD;
-  const double* U = Bb + nd.offB;
-  for (int64_t c = 0; c < nrhs; ++c) {
-    for (int i = threadIdx.x; i < n; i += blockDim.x) sx[i] = x[perm[nd.lo + i] + c * ld];
-    if (has_yt)
-      for (int j = threadIdx.x; j < r; j += blockDim.x) sy[j] = yt[nd.offR * nrhs + j + c * r];
-    __syncthreads();
-    for (int i = threadIdx.x; i < n; i += blockDim.x) {
-      double acc = 0.0;
-      for (int k = 0; k < n; ++k) acc += D[i + (int64_t)k * n] * sx[k];
-      if (has_yt)
-        for (int j = 0; j < r; ++j) acc += U[i + (int64_t)j * n] * sy[j];
-      y[perm[nd.lo + i] + c * ld] = acc;
-    }
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------------------
 // host drivers
 // ---------------------------------------------------------------------------
 
@@ -868,40 +746,6 @@ void factor_solve_fp64(hss_matrix_t m, const double* b, double* x, int64_t nrhs,
                        s);
   if (nrhs > RC)
     solve_impl<double>(m, m->dF, m->dV, m->dW, m->dSg, m->dvec, m->dLi, m->inv_used64, b, x, nrhs, ld, RC);
-}
-
-// y = A x over the stages: up-sweep (leaves, then upward), couplings of every
-// internal node, down-sweep (downward), leaves. Roots have rank 0.
-void matvec_fp64(hss_matrix_t m, const double* x, double* y, int64_t nrhs, int64_t ld) {
-  hipStream_t s = m->ctx->stream;
-  ensure_vec_ws(m, nrhs);
-  const int64_t* perm = m->dperm;
-  const int ns = (int)m->stages.size();
-  const LevelPlan& leaves = m->stages[0];
-  hipLaunchKernelGGL(k_mv_up_leaf, dim3(leaves.count), dim3(256), 0, s, m->dnodes, leaves.first,
-                     (const double*)m->dB, x, ld, nrhs, perm, m->dxt);
-  HSS_HIP(hipGetLastError());
-  for (int si = 1; si < ns; ++si) {
-    const LevelPlan& lp = m->stages[si];
-    hipLaunchKernelGGL(k_mv_up, dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const double*)m->dB, nrhs,
-                       m->dxt);
-    HSS_HIP(hipGetLastError());
-  }
-  for (int si = 1; si < ns; ++si) {
-    const LevelPlan& lp = m->stages[si];
-    hipLaunchKernelGGL(k_mv_coupling, dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const double*)m->dS,
-                       nrhs, (const double*)m->dxt, m->dyt);
-    HSS_HIP(hipGetLastError());
-  }
-  for (int si = ns - 1; si >= 1; --si) {
-    const LevelPlan& lp = m->stages[si];
-    hipLaunchKernelGGL(k_mv_down, dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const double*)m->dB, nrhs,
-                       m->dyt);
-    HSS_HIP(hipGetLastError());
-  }
-  hipLaunchKernelGGL(k_mv_leaf, dim3(leaves.count), dim3(256), 0, s, m->dnodes, leaves.first, (const double*)m->dD,
-                     (const double*)m->dB, x, y, ld, nrhs, perm, (const double*)m->dyt, 1);
-  HSS_HIP(hipGetLastError());
 }
 
 }  // namespace hss

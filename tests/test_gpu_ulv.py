@@ -12,7 +12,7 @@ import pytest
 import synth
 from oracle import hss_oracle as O
 
-from gpu_util import oracle_to_dict, rel
+from gpu_util import maxrel, oracle_to_dict, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -50,12 +50,14 @@ def factor_and_compare(ctx, torch, h, nrhs=1, seed=7, xtol=1e-10, check_blocks=T
         torch.cuda.synchronize()
         x = xd.cpu().numpy()
         assert rel(x, x_or) <= xtol, rel(x, x_or)
+        assert maxrel(x, x_or) <= xtol, maxrel(x, x_or)
         ld = hss.hss_logdet(ctx, m)
         scale = abs(F.logdet) + 1.0
         assert abs(ld - F.logdet) <= 1e-10 * scale, (ld, F.logdet)
         y = hss.hss_matvec(ctx, m, bd).cpu().numpy()
         y_or = O.matvec(h, b)
         assert rel(y, y_or) <= 1e-13
+        assert maxrel(y, y_or) <= 1e-13, maxrel(y, y_or)
         if check_blocks and h.levels > 0:
             L = h.levels
             for l in range(1, L + 1):
@@ -63,8 +65,10 @@ def factor_and_compare(ctx, torch, h, nrhs=1, seed=7, xtol=1e-10, check_blocks=T
                     k = 2 ** l - 1 + i
                     sig = hss.hss_debug_node_block(ctx, m, k, 0, h.rank[l][i])
                     assert rel(sig, F.Sigma[l][i]) <= 1e-11, (l, i, rel(sig, F.Sigma[l][i]))
+                    assert maxrel(sig, F.Sigma[l][i]) <= 1e-11, (l, i, maxrel(sig, F.Sigma[l][i]))
             root = hss.hss_debug_node_block(ctx, m, 0, 1, F.root_block.shape[0])
             assert rel(root, F.root_block) <= 1e-11
+            assert maxrel(root, F.root_block) <= 1e-11
         return x, x_or
     finally:
         hss.hss_matrix_destroy(m)
