@@ -252,6 +252,22 @@ hss_status hss_ulv_factor(hss_ctx_t ctx, hss_matrix_t m, const hss_factor_opts* 
 hss_status hss_ulv_solve(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, double* d_x,
                          int64_t nrhs, int64_t ld);
 
+/* The solve of hss_ulv_solve for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same launches and results, bit for bit, with the per-node
+ * vector workspace taken from a static device array of 2^22 doubles (32 MiB,
+ * resolved by hss_ctx_create and held by each GPU until the process ends)
+ * instead of the matrix's own workspace. Nothing is allocated, no graph is
+ * recorded, and per-launch profiling is bypassed. The workspace needs
+ * sum_n x nrhs doubles, sum_n being the sum of the block sizes of all nodes
+ * (N plus, over the non-leaf nodes, the sum of their children's ranks; 458 560
+ * at N = 262144, leaf 256, rank 96: up to nine right-hand sides); larger
+ * requests fail with UNSUPPORTED and a message naming the limit. Every call on
+ * one GPU shares the array: calls that overlap on one GPU (two streams, two
+ * threads) race. Arguments, state and errors as hss_ulv_solve. */
+hss_status hss_ulv_solve_noalloc(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, double* d_x, int64_t nrhs,
+                                 int64_t ld);
+
 /* FP64 factorization and solve in one call (Alg. 2, then Eq. 17): the same
  * results as hss_ulv_factor (FP64) followed by hss_ulv_solve, for callers that
  * hold the right-hand sides at factorization time. A stage's forward sweep

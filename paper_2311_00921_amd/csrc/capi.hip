@@ -282,6 +282,7 @@ hss_status hss_ctx_create(int32_t device, void* hip_stream, hss_ctx_t* out) {
   HSS_HIP(hipGetDeviceCount(&count));
   HSS_CHECK(device >= 0 && device < count, HSS_ERR_INVALID_ARGUMENT, "device index out of range");
   HSS_HIP(hipSetDevice(device));
+  noalloc_init(device);  // the static scratch array of the no-allocation solve, on this device
   hss_ctx_t c = new hss_ctx_s();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;

@@ -307,6 +307,10 @@ void drop_graphs(hss_matrix_t m);
 // solve.hip
 void ensure_vec_ws(hss_matrix_t m, int64_t nrhs);
 void solve_fp64(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld);
+void solve_fp64_ws(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld, double* vec);
+
+// noalloc.hip: resolves the static scratch array's address on the current device
+void noalloc_init(int device);
 void matvec_fp64(hss_matrix_t m, const double* x, double* y, int64_t nrhs, int64_t ld);
 
 // construct.hip

@@ -707,7 +707,13 @@ static void solve_impl(hss_matrix_t m, const T* F, const T* V, const T* Yw, cons
 
 void solve_fp64(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld) {
   ensure_vec_ws(m, nrhs);
-  solve_impl<double>(m, m->dF, m->dV, m->dW, m->dSg, m->dvec, m->dLi, m->inv_used64, b, x, nrhs, ld);
+  solve_fp64_ws(m, b, x, nrhs, ld, m->dvec);
+}
+
+// The solve with a caller-provided per-node vector workspace (sum_n x nrhs
+// doubles); launches kernels only.
+void solve_fp64_ws(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld, double* vec) {
+  solve_impl<double>(m, m->dF, m->dV, m->dW, m->dSg, vec, m->dLi, m->inv_used64, b, x, nrhs, ld);
 }
 
 

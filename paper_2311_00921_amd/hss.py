@@ -101,6 +101,7 @@ SIGNATURES = {
     "hss_ulv_factor": (C.c_int, [_P, _P, C.POINTER(hss_factor_opts)]),
     "hss_ulv_solve": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64]),
     "hss_ulv_factor_solve": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64]),
+    "hss_ulv_solve_noalloc": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64]),
     "hss_ulv_solve_refined": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64, C.c_double, C.c_int32,
                                         C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "hss_matvec": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64]),
@@ -180,6 +181,8 @@ def _colmajor(t, n):
     """View a (n,) or (n, k) tensor as column-major n x k: returns (tensor, k, ld)."""
     if t.dim() == 1:
         return t.contiguous(), 1, n
+    if t.stride(0) == 1 and t.shape[1] == 1:
+        return t, 1, n  # one column: its stride is never used
     if t.stride(0) == 1 and t.stride(1) >= n:
         return t, t.shape[1], t.stride(1)
     tc = t.t().contiguous().t()
@@ -391,6 +394,20 @@ def hss_ulv_solve(ctx, m, b, x=None):
     """x = A^{-1} b for a (N,) or (N, nrhs) float64 device tensor b."""
     bc, k, ld, x = _vec_args(m, b, x)
     _check(load().hss_ulv_solve(ctx, m, _ptr(bc), _ptr(x), k, ld), "hss_ulv_solve")
+    return x
+
+
+def hss_ulv_solve_noalloc(ctx, m, b, x):
+    """x = A^{-1} b like hss_ulv_solve, with the library allocating nothing: the
+    output x must be given (same shape and strides as b)."""
+    if x is None:
+        raise ValueError("hss_ulv_solve_noalloc needs the output tensor x")
+    colmajor = (b.dim() == 1 and b.is_contiguous()) or (
+        b.dim() == 2 and b.stride(0) == 1 and (b.shape[1] == 1 or b.stride(1) >= b.shape[0]))
+    if not colmajor:
+        raise ValueError("hss_ulv_solve_noalloc needs b in column-major layout (a copy would allocate)")
+    bc, k, ld, x = _vec_args(m, b, x)
+    _check(load().hss_ulv_solve_noalloc(ctx, m, _ptr(bc), _ptr(x), k, ld), "hss_ulv_solve_noalloc")
     return x
 
 
