@@ -77,8 +77,8 @@ typedef enum { HSS_COMPRESS_SCALED = 1 } hss_compress_mode;
 typedef struct {
   int32_t leaf_size;   /* >= 2: maximum points per leaf */
   int32_t levels;      /* 0 = derive ceil(log2(N/leaf_size)); otherwise must equal it */
-  int32_t rank;        /* > 0 fixed rank per node; 0 = adaptive by tol */
-  int32_t max_rank;    /* cap for adaptive ranks (0 = none) */
+  int32_t rank;        /* 1..256 fixed rank per node; 0 = adaptive by tol */
+  int32_t max_rank;    /* cap for adaptive ranks (0 = 128; at most 256) */
   double tol;          /* adaptive truncation: keep pivots with |R_jj| > tol*|R_00| */
   int32_t mode;        /* hss_compress_mode */
   /* Sample sizing (adaptive ranks, tol > 0). With neither of the two below,
@@ -226,7 +226,7 @@ hss_status hss_get_construct_stats(hss_matrix_t m, hss_construct_stats* out);
  * (the host buffers may be freed on return) and synchronizes. Leaves the
  * matrix CONSTRUCTED. Errors: INVALID_ARGUMENT for NULL or inconsistent sizes
  * or a perm that is not a permutation; UNSUPPORTED for blocks above 512 rows
- * or ranks above 128. */
+ * or ranks above 256. */
 hss_status hss_import(hss_ctx_t ctx, const hss_desc* desc, hss_matrix_t* out);
 
 /* Sizes (in elements) of the arrays hss_export writes: leaf_lo, rank, D, U, E, S, perm. */

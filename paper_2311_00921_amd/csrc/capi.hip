@@ -389,8 +389,8 @@ hss_status hss_import(hss_ctx_t ctx, const hss_desc* d, hss_matrix_t* out) {
   for (int k = 1; k < m->nnodes; ++k) m->nodes[k].r = d->rank[k];
   layout_representation(m);
   for (int k = 1; k < m->nnodes; ++k)
-    HSS_CHECK(m->nodes[k].n <= 512 && m->nodes[k].r <= 128, HSS_ERR_UNSUPPORTED,
-              "blocks above 512 rows or ranks above 128 are not supported");
+    HSS_CHECK(m->nodes[k].n <= 512 && m->nodes[k].r <= 256, HSS_ERR_UNSUPPORTED,
+              "blocks above 512 rows or ranks above 256 are not supported");
   HSS_CHECK(m->nodes[0].n <= 512, HSS_ERR_UNSUPPORTED, "root block above 512 rows");
   hipStream_t s = ctx->stream;
   HSS_HIP(hipMemcpyAsync(m->dD, d->D, sizeof(double) * m->lenD, hipMemcpyHostToDevice, s));
@@ -440,7 +440,7 @@ hss_status hss_construct(hss_ctx_t ctx, const double* d_points, int64_t n, int32
     HSS_CHECK(n >= 1, HSS_ERR_INVALID_ARGUMENT, "n must be >= 1");
     HSS_CHECK(dim >= 1 && dim <= 3, HSS_ERR_INVALID_ARGUMENT, "dim must be 1, 2 or 3");
     HSS_CHECK(opts->leaf_size >= 2 && opts->leaf_size <= 512, HSS_ERR_INVALID_ARGUMENT, "leaf_size must be in [2, 512]");
-    HSS_CHECK(opts->rank >= 0 && opts->rank <= 128, HSS_ERR_INVALID_ARGUMENT, "rank must be in [0, 128]");
+    HSS_CHECK(opts->rank >= 0 && opts->rank <= 256, HSS_ERR_INVALID_ARGUMENT, "rank must be in [0, 256]");
     HSS_CHECK(opts->rank > 0 || opts->tol > 0.0, HSS_ERR_INVALID_ARGUMENT, "adaptive rank needs tol > 0");
     HSS_CHECK(opts->max_rank >= 0, HSS_ERR_INVALID_ARGUMENT, "max_rank must be >= 0");
     HSS_CHECK(opts->mode == HSS_COMPRESS_SCALED, HSS_ERR_INVALID_ARGUMENT, "unknown compression mode");

@@ -389,7 +389,7 @@ __global__ __launch_bounds__(256) void k_judge(const CNode* __restrict__ cn, con
   const double* Y = Yb + c.offY + (int64_t)sb * n;
   const double* Q = Qb + c.offQ;
   __shared__ double y[512];
-  __shared__ double cq[128];
+  __shared__ double cq[256];
   __shared__ double red[2][256];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   double num = 0.0, den = 0.0;
@@ -631,7 +631,7 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
   }
   const int kfix = o.rank;
   int kcap = o.rank > 0 ? o.rank : (o.max_rank > 0 ? o.max_rank : 128);
-  kcap = std::min(kcap, 128);
+  kcap = std::min(kcap, 256);
   if (sp.s_basis == 0) {
     // sample count from the learned rank model: largest predicted node rank + 8
     const std::vector<float> f = node_features(P, perm, dim, L, leaf_lo, kern.length > 0.0 ? kern.length : 1.0, o.tol);

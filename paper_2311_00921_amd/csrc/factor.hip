@@ -248,6 +248,105 @@ __global__ __launch_bounds__(256) void k_tri_inv(const NodeDesc* __restrict__ no
 }
 
 // ---------------------------------------------------------------------------
+// Basis QR for ranks above 128 (one workgroup per node, in global memory): the
+// Householder QR of the orthonormal basis B (n x r), H_j = I - tau_j v_j v_j^T
+// with v_j unit lower trapezoidal, accumulated as H = H_1 ... H_r = I - V T V^T
+// (T upper triangular, T_jj = tau_j, T[:j, j] = -tau_j T[:j, :j] V[:, :j]^T v_j).
+// B = H R with R = diag(beta) up to rounding (B is orthonormal), so the first r
+// columns of H are B diag(Sg) with Sg_j = sign(beta_j). Writes V (into its slot,
+// unit diagonal and zeros above it), T and Sg; Y = V T follows as a GEMM.
+// ---------------------------------------------------------------------------
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_house_basis(const NodeDesc* __restrict__ nodes, int first,
+                                                     const T* __restrict__ Bbase, T* __restrict__ Vbase,
+                                                     T* __restrict__ Tbase, T* __restrict__ Sgbase) {
+  const NodeDesc nd = nodes[first + blockIdx.x];
+  const int n = nd.n, r = nd.r;
+  if (r == 0) return;
+  const T* B = Bbase + nd.offB;
+  T* V = Vbase + nd.offV;
+  T* Tm = Tbase + nd.offT;
+  T* Sg = Sgbase + nd.offSg;
+  __shared__ double red[256];
+  __shared__ double tau[256];     // r <= 256
+  __shared__ double w[256];
+  __shared__ double bcast[2];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int64_t e = tid; e < (int64_t)n * r; e += 256) V[e] = B[e];
+  __syncthreads();
+  for (int j = 0; j < r; ++j) {
+    T* x = V + (int64_t)j * n;
+    // norm of x[j+1:n] and x0 = x[j]
+    double p = 0.0;
+    for (int i = j + 1 + tid; i < n; i += 256) p += (double)x[i] * (double)x[i];
+    red[tid] = p;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) red[tid] += red[tid + o];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double x0 = (double)x[j], sig = red[0];
+      const double alpha = sqrt(x0 * x0 + sig);
+      // beta = -sign(x0) alpha, tau = (beta - x0) / beta, v = x / (x0 - beta) with v_0 = 1
+      const double beta = x0 >= 0.0 ? -alpha : alpha;
+      const double t = alpha > 0.0 ? (beta - x0) / beta : 0.0;
+      const double scale = alpha > 0.0 ? 1.0 / (x0 - beta) : 0.0;
+      tau[j] = t;
+      bcast[0] = scale;
+      Sg[j] = (T)(beta >= 0.0 ? 1.0 : -1.0);
+    }
+    __syncthreads();
+    const double scale = bcast[0], tj = tau[j];
+    for (int i = j + 1 + tid; i < n; i += 256) x[i] = (T)((double)x[i] * scale);
+    if (tid == 0) x[j] = (T)1.0;
+    __syncthreads();
+    // apply H_j to the remaining columns: y -= tau v (v^T y), one column per wave
+    for (int c = j + 1 + wid; c < r; c += 4) {
+      T* y = V + (int64_t)c * n;
+      double d = 0.0;
+      for (int i = j + lane; i < n; i += 64) d += (double)x[i] * (double)y[i];
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+      d *= tj;
+      for (int i = j + lane; i < n; i += 64) y[i] = (T)((double)y[i] - d * (double)x[i]);
+    }
+    __syncthreads();
+  }
+  // unit diagonal, zeros above it
+  for (int64_t e = tid; e < (int64_t)r * r; e += 256) {
+    const int i = (int)(e % r), c = (int)(e / r);
+    if (i < c) V[i + (int64_t)c * n] = (T)0;
+  }
+  __syncthreads();
+  // T column by column: w = V[:, :j]^T v_j, T[:j, j] = -tau_j T[:j, :j] w
+  for (int j = 0; j < r; ++j) {
+    const T* vj = V + (int64_t)j * n;
+    for (int c = wid; c < j; c += 4) {
+      const T* vc = V + (int64_t)c * n;
+      double d = 0.0;
+      for (int i = j + lane; i < n; i += 64) d += (double)vc[i] * (double)vj[i];  // v_j is zero above row j
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
+      if (lane == 0) w[c] = d;
+    }
+    __syncthreads();
+    for (int i = tid; i < r; i += 256) {
+      double t = 0.0;
+      if (i < j) {
+        for (int c = i; c < j; ++c) t += (double)Tm[i + (int64_t)c * r] * w[c];
+        t *= -tau[j];
+      } else if (i == j) {
+        t = tau[j];
+      }
+      Tm[i + (int64_t)j * r] = (T)t;
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fused basis QR for r <= RM <= 96 (one workgroup per node, everything in LDS):
 //   blocked LU without pivoting of the top r x r block of B - [Sg; 0]
 //   (16-column panels factored by one wave, U_12 by a unit-lower solve per
@@ -2065,6 +2164,11 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
         }
         Prof pf(cx, "gemm_V2", l);
         gemm_run<T>(st[0], false, false, 1.0, 0.0, s);    // V_2 = B_2 U_1^{-1}
+      } else if (lp.rmax > 128) {
+        Prof pf(cx, "basis_qr", l);
+        hipLaunchKernelGGL((k_house_basis<T>), dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, b.B, b.V,
+                           b.Tm, b.Sg);
+        HSS_HIP(hipGetLastError());
       } else {
         Prof pf(cx, "basis_qr", l);
         launch_lu_top<T>(m, lp, b.B, b.V, b.Tm, b.Sg, s);   // V_1, U_1 (in the T slot), Sg

@@ -457,7 +457,7 @@ __device__ __forceinline__ void lower_t_solve_cols(const T* __restrict__ F, int 
   }
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int RMX>
 __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_fwd(const NodeDesc* __restrict__ nodes, int first,
                                                   const T* __restrict__ Fb, const T* __restrict__ Vb,
                                                   const T* __restrict__ Yb, const T* __restrict__ Sgb,
@@ -470,9 +470,9 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_fwd(const NodeDesc* __r
   const NodeDesc nd = nodes[p];
   const int n = nd.n, r = nd.r, m = nd.m;
   __shared__ T sb[512 * RC];
-  __shared__ T st[128 * RC];
-  __shared__ T su[128 * RC];
-  __shared__ T tm[128 * RC];
+  __shared__ T st[RMX * RC];
+  __shared__ T su[RMX * RC];
+  __shared__ T tm[RMX * RC];
   __shared__ T red[NT * RC];  // row_gemv_wide needs (NT / 256) * 512, col_dots_split NT * RC
   T* vp = vec + nd.offVec * nrhs;
   const T* F = Fb + nd.offF;
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_fwd(const NodeDesc* __r
     for (int c = 0; c < nc; ++c) pp[nd.child_row + j + (int64_t)(c0 + c) * par.n] = Sg[j] * sb[j + c * n];
 }
 
-template <typename T, int NT>
+template <typename T, int NT, int RMX>
 __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_bwd(const NodeDesc* __restrict__ nodes, int first,
                                                   const T* __restrict__ Fb, const T* __restrict__ Vb,
                                                   const T* __restrict__ Yb, const T* __restrict__ Sgb,
@@ -553,8 +553,8 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_bwd(const NodeDesc* __r
   const NodeDesc nd = nodes[p];
   const int n = nd.n, r = nd.r, m = nd.m;
   __shared__ T sx[512 * RC];
-  __shared__ T st[128 * RC];
-  __shared__ T su[128 * RC];
+  __shared__ T st[RMX * RC];
+  __shared__ T su[RMX * RC];
   __shared__ T scr[SNB * RC];
   __shared__ T tm[512 * RC];
   __shared__ T red[NT * RC];  // row_gemv_wide needs (NT / 256) * 512, col_dots_split NT * RC
@@ -658,14 +658,17 @@ template <typename T>
 static void launch_fwd(hss_matrix_t m, int si, const T* F, const T* V, const T* Yw, const T* Sg, T* vec, const T* Li,
                        int inv, const double* b, int64_t nrhs, int64_t c0, int nc, int64_t ld, hipStream_t s) {
   const LevelPlan& lp = m->stages[si];
-  if (lp.count <= kSolveWideNodes)
-    hipLaunchKernelGGL((k_solve_fwd<T, 1024>), dim3(lp.count), dim3(1024), 0, s, m->dnodes, lp.first, F, V, Yw, Sg,
-                       vec, nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, lp.leaf, Li,
-                       (const int64_t*)m->dOffLi, inv);
-  else
-    hipLaunchKernelGGL((k_solve_fwd<T, 256>), dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, F, V, Yw, Sg,
-                       vec, nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, lp.leaf, Li,
-                       (const int64_t*)m->dOffLi, inv);
+#define HSS_FWD(NT, RMX)                                                                                          \
+  hipLaunchKernelGGL((k_solve_fwd<T, NT, RMX>), dim3(lp.count), dim3(NT), 0, s, m->dnodes, lp.first, F, V, Yw, Sg, \
+                     vec, nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, lp.leaf, Li, (const int64_t*)m->dOffLi, \
+                     inv)
+  HSS_CHECK(lp.rmax <= 256 && lp.nmax <= 512, HSS_ERR_UNSUPPORTED, "solve: rank above 256 or block above 512");
+  if (lp.count <= kSolveWideNodes) {
+    if (lp.rmax <= 128) HSS_FWD(1024, 128); else HSS_FWD(1024, 256);
+  } else {
+    if (lp.rmax <= 128) HSS_FWD(256, 128); else HSS_FWD(256, 256);
+  }
+#undef HSS_FWD
   HSS_HIP(hipGetLastError());
 }
 
@@ -673,14 +676,16 @@ template <typename T>
 static void launch_bwd(hss_matrix_t m, int si, const T* F, const T* V, const T* Yw, const T* Sg, T* vec, const T* Li,
                        int inv, double* x, int64_t nrhs, int64_t c0, int nc, int64_t ld, hipStream_t s) {
   const LevelPlan& lp = m->stages[si];
-  if (lp.count <= kSolveWideNodes)
-    hipLaunchKernelGGL((k_solve_bwd<T, 1024>), dim3(lp.count), dim3(1024), 0, s, m->dnodes, lp.first, F, V, Yw, Sg,
-                       vec, nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, lp.leaf, Li,
-                       (const int64_t*)m->dOffLi, inv);
-  else
-    hipLaunchKernelGGL((k_solve_bwd<T, 256>), dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, F, V, Yw, Sg,
-                       vec, nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, lp.leaf, Li,
-                       (const int64_t*)m->dOffLi, inv);
+#define HSS_BWD(NT, RMX)                                                                                          \
+  hipLaunchKernelGGL((k_solve_bwd<T, NT, RMX>), dim3(lp.count), dim3(NT), 0, s, m->dnodes, lp.first, F, V, Yw, Sg, \
+                     vec, nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, lp.leaf, Li, (const int64_t*)m->dOffLi, \
+                     inv)
+  if (lp.count <= kSolveWideNodes) {
+    if (lp.rmax <= 128) HSS_BWD(1024, 128); else HSS_BWD(1024, 256);
+  } else {
+    if (lp.rmax <= 128) HSS_BWD(256, 128); else HSS_BWD(256, 256);
+  }
+#undef HSS_BWD
   HSS_HIP(hipGetLastError());
 }
 

@@ -88,7 +88,10 @@ def test_exp2d_n2048_plain_vs_oracle_and_dense(ctx, torch_dev):
 
 
 @pytest.mark.parametrize("levels,leaf,rank", [(1, 32, 8), (3, 64, 16), (2, 256, 96), (2, 512, 128), (5, 32, 12),
-                                               (2, 128, 16), (1, 200, 40), (3, 250, 90)])
+                                               (2, 128, 16), (1, 200, 40), (3, 250, 90),
+                                               # ranks above 128 (generic Householder basis, rank-256 solves):
+                                               # Table 2's (200, 256) and (200, 512) shapes and the largest blocks
+                                               (3, 256, 200), (2, 512, 200), (2, 512, 256), (2, 300, 136)])
 def test_random_hss_shapes(ctx, torch_dev, levels, leaf, rank):
     d = synth.random_hss(levels, leaf, rank, seed=levels * 100 + rank)
     h = O.HSS(d["n"], d["levels"], d["ranges"], d["rank"], d["D"], d["U"], d["E"], d["S"])
