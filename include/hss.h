@@ -68,11 +68,20 @@ typedef struct {
   double eps;       /* Laplace/Yukawa regulariser (Table 3: 1e-9) */
 } hss_kernel;
 
-/* Construction modes. SCALED compresses each node's off-diagonal row block
- * after scaling by the inverse Cholesky factor of its diagonal block, which
- * keeps the HSS matrix SPD for any truncation; the output is in the paper's
- * format (orthonormal nested bases U/E and couplings S, Sec. 2 Eq. 6). */
-typedef enum { HSS_COMPRESS_SCALED = 1 } hss_compress_mode;
+/* Construction modes; both sample each node's off-diagonal row block with the
+ * caller's Gaussian test matrix and give the paper's format (orthonormal nested
+ * bases U/E and couplings S, Sec. 2 Eq. 6).
+ *  PLAIN: the paper's construction (Sec. 2, Eq. 2): each node's basis is the
+ *         first k columns of the pivoted QR of the samples of its off-diagonal
+ *         row block, projected onto the children's bases above the leaves, and
+ *         each sibling coupling is the orthogonal projection of the exact block.
+ *         The compressed matrix can be indefinite where the truncation error
+ *         exceeds the smallest eigenvalues (the factorization then reports
+ *         NOT_SPD).
+ *  SCALED: the samples of a node are first scaled by the inverse Cholesky
+ *         factor of its diagonal block, which keeps the HSS matrix SPD for any
+ *         truncation (at a larger truncation error on smooth kernels). */
+typedef enum { HSS_COMPRESS_PLAIN = 0, HSS_COMPRESS_SCALED = 1 } hss_compress_mode;
 
 typedef struct {
   int32_t leaf_size;   /* >= 2: maximum points per leaf */
@@ -199,9 +208,8 @@ hss_status hss_ctx_set_stream(hss_ctx_t ctx, void* hip_stream);
  *            s >= the largest rank to be found (adaptive).
  * Steps: recursive coordinate bisection (longest box side, ties -> lowest
  * axis, order by (coordinate, index), left child = ceil(size/2)); leaf blocks
- * by kernel evaluation; scaled randomized compression level by level with
- * column-pivoted QR truncation (Eq. 2). Synchronizes once per level when
- * ranks are adaptive. Errors: INVALID_ARGUMENT for bad sizes or options,
+ * by kernel evaluation; randomized compression (opts->mode) level by level
+ * with column-pivoted QR truncation (Eq. 2). Synchronizes once per level. Errors: INVALID_ARGUMENT for bad sizes or options,
  * NOT_SPD if a diagonal block is not positive definite. */
 hss_status hss_construct(hss_ctx_t ctx, const double* d_points, int64_t n, int32_t dim,
                          const hss_kernel* kernel, const hss_construct_opts* opts,

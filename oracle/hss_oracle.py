@@ -360,6 +360,76 @@ def construct_plain(X: np.ndarray, tree: Tree, kern: Kernel, rank: int = 0, tol:
     return HSS(n, L, tree.ranges, ranks, D, U, E, S, meta={"mode": "plain"})
 
 
+def construct_plain_sampled(X: np.ndarray, tree: Tree, kern: Kernel, omega: np.ndarray, rank: int = 0,
+                            tol: float = 0.0, max_rank: int = 0, A: np.ndarray | None = None) -> HSS:
+    """The paper's construction (Sec. 2, Eq. 2 and Eq. 6) with the off-diagonal
+    row blocks seen through random samples instead of formed (small N only).
+
+    The test matrix Omega (N x s, tree order) is given. The samples of the leaves'
+    off-diagonal row blocks are the block rows of (A - blkdiag(D)) Omega, i.e.
+    A[I_i, I_i^c] Omega[I_i^c]. At every level, from the leaves, node p's basis
+    (U at a leaf, the transfer matrix E above) is the first k columns of the
+    pivoted QR of its samples Z_p. The coupling of siblings is the orthogonal
+    projection Ubig_c1^T A[I_c1, I_c2] Ubig_c2. The samples move up by
+    projecting onto the children's bases and removing the sibling block through
+    its compressed form:
+      Phi_p = [B_c1^T Phi_c1; B_c2^T Phi_c2]        (Phi = Omega at the leaves)
+      Z_p   = [B_c1^T Z_c1 - S Phi_c2; B_c2^T Z_c2 - S^T Phi_c1]
+    (B the child's basis), which samples the children-projected row block
+    blkdiag(Ubig_c1, Ubig_c2)^T A[I_p, I_p^c] of the exact construction exactly
+    when the sibling block equals its compressed form.
+    """
+    if A is None:
+        A = dense_matrix(kern, X[tree.perm])
+    n = A.shape[0]
+    L = tree.levels
+    if L == 0:
+        return HSS(n, 0, tree.ranges, [[]], [A.copy()], [], [], [], meta={"mode": "plain_sampled"})
+    s = omega.shape[1]
+    ranks = [[] for _ in range(L + 1)]
+    D = [A[lo:hi, lo:hi].copy() for (lo, hi) in tree.ranges[L]]
+    Aoff = A.copy()
+    for (lo, hi) in tree.ranges[L]:
+        Aoff[lo:hi, lo:hi] = 0.0
+    Zall = Aoff @ omega
+    Z = [Zall[lo:hi] for (lo, hi) in tree.ranges[L]]
+    Phi = [omega[lo:hi] for (lo, hi) in tree.ranges[L]]
+    U = []
+    E = [[] for _ in range(L)]
+    S = [[] for _ in range(L)]
+    Ubig_prev = None
+    for l in range(L, 0, -1):
+        nodes = 2 ** l
+        Bs = []
+        for p in range(nodes):
+            Q, R, _ = qrcp(Z[p], rank if rank > 0 else min(Z[p].shape))
+            k = choose_rank(R, rank, tol, max_rank, Z[p].shape[0])
+            B = Q[:, :k].copy()
+            Bs.append(B)
+            ranks[l].append(k)
+            if l == L:
+                U.append(B)
+            else:
+                E[l].append(B)
+        if l == L:
+            Ubig = Bs
+        else:
+            Ubig = [sla.block_diag(Ubig_prev[2 * p], Ubig_prev[2 * p + 1]) @ Bs[p] for p in range(nodes)]
+        newZ, newPhi = [], []
+        for g in range(nodes // 2):
+            p1, p2 = 2 * g, 2 * g + 1
+            a1, b1 = tree.ranges[l][p1]
+            a2, b2 = tree.ranges[l][p2]
+            Sg = Ubig[p1].T @ A[a1:b1, a2:b2] @ Ubig[p2]
+            S[l - 1].append(Sg)
+            ph1 = Bs[p1].T @ Phi[p1]
+            ph2 = Bs[p2].T @ Phi[p2]
+            newPhi.append(np.vstack([ph1, ph2]))
+            newZ.append(np.vstack([Bs[p1].T @ Z[p1] - Sg @ ph2, Bs[p2].T @ Z[p2] - Sg.T @ ph1]))
+        Z, Phi, Ubig_prev = newZ, newPhi, Ubig
+    return HSS(n, L, tree.ranges, ranks, D, U, E, S, meta={"mode": "plain_sampled", "s": s})
+
+
 # ----------------------------------------------------------------------------
 # Construction, scaled (Cholesky-scaled compression; keeps the HSS matrix SPD)
 # ----------------------------------------------------------------------------

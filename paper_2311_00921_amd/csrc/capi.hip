@@ -443,7 +443,8 @@ hss_status hss_construct(hss_ctx_t ctx, const double* d_points, int64_t n, int32
     HSS_CHECK(opts->rank >= 0 && opts->rank <= 256, HSS_ERR_INVALID_ARGUMENT, "rank must be in [0, 256]");
     HSS_CHECK(opts->rank > 0 || opts->tol > 0.0, HSS_ERR_INVALID_ARGUMENT, "adaptive rank needs tol > 0");
     HSS_CHECK(opts->max_rank >= 0, HSS_ERR_INVALID_ARGUMENT, "max_rank must be >= 0");
-    HSS_CHECK(opts->mode == HSS_COMPRESS_SCALED, HSS_ERR_INVALID_ARGUMENT, "unknown compression mode");
+    HSS_CHECK(opts->mode == HSS_COMPRESS_SCALED || opts->mode == HSS_COMPRESS_PLAIN, HSS_ERR_INVALID_ARGUMENT,
+              "unknown compression mode");
     HSS_CHECK(kernel->kind >= 0 && kernel->kind <= 4, HSS_ERR_INVALID_ARGUMENT, "unknown kernel");
     HSS_CHECK(kernel->kind >= HSS_K_LAPLACE2D || kernel->length > 0.0, HSS_ERR_INVALID_ARGUMENT,
               "kernel length must be > 0");

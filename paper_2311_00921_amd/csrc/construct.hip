@@ -1,6 +1,10 @@
 // HSS construction on the GPU (Sec. 2: shared bases from a pivoted QR, Eq. 2;
-// nested bases and skeleton couplings, Eq. 6), in the Cholesky-scaled
-// randomized form that keeps the represented matrix SPD:
+// nested bases and skeleton couplings, Eq. 6), from random samples of the
+// off-diagonal row blocks, in two modes. PLAIN is the paper's construction: each
+// node's basis is the pivoted QR of the samples of its off-diagonal row block,
+// and the couplings are orthogonal projections. SCALED (the default of the
+// workloads) first scales each node's samples by the inverse Cholesky factor of
+// its diagonal block, which keeps the represented matrix SPD:
 //
 //   tree      recursive coordinate bisection (longest box side, ties -> lowest
 //             axis, order by (coordinate, index), left child = ceil(size/2))
@@ -14,6 +18,8 @@
 //               M_g = [[Sigma_p1, S_g], [S_g^T, Sigma_p2]],
 //               Phi_g = [B_p1^T Phi_p1; B_p2^T Phi_p2],
 //               Z_g = [W_p1^T Z_p1 - S_g Phi'_p2; W_p2^T Z_p2 - S_g^T Phi'_p1]
+// PLAIN is the same sweep with Lc = I: Psi = Omega, Y = Z_p, basis = W_p = V,
+// and no merged diagonal blocks.
 #include <algorithm>
 #include <cmath>
 #include <numeric>
@@ -112,8 +118,13 @@ __device__ __forceinline__ v4d mfma64(double a, double b, v4d c) {
 
 constexpr int KBM = 64, KBN = 128, KBK = 16;
 
+// With blk (the leaf of each tree position), pairs of points in one leaf count
+// as zero: the product with A - blkdiag(D) without forming A x and subtracting
+// D x (a kernel whose diagonal dwarfs its off-diagonal entries would lose
+// digits to the cancellation).
 __global__ __launch_bounds__(256) void k_kgemm(const KGemmDesc* __restrict__ descs, KParams kp,
-                                               const double* __restrict__ X, int64_t N, int dim, int accumulate) {
+                                               const double* __restrict__ X, int64_t N, int dim, int accumulate,
+                                               const int32_t* __restrict__ blk) {
   const KGemmDesc d = descs[blockIdx.y];
   const int tilesM = (d.nr + KBM - 1) / KBM;
   const int tilesN = (d.s + KBN - 1) / KBN;
@@ -146,7 +157,7 @@ __global__ __launch_bounds__(256) void k_kgemm(const KGemmDesc* __restrict__ des
       const int r = e % KBM, kk = e / KBM;
       const int64_t gi = d.r0 + row0 + r, gj = d.c0 + k0 + kk;
       double v = 0.0;
-      if (row0 + r < d.nr && k0 + kk < d.nc) {
+      if (row0 + r < d.nr && k0 + kk < d.nc && !(blk && blk[gi] == blk[gj])) {
         double acc2 = 0.0;
         for (int a = 0; a < dim; ++a) {
           const double df = xr[a][r] - X[a * N + gj];
@@ -430,6 +441,22 @@ __global__ void k_points_soa(const double* __restrict__ pts, const int64_t* __re
     for (int a = 0; a < dim; ++a) X[a * n + t] = pts[perm[t] * dim + a];
 }
 
+// dst[i + j ldd] = src[i + j lds] for i < rows, j < cols, one descriptor per grid.y
+struct Copy2D {
+  const double* src;
+  double* dst;
+  int32_t rows, cols, lds, ldd;
+};
+
+__global__ void k_copy2d(const Copy2D* __restrict__ descs) {
+  const Copy2D d = descs[blockIdx.y];
+  const int64_t tot = (int64_t)d.rows * d.cols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < tot; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e % d.rows), j = (int)(e / d.rows);
+    d.dst[i + (int64_t)j * d.ldd] = d.src[i + (int64_t)j * d.lds];
+  }
+}
+
 __global__ void k_copy_blocks(const double* __restrict__ src, const int64_t* __restrict__ soff,
                               double* __restrict__ dst, const int64_t* __restrict__ doff,
                               const int64_t* __restrict__ len) {
@@ -508,6 +535,18 @@ struct DevArr {
   }
 };
 
+static void run_copy2d(const std::vector<Copy2D>& h, hipStream_t st) {
+  if (h.empty()) return;
+  DevArr<Copy2D> d;
+  d.upload(h, st);
+  for (size_t c0 = 0; c0 < h.size(); c0 += 65535) {
+    const int cnt = (int)std::min<size_t>(65535, h.size() - c0);
+    hipLaunchKernelGGL(k_copy2d, dim3(16, cnt), dim3(256), 0, st, (const Copy2D*)(d.p + c0));
+    HSS_HIP(hipGetLastError());
+  }
+  HSS_HIP(hipStreamSynchronize(st));
+}
+
 static void run_gemm(std::vector<GemmDesc>&& v, bool ta, bool tb, double alpha, double beta, hipStream_t s) {
   GemmBatch b;
   b.host = std::move(v);
@@ -518,7 +557,7 @@ static void run_gemm(std::vector<GemmDesc>&& v, bool ta, bool tb, double alpha, 
 }
 
 static void run_kgemm(const std::vector<KGemmDesc>& v, const KParams& kp, const double* X, int64_t N, int dim,
-                      int accumulate, hipStream_t s) {
+                      int accumulate, hipStream_t s, const int32_t* blk = nullptr) {
   if (v.empty()) return;
   int tiles = 0;
   for (auto& d : v) tiles = std::max(tiles, ((d.nr + KBM - 1) / KBM) * ((d.s + KBN - 1) / KBN));
@@ -526,7 +565,7 @@ static void run_kgemm(const std::vector<KGemmDesc>& v, const KParams& kp, const 
   dv.upload(v, s);
   for (size_t b0 = 0; b0 < v.size(); b0 += 65535) {
     const int cnt = (int)std::min<size_t>(65535, v.size() - b0);
-    hipLaunchKernelGGL(k_kgemm, dim3(tiles, cnt), dim3(256), 0, s, dv.p + b0, kp, X, N, dim, accumulate);
+    hipLaunchKernelGGL(k_kgemm, dim3(tiles, cnt), dim3(256), 0, s, dv.p + b0, kp, X, N, dim, accumulate, blk);
     HSS_HIP(hipGetLastError());
   }
   HSS_HIP(hipStreamSynchronize(s));
@@ -595,6 +634,7 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
   hipStream_t st = m->ctx->stream;
   const int64_t N = m->n;
   const int L = m->L;
+  const bool plain = o.mode == HSS_COMPRESS_PLAIN;
   KParams kp{kern.kind, kern.length, kern.sigma2, kern.nugget, kern.alpha, kern.eps};
   // ---- tree (host bisection of the points) ----
   std::vector<double> P((size_t)N * dim);
@@ -734,8 +774,10 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
     Hb.ensure(oH);
     Qb.ensure(oH);
     Rb.ensure(oR);
-    // ---- Lc = chol(M_p) ----
-    if (l == L) {
+    // ---- Lc = chol(M_p) (SCALED only) ----
+    if (plain) {
+      // no scaling
+    } else if (l == L) {
       for (int i = 0; i < cnt; ++i) {
         const NodeDesc& nd = m->nodes[first + i];
         HSS_HIP(hipMemcpyAsync(Lb.p + cur[i].offL, m->dD + nd.offD, sizeof(double) * cur[i].n * cur[i].n,
@@ -744,7 +786,7 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
     } else {
       HSS_HIP(hipMemcpyAsync(Lb.p, Mb.p, sizeof(double) * oM, hipMemcpyDeviceToDevice, st));
     }
-    {
+    if (!plain) {
       std::vector<NodeDesc> tn(cnt);
       for (int i = 0; i < cnt; ++i) {
         tn[i] = NodeDesc{};
@@ -765,36 +807,45 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
                     ") is not positive definite");
     }
     dcur.upload(cur, st);
-    hipLaunchKernelGGL(k_trinv, dim3(cnt), dim3(256), 0, st, (const CNode*)dcur.p, Lb.p, Ib.p);
-    HSS_HIP(hipGetLastError());
+    if (!plain) {
+      hipLaunchKernelGGL(k_trinv, dim3(cnt), dim3(256), 0, st, (const CNode*)dcur.p, Lb.p, Ib.p);
+      HSS_HIP(hipGetLastError());
+    }
     if (l == L) {
-      // Psi = Lc^{-T} Omega (leaf rows), Z = A Psi - D Psi
-      std::vector<GemmDesc> g;
+      // Psi = Lc^{-T} Omega (leaf rows; Omega itself for PLAIN), Z = A Psi - D Psi
+      if (plain) {
+        HSS_HIP(hipMemcpyAsync(PsiN.p, Om.p, sizeof(double) * N * s, hipMemcpyDeviceToDevice, st));
+      } else {
+        std::vector<GemmDesc> g;
+        for (int i = 0; i < cnt; ++i)
+          g.push_back({Ib.p + cur[i].offI, Om.p + cur[i].lo, nullptr, PsiN.p + cur[i].lo, cur[i].n, (int)s, cur[i].n,
+                       cur[i].n, (int)N, 0, (int)N, 0, 0});
+        run_gemm(std::move(g), true, false, 1.0, 0.0, st);
+      }
+      // Z = (A - blkdiag D) Psi: pairs within a leaf skipped in the product
+      std::vector<int32_t> leafid(N);
       for (int i = 0; i < cnt; ++i)
-        g.push_back({Ib.p + cur[i].offI, Om.p + cur[i].lo, nullptr, PsiN.p + cur[i].lo, cur[i].n, (int)s, cur[i].n,
-                     cur[i].n, (int)N, 0, (int)N, 0, 0});
-      run_gemm(std::move(g), true, false, 1.0, 0.0, st);
+        for (int64_t t = leaf_lo[i]; t < leaf_lo[i + 1]; ++t) leafid[t] = i;
+      DevArr<int32_t> dleaf;
+      dleaf.upload(leafid, st);
       std::vector<KGemmDesc> kg;
       const int64_t chunk = 1 << 16;
       for (int64_t r0 = 0; r0 < N; r0 += chunk)
         kg.push_back({r0, 0, (int32_t)std::min<int64_t>(chunk, N - r0), (int32_t)N, (int32_t)s, (int32_t)N,
                       (int32_t)N, PsiN.p, Zfull.p + r0});
-      run_kgemm(kg, kp, Xs.p, N, dim, 0, st);
-      std::vector<GemmDesc> g2;
-      for (int i = 0; i < cnt; ++i) {
-        const NodeDesc& nd = m->nodes[first + i];
-        g2.push_back({m->dD + nd.offD, PsiN.p + cur[i].lo, Zfull.p + cur[i].lo, Zfull.p + cur[i].lo, cur[i].n, (int)s,
-                      cur[i].n, cur[i].n, (int)N, (int)N, (int)N, 0, 0});
-      }
-      run_gemm(std::move(g2), false, false, -1.0, 1.0, st);
+      run_kgemm(kg, kp, Xs.p, N, dim, 0, st, dleaf.p);
       for (int i = 0; i < cnt; ++i) {
         zp[i] = Zfull.p + cur[i].lo;
         php[i] = PsiN.p + cur[i].lo;
         ldz[i] = (int)N;
       }
     }
-    // ---- Y = Lc^{-1} Z, V = QRCP(Y)[:, :k] ----
-    {
+    // ---- Y = Lc^{-1} Z (Y = Z for PLAIN), V = QRCP(Y)[:, :k] ----
+    if (plain) {
+      std::vector<Copy2D> cp;
+      for (int i = 0; i < cnt; ++i) cp.push_back({zp[i], Yb.p + cur[i].offY, cur[i].n, (int)s, ldz[i], cur[i].n});
+      run_copy2d(cp, st);
+    } else {
       std::vector<GemmDesc> g;
       for (int i = 0; i < cnt; ++i)
         g.push_back({Ib.p + cur[i].offI, zp[i], nullptr, Yb.p + cur[i].offY, cur[i].n, (int)s, cur[i].n, cur[i].n,
@@ -840,15 +891,24 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
     Wb.ensure(oK);
     Rk.ensure(oKK);
     Sig.ensure(oKK);
-    HSS_HIP(hipMemsetAsync(Rk.p, 0, sizeof(double) * std::max<int64_t>(oKK, 1), st));
-    {
+    if (plain) {
+      // the basis is V itself (orthonormal), and so is W
+      std::vector<Copy2D> cp;
+      for (int i = 0; i < cnt; ++i) {
+        cp.push_back({Qb.p + cur[i].offQ, Bb.p + offK[i], cur[i].n, cur[i].k, cur[i].n, cur[i].n});
+        cp.push_back({Qb.p + cur[i].offQ, Wb.p + offK[i], cur[i].n, cur[i].k, cur[i].n, cur[i].n});
+      }
+      run_copy2d(cp, st);
+    }
+    if (!plain) HSS_HIP(hipMemsetAsync(Rk.p, 0, sizeof(double) * std::max<int64_t>(oKK, 1), st));
+    if (!plain) {
       std::vector<GemmDesc> g;
       for (int i = 0; i < cnt; ++i)
         g.push_back({Lb.p + cur[i].offL, Qb.p + cur[i].offQ, nullptr, Kb.p + offK[i], cur[i].n, cur[i].k, cur[i].n,
                      cur[i].n, cur[i].n, 0, cur[i].n, 0, 0});
       run_gemm(std::move(g), false, false, 1.0, 0.0, st);
     }
-    {
+    if (!plain) {
       std::vector<int> ks;
       for (auto& c : cur) ks.push_back(c.k);
       std::sort(ks.begin(), ks.end());
@@ -872,7 +932,7 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
         HSS_HIP(hipStreamSynchronize(st));
       }
     }
-    {
+    if (!plain) {
       std::vector<GemmDesc> g1, g2, g3;
       for (int i = 0; i < cnt; ++i) {
         const int n = cur[i].n, k = cur[i].k;
@@ -993,7 +1053,7 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
       run_gemm(std::move(g1), false, false, -1.0, 1.0, st);
       run_gemm(std::move(g2), true, false, -1.0, 1.0, st);
     }
-    {
+    if (!plain) {  // the parents' diagonal blocks [[Sigma_p1, S], [S^T, Sigma_p2]] (SCALED only)
       std::vector<int64_t> oSig(cnt), oSS(np);
       for (int i = 0; i < cnt; ++i) oSig[i] = offKK[i];
       for (int g = 0; g < np; ++g) oSS[g] = offS[g];

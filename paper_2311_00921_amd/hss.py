@@ -27,7 +27,9 @@ HSS_ERR_UNSUPPORTED = 7
 KERNELS = {"exponential": 0, "matern32": 1, "gaussian": 2, "laplace2d": 3, "yukawa": 4}
 HSS_P_FP64 = 0
 HSS_P_FP32 = 1
+HSS_COMPRESS_PLAIN = 0
 HSS_COMPRESS_SCALED = 1
+MODES = {"plain": HSS_COMPRESS_PLAIN, "scaled": HSS_COMPRESS_SCALED}
 
 
 class HSSError(RuntimeError):
@@ -362,8 +364,9 @@ def unpack_desc(p: dict) -> dict:
 def hss_construct(ctx, points, kernel: str, leaf: int, rank: int = 0, tol: float = 0.0, max_rank: int = 0,
                   omega=None, length: float = 1.0, nugget: float = 0.0, sigma2: float = 1.0,
                   alpha: float = 1.0, eps: float = 1e-9, levels: int = 0, rank_model=None,
-                  sample_start: int = 0, probes: int = 0, judge_factor: float = 0.0):
-    """Builds the HSS approximation of the kernel matrix on device points (N x dim, row-major)."""
+                  sample_start: int = 0, probes: int = 0, judge_factor: float = 0.0, mode: str = "scaled"):
+    """Builds the HSS approximation of the kernel matrix on device points (N x dim,
+    row-major); mode "scaled" (SPD for any truncation) or "plain" (the paper's)."""
     import torch
 
     lib = load()
@@ -377,7 +380,7 @@ def hss_construct(ctx, points, kernel: str, leaf: int, rank: int = 0, tol: float
     if ld != n:
         om = om.t().contiguous().t()
     k = hss_kernel(KERNELS[kernel], length, sigma2, nugget, alpha, eps)
-    o = hss_construct_opts(leaf, levels, rank, max_rank, tol, HSS_COMPRESS_SCALED, rank_model, sample_start,
+    o = hss_construct_opts(leaf, levels, rank, max_rank, tol, MODES[mode], rank_model, sample_start,
                            probes, judge_factor)
     out = C.c_void_p()
     _check(lib.hss_construct(ctx, _ptr(pts), n, dim, C.byref(k), C.byref(o), _ptr(om), s, C.byref(out)),

@@ -1,5 +1,5 @@
-"""GPU construction vs the oracle's scaled randomized construction on the same
-points and the same Gaussian test matrix.
+"""GPU construction vs the oracle's randomized constructions (scaled, and the
+paper's plain one) on the same points and the same Gaussian test matrix.
 
 Integer outputs (tree permutation, ranks) must match exactly; floating-point
 outputs (D, bases, couplings, the densified matrix) to a tolerance set by the
@@ -12,7 +12,7 @@ import pytest
 import synth
 from oracle import hss_oracle as O
 
-from gpu_util import rel
+from gpu_util import maxrel, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -30,18 +30,20 @@ def env():
     hss.hss_ctx_destroy(ctx)
 
 
-def build_both(env, n, dim, kernel, length, nugget, leaf, rank, s, tol=0.0, seed=1):
+def build_both(env, n, dim, kernel, length, nugget, leaf, rank, s, tol=0.0, seed=1, mode="scaled", X=None):
     torch, hss, ctx = env
-    print(f"construct n={n} dim={dim} kernel={kernel} leaf={leaf} rank={rank} tol={tol} s={s}", flush=True)
-    X = synth.points_uniform(n, dim, 1000 + seed)
+    print(f"construct n={n} dim={dim} kernel={kernel} leaf={leaf} rank={rank} tol={tol} s={s} mode={mode}",
+          flush=True)
+    X = synth.points_uniform(n, dim, 1000 + seed) if X is None else X
     Om = synth.test_matrix(n, s, 3000 + seed)
     kern = O.Kernel(kernel, length, nugget)
     tree = O.build_tree(X, leaf)
-    h_or = O.construct_scaled(X, tree, kern, Om[tree.perm], rank=rank, tol=tol, max_rank=128 if rank == 0 else 0)
+    build = O.construct_scaled if mode == "scaled" else O.construct_plain_sampled
+    h_or = build(X, tree, kern, Om[tree.perm], rank=rank, tol=tol, max_rank=128 if rank == 0 else 0)
     Xd = torch.from_numpy(X).cuda()
     Omd = torch.from_numpy(np.ascontiguousarray(Om.T)).cuda().t()
     m = hss.hss_construct(ctx, Xd, kernel, leaf, rank=rank, tol=tol, max_rank=128 if rank == 0 else 0,
-                          omega=Omd, length=length, nugget=nugget)
+                          omega=Omd, length=length, nugget=nugget, mode=mode)
     p = hss.hss_export(ctx, m)
     h_gpu = hss.unpack_desc(p)
     return torch, hss, ctx, m, tree, h_or, h_gpu, p
@@ -78,6 +80,55 @@ def test_construct_matches_oracle(env, n, dim, kernel, length, nugget, leaf, ran
         F = O.ulv_factor(hg)
         hss.hss_ulv_factor(ctx, m)
         b = synth.rhs_normal(n, 1, 5)[:, 0]
+        x = hss.hss_ulv_solve(ctx, m, torch.from_numpy(b).cuda()).cpu().numpy()
+        x_or = O.from_tree_order(tree, O.ulv_solve(hg, F, b[tree.perm]))
+        assert rel(x, x_or) < 1e-9
+        assert abs(hss.hss_logdet(ctx, m) - F.logdet) < 1e-10 * (abs(F.logdet) + 1)
+    finally:
+        hss.hss_matrix_destroy(m)
+
+
+@pytest.mark.parametrize("kernel,length,nugget,leaf,rank,s", [
+    ("exponential", 0.03, 0.0, 256, 100, 116),   # Table 3's Matern (rho = 1/2, mu = 0.03), Table 2's (100, 256)
+    ("laplace2d", 1.0, 0.0, 256, 64, 80),
+    ("yukawa", 1.0, 0.0, 128, 48, 64),
+    ("exponential", 0.03, 0.0, 512, 200, 216),   # Table 2's (200, 512) shape: rank above 128
+])
+def test_construct_plain_matches_oracle_on_the_grid(env, kernel, length, nugget, leaf, rank, s):
+    # The paper's own construction (pivoted QR of the sampled off-diagonal row
+    # blocks, Eq. 2; projected couplings, Eq. 6) on the paper's uniform 2-D grid
+    # (64 x 64 here), element by element against the oracle with the same samples;
+    # then the GPU factorization of the GPU-built matrix against the oracle's ULV.
+    n = 4096
+    X = synth.points_grid2d(n)
+    torch, hss, ctx, m, tree, h_or, h_gpu, p = build_both(env, n, 2, kernel, length, nugget, leaf, rank, s,
+                                                          seed=40 + leaf, mode="plain", X=X)
+    try:
+        assert np.array_equal(p["perm"], tree.perm)
+        L = tree.levels
+        for l in range(1, L + 1):
+            assert h_gpu["rank"][l] == h_or.rank[l]
+        # The trailing columns of a pivoted QR (pivots near the truncation) turn
+        # with the rounding of the samples (kernel values and sums in another
+        # order): what is unique is the compressed matrix and the leading,
+        # well-separated columns. Measured on the oracle alone, a 1e-15 relative
+        # perturbation of A moves the trailing columns by ~1e-9 and the densified
+        # matrix by ~4e-15.
+        half = rank // 2
+        for a, b in zip(h_gpu["U"], h_or.U):
+            assert maxrel(a[:, :half], b[:, :half]) < 1e-8
+        for l in range(1, L):
+            for a, b in zip(h_gpu["E"][l], h_or.E[l]):
+                assert maxrel(a[:, :half], b[:, :half]) < 1e-8
+        hg = O.HSS(h_gpu["n"], L, h_gpu["ranges"], h_gpu["rank"], h_gpu["D"], h_gpu["U"], h_gpu["E"], h_gpu["S"])
+        Ag = O.densify(hg)
+        Ao = O.densify(h_or)
+        assert rel(Ag, Ao) < 1e-8 and maxrel(Ag, Ao) < 1e-8
+        for Q in list(hg.U) + [e for l in range(1, L) for e in hg.E[l]]:
+            assert np.abs(Q.T @ Q - np.eye(Q.shape[1])).max() < 1e-13
+        F = O.ulv_factor(hg)
+        hss.hss_ulv_factor(ctx, m)
+        b = synth.rhs_normal(n, 1, 6)[:, 0]
         x = hss.hss_ulv_solve(ctx, m, torch.from_numpy(b).cuda()).cpu().numpy()
         x_or = O.from_tree_order(tree, O.ulv_solve(hg, F, b[tree.perm]))
         assert rel(x, x_or) < 1e-9

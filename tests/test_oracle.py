@@ -392,6 +392,59 @@ def test_plain_leaf_truncation_respects_eckart_young(cfg1):
         assert err <= 50 * s[k]
 
 
+def _exact_hss_dense(levels, leaf, rank, seed):
+    d = synth.random_hss(levels, leaf, rank, seed=seed)
+    h0 = O.HSS(d["n"], d["levels"], d["ranges"], d["rank"], d["D"], d["U"], d["E"], d["S"])
+    return h0, O.densify(h0), O.Tree(np.arange(h0.n), levels, h0.ranges)
+
+
+@pytest.mark.parametrize("levels,leaf,rank", [(3, 32, 6), (2, 48, 10), (4, 16, 5)])
+def test_plain_sampled_recovers_an_exact_hss_matrix(levels, leaf, rank):
+    # A matrix that is exactly HSS with rank r: every off-diagonal row block has
+    # rank <= r, so r + 8 random samples see its whole range, the pivoted QR keeps
+    # it, and the sibling blocks equal their compressed forms; the construction
+    # must reproduce the matrix to rounding. A dropped sibling subtraction, S in
+    # place of S^T, or the children's bases left out of the projection breaks it.
+    h0, A, tree = _exact_hss_dense(levels, leaf, rank, seed=9 + levels)
+    h = O.construct_plain_sampled(None, tree, None, synth.test_matrix(h0.n, rank + 8, 3 + levels), rank=rank, A=A)
+    assert np.abs(O.densify(h) - A).max() <= 1e-13 * np.abs(A).max()
+    assert h.rank[levels] == [rank] * 2 ** levels
+
+
+def test_plain_sampled_full_rank_is_exact_and_bases_orthonormal():
+    # with as many samples as rows and no truncation every basis is square:
+    # the HSS form is the matrix itself
+    _, A, tree = _exact_hss_dense(3, 24, 4, seed=21)
+    rng = np.random.default_rng(2)
+    R = rng.standard_normal(A.shape)
+    B = A + 0.5 * np.eye(A.shape[0]) + 1e-2 * (R + R.T)  # full-rank off-diagonal blocks
+    h = O.construct_plain_sampled(None, tree, None, synth.test_matrix(B.shape[0], B.shape[0], 5), rank=B.shape[0],
+                                  A=B)
+    assert np.abs(O.densify(h) - B).max() <= 1e-13 * np.abs(B).max()
+    for Q in list(h.U) + [e for l in range(1, h.levels) for e in h.E[l]]:
+        assert np.abs(Q.T @ Q - np.eye(Q.shape[1])).max() <= 1e-13
+
+
+def test_plain_sampled_truncation_near_the_optimum(cfg1):
+    # leaf bases from samples: the truncation error of each leaf's off-diagonal
+    # row block is at least sigma_{k+1} (Eckart-Young) and, with 8 samples of
+    # oversampling on this fast-decaying kernel, within a small factor of it; the
+    # whole matrix is about as accurate as the exact-block construction.
+    w, tree, kern, A, h_exact = cfg1["w"], cfg1["tree"], cfg1["kern"], cfg1["A"], cfg1["h"]
+    h = O.construct_plain_sampled(cfg1["X"], tree, kern, synth.test_matrix(w.n, w.rank + 8, 3001)[tree.perm],
+                                  rank=w.rank, A=A)
+    L = tree.levels
+    for i, (lo, hi) in enumerate(tree.ranges[L]):
+        Boff = np.concatenate([A[lo:hi, :lo], A[lo:hi, hi:]], axis=1)
+        sv = np.linalg.svd(Boff, compute_uv=False)
+        U = h.U[i]
+        err = np.linalg.norm(Boff - U @ (U.T @ Boff), 2)
+        assert sv[w.rank] * (1 - 1e-10) <= err <= 20 * sv[w.rank]
+    e_s = np.linalg.norm(O.densify(h) - A) / np.linalg.norm(A)
+    e_x = np.linalg.norm(O.densify(h_exact) - A) / np.linalg.norm(A)
+    assert e_s <= 3 * e_x
+
+
 def test_scaled_construction_spd_where_plain_is_not():
     # Matern-3/2, l = 0.2, nugget 1e-6 in the unit cube: the plain projection
     # loses definiteness at these ranks, the scaled compression keeps it.
