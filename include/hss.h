@@ -192,9 +192,27 @@ typedef struct {
 
 /* ---- context ------------------------------------------------------------ */
 
+/* Device memory for the library's own buffers (the representation, factors,
+ * workspaces): alloc returns at least `bytes` of device memory on the
+ * context's device (NULL on failure), free takes back a block alloc returned.
+ * A block is freed through the allocator it came from, after the device has
+ * finished all work (the library synchronizes the device first). Both NULL:
+ * hipMalloc and hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, void* user);
+  void* user;
+} hss_allocator;
+
 /* Creates a context on HIP device `device` that enqueues on `hip_stream`
- * (a hipStream_t; NULL = the default stream). */
-hss_status hss_ctx_create(int32_t device, void* hip_stream, hss_ctx_t* out);
+ * (a hipStream_t; NULL = the default stream) and allocates the library's
+ * device memory through `allocator` (NULL, or both functions NULL: hipMalloc;
+ * copied, so the struct may be freed on return). Every later call with this
+ * context -- and hss_matrix_destroy of its matrices -- uses that allocator.
+ * Also resolves the static scratch array of hss_ulv_solve_noalloc on the
+ * device. Errors: INVALID_ARGUMENT for NULL out, a bad device index or an
+ * allocator with only one of its functions. */
+hss_status hss_ctx_create(int32_t device, void* hip_stream, const hss_allocator* allocator, hss_ctx_t* out);
 hss_status hss_ctx_destroy(hss_ctx_t ctx);
 /* Replaces the stream work is enqueued on. */
 hss_status hss_ctx_set_stream(hss_ctx_t ctx, void* hip_stream);

@@ -336,6 +336,7 @@ extern "C" {
 
 hss_status hss_batch_create(hss_ctx_t ctx, int32_t count, const hss_matrix_t* mats, hss_matrix_t* out) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && mats && out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(count >= 1, HSS_ERR_INVALID_ARGUMENT, "count must be >= 1");
   std::vector<hss_matrix_t> v(mats, mats + count);
@@ -357,6 +358,7 @@ hss_status hss_construct_batched(hss_ctx_t ctx, int32_t count, const double* con
                                  int32_t dim, const hss_kernel* kernels, const hss_construct_opts* opts,
                                  const double* const* d_omega, const int32_t* s, hss_matrix_t* out) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && d_points && n && kernels && opts && d_omega && s && out, HSS_ERR_INVALID_ARGUMENT,
             "NULL argument");
   HSS_CHECK(count >= 1, HSS_ERR_INVALID_ARGUMENT, "count must be >= 1");
@@ -378,6 +380,7 @@ hss_status hss_construct_batched(hss_ctx_t ctx, int32_t count, const double* con
 hss_status hss_batch_query(hss_ctx_t ctx, hss_matrix_t m, int32_t count, int64_t* h_offsets, int32_t* h_failed,
                            double* h_logdet) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(count == m->nsys, HSS_ERR_INVALID_ARGUMENT, "count must equal the number of systems");
   if (h_offsets) {
@@ -403,6 +406,7 @@ hss_status hss_batch_query(hss_ctx_t ctx, hss_matrix_t m, int32_t count, int64_t
 
 hss_status hss_use_graphs(hss_ctx_t ctx, hss_matrix_t m, int32_t on) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_HIP(hipStreamSynchronize(ctx->stream));
   drop_graphs(m);
@@ -412,6 +416,7 @@ hss_status hss_use_graphs(hss_ctx_t ctx, hss_matrix_t m, int32_t on) {
 
 hss_status hss_autotune(hss_ctx_t ctx, hss_matrix_t m, int32_t precision, int32_t reps, float* h_report) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(precision == HSS_P_FP64 || precision == HSS_P_FP32, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
   HSS_CHECK(reps >= 1 && reps <= 100, HSS_ERR_INVALID_ARGUMENT, "reps must be in [1, 100]");
@@ -439,6 +444,7 @@ hss_status hss_gemm_variants(hss_matrix_t m, int32_t precision, int32_t* h_out, 
 hss_status hss_set_gemm_variants(hss_ctx_t ctx, hss_matrix_t m, int32_t precision, const int32_t* h_variants,
                                  int64_t count) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m && h_variants, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(precision == HSS_P_FP64 || precision == HSS_P_FP32, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
   prepare_factor(m, precision);

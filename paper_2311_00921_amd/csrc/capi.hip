@@ -2,7 +2,9 @@
 // device layout of the HSS representation, import and export.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <new>
+#include <unordered_map>
 
 #include "hss_internal.h"
 
@@ -12,9 +14,29 @@ static thread_local std::string g_last_error;
 
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+// Device memory: from the allocator of the context whose call is running on
+// this thread (CtxScope), else hipMalloc. Every block remembers the allocator
+// it came from, so that it goes back to it whenever it is freed.
+thread_local hss_ctx_t g_alloc_ctx = nullptr;
+
+namespace {
+std::mutex g_blocks_mu;
+std::unordered_map<void*, hss_allocator> g_blocks;  // blocks from a caller's allocator
+}  // namespace
+
 void* dev_alloc(size_t bytes) {
+  const size_t nb = bytes == 0 ? 8 : bytes;
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes == 0 ? 8 : bytes);
+  if (g_alloc_ctx && g_alloc_ctx->allocator.alloc) {
+    const hss_allocator a = g_alloc_ctx->allocator;
+    p = a.alloc(nb, a.user);
+    if (!p) throw Error{HSS_ERR_OUT_OF_MEMORY, "the caller's allocator returned no block of " + std::to_string(nb) +
+                                                   " bytes"};
+    std::lock_guard<std::mutex> lk(g_blocks_mu);
+    g_blocks[p] = a;
+    return p;
+  }
+  hipError_t e = hipMalloc(&p, nb);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     throw Error{HSS_ERR_OUT_OF_MEMORY, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
@@ -23,7 +45,26 @@ void* dev_alloc(size_t bytes) {
 }
 
 void dev_free(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  hss_allocator a{};
+  bool custom = false;
+  {
+    std::lock_guard<std::mutex> lk(g_blocks_mu);
+    auto it = g_blocks.find(p);
+    if (it != g_blocks.end()) {
+      a = it->second;
+      custom = true;
+      g_blocks.erase(it);
+    }
+  }
+  if (custom) {
+    // the caller's allocator may hand the block out again at once, on any
+    // stream: no work of ours may still use it
+    (void)hipDeviceSynchronize();
+    a.free(p, a.user);
+  } else {
+    (void)hipFree(p);
+  }
 }
 
 static hipEvent_t pool_event(hss_ctx_t c) {
@@ -275,9 +316,11 @@ const char* hss_status_string(hss_status s) {
 
 const char* hss_last_error(void) { return g_last_error.c_str(); }
 
-hss_status hss_ctx_create(int32_t device, void* hip_stream, hss_ctx_t* out) {
+hss_status hss_ctx_create(int32_t device, void* hip_stream, const hss_allocator* allocator, hss_ctx_t* out) {
   HSS_API_BEGIN
   HSS_CHECK(out != nullptr, HSS_ERR_INVALID_ARGUMENT, "out is NULL");
+  HSS_CHECK(!allocator || (allocator->alloc && allocator->free) || (!allocator->alloc && !allocator->free),
+            HSS_ERR_INVALID_ARGUMENT, "an allocator needs both alloc and free");
   int count = 0;
   HSS_HIP(hipGetDeviceCount(&count));
   HSS_CHECK(device >= 0 && device < count, HSS_ERR_INVALID_ARGUMENT, "device index out of range");
@@ -286,6 +329,7 @@ hss_status hss_ctx_create(int32_t device, void* hip_stream, hss_ctx_t* out) {
   hss_ctx_t c = new hss_ctx_s();
   c->device = device;
   c->stream = (hipStream_t)hip_stream;
+  if (allocator) c->allocator = *allocator;
   HSS_HIP(hipEventCreate(&c->ev0));
   HSS_HIP(hipEventCreate(&c->ev1));
   *out = c;
@@ -362,6 +406,7 @@ hss_status hss_profile_read(hss_ctx_t ctx, char* buf, int64_t capacity, int64_t*
 }
 
 hss_status hss_import(hss_ctx_t ctx, const hss_desc* d, hss_matrix_t* out) {
+  hss::CtxScope cs_(ctx);
   hss_matrix_t m = nullptr;
   HSS_API_BEGIN
   HSS_CHECK(ctx && d && out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
@@ -434,6 +479,7 @@ hss_status hss_import(hss_ctx_t ctx, const hss_desc* d, hss_matrix_t* out) {
 
 hss_status hss_construct(hss_ctx_t ctx, const double* d_points, int64_t n, int32_t dim, const hss_kernel* kernel,
                          const hss_construct_opts* opts, const double* d_omega, int32_t s, hss_matrix_t* out) {
+  hss::CtxScope cs_(ctx);
   hss_matrix_t m = nullptr;
   try {
     HSS_CHECK(ctx && d_points && kernel && opts && out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
@@ -530,6 +576,7 @@ hss_status hss_export_sizes(hss_matrix_t m, int64_t sizes[7]) {
 
 hss_status hss_export(hss_ctx_t ctx, hss_matrix_t m, hss_desc_out* o) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m && o, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(m->nsys == 1, HSS_ERR_UNSUPPORTED, "a batch cannot be exported; export its systems");
   hipStream_t s = ctx->stream;
@@ -585,6 +632,7 @@ static void factor_checked(hss_ctx_t ctx, hss_matrix_t m, int prec, const std::f
 
 hss_status hss_ulv_factor(hss_ctx_t ctx, hss_matrix_t m, const hss_factor_opts* opts) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   const int prec = opts ? opts->precision : HSS_P_FP64;
   HSS_CHECK(prec == HSS_P_FP64 || prec == HSS_P_FP32, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
@@ -595,6 +643,7 @@ hss_status hss_ulv_factor(hss_ctx_t ctx, hss_matrix_t m, const hss_factor_opts* 
 hss_status hss_ulv_factor_solve(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, double* d_x, int64_t nrhs,
                                 int64_t ld) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m && d_b && d_x, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(nrhs >= 1 && ld >= m->n, HSS_ERR_INVALID_ARGUMENT, "need nrhs >= 1 and ld >= n");
   factor_checked(ctx, m, HSS_P_FP64, [&] {
@@ -611,6 +660,7 @@ hss_status hss_ulv_factor_solve(hss_ctx_t ctx, hss_matrix_t m, const double* d_b
 
 hss_status hss_ulv_solve(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, double* d_x, int64_t nrhs, int64_t ld) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m && d_b && d_x, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(nrhs >= 1 && ld >= m->n, HSS_ERR_INVALID_ARGUMENT, "need nrhs >= 1 and ld >= n");
   HSS_CHECK(m->state == 1, HSS_ERR_BAD_STATE, "matrix is not factored");
@@ -623,6 +673,7 @@ hss_status hss_ulv_solve(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, doubl
 
 hss_status hss_matvec(hss_ctx_t ctx, hss_matrix_t m, const double* d_x, double* d_y, int64_t nrhs, int64_t ld) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m && d_x && d_y, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(nrhs >= 1 && ld >= m->n, HSS_ERR_INVALID_ARGUMENT, "need nrhs >= 1 and ld >= n");
   HSS_CHECK(d_x != d_y, HSS_ERR_INVALID_ARGUMENT, "x and y must not alias");
@@ -632,6 +683,7 @@ hss_status hss_matvec(hss_ctx_t ctx, hss_matrix_t m, const double* d_x, double* 
 
 hss_status hss_logdet(hss_ctx_t ctx, hss_matrix_t m, double* h_out) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m && h_out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(m->state == 1, HSS_ERR_BAD_STATE, "matrix is not factored");
   *h_out = read_logdet(m);
@@ -662,6 +714,7 @@ hss_status hss_get_info(hss_matrix_t m, hss_info* o) {
 
 hss_status hss_get_permutation(hss_ctx_t ctx, hss_matrix_t m, int64_t* d_perm) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m && d_perm, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_HIP(hipMemcpyAsync(d_perm, m->dperm, sizeof(int64_t) * m->n, hipMemcpyDeviceToDevice, ctx->stream));
   HSS_API_END
@@ -670,6 +723,7 @@ hss_status hss_get_permutation(hss_ctx_t ctx, hss_matrix_t m, int64_t* d_perm) {
 hss_status hss_debug_node_block(hss_ctx_t ctx, hss_matrix_t m, int32_t node, int32_t what, double* h_out,
                                 int64_t capacity) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m && h_out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(node >= 0 && node < m->nnodes, HSS_ERR_INVALID_ARGUMENT, "node out of range");
   HSS_CHECK(m->state == 1, HSS_ERR_BAD_STATE, "matrix is not factored");

@@ -149,6 +149,7 @@ struct ProfRec {
 struct hss_ctx_s {
   int device = 0;
   hipStream_t stream = nullptr;
+  hss_allocator allocator{nullptr, nullptr, nullptr};  // the caller's device allocator (alloc NULL: hipMalloc)
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   // per-launch event profiling (off unless enabled)
   bool prof = false;
@@ -259,9 +260,18 @@ struct Prof {
   ~Prof();
 };
 
-// allocation helpers (throw on failure)
+// allocation helpers (throw on failure): the allocator of the context set by
+// the innermost CtxScope on this thread, else hipMalloc
 void* dev_alloc(size_t bytes);
 void dev_free(void* p);
+extern thread_local hss_ctx_t g_alloc_ctx;
+struct CtxScope {
+  hss_ctx_t prev;
+  explicit CtxScope(hss_ctx_t c) : prev(g_alloc_ctx) { g_alloc_ctx = c; }
+  ~CtxScope() { g_alloc_ctx = prev; }
+  CtxScope(const CtxScope&) = delete;
+  CtxScope& operator=(const CtxScope&) = delete;
+};
 
 // Sample sizing of one construction attempt (construct.hip).
 struct SamplePlan {

@@ -290,6 +290,7 @@ hss_status hss_rankmlp_param_count(int64_t* out) {
 
 hss_status hss_rankmlp_create(hss_ctx_t ctx, hss_rankmlp_t* out) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_HIP(hipSetDevice(ctx->device));
   hss_rankmlp_t r = new hss_rankmlp_s();
@@ -339,6 +340,7 @@ hss_status hss_rankmlp_destroy(hss_rankmlp_t r) {
 
 hss_status hss_rankmlp_set_weights(hss_ctx_t ctx, hss_rankmlp_t r, const float* h_params) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && r && h_params, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   const int64_t np = param_count();
   std::vector<float> z(np, 0.0f);
@@ -352,6 +354,7 @@ hss_status hss_rankmlp_set_weights(hss_ctx_t ctx, hss_rankmlp_t r, const float* 
 
 hss_status hss_rankmlp_get_weights(hss_ctx_t ctx, hss_rankmlp_t r, float* h_params) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && r && h_params, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_HIP(hipMemcpyAsync(h_params, r->P, sizeof(float) * param_count(), hipMemcpyDeviceToHost, ctx->stream));
   HSS_HIP(hipStreamSynchronize(ctx->stream));
@@ -360,6 +363,7 @@ hss_status hss_rankmlp_get_weights(hss_ctx_t ctx, hss_rankmlp_t r, float* h_para
 
 hss_status hss_rankmlp_forward(hss_ctx_t ctx, hss_rankmlp_t r, const float* d_feats, int64_t n, float* d_out) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && r && d_feats && d_out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(n >= 1, HSS_ERR_INVALID_ARGUMENT, "n must be >= 1");
   const int64_t chunk = 65536;
@@ -377,6 +381,7 @@ hss_status hss_rankmlp_forward(hss_ctx_t ctx, hss_rankmlp_t r, const float* d_fe
 hss_status hss_rankmlp_predict(hss_ctx_t ctx, hss_rankmlp_t r, const float* d_feats, int64_t n, int32_t cap,
                                int32_t* d_ranks) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && r && d_feats && d_ranks, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(n >= 1 && cap >= 1, HSS_ERR_INVALID_ARGUMENT, "need n >= 1 and cap >= 1");
   rankmlp_predict(r, d_feats, n, cap, d_ranks);
@@ -386,6 +391,7 @@ hss_status hss_rankmlp_predict(hss_ctx_t ctx, hss_rankmlp_t r, const float* d_fe
 hss_status hss_rankmlp_grad(hss_ctx_t ctx, hss_rankmlp_t r, const float* d_feats, const float* d_targets, int64_t n,
                             float tau, float* h_grads, float* h_loss) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && r && d_feats && d_targets, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(n >= 1 && n <= 65536, HSS_ERR_INVALID_ARGUMENT, "n must be in [1, 65536]");
   HSS_CHECK(tau > 0.0f && tau < 1.0f, HSS_ERR_INVALID_ARGUMENT, "tau must be in (0, 1)");
@@ -406,6 +412,7 @@ hss_status hss_rankmlp_grad(hss_ctx_t ctx, hss_rankmlp_t r, const float* d_feats
 hss_status hss_rankmlp_train(hss_ctx_t ctx, hss_rankmlp_t r, const float* d_feats, const float* d_targets, int64_t n,
                              const int64_t* d_order, int64_t order_len, const hss_train_opts* o, float* h_losses) {
   HSS_API_BEGIN
+  hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && r && d_feats && d_targets && d_order && o, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   HSS_CHECK(n >= 1 && order_len >= 1, HSS_ERR_INVALID_ARGUMENT, "need n >= 1 and order_len >= 1");
   HSS_CHECK(o->batch >= 1 && o->batch <= 65536, HSS_ERR_INVALID_ARGUMENT, "batch must be in [1, 65536]");

@@ -199,6 +199,7 @@ extern "C" hss_status hss_ulv_solve_refined(hss_ctx_t ctx, hss_matrix_t m, const
                                             int64_t nrhs, int64_t ld, double tol, int32_t max_iters,
                                             int32_t* iters_out, double* relres_out) {
   try {
+    hss::CtxScope cs_(ctx);
     HSS_CHECK(ctx && m && d_b && d_x, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
     HSS_CHECK(nrhs >= 1 && ld == m->n, HSS_ERR_INVALID_ARGUMENT, "need nrhs >= 1 and ld == n");
     HSS_CHECK(d_b != d_x, HSS_ERR_INVALID_ARGUMENT, "b and x must not alias");

@@ -43,6 +43,14 @@ class hss_kernel(C.Structure):
                 ("nugget", C.c_double), ("alpha", C.c_double), ("eps", C.c_double)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class hss_allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
 class hss_construct_opts(C.Structure):
     _fields_ = [("leaf_size", C.c_int32), ("levels", C.c_int32), ("rank", C.c_int32),
                 ("max_rank", C.c_int32), ("tol", C.c_double), ("mode", C.c_int32),
@@ -92,7 +100,7 @@ class hss_info(C.Structure):
 # Every symbol include/hss.h declares, with its ctypes signature.
 _P = C.c_void_p
 SIGNATURES = {
-    "hss_ctx_create": (C.c_int, [C.c_int32, _P, C.POINTER(_P)]),
+    "hss_ctx_create": (C.c_int, [C.c_int32, _P, C.POINTER(hss_allocator), C.POINTER(_P)]),
     "hss_ctx_destroy": (C.c_int, [_P]),
     "hss_ctx_set_stream": (C.c_int, [_P, _P]),
     "hss_construct": (C.c_int, [_P, _P, C.c_int64, C.c_int32, C.POINTER(hss_kernel),
@@ -240,10 +248,42 @@ def _vec_args(m, b, x, bname="b", xname="x"):
 # --------------------------------------------------------------------------
 
 
-def hss_ctx_create(device: int = 0, stream=None):
+# The callbacks of every allocator handed to the library stay referenced for
+# the life of the process: blocks may be returned to them until then.
+_ALLOCATORS = []
+
+
+def torch_allocator(device: int = 0, stream=None) -> hss_allocator:
+    """An hss_allocator backed by PyTorch's caching allocator on `device`
+    (blocks associated with `stream`, default the current stream)."""
+    import torch
+
+    def alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device=device, stream=stream)
+        except Exception:  # out of memory: the library reports it
+            return None
+
+    def free(ptr, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a, f = _ALLOC_FN(alloc), _FREE_FN(free)
+    _ALLOCATORS.append((a, f))
+    return hss_allocator(a, f, None)
+
+
+def hss_ctx_create(device: int = 0, stream=None, allocator="torch"):
+    """Context on `device` enqueueing on `stream` (default: torch's current
+    stream). allocator "torch" (default): the library's device memory comes from
+    PyTorch's caching allocator; None: hipMalloc; or an hss_allocator."""
     lib = load()
     out = C.c_void_p()
-    _check(lib.hss_ctx_create(device, _stream_ptr(stream), C.byref(out)), "hss_ctx_create")
+    if isinstance(allocator, str):
+        if allocator != "torch":
+            raise ValueError("allocator must be 'torch', None or an hss_allocator")
+        allocator = torch_allocator(device, stream)
+    aptr = C.byref(allocator) if allocator is not None else None
+    _check(lib.hss_ctx_create(device, _stream_ptr(stream), aptr, C.byref(out)), "hss_ctx_create")
     return out
 
 

@@ -232,3 +232,50 @@ def test_fused_factor_solve_reports_not_spd(ctx, torch_dev):
         assert es.value.status == hss.HSS_ERR_BAD_STATE
     finally:
         hss.hss_matrix_destroy(m)
+
+
+def test_caller_allocator_supplies_every_block(torch_dev):
+    # hss_ctx_create's allocator: every device block of a matrix (representation,
+    # factors, workspaces) comes from the caller's functions -- here PyTorch's
+    # caching allocator behind a counter -- and goes back to them on destroy; the
+    # results equal those of a context on hipMalloc bit for bit.
+    from paper_2311_00921_amd import hss
+
+    torch = torch_dev
+    live, calls = {}, {"alloc": 0, "free": 0}
+
+    def alloc(nbytes, user):
+        p = torch.cuda.caching_allocator_alloc(int(nbytes), device=0)
+        live[p] = int(nbytes)
+        calls["alloc"] += 1
+        return p
+
+    def free(ptr, user):
+        assert ptr in live
+        del live[ptr]
+        calls["free"] += 1
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a, f = hss._ALLOC_FN(alloc), hss._FREE_FN(free)
+    counted = hss.hss_allocator(a, f, None)
+    d = synth.random_hss(3, 64, 16, seed=77)
+    h = O.HSS(d["n"], d["levels"], d["ranges"], d["rank"], d["D"], d["U"], d["E"], d["S"])
+    b = torch.from_numpy(synth.rhs_normal(h.n, 1, 3)[:, 0].copy()).cuda()
+    out = []
+    for allocator in (counted, None):
+        c = hss.hss_ctx_create(0, allocator=allocator)
+        m = hss.hss_import(c, oracle_to_dict(h))
+        hss.hss_ulv_factor(c, m)
+        x = hss.hss_ulv_solve(c, m, b)
+        y = hss.hss_matvec(c, m, b)
+        hss.hss_ulv_factor(c, m, hss.HSS_P_FP32)
+        xr, _, _, ok = hss.hss_ulv_solve_refined(c, m, b, 1e-12, 20)
+        out.append((x.cpu().numpy(), y.cpu().numpy(), xr.cpu().numpy(), ok))
+        if allocator is not None:
+            assert calls["alloc"] > 10 and len(live) > 0
+        hss.hss_matrix_destroy(m)
+        hss.hss_ctx_destroy(c)
+    assert len(live) == 0 and calls["alloc"] == calls["free"]
+    for u, v in zip(out[0][:3], out[1][:3]):
+        assert np.array_equal(u, v)
+    assert out[0][3] and out[1][3]
