@@ -28,6 +28,9 @@ Parity status per function:
     rank, Schur complement equals R R^T of the scaled basis QR).
   * qrcp: pinned against brute force (pivot = argmax of residual column norms,
     A P = Q R reconstruction).
+  * blr2_factor / blr2_solve / blr2_logdet: pinned (dense solve and slogdet of
+    the densified matrix, agreement with the HSS-ULV solve, single-level case
+    where the skeleton matrix is the root block).
 """
 from __future__ import annotations
 
@@ -693,55 +696,121 @@ def ulv_solve(h: HSS, F: ULVFactor, b: np.ndarray) -> np.ndarray:
 # ----------------------------------------------------------------------------
 
 
-def blr2_logdet(h: HSS) -> float:
-    """Alg. 1 applied to the HSS matrix viewed at its leaf level: diagonal product
-    and partial Cholesky of every leaf block (Eq. 7, 10-12), then the permutation
-    of all skeleton rows to the end and one dense Cholesky of the resulting
-    (sum of leaf ranks) square matrix (Eq. 13). Returns the log-determinant."""
+@dataclass
+class BLR2Factor:
+    """BLR^2-ULV factors (Alg. 1): per leaf i, Q_i = [U^R_i U^S_i] (Eq. 9), L_RR
+    and L_SR (Eq. 10-11); the dense Cholesky factor Lss of the permuted
+    skeleton matrix (Eq. 13), whose block (i, j) is Sigma_i on the diagonal
+    (Eq. 12) and U_i^T A_ij U_j off it; offs[i] = first skeleton row of leaf i."""
+
+    Q: list
+    LRR: list
+    LSR: list
+    Lss: np.ndarray
+    offs: np.ndarray
+    logdet: float
+
+
+def blr2_skeleton_matrix(h: HSS):
+    """The skeleton-space matrix of Alg. 1's last step before its Cholesky, with
+    the per-leaf factors: Sigma_i on the diagonal and, between leaves i and j
+    under the two children of node (l, g), the coupling S_(l,g) expressed in the
+    leaves' own bases through the transfer matrices below it (Eq. 6)."""
     L = h.levels
-    if L == 0:
-        return 2.0 * float(np.sum(np.log(np.diag(np.linalg.cholesky(h.D[0])))))
-    Ub = _big_bases(h)
+    Qs, LRRs, LSRs, sig = [], [], [], []
     logdet = 0.0
-    sig = []
     for i in range(2 ** L):
         Us = h.U[i]
         n, k = Us.shape
         m = n - k
         Q = np.hstack([complement_basis(Us), Us])
-        Ahat = Q.T @ h.D[i] @ Q
+        Ahat = Q.T @ h.D[i] @ Q                                     # Eq. 7 with U^F of Eq. 9
         if m > 0:
-            LRR = np.linalg.cholesky(Ahat[:m, :m])
-            LSR = sla.solve_triangular(LRR, Ahat[:m, m:], lower=True).T
+            LRR = _chol(Ahat[:m, :m], L, i)                          # Eq. 10
+            LSR = sla.solve_triangular(LRR, Ahat[:m, m:], lower=True).T  # Eq. 11
             logdet += 2.0 * float(np.sum(np.log(np.diag(LRR))))
-            sig.append(Ahat[m:, m:] - LSR @ LSR.T)
+            sig.append(Ahat[m:, m:] - LSR @ LSR.T)                   # Eq. 12
         else:
+            LRR, LSR = np.zeros((0, 0)), np.zeros((k, 0))
             sig.append(Ahat)
-    # skeleton-space matrix: diagonal blocks Sigma_i, off-diagonal blocks U_i^T A_ij U_j
+        Qs.append(Q)
+        LRRs.append(LRR)
+        LSRs.append(LSR)
     offs = np.cumsum([0] + [u.shape[1] for u in h.U])
-    K = offs[-1]
+    K = int(offs[-1])
     Ass = np.zeros((K, K))
     for i in range(2 ** L):
         Ass[offs[i]:offs[i + 1], offs[i]:offs[i + 1]] = sig[i]
-    # off-diagonal skeleton couplings from every ancestor level
     for l in range(0, L):
         for g in range(2 ** l):
             c1, c2 = 2 * g, 2 * g + 1
-            S = h.S[l][g]
-            # leaves under c1 and c2 on level l+1
             span = 2 ** (L - l - 1)
-            leaves1 = range(c1 * span, (c1 + 1) * span)
-            leaves2 = range(c2 * span, (c2 + 1) * span)
-            # leaf-local skeleton coords: U_i^T Ubig_c = rows of the nested transfer product
             T1 = _leaf_to_node(h, l + 1, c1)
             T2 = _leaf_to_node(h, l + 1, c2)
-            blk = T1 @ S @ T2.T
-            r1 = np.concatenate([np.arange(offs[i], offs[i + 1]) for i in leaves1])
-            r2 = np.concatenate([np.arange(offs[i], offs[i + 1]) for i in leaves2])
+            blk = T1 @ h.S[l][g] @ T2.T
+            r1 = np.arange(offs[c1 * span], offs[(c1 + 1) * span])
+            r2 = np.arange(offs[c2 * span], offs[(c2 + 1) * span])
             Ass[np.ix_(r1, r2)] = blk
             Ass[np.ix_(r2, r1)] = blk.T
-    Lss = np.linalg.cholesky(Ass)
-    return logdet + 2.0 * float(np.sum(np.log(np.diag(Lss))))
+    return Ass, offs, Qs, LRRs, LSRs, logdet
+
+
+def blr2_factor(h: HSS) -> BLR2Factor:
+    """Alg. 1 applied to the HSS matrix viewed at its leaf level (a weakly
+    admissible BLR^2 matrix with shared leaf bases): diagonal product and
+    partial Cholesky of every leaf block (Eq. 7, 10-12), then the permutation of
+    all skeleton rows to the end and one dense Cholesky of the resulting
+    (sum of leaf ranks) square matrix (Eq. 13)."""
+    L = h.levels
+    if L == 0:
+        L0 = _chol(h.D[0], 0, 0)
+        return BLR2Factor([np.eye(h.n)], [L0], [np.zeros((0, h.n))], np.zeros((0, 0)), np.array([0, 0]),
+                          2.0 * float(np.sum(np.log(np.diag(L0)))))
+    Ass, offs, Qs, LRRs, LSRs, logdet = blr2_skeleton_matrix(h)
+    Lss = _chol(Ass, 0, 0)
+    logdet += 2.0 * float(np.sum(np.log(np.diag(Lss))))
+    return BLR2Factor(Qs, LRRs, LSRs, Lss, offs, logdet)
+
+
+def blr2_logdet(h: HSS) -> float:
+    """log det of the matrix from its BLR^2-ULV factors: twice the sum of the
+    logarithms of every leaf pivot and of the skeleton factor's diagonal."""
+    return blr2_factor(h).logdet
+
+
+def blr2_solve(h: HSS, F: BLR2Factor, b: np.ndarray) -> np.ndarray:
+    """BLR^2-ULV solve (Eq. 14) in tree order, read as ordered products:
+    per leaf, b^ = Q^T b, y_R = L_RR^{-1} b^_R and z_S = b^_S - L_SR y_R; the
+    skeleton parts of all leaves, gathered in leaf order (the permutation P),
+    are solved with Lss Lss^T; then per leaf x_R = L_RR^{-T}(y_R - L_SR^T x_S)
+    and x = Q [x_R; x_S]."""
+    vec = b.ndim == 1
+    B = b[:, None] if vec else b
+    L = h.levels
+    if L == 0:
+        L0 = F.LRR[0]
+        x = sla.solve_triangular(L0, sla.solve_triangular(L0, B, lower=True), lower=True, trans="T")
+        return x[:, 0] if vec else x
+    ys, zs = [], []
+    for i, (lo, hi) in enumerate(h.ranges[L]):
+        m = F.LRR[i].shape[0]
+        bh = F.Q[i].T @ B[lo:hi]
+        yR = sla.solve_triangular(F.LRR[i], bh[:m], lower=True) if m > 0 else bh[:0]
+        ys.append(yR)
+        zs.append(bh[m:] - F.LSR[i] @ yR)
+    z = np.vstack(zs)
+    w = sla.solve_triangular(F.Lss, z, lower=True)
+    w = sla.solve_triangular(F.Lss, w, lower=True, trans="T")
+    X = np.zeros_like(B)
+    for i, (lo, hi) in enumerate(h.ranges[L]):
+        m = F.LRR[i].shape[0]
+        xS = w[F.offs[i]:F.offs[i + 1]]
+        if m > 0:
+            xR = sla.solve_triangular(F.LRR[i], ys[i] - F.LSR[i].T @ xS, lower=True, trans="T")
+        else:
+            xR = xS[:0]
+        X[lo:hi] = F.Q[i] @ np.vstack([xR, xS])
+    return X[:, 0] if vec else X
 
 
 def _leaf_to_node(h: HSS, l: int, i: int) -> np.ndarray:

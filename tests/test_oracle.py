@@ -363,6 +363,53 @@ def test_blr2_ulv_equals_hss_ulv_logdet(cfg1):
     assert abs(O.blr2_logdet(cfg1["h"]) - cfg1["F"].logdet) < 1e-10 * abs(cfg1["F"].logdet)
 
 
+def test_blr2_solve_equals_dense_solve(cfg1):
+    # Eq. 14 on the exp2d workload against a dense solve of the matrix the HSS
+    # form represents, and against the HSS-ULV solve of Alg. 2 / Eq. 17.
+    h, b = cfg1["h"], cfg1["b"]
+    A = O.densify(h)
+    F2 = O.blr2_factor(h)
+    x = O.blr2_solve(h, F2, b)
+    xd = np.linalg.solve(A, b)
+    assert np.linalg.norm(x - xd) / np.linalg.norm(xd) < 1e-10
+    xh = O.ulv_solve(h, cfg1["F"], b)
+    assert np.linalg.norm(x - xh) / np.linalg.norm(xh) < 1e-10
+    sign, ld = np.linalg.slogdet(A)
+    assert sign > 0 and abs(F2.logdet - ld) < 1e-10 * abs(ld)
+
+
+@pytest.mark.parametrize("levels,leaf,rank", [(1, 16, 5), (3, 24, 7), (4, 12, 12)])
+def test_blr2_on_random_hss(levels, leaf, rank):
+    # random HSS matrices (rank = leaf: uncompressed leaves, m = 0), several
+    # right-hand sides; the skeleton matrix has sum(leaf ranks) rows
+    h = hss_from_dict(synth.random_hss(levels, leaf, rank, seed=40 + levels))
+    A = O.densify(h)
+    F2 = O.blr2_factor(h)
+    assert F2.Lss.shape == (rank * 2 ** levels,) * 2
+    B = synth.rhs_normal(h.n, 3, 41)
+    X = O.blr2_solve(h, F2, B)
+    assert np.linalg.norm(A @ X - B) / np.linalg.norm(B) < 1e-12
+    sign, ld = np.linalg.slogdet(A)
+    assert sign > 0 and abs(F2.logdet - ld) < 1e-11 * max(1.0, abs(ld))
+
+
+def test_blr2_skeleton_matrix_is_the_schur_complement():
+    # The skeleton matrix equals the Schur complement of the redundant rows in
+    # Q^T A Q (Q = blkdiag of the leaves' [U^R U^S]), formed here densely: a
+    # dropped or transposed coupling, or a wrong leaf offset, breaks it.
+    h = hss_from_dict(synth.random_hss(3, 20, 6, seed=47))
+    A = O.densify(h)
+    Ass, offs, Qs, _, _, _ = O.blr2_skeleton_matrix(h)
+    Q = sla.block_diag(*Qs)
+    Ah = Q.T @ A @ Q
+    ms = [q.shape[1] - (offs[i + 1] - offs[i]) for i, q in enumerate(Qs)]
+    lo = np.cumsum([0] + [q.shape[1] for q in Qs])
+    R = np.concatenate([np.arange(lo[i], lo[i] + ms[i]) for i in range(len(Qs))])
+    S = np.concatenate([np.arange(lo[i] + ms[i], lo[i + 1]) for i in range(len(Qs))])
+    schur = Ah[np.ix_(S, S)] - Ah[np.ix_(S, R)] @ np.linalg.solve(Ah[np.ix_(R, R)], Ah[np.ix_(R, S)])
+    assert np.abs(Ass - schur).max() < 1e-11 * np.abs(schur).max()
+
+
 def test_two_leaf_hand_derivation():
     # L = 1, hand-derived: with Q_i = [U^R_i U_i], the root block is
     # [[Sigma_0, S], [S^T, Sigma_1]] with Sigma_i = (U_i^T D_i^{-1} U_i)^{-1}.
