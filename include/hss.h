@@ -330,6 +330,41 @@ hss_status hss_matvec(hss_ctx_t ctx, hss_matrix_t m, const double* d_x, double* 
  * (the orthogonal transforms have |det| = 1). Requires FACTORED. Synchronizes. */
 hss_status hss_logdet(hss_ctx_t ctx, hss_matrix_t m, double* h_out);
 
+/* BLR^2-ULV (Sec. 3.1, Alg. 1), a variant factorization of the same matrix:
+ * the leaf blocks with their shared bases are read as a weakly admissible
+ * BLR^2 matrix (Sec. 2, the coupling between leaves i and j being their lowest
+ * common ancestor's S carried into the leaf bases by the transfer matrices of
+ * Eq. 6). Alg. 1: the diagonal product and partial Cholesky of every leaf
+ * (Eq. 7, 10-12; the leaf stage of hss_ulv_factor), the permutation of all
+ * skeleton rows to the end, and one dense Cholesky of that K x K skeleton
+ * matrix (Eq. 13), K = sum of the leaf ranks. Storage K^2 doubles, work
+ * K^3 / 3 flops: the cost that the nested basis of the HSS-ULV avoids.
+ * Single trees whose leaves all sit on the deepest level; K <= 65536
+ * (UNSUPPORTED otherwise). Shares the leaf factor buffers with hss_ulv_factor:
+ * each factorization leaves the other's stale (hss_ulv_solve then returns
+ * BAD_STATE until hss_ulv_factor runs again, and vice versa). FP64 only.
+ * Synchronizes. Errors: NOT_SPD (a leaf pivot or a pivot of the skeleton
+ * matrix; the message names which), OUT_OF_MEMORY. */
+hss_status hss_blr2_factor(hss_ctx_t ctx, hss_matrix_t m);
+
+/* BLR^2-ULV solve (Eq. 14): the leaf forward sweep, the two triangular solves
+ * with the skeleton matrix's Cholesky factor, the leaf backward sweep.
+ * Arguments as hss_ulv_solve (d_x may equal d_b); BAD_STATE without a valid
+ * hss_blr2_factor. */
+hss_status hss_blr2_solve(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, double* d_x,
+                          int64_t nrhs, int64_t ld);
+
+/* log det A from the BLR^2-ULV factors: 2 * sum of log pivots of every leaf
+ * L_RR and of the skeleton matrix's Cholesky factor. BAD_STATE without a
+ * valid hss_blr2_factor. */
+hss_status hss_blr2_logdet(hss_ctx_t ctx, hss_matrix_t m, double* h_out);
+
+/* The skeleton matrix order K of the BLR^2-ULV (valid before any
+ * factorization) and, in *factor_ms (nullable), the GPU time of the last
+ * successful hss_blr2_factor (0 if none). Errors: UNSUPPORTED for shapes the
+ * BLR^2-ULV does not take. */
+hss_status hss_blr2_stats(hss_matrix_t m, int64_t* skeleton_rows, float* factor_ms);
+
 hss_status hss_get_info(hss_matrix_t m, hss_info* out);
 /* N entries: tree position -> caller's point index. */
 hss_status hss_get_permutation(hss_ctx_t ctx, hss_matrix_t m, int64_t* d_perm);

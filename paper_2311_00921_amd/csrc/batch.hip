@@ -309,6 +309,7 @@ static void autotune(hss_matrix_t m, int precision, int reps, std::vector<float>
     }
   if (report) report->assign(total, total + kGemmVariants + 1);
   m->state = 0;  // tuning runs leave no usable factorization state behind
+  blr2_invalidate(m);
 }
 
 }  // namespace hss

@@ -269,6 +269,7 @@ static void destroy_matrix(hss_matrix_t m) {
   if (!m) return;
   if (m->ctx) (void)hipStreamSynchronize(m->ctx->stream);
   drop_graphs(m);
+  blr2_free(m);
   free_factor(m);
   void* ptrs[] = {m->dnodes, m->dD, m->dB, m->dS, m->dperm, m->dvec, m->dxt, m->dyt, m->dtmp,
                   m->dOffLi, m->dOffS2};
@@ -606,6 +607,7 @@ hss_status hss_export(hss_ctx_t ctx, hss_matrix_t m, hss_desc_out* o) {
 static void factor_checked(hss_ctx_t ctx, hss_matrix_t m, int prec, const std::function<void()>& run) {
   hipStream_t s = ctx->stream;
   m->state = 0;
+  blr2_invalidate(m);
   m->failed_level = m->failed_node = m->failed_pivot = m->failed_system = -1;
   HSS_HIP(hipEventRecord(ctx->ev0, s));
   run();

@@ -2079,10 +2079,13 @@ static int promote_failed(hss_matrix_t m, const FBufs<T>& b, T* msink) {
 // nodes of those stages whose pivots fail are promoted to FP64.
 template <typename T>
 static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::vector<GemmBatch>>& plan,
-                          bool mixed) {
+                          bool mixed, int nst = -1) {
   hipStream_t s = m->ctx->stream;
   hss_ctx_t cx = m->ctx;
-  const bool hoist = plan.size() > m->stages.size();
+  // nst < 0: every stage; else the first nst stages only, each leaving its
+  // Schur complements in F (no hoisted basis, no direct writes to the parents)
+  if (nst < 0) nst = (int)m->stages.size();
+  const bool hoist = nst == (int)m->stages.size() && plan.size() > m->stages.size();
   // When every stage's Schur complements come from k_sr_schur or the fused
   // LDS Cholesky, those kernels write Sg Sigma Sg straight into the parents'
   // merged blocks, the coupling blocks are written once on the second stream,
@@ -2143,7 +2146,7 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
     cx->stream = s;
     if (!serial) HSS_HIP(hipEventRecord(cx->ev_join, a));
   };
-  for (size_t si = 0; si < m->stages.size(); ++si) {
+  for (size_t si = 0; si < (size_t)nst; ++si) {
     const LevelPlan& lp = m->stages[si];
     const int l = lp.level;
     const bool basis_done = hoist && si > 0;
@@ -2253,6 +2256,27 @@ void factor_mixed(hss_matrix_t m) {
   hipLaunchKernelGGL(k_sum_logdet, dim3(1), dim3(256), 0, s, (const double*)m->dlogdet, m->nnodes,
                      m->dlogdet + m->nnodes);
   HSS_HIP(hipGetLastError());
+}
+
+// The leaf stage of Alg. 2 alone (FP64), which is also the leaf step of the
+// BLR^2-ULV of Alg. 1: diagonal product and partial Cholesky of every leaf
+// (Eq. 7, 10-12), then the merged block [[Sg1 Sigma_1 Sg1, S], [S^T, Sg2 Sigma_2
+// Sg2]] of every node of the stage above. Status words and the per-node
+// log-determinant sums are cleared first; the leaves' sums are left per node.
+void factor_leaf_stage_fp64(hss_matrix_t m) {
+  hipStream_t s = m->ctx->stream;
+  alloc_factor(m);
+  clear_status(m, s);
+  m->promoted = 0;
+  const FBufs<double> b = fbufs(m);
+  factor_stages<double>(m, b, m->gemm_plan, false, 1);
+  if (m->stages.size() > 1) {
+    const LevelPlan& lp = m->stages[1];
+    const int tpr = (lp.nmax + 31) / 32;
+    hipLaunchKernelGGL((k_merge<double>), dim3(lp.count, tpr * tpr), dim3(256), 0, s, m->dnodes, lp.first,
+                       (const double*)b.F, (const double*)b.Sg, b.S, b.M, 0);
+    HSS_HIP(hipGetLastError());
+  }
 }
 
 double read_logdet(hss_matrix_t m) {

@@ -139,6 +139,7 @@ struct GemmTimer {
 // ---------------------------------------------------------------------------
 
 namespace hss {
+struct Blr2State;  // BLR^2-ULV factors of a matrix (blr2.hip)
 struct ProfRec {
   const char* name;
   int32_t level;
@@ -219,6 +220,9 @@ struct hss_matrix_s {
   std::vector<double> leaf_trace;  // per node (leaves): trace of D, the FP32 error scale
   std::vector<char> fp64_leaf;     // per node: leaf redone in FP64 by the last mixed factorization
   std::vector<std::vector<hss::GemmBatch>> gemm_plan32;
+
+  // BLR^2-ULV factorization of the leaf level (Alg. 1); nullptr until used
+  hss::Blr2State* blr2 = nullptr;
 
   // solve / matvec workspaces (device), sized for ws_nrhs columns
   double* dvec = nullptr;   // per-node vectors, sum(n) x nrhs
@@ -304,6 +308,7 @@ void gemm_launch_f32(const GemmBatch& b, bool ta, bool tb, float alpha, float be
 void factor_fp64(hss_matrix_t m);
 void factor_mixed(hss_matrix_t m);
 double read_logdet(hss_matrix_t m);
+void factor_leaf_stage_fp64(hss_matrix_t m);
 void free_factor(hss_matrix_t m);
 
 void prepare_factor(hss_matrix_t m, int precision);
@@ -318,6 +323,14 @@ void drop_graphs(hss_matrix_t m);
 void ensure_vec_ws(hss_matrix_t m, int64_t nrhs);
 void solve_fp64(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld);
 void solve_fp64_ws(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld, double* vec);
+void solve_leaf_sweep(hss_matrix_t m, bool forward, const double* b, double* x, int64_t nrhs, int64_t c0, int nc,
+                      int64_t ld);
+int solve_chunk();
+
+// blr2.hip: releases the BLR^2-ULV factors of a matrix; marks them stale (any
+// other factorization overwrites the leaf factors they share)
+void blr2_free(hss_matrix_t m);
+void blr2_invalidate(hss_matrix_t m);
 
 // noalloc.hip: resolves the static scratch array's address on the current device
 void noalloc_init(int device);

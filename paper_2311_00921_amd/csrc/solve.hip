@@ -710,6 +710,20 @@ static void solve_impl(hss_matrix_t m, const T* F, const T* V, const T* Yw, cons
   }
 }
 
+// One sweep of the leaf stage alone (FP64 factors): forward (b in, the
+// parents' slots of the vector workspace out) or backward (the parents' slots
+// in, x out), for right-hand sides c0 .. c0 + nc - 1 (nc <= solve_chunk()).
+void solve_leaf_sweep(hss_matrix_t m, bool forward, const double* b, double* x, int64_t nrhs, int64_t c0, int nc,
+                      int64_t ld) {
+  hipStream_t s = m->ctx->stream;
+  if (forward)
+    launch_fwd<double>(m, 0, m->dF, m->dV, m->dW, m->dSg, m->dvec, m->dLi, m->inv_used64[0], b, nrhs, c0, nc, ld, s);
+  else
+    launch_bwd<double>(m, 0, m->dF, m->dV, m->dW, m->dSg, m->dvec, m->dLi, m->inv_used64[0], x, nrhs, c0, nc, ld, s);
+}
+
+int solve_chunk() { return RC; }
+
 void solve_fp64(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_t ld) {
   ensure_vec_ws(m, nrhs);
   solve_fp64_ws(m, b, x, nrhs, ld, m->dvec);

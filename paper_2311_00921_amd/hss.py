@@ -116,6 +116,10 @@ SIGNATURES = {
                                         C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
     "hss_matvec": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64]),
     "hss_logdet": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
+    "hss_blr2_factor": (C.c_int, [_P, _P]),
+    "hss_blr2_solve": (C.c_int, [_P, _P, _P, _P, C.c_int64, C.c_int64]),
+    "hss_blr2_logdet": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
+    "hss_blr2_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_float)]),
     "hss_get_info": (C.c_int, [_P, C.POINTER(hss_info)]),
     "hss_get_permutation": (C.c_int, [_P, _P, _P]),
     "hss_debug_node_block": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
@@ -483,6 +487,32 @@ def hss_logdet(ctx, m) -> float:
     out = C.c_double()
     _check(load().hss_logdet(ctx, m, C.byref(out)), "hss_logdet")
     return float(out.value)
+
+
+def hss_blr2_factor(ctx, m):
+    """BLR^2-ULV factorization (Alg. 1) of the matrix's leaf level."""
+    _check(load().hss_blr2_factor(ctx, m), "hss_blr2_factor")
+
+
+def hss_blr2_solve(ctx, m, b, x=None):
+    """x = A^{-1} b with the BLR^2-ULV factors (Eq. 14)."""
+    bc, k, ld, x = _vec_args(m, b, x)
+    _check(load().hss_blr2_solve(ctx, m, _ptr(bc), _ptr(x), k, ld), "hss_blr2_solve")
+    return x
+
+
+def hss_blr2_logdet(ctx, m) -> float:
+    out = C.c_double()
+    _check(load().hss_blr2_logdet(ctx, m, C.byref(out)), "hss_blr2_logdet")
+    return float(out.value)
+
+
+def hss_blr2_stats(m):
+    """(skeleton matrix order K, GPU milliseconds of the last BLR^2 factorization)."""
+    k = C.c_int64()
+    ms = C.c_float()
+    _check(load().hss_blr2_stats(m, C.byref(k), C.byref(ms)), "hss_blr2_stats")
+    return int(k.value), float(ms.value)
 
 
 def hss_get_info(m) -> hss_info:
