@@ -84,6 +84,8 @@ def main():
     ap.add_argument("--no-fused", action="store_true", help="skip the one-call factor + solve")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 + refinement leg")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-rank ablation leg")
+    ap.add_argument("--no-config2", action="store_true",
+                    help="skip the 16-right-hand-side leg (HSS-ULV and BLR^2-ULV at N = 65536)")
     ap.add_argument("--learned-workload", default="matern32_n262144",
                     help="workload of the learned-rank ablation (matern32_n262144 with tol 1e-6 and cap 96, "
                          "or exp3d_n1048576 with its tol 1e-8 and cap 128)")
@@ -376,11 +378,84 @@ def main():
         result["mixed_exp3d"] = mixed_exp_leg(hss, torch, np, ctx, args.steps, args.warmup, args.no_tune)
     if not args.no_learned:
         result["learned_rank"] = learned_leg(hss, torch, np, ctx, args.learned_workload)
+    if not args.no_config2:
+        result["config2"] = config2_leg(hss, torch, np, ctx, args.steps, args.warmup, args.no_tune)
 
     if not args.no_cpu_baseline:
         result["cpu_baseline"] = cpu_baseline(exp, w, b.cpu().numpy(), x.cpu().numpy())
     hss.hss_ctx_destroy(ctx)
     print(json.dumps(result))
+
+
+def config2_leg(hss, torch, np, ctx, steps, warmup, no_tune):
+    """The 16-right-hand-side workload (Matern-3/2, N = 65536, leaf 256, rank
+    64): the autotuned FP64 one-call factor + solve of all 16 columns, and the
+    BLR^2-ULV (Alg. 1) of the same matrix beside it: its leaf stage is the
+    same, its skeleton matrix (256 leaves x rank 64 = 16384 rows) is factored
+    densely, which is what the nested basis of the HSS-ULV avoids."""
+    import synth
+
+    w = synth.WORKLOADS["matern32_n65536"]
+    print(f"# config2 leg on {w.name}", file=sys.stderr, flush=True)
+    s = w.rank + w.oversample
+    X = torch.from_numpy(w.points()).cuda()
+    Om = torch.from_numpy(np.ascontiguousarray(w.omega(s).T)).cuda().t()
+    B = torch.from_numpy(np.ascontiguousarray(w.rhs().T)).cuda().t()
+    t0 = time.perf_counter()
+    m = hss.hss_construct(ctx, X, w.kernel, w.leaf, rank=w.rank, omega=Om, length=w.length, nugget=w.nugget)
+    torch.cuda.synchronize()
+    construct_s = time.perf_counter() - t0
+    del X, Om
+    try:
+        if not no_tune:
+            hss.hss_autotune(ctx, m, hss.HSS_P_FP64, 2)
+
+        def timed(fn, n):
+            ts = []
+            out = None
+            for _ in range(n):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                out = fn()
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t)
+            return float(np.median(ts)), out
+
+        for _ in range(warmup):
+            hss.hss_ulv_factor_solve(ctx, m, B)
+        t_hss, x_h = timed(lambda: hss.hss_ulv_factor_solve(ctx, m, B), steps)
+        ld_h = hss.hss_logdet(ctx, m)
+        rr = torch.linalg.norm(B - hss.hss_matvec(ctx, m, x_h), dim=0) / torch.linalg.norm(B, dim=0)
+        K, _ = hss.hss_blr2_stats(m)
+
+        def blr2_step():
+            hss.hss_blr2_factor(ctx, m)
+            return hss.hss_blr2_solve(ctx, m, B)
+
+        blr2_step()
+        t_blr2, x_b = timed(blr2_step, max(1, min(steps, 3)))
+        f_ms = hss.hss_blr2_stats(m)[1]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        hss.hss_blr2_solve(ctx, m, B)
+        torch.cuda.synchronize()
+        t_bsolve = time.perf_counter() - t
+        ld_b = hss.hss_blr2_logdet(ctx, m)
+        rr_b = torch.linalg.norm(B - hss.hss_matvec(ctx, m, x_b), dim=0) / torch.linalg.norm(B, dim=0)
+        chol_gflop = K ** 3 / 3 / 1e9
+        return {"workload": w.name, "N": w.n, "leaf": w.leaf, "rank": w.rank, "nrhs": 16,
+                "construct_s": round(construct_s, 3),
+                "hss_factor_plus_solve_s": round(t_hss, 6), "hss_relres_max": float(rr.max()),
+                "blr2": {"skeleton_rows": K, "factor_plus_solve_s": round(t_blr2, 6),
+                         "factor_ms_events": round(f_ms, 3), "solve_s": round(t_bsolve, 6),
+                         "skeleton_cholesky_gflop": round(chol_gflop, 1),
+                         "cholesky_gflop_over_factor_ms": round(chol_gflop / f_ms, 2) if f_ms > 0 else None,
+                         "relres_max": float(rr_b.max()),
+                         "rel_diff_x_vs_hss": float(torch.linalg.norm(x_b - x_h) / torch.linalg.norm(x_h)),
+                         "logdet_abs_diff_vs_hss": abs(ld_b - ld_h)},
+                "hss_speedup_vs_blr2": round(t_blr2 / t_hss, 1)}
+    finally:
+        hss.hss_matrix_destroy(m)
 
 
 def mixed_exp_leg(hss, torch, np, ctx, steps, warmup, no_tune):
