@@ -104,7 +104,7 @@ typedef struct {
   double judge_factor;       /* 0 = 10 */
 } hss_construct_opts;
 
-/* Precision of the factorization (the north-star "precision" form; the paper
+/* Precision of the factorization (the mixed-precision form of the path; the paper
  * itself is FP64). Both leave FP64 factors, applied by the same FP64 solve.
  *  FP64: every step in FP64.
  *  FP32: the leaf stage's four contractions of the diagonal product (Eq. 7:

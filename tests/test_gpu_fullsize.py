@@ -160,7 +160,7 @@ def test_fullsize_sampled_sigma_vs_oracle(full, rep, level, idx):
 def test_fullsize_transform_is_orthogonal(full, node):
     # The full-basis QR of a node (Eq. 3) as stored for the solve: H = I - V T V^T
     # with V n x r and T r x r; its first r columns are the node's basis up to the
-    # signs Sg. Gate of the benchmark spec: |H^T H - I|_max <= 1e-13.
+    # signs Sg. Gate: |H^T H - I|_max <= 1e-13 (FP64 rounding of an orthogonal transform).
     torch, hss, ctx, m = full
     hss.hss_ulv_factor(ctx, m)
     r = W.rank  # fixed rank at every node but the root

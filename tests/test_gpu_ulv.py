@@ -98,6 +98,43 @@ def test_random_hss_shapes(ctx, torch_dev, levels, leaf, rank):
     factor_and_compare(ctx, torch_dev, h)
 
 
+@pytest.mark.parametrize("levels,leaf,rank", [(2, 256, 96), (3, 250, 90), (2, 512, 200), (5, 32, 13)])
+def test_every_tile_shape_gives_the_oracle_factorization(ctx, torch_dev, levels, leaf, rank):
+    # every GEMM batch forced to one tile shape in turn (rank 13 leaves ragged
+    # tiles and a partial K slice), FP64 against the oracle, and the mixed
+    # factorization + refinement with the FP32 products on two of the shapes
+    from paper_2311_00921_amd import hss
+
+    torch = torch_dev
+    d = synth.random_hss(levels, leaf, rank, seed=500 + levels * 7 + rank)
+    h = O.HSS(d["n"], d["levels"], d["ranges"], d["rank"], d["D"], d["U"], d["E"], d["S"])
+    F = O.ulv_factor(h)
+    b = synth.rhs_normal(h.n, 2, 17)
+    x_or = O.ulv_solve(h, F, b)
+    bd = torch.from_numpy(np.ascontiguousarray(b.T)).cuda().t()
+    m = hss.hss_import(ctx, oracle_to_dict(h))
+    try:
+        hss.hss_ulv_factor(ctx, m)
+        nb = len(hss.hss_gemm_variants(m))
+        for v in range(len(hss.GEMM_TILES)):
+            print(f"case tile {hss.GEMM_TILES[v]} n={h.n} rank={rank}", flush=True)
+            hss.hss_set_gemm_variants(ctx, m, [v] * nb)
+            hss.hss_ulv_factor(ctx, m)
+            x = hss.hss_ulv_solve(ctx, m, bd).cpu().numpy()
+            assert rel(x, x_or) <= 1e-10 and maxrel(x, x_or) <= 1e-10, (v, rel(x, x_or))
+            assert abs(hss.hss_logdet(ctx, m) - F.logdet) <= 1e-10 * (abs(F.logdet) + 1.0), v
+        hss.hss_ulv_factor(ctx, m, hss.HSS_P_FP32)
+        n32 = len(hss.hss_gemm_variants(m, hss.HSS_P_FP32))
+        for v in (0, len(hss.GEMM_TILES) - 1):
+            hss.hss_set_gemm_variants(ctx, m, [v] * n32, hss.HSS_P_FP32)
+            hss.hss_ulv_factor(ctx, m, hss.HSS_P_FP32)
+            x, it, rr, ok = hss.hss_ulv_solve_refined(ctx, m, bd, 1e-12, 20)
+            assert ok, (v, it, rr)
+            assert rel(x.cpu().numpy(), x_or) <= 1e-10, (v, rel(x.cpu().numpy(), x_or))
+    finally:
+        hss.hss_matrix_destroy(m)
+
+
 def test_multiple_rhs_ragged_chunk(ctx, torch_dev):
     d = synth.random_hss(3, 48, 10, seed=3)
     h = O.HSS(d["n"], d["levels"], d["ranges"], d["rank"], d["D"], d["U"], d["E"], d["S"])
