@@ -522,19 +522,24 @@ def sweep_leg(hss, torch, np, ctx, steps, warmup):
     """One-GPU scaling sweeps for the paper's linear-complexity and leaf-size
     claims (Sec. 5.4-5.5): the FP64 one-call factor + solve (autotuned tiles)
     of the Matern-3/2 workload (3-D uniform points, length 0.2, nugget 1e-6,
-    scaled construction, rank 96) for N = 4096 .. 262144 at leaf 256, and for
-    leaf 128 and 512 at N = 262144."""
+    scaled construction, rank 100) for N = 4096 .. 262144 at leaf 256, and for
+    leaf 128, 512 and 1024 at N = 262144 (leaf 1024 exceeds the 512-row block
+    limit and is reported as unsupported)."""
     import dataclasses
 
     import synth
 
-    base = synth.WORKLOADS["matern32_n262144"]
-    configs = [dataclasses.replace(base, name=f"matern32_n{n}", n=n) for n in
+    base = dataclasses.replace(synth.WORKLOADS["matern32_n262144"], rank=100)
+    configs = [dataclasses.replace(base, name=f"matern32_n{n}_r100", n=n) for n in
                (4096, 8192, 16384, 32768, 65536, 131072, 262144)]
-    configs += [dataclasses.replace(base, name=f"matern32_n262144_leaf{lf}", leaf=lf) for lf in (128, 512)]
+    configs += [dataclasses.replace(base, name=f"matern32_n262144_r100_leaf{lf}", leaf=lf) for lf in (128, 512, 1024)]
     out = []
     for w in configs:
         print(f"# sweep: {w.name} N={w.n} leaf={w.leaf}", file=sys.stderr, flush=True)
+        if w.leaf > 512:
+            out.append({"workload": w.name, "N": w.n, "leaf": w.leaf, "rank": w.rank,
+                        "error": "unsupported: leaf blocks above 512 rows"})
+            continue
         s = w.rank + w.oversample
         X = torch.from_numpy(w.points()).cuda()
         Om = torch.from_numpy(np.ascontiguousarray(w.omega(s).T)).cuda().t()
