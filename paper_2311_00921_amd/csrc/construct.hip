@@ -6,8 +6,9 @@
 // workloads) first scales each node's samples by the inverse Cholesky factor of
 // its diagonal block, which keeps the represented matrix SPD:
 //
-//   tree      recursive coordinate bisection (longest box side, ties -> lowest
-//             axis, order by (coordinate, index), left child = ceil(size/2))
+//   tree      recursive coordinate bisection on the device (tree.hip: longest box
+//             side, ties -> lowest axis, order by (coordinate, index), left child =
+//             ceil(size/2))
 //   leaves    D_i = K(X_i, X_i) + nugget I, Psi_i = chol(D_i)^{-T} Omega_i,
 //             Z = (A - blkdiag D) Psi  (one kernel-evaluating product over all pairs)
 //   level l   for each node p with diagonal block M_p and samples Z_p:
@@ -469,41 +470,6 @@ __global__ void k_copy_blocks(const double* __restrict__ src, const int64_t* __r
 // host side
 // ---------------------------------------------------------------------------
 
-// recursive coordinate bisection on the host (the points are copied once)
-static std::vector<int64_t> bisect(const std::vector<double>& P, int64_t n, int dim, int L,
-                                   std::vector<int64_t>& leaf_lo) {
-  std::vector<int64_t> perm(n);
-  std::iota(perm.begin(), perm.end(), 0);
-  std::vector<std::pair<int64_t, int64_t>> cur{{0, n}};
-  for (int l = 0; l < L; ++l) {
-    std::vector<std::pair<int64_t, int64_t>> nxt;
-    for (auto [lo, hi] : cur) {
-      double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300};
-      for (int64_t t = lo; t < hi; ++t)
-        for (int a = 0; a < dim; ++a) {
-          const double v = P[perm[t] * dim + a];
-          mn[a] = std::min(mn[a], v);
-          mx[a] = std::max(mx[a], v);
-        }
-      int axis = 0;
-      for (int a = 1; a < dim; ++a)
-        if (mx[a] - mn[a] > mx[axis] - mn[axis]) axis = a;
-      std::sort(perm.begin() + lo, perm.begin() + hi, [&](int64_t x, int64_t y) {
-        const double cx = P[x * dim + axis], cy = P[y * dim + axis];
-        return cx < cy || (cx == cy && x < y);
-      });
-      const int64_t mid = lo + (hi - lo + 1) / 2;
-      nxt.push_back({lo, mid});
-      nxt.push_back({mid, hi});
-    }
-    cur.swap(nxt);
-  }
-  leaf_lo.clear();
-  for (auto& pr : cur) leaf_lo.push_back(pr.first);
-  leaf_lo.push_back(n);
-  return perm;
-}
-
 struct DevBuf {
   double* p = nullptr;
   int64_t len = 0;
@@ -578,24 +544,19 @@ void launch_pchol_external(const NodeDesc* nodes, int first, int count, int nmax
 // (node k >= 1): log2 of the point count clipped at 13, bounding-box extents in
 // decreasing order over the kernel length, gap to the sibling's box over the
 // kernel length, log10 of the length, -log10 of the tolerance.
-static std::vector<float> node_features(const std::vector<double>& P, const std::vector<int64_t>& perm, int dim,
-                                        int L, const std::vector<int64_t>& leaf_lo, double length, double tol) {
+// The leaves' boxes come from the tree kernels (leafbox: 2^L x 6, lo then hi,
+// zero beyond dim); the boxes above are unions of their children's.
+static std::vector<float> node_features(const std::vector<double>& leafbox, int L, const std::vector<int64_t>& leaf_lo,
+                                        double length, double tol) {
   const int nn = (2 << L) - 1, nl = 1 << L;
   std::vector<double> lo((size_t)nn * 3, 0.0), hi((size_t)nn * 3, 0.0);
   std::vector<int64_t> np(nn, 0);
   for (int i = 0; i < nl; ++i) {
     const int k = nl - 1 + i;
     for (int d = 0; d < 3; ++d) {
-      lo[3 * k + d] = 1e300;
-      hi[3 * k + d] = -1e300;
+      lo[3 * k + d] = leafbox[(size_t)i * 6 + d];
+      hi[3 * k + d] = leafbox[(size_t)i * 6 + 3 + d];
     }
-    for (int64_t t = leaf_lo[i]; t < leaf_lo[i + 1]; ++t)
-      for (int d = 0; d < dim; ++d) {
-        const double v = P[(size_t)perm[t] * dim + d];
-        lo[3 * k + d] = std::min(lo[3 * k + d], v);
-        hi[3 * k + d] = std::max(hi[3 * k + d], v);
-      }
-    for (int d = dim; d < 3; ++d) lo[3 * k + d] = hi[3 * k + d] = 0.0;
     np[k] = leaf_lo[i + 1] - leaf_lo[i];
   }
   for (int k = nl - 2; k >= 0; --k) {
@@ -636,12 +597,8 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
   const int L = m->L;
   const bool plain = o.mode == HSS_COMPRESS_PLAIN;
   KParams kp{kern.kind, kern.length, kern.sigma2, kern.nugget, kern.alpha, kern.eps};
-  // ---- tree (host bisection of the points) ----
-  std::vector<double> P((size_t)N * dim);
-  HSS_HIP(hipMemcpyAsync(P.data(), d_points, sizeof(double) * N * dim, hipMemcpyDeviceToHost, st));
-  HSS_HIP(hipStreamSynchronize(st));
-  std::vector<int64_t> leaf_lo;
-  std::vector<int64_t> perm = bisect(P, N, dim, L, leaf_lo);
+  // ---- tree: node ranges from the sizes, the permutation on the device ----
+  const std::vector<int64_t> leaf_lo = tree_leaf_lo(N, L);
   const int nleaves = 1 << L;
   m->nnodes = (2 << L) - 1;
   m->nodes.assign(m->nnodes, NodeDesc{});
@@ -654,7 +611,10 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
   // provisional ranks: the leaf layout (D offsets) depends on the leaves only
   for (int k = 1; k < m->nnodes; ++k) m->nodes[k].r = 1;
   layout_representation(m);
-  HSS_HIP(hipMemcpyAsync(m->dperm, perm.data(), sizeof(int64_t) * N, hipMemcpyHostToDevice, st));
+  const bool want_boxes = sp.s_basis == 0;  // the rank model needs the leaves' boxes
+  DevBuf lbox;
+  lbox.ensure(want_boxes ? (int64_t)nleaves * 6 : 1);
+  build_tree(st, d_points, N, dim, L, m->dperm, want_boxes ? lbox.p : nullptr);
   DevBuf Xs;
   Xs.ensure(N * dim);
   hipLaunchKernelGGL(k_points_soa, dim3(1024), dim3(256), 0, st, d_points, (const int64_t*)m->dperm, N, dim, Xs.p);
@@ -674,7 +634,10 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
   kcap = std::min(kcap, 256);
   if (sp.s_basis == 0) {
     // sample count from the learned rank model: largest predicted node rank + 8
-    const std::vector<float> f = node_features(P, perm, dim, L, leaf_lo, kern.length > 0.0 ? kern.length : 1.0, o.tol);
+    std::vector<double> hb((size_t)nleaves * 6);
+    HSS_HIP(hipMemcpyAsync(hb.data(), lbox.p, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, st));
+    HSS_HIP(hipStreamSynchronize(st));
+    const std::vector<float> f = node_features(hb, L, leaf_lo, kern.length > 0.0 ? kern.length : 1.0, o.tol);
     const int64_t cntf = (int64_t)f.size() / 7;
     float* dF = (float*)dev_alloc(sizeof(float) * f.size());
     int32_t* dR = (int32_t*)dev_alloc(sizeof(int32_t) * cntf);
@@ -1159,13 +1122,19 @@ extern "C" hss_status hss_rank_features(hss_ctx_t ctx, const double* d_points, i
     *needed = cnt * 7;
     if (!h_out) return HSS_OK;
     HSS_CHECK(capacity >= cnt * 7, HSS_ERR_INVALID_ARGUMENT, "output too small");
-    std::vector<double> P((size_t)n * dim);
-    HSS_HIP(hipMemcpyAsync(P.data(), d_points, sizeof(double) * n * dim, hipMemcpyDeviceToHost, ctx->stream));
-    HSS_HIP(hipStreamSynchronize(ctx->stream));
-    std::vector<int64_t> leaf_lo;
-    std::vector<int64_t> perm = bisect(P, n, dim, L, leaf_lo);
     if (L == 0) return HSS_OK;
-    const std::vector<float> f = node_features(P, perm, dim, L, leaf_lo, length, tol);
+    CtxScope cs_(ctx);
+    const std::vector<int64_t> leaf_lo = tree_leaf_lo(n, L);
+    std::vector<double> hb((size_t)6 << L);
+    {
+      DevBuf perm, box;
+      perm.ensure(n);  // int64 entries, same size as doubles
+      box.ensure((int64_t)hb.size());
+      build_tree(ctx->stream, d_points, n, dim, L, (int64_t*)perm.p, box.p);
+      HSS_HIP(hipMemcpyAsync(hb.data(), box.p, sizeof(double) * hb.size(), hipMemcpyDeviceToHost, ctx->stream));
+      HSS_HIP(hipStreamSynchronize(ctx->stream));
+    }
+    const std::vector<float> f = node_features(hb, L, leaf_lo, length, tol);
     std::copy(f.begin(), f.end(), h_out);
     return HSS_OK;
   } catch (const hss::Error& e) {

@@ -336,6 +336,15 @@ void blr2_invalidate(hss_matrix_t m);
 void noalloc_init(int device);
 void matvec_fp64(hss_matrix_t m, const double* x, double* y, int64_t nrhs, int64_t ld);
 
+// tree.hip: node ranges of the bisection tree from the point count (leaf i
+// owns [leaf_lo[i], leaf_lo[i+1])), and the tree itself on the device: d_perm
+// (n entries) receives tree position -> caller's index, d_leafbox (nullable,
+// 2^L x 6: lo[3], hi[3], zero beyond dim) the leaves' bounding boxes.
+// Synchronizes the stream.
+std::vector<int64_t> tree_leaf_lo(int64_t n, int L);
+void build_tree(hipStream_t st, const double* d_points, int64_t n, int dim, int L, int64_t* d_perm,
+                double* d_leafbox);
+
 // construct.hip
 
 

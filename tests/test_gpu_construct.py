@@ -137,6 +137,44 @@ def test_construct_plain_matches_oracle_on_the_grid(env, kernel, length, nugget,
         hss.hss_matrix_destroy(m)
 
 
+def _tree_inputs():
+    neg = synth.points_uniform(3000, 3, 4) - 0.5
+    neg[::7, 0] = -0.0
+    neg[::11, 0] = 0.0
+    neg[::13, 1] = 0.0
+    return [
+        ("uniform3d", synth.points_uniform(20000, 3, 11), 64),
+        ("uniform2d_ragged", synth.points_uniform(3001, 2, 12), 40),
+        ("uniform1d", synth.points_uniform(777, 1, 13), 30),
+        ("grid_ties", synth.points_grid2d(16384), 256),
+        ("negative_zero", neg, 50),
+        ("duplicates", np.round(synth.points_uniform(6000, 3, 15) * 8) / 8, 37),
+        ("tiny", synth.points_uniform(5, 2, 16), 2),
+        ("one_leaf", synth.points_uniform(100, 3, 17), 128),
+        ("leaf512", synth.points_uniform(70000, 3, 18), 512),
+    ]
+
+
+@pytest.mark.parametrize("case", range(9))
+def test_tree_permutation_bit_exact(env, case):
+    # the GPU bisection (radix select per node, LDS sort at the last level)
+    # against the oracle's tree: equal coordinates (the grid, rounded points,
+    # -0.0 beside 0.0), 1-D and 2-D points, ragged and single-leaf trees
+    torch, hss, ctx = env
+    name, X, leaf = _tree_inputs()[case]
+    print(f"case tree {name} n={X.shape[0]} dim={X.shape[1]} leaf={leaf}", flush=True)
+    tree = O.build_tree(X, leaf)
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    Om = torch.from_numpy(np.ascontiguousarray(synth.test_matrix(X.shape[0], 9, 3000 + case).T)).cuda().t()
+    m = hss.hss_construct(ctx, Xd, "exponential", leaf, rank=1, omega=Om, length=0.2, nugget=1e-3)
+    try:
+        perm = torch.empty(X.shape[0], dtype=torch.int64, device="cuda")
+        hss.hss_get_permutation(ctx, m, perm)
+        assert np.array_equal(perm.cpu().numpy(), tree.perm)
+    finally:
+        hss.hss_matrix_destroy(m)
+
+
 def test_construct_adaptive_rank_matches_oracle(env):
     torch, hss, ctx, m, tree, h_or, h_gpu, p = build_both(env, 1024, 3, "exponential", 0.1, 0.0, 64, 0, 48,
                                                           tol=1e-3)
