@@ -86,9 +86,6 @@ def main():
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-rank ablation leg")
     ap.add_argument("--no-config2", action="store_true",
                     help="skip the 16-right-hand-side leg (HSS-ULV and BLR^2-ULV at N = 65536)")
-    ap.add_argument("--learned-workload", default="matern32_n262144",
-                    help="workload of the learned-rank ablation (matern32_n262144 with tol 1e-6 and cap 96, "
-                         "or exp3d_n1048576 with its tol 1e-8 and cap 128)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (for scaling hardware byte counters) and exit")
     ap.add_argument("--sweep", action="store_true",
@@ -377,7 +374,7 @@ def main():
     if not args.no_mixed:
         result["mixed_exp3d"] = mixed_exp_leg(hss, torch, np, ctx, args.steps, args.warmup, args.no_tune)
     if not args.no_learned:
-        result["learned_rank"] = learned_leg(hss, torch, np, ctx, args.learned_workload)
+        result["learned_rank"] = learned_leg(hss, torch, np, ctx)
     if not args.no_config2:
         result["config2"] = config2_leg(hss, torch, np, ctx, args.steps, args.warmup, args.no_tune)
 
@@ -657,16 +654,51 @@ def measured_traffic(label, workload, tile):
     return ent["hbm_bytes_per_launch"]
 
 
-def learned_leg(hss, torch, np, ctx, workload):
-    """Learned rank model: trained on the GPU on the oracle's rank labels, then
-    three ways of sizing the randomized samples of one construction compared:
-    model-presized, fixed conservative (cap + 8 samples) and adaptive doubling
-    from 16, all with the 8-column probe judge."""
+def gpu_rank_labels(hss, torch, np, ctx, problems, cap=128, samples=136):
+    """(features, ranks) of every non-root node of the plain adaptive
+    construction (Eq. 2 with |R_jj| > tol |R_00|, capped) of each problem: the
+    labels the rank model learns, produced by the library's own construction
+    (its ranks are pinned to the oracle's pivoted QR in the construction tests)."""
     import synth
 
-    d = np.load(os.path.join(ROOT, "tests", "golden", "rank_labels.npz"))
-    F = torch.from_numpy(d["features"]).cuda()
-    ranks = d["ranks"]
+    feats, ranks = [], []
+    cache = {}
+    for (n, geo, seed, leaf, tol) in problems:
+        key = (n, geo, seed)
+        if key not in cache:
+            cache.clear()
+            X = synth.points_grid2d(n) if geo == "grid2d" else synth.points_uniform(n, 2, 1200 + seed)
+            Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+            Om = torch.from_numpy(np.ascontiguousarray(synth.test_matrix(n, samples, 3200 + seed).T)).cuda().t()
+            cache[key] = (Xd, Om)
+        Xd, Om = cache[key]
+        m = hss.hss_construct(ctx, Xd, "laplace2d", leaf, tol=tol, max_rank=cap, omega=Om, length=1.0, eps=1e-9,
+                              mode="plain")
+        try:
+            rk = hss.hss_get_ranks(m)[1:]
+        finally:
+            hss.hss_matrix_destroy(m)
+        f = hss.hss_rank_features(ctx, Xd, leaf, 1.0, tol).reshape(-1, 7)
+        assert f.shape[0] == rk.shape[0]
+        feats.append(f)
+        ranks.append(rk)
+    return np.concatenate(feats), np.concatenate(ranks)
+
+
+def learned_leg(hss, torch, np, ctx):
+    """Learned rank model (form 4): trained on the GPU on about 1e5 labelled
+    nodes of Laplace-2D constructions whose ranks vary below the cap (plain
+    construction, tolerances 3e-2 .. 1e-8), then three ways of sizing the
+    random samples of a held-out construction -- the 256 x 256 grid of Table 2,
+    leaf 256, cap 128, at two tolerances -- compared: model-presized, fixed
+    conservative (cap + 8 samples) and adaptive doubling from 16, all with the
+    8-column probe judge."""
+    import synth
+
+    t0 = time.perf_counter()
+    feats, ranks = gpu_rank_labels(hss, torch, np, ctx, synth.rank_label_problems())
+    label_s = time.perf_counter() - t0
+    F = torch.from_numpy(feats).cuda()
     T = torch.from_numpy(np.log2(1.0 + ranks).astype(np.float32)).cuda()
     mlp = hss.hss_rankmlp_create(ctx)
     init = synth.mlp_init((7, 128, 128, 128, 1), seed=5000)
@@ -675,63 +707,62 @@ def learned_leg(hss, torch, np, ctx, workload):
     order = torch.from_numpy(synth.minibatch_order(len(ranks), epochs, seed=5100)).cuda()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    losses = hss.hss_rankmlp_train(ctx, mlp, F, T, order, 256, lr=1e-3, tau=0.9, record_losses=False)
+    hss.hss_rankmlp_train(ctx, mlp, F, T, order, 256, lr=1e-3, tau=0.9, record_losses=False)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     pred = hss.hss_rankmlp_predict(ctx, mlp, F, 128).cpu().numpy()
-    out = {"train": {"samples": int(len(ranks)), "epochs": epochs, "batch": 256, "steps": int(len(order) // 256 + 1),
+    out = {"labels": {"kernel": "laplace2d", "construction": "plain", "problems": len(synth.rank_label_problems()),
+                      "nodes": int(len(ranks)), "generate_s": round(label_s, 2),
+                      "rank_quartiles": [int(v) for v in np.percentile(ranks, [25, 50, 75])],
+                      "at_cap": float(np.mean(ranks >= 128))},
+           "train": {"epochs": epochs, "batch": 256, "steps": int((len(order) + 255) // 256),
                      "train_s": round(train_s, 3), "coverage_pred_ge_label": float(np.mean(pred >= ranks)),
                      "mean_abs_rank_error": float(np.mean(np.abs(pred - ranks)))}}
-    del losses
-    w = synth.WORKLOADS[workload]
-    if workload == "matern32_n262144":
-        tol, cap = 1e-6, 96
-    else:
-        tol, cap = w.tol, 128
+    cap = 128
     s = cap + 8 + 8
+    n = 65536
+    w = synth.Workload("laplace2d_grid_n65536", n, 2, "laplace2d", 1.0, 0.0, 256, 0, geometry="grid2d",
+                       extra={"eps": 1e-9, "alpha": 1.0}, seed_k=7)
     X = torch.from_numpy(w.points()).cuda()
     Om = torch.from_numpy(np.ascontiguousarray(w.omega(s).T)).cuda().t()
     b = torch.from_numpy(np.ascontiguousarray(w.rhs()[:, 0])).cuda()
-    rows = torch.from_numpy(np.random.default_rng(77).choice(w.n, 256, replace=False)).cuda()
-    y_exact = None
-    modes = (("model", dict(rank_model=mlp)), ("fixed", dict(sample_start=cap + 8)),
-             ("doubling_from_16", dict(sample_start=16)))
-    out["workload"] = {"name": w.name, "N": w.n, "kernel": w.kernel, "length": w.length, "tol": tol, "cap": cap,
-                       "s_available": s}
-    for name, kw in modes:
-        print(f"# learned-rank leg: {name}", file=sys.stderr, flush=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        m = hss.hss_construct(ctx, X, w.kernel, w.leaf, tol=tol, max_rank=cap, omega=Om, length=w.length,
-                              nugget=w.nugget, **kw)
-        torch.cuda.synchronize()
-        cs = time.perf_counter() - t0
-        st = hss.hss_get_construct_stats(m)
-        rec = {"construct_s": round(cs, 3), "attempts": st.attempts, "samples": st.samples, "probes": st.probes,
-               "judge_failures": st.judge_failures, "predicted_max": st.predicted_max, "max_rank": st.max_rank,
-               "sample_buffer_bytes": int(st.sample_bytes)}
-        try:
-            hss.hss_ulv_factor(ctx, m, hss.HSS_P_FP64)
-            x = hss.hss_ulv_solve(ctx, m, b)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            for _ in range(3):
-                hss.hss_ulv_factor(ctx, m, hss.HSS_P_FP64)
-                x = hss.hss_ulv_solve(ctx, m, b)
-            torch.cuda.synchronize()
-            rec["factor_plus_solve_s"] = round((time.perf_counter() - t0) / 3, 6)
-            r = b - hss.hss_matvec(ctx, m, x)
-            rec["relres"] = float(torch.linalg.norm(r) / torch.linalg.norm(b))
-            # compression error on 256 sampled rows of A x (Eq. 18), exact rows by direct kernel evaluation
-            if y_exact is None:
-                y_exact = exact_rows(torch, X, b, rows, w)
-            y = hss.hss_matvec(ctx, m, b)[rows]
-            rec["construction_error_rows"] = float(torch.linalg.norm(y - y_exact) / torch.linalg.norm(y_exact))
-        except hss.HSSError as e:
-            rec["error"] = str(e)
-        hss.hss_matrix_destroy(m)
-        out[name] = rec
-        print(f"# {name}: {rec}", file=sys.stderr, flush=True)
+    rows = torch.from_numpy(np.random.default_rng(77).choice(n, 256, replace=False)).cuda()
+    y_exact = exact_rows(torch, X, b, rows, w)
+    out["heldout"] = {"name": w.name, "N": n, "leaf": w.leaf, "cap": cap, "s_available": s}
+    for tol in (1e-2, 1e-3):
+        res = {}
+        for name, kw in (("model", dict(rank_model=mlp)), ("fixed", dict(sample_start=cap + 8)),
+                         ("doubling_from_16", dict(sample_start=16))):
+            print(f"# learned-rank leg: tol {tol:g} {name}", file=sys.stderr, flush=True)
+            ts = []
+            m = None
+            for rep in range(3):
+                if m is not None:
+                    hss.hss_matrix_destroy(m)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                m = hss.hss_construct(ctx, X, w.kernel, w.leaf, tol=tol, max_rank=cap, omega=Om, length=1.0,
+                                      eps=1e-9, mode="plain", **kw)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            st = hss.hss_get_construct_stats(m)
+            rec = {"construct_s": round(float(np.median(ts)), 4), "attempts": st.attempts, "samples": st.samples,
+                   "probes": st.probes, "judge_failures": st.judge_failures, "predicted_max": st.predicted_max,
+                   "max_rank": st.max_rank, "sample_buffer_bytes": int(st.sample_bytes)}
+            try:
+                y = hss.hss_matvec(ctx, m, b)[rows]
+                rec["construction_error_rows"] = float(torch.linalg.norm(y - y_exact) / torch.linalg.norm(y_exact))
+                x = hss.hss_ulv_factor_solve(ctx, m, b)
+                rec["relres"] = float(torch.linalg.norm(b - hss.hss_matvec(ctx, m, x)) / torch.linalg.norm(b))
+            except hss.HSSError as e:
+                rec["error"] = str(e)
+            hss.hss_matrix_destroy(m)
+            res[name] = rec
+            print(f"# {name}: {rec}", file=sys.stderr, flush=True)
+        res["model_vs_fixed"] = {
+            "construct_time_ratio": round(res["model"]["construct_s"] / res["fixed"]["construct_s"], 3),
+            "sample_bytes_ratio": round(res["model"]["sample_buffer_bytes"] / res["fixed"]["sample_buffer_bytes"], 3)}
+        out[f"tol_{tol:g}"] = res
     hss.hss_rankmlp_destroy(mlp)
     return out
 

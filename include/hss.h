@@ -366,6 +366,13 @@ hss_status hss_blr2_logdet(hss_ctx_t ctx, hss_matrix_t m, double* h_out);
 hss_status hss_blr2_stats(hss_matrix_t m, int64_t* skeleton_rows, float* factor_ms);
 
 hss_status hss_get_info(hss_matrix_t m, hss_info* out);
+/* The basis rank of every node (Sec. 2: columns of U at a leaf, of E above;
+ * 0 at a root), into h_out (host, nullable for a size query; capacity
+ * entries), in node order: heap order for a constructed or imported single
+ * matrix (node 0 the root, node k with children 2k+1 and 2k+2). *needed
+ * receives the node count. Errors: INVALID_ARGUMENT for NULL or a short
+ * buffer. */
+hss_status hss_get_ranks(hss_matrix_t m, int32_t* h_out, int64_t capacity, int64_t* needed);
 /* N entries: tree position -> caller's point index. */
 hss_status hss_get_permutation(hss_ctx_t ctx, hss_matrix_t m, int64_t* d_perm);
 

@@ -714,6 +714,16 @@ hss_status hss_get_info(hss_matrix_t m, hss_info* o) {
   HSS_API_END
 }
 
+hss_status hss_get_ranks(hss_matrix_t m, int32_t* h_out, int64_t capacity, int64_t* needed) {
+  HSS_API_BEGIN
+  HSS_CHECK(m && needed, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
+  *needed = m->nnodes;
+  if (!h_out) return HSS_OK;
+  HSS_CHECK(capacity >= m->nnodes, HSS_ERR_INVALID_ARGUMENT, "output too small");
+  for (int k = 0; k < m->nnodes; ++k) h_out[k] = m->nodes[k].r;
+  HSS_API_END
+}
+
 hss_status hss_get_permutation(hss_ctx_t ctx, hss_matrix_t m, int64_t* d_perm) {
   HSS_API_BEGIN
   hss::CtxScope cs_(ctx);

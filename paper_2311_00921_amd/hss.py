@@ -121,6 +121,7 @@ SIGNATURES = {
     "hss_blr2_logdet": (C.c_int, [_P, _P, C.POINTER(C.c_double)]),
     "hss_blr2_stats": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_float)]),
     "hss_get_info": (C.c_int, [_P, C.POINTER(hss_info)]),
+    "hss_get_ranks": (C.c_int, [_P, C.POINTER(C.c_int32), C.c_int64, C.POINTER(C.c_int64)]),
     "hss_get_permutation": (C.c_int, [_P, _P, _P]),
     "hss_debug_node_block": (C.c_int, [_P, _P, C.c_int32, C.c_int32, C.POINTER(C.c_double), C.c_int64]),
     "hss_profile_enable": (C.c_int, [_P, C.c_int32]),
@@ -519,6 +520,16 @@ def hss_get_info(m) -> hss_info:
     info = hss_info()
     _check(load().hss_get_info(m, C.byref(info)), "hss_get_info")
     return info
+
+
+def hss_get_ranks(m) -> np.ndarray:
+    """Basis rank of every node (heap order for a single matrix; 0 at the root)."""
+    lib = load()
+    need = C.c_int64(0)
+    _check(lib.hss_get_ranks(m, None, 0, C.byref(need)), "hss_get_ranks")
+    out = np.zeros(max(1, need.value), dtype=np.int32)
+    _check(lib.hss_get_ranks(m, out.ctypes.data_as(C.POINTER(C.c_int32)), out.size, C.byref(need)), "hss_get_ranks")
+    return out[:need.value]
 
 
 def hss_get_permutation(ctx, m, out):

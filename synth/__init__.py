@@ -107,6 +107,25 @@ WORKLOADS = {
 }
 
 
+LAPLACE_TOLS = (3e-2, 1e-2, 3e-3, 1e-3, 3e-4, 1e-4, 1e-6, 1e-8)
+
+
+def rank_label_problems():
+    """Rank-label problems of the Laplace-2D kernel (Table 3, eps 1e-9) for the
+    learned rank model, as (n, geometry, seed, leaf, tol): the paper's grid at
+    128^2 and 512^2 points and uniform points in the unit square (seed 1200+k)
+    at four sizes, leaf 128 and 256, eight tolerances. Test matrices use seed
+    3200+k (k = 0 for the grids). The 256^2 grid is kept out, for held-out
+    checks."""
+    probs = []
+    for n, geo, seed in ((16384, "grid2d", 0), (262144, "grid2d", 0), (16384, "uniform", 20), (32768, "uniform", 21),
+                         (65536, "uniform", 22), (131072, "uniform", 23)):
+        for leaf in (128, 256):
+            for tol in LAPLACE_TOLS:
+                probs.append((n, geo, seed, leaf, tol))
+    return probs
+
+
 def random_hss(n_leaves_log2: int, leaf: int, rank: int, seed: int, coupling: float = 0.3,
                margin: float = 1.0):
     """A random HSS matrix with orthonormal bases, for factorization tests that

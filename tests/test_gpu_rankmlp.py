@@ -199,6 +199,76 @@ def test_model_sized_construction_equals_fixed_samples(env, trained):
         hss.hss_matrix_destroy(A)
 
 
+def _laplace_labels(torch, hss, ctx):
+    """Rank labels on the GPU: the plain adaptive construction (cap 128, 136
+    samples) of every Laplace-2D problem of synth.rank_label_problems()."""
+    feats, ranks = [], []
+    cache = {}
+    for (n, geo, seed, leaf, tol) in synth.rank_label_problems():
+        if (n, geo, seed) not in cache:
+            cache.clear()
+            X = synth.points_grid2d(n) if geo == "grid2d" else synth.points_uniform(n, 2, 1200 + seed)
+            Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+            om = torch.from_numpy(np.ascontiguousarray(synth.test_matrix(n, 136, 3200 + seed).T)).cuda().t()
+            cache[(n, geo, seed)] = (Xd, om)
+        Xd, om = cache[(n, geo, seed)]
+        A = hss.hss_construct(ctx, Xd, "laplace2d", leaf, tol=tol, max_rank=128, omega=om, length=1.0, eps=1e-9,
+                              mode="plain")
+        try:
+            rk = hss.hss_get_ranks(A)[1:]
+        finally:
+            hss.hss_matrix_destroy(A)
+        f = hss.hss_rank_features(ctx, Xd, leaf, 1.0, tol).reshape(-1, 7)
+        assert f.shape[0] == rk.shape[0]
+        feats.append(f)
+        ranks.append(rk)
+    return np.concatenate(feats), np.concatenate(ranks)
+
+
+def test_model_sizing_saves_samples_where_ranks_vary(env):
+    # Form 4's purpose: on a kernel whose ranks stay below the cap, the model
+    # presizes the random samples of a construction it has not seen (the
+    # 256^2 grid, leaf 256, tol 1e-3) with fewer columns than the fixed
+    # cap + 8, in one attempt, with the judge passing as it does for the fixed
+    # sizing and the same accuracy of the constructed matrix.
+    torch, hss, ctx = env
+    print("case laplace-2d labels", flush=True)
+    feats, ranks = _laplace_labels(torch, hss, ctx)
+    assert len(ranks) > 90000 and np.median(ranks) < 64
+    F = torch.from_numpy(feats).cuda()
+    T = torch.from_numpy(np.log2(1.0 + ranks).astype(np.float32)).cuda()
+    mlp = hss.hss_rankmlp_create(ctx)
+    try:
+        hss.hss_rankmlp_set_weights(ctx, mlp, synth.mlp_init((7, 128, 128, 128, 1), seed=5000))
+        order = torch.from_numpy(synth.minibatch_order(len(ranks), 8, seed=5100)).cuda()
+        hss.hss_rankmlp_train(ctx, mlp, F, T, order, 256, lr=1e-3, tau=0.9, record_losses=False)
+        n, cap, tol = 65536, 128, 1e-3
+        X = torch.from_numpy(synth.points_grid2d(n)).cuda()
+        om = torch.from_numpy(np.ascontiguousarray(synth.test_matrix(n, cap + 16, 3007).T)).cuda().t()
+        b = torch.from_numpy(synth.rhs_normal(n, 1, 2007)[:, 0].copy()).cuda()
+        out = {}
+        for name, kw in (("model", dict(rank_model=mlp)), ("fixed", dict(sample_start=cap + 8))):
+            print(f"case held-out grid n={n} tol={tol} sizing={name}", flush=True)
+            A = hss.hss_construct(ctx, X, "laplace2d", 256, tol=tol, max_rank=cap, omega=om, length=1.0, eps=1e-9,
+                                  mode="plain", **kw)
+            try:
+                st = hss.hss_get_construct_stats(A)
+                x = hss.hss_ulv_factor_solve(ctx, A, b)
+                rr = float(torch.linalg.norm(b - hss.hss_matvec(ctx, A, x)) / torch.linalg.norm(b))
+                out[name] = (st.samples, st.sample_bytes, st.attempts, st.judge_failures, st.max_rank, rr)
+            finally:
+                hss.hss_matrix_destroy(A)
+        print(f"model {out['model']} fixed {out['fixed']}", flush=True)
+        ms, mb, ma, mj, mr, mrr = out["model"]
+        fs, fb, fa, fj, fr, frr = out["fixed"]
+        assert ma == 1 and mj == 0 and fj == 0
+        assert ms < fs and mb < fb
+        assert mr >= 0.8 * fr  # the fewer samples still find the ranks the tolerance asks for
+        assert mrr <= 1e-8 and frr <= 1e-8
+    finally:
+        hss.hss_rankmlp_destroy(mlp)
+
+
 def test_adaptive_doubling_restarts_until_the_judge_passes(env):
     torch, hss, ctx = env
     n, leaf = 4096, 128
