@@ -75,6 +75,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="matern32_n262144")
+    ap.add_argument("--rank", type=int, default=0, help="override the workload's fixed rank (profiling runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 64-system batched leg")
     ap.add_argument("--no-tune", action="store_true", help="skip autotuning and graph replay")
@@ -127,6 +128,10 @@ def main():
         hss.hss_ctx_destroy(ctx)
         return
     w = synth.WORKLOADS[args.workload]
+    if args.rank:
+        import dataclasses
+
+        w = dataclasses.replace(w, name=f"{w.name}_r{args.rank}", rank=args.rank)
     s = (w.rank if w.rank > 0 else 128) + w.oversample
     X = torch.from_numpy(w.points()).cuda()
     Om = torch.from_numpy(np.ascontiguousarray(w.omega(s).T)).cuda().t()

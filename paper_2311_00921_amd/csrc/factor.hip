@@ -105,149 +105,6 @@ __device__ __forceinline__ void stage_frame(double (*X)[RM + kLdsPad], const T* 
 }
 
 // ---------------------------------------------------------------------------
-// Householder reconstruction of an orthonormal basis B (n x r) -> V, T, Sg.
-// With Sg chosen during the LU, B - [Sg; 0] = V U_lu where V is unit lower
-// trapezoidal. The LU only needs the top r x r block (rows below follow from
-// V_2 = B_2 U_1^{-1}), and T follows from T^{-1} = striu(V^T V) + diag(V^T V)/2.
-//   k_lu_top       LU of the top block in LDS: V_1 -> V, U_1 -> T buffer, Sg
-//   k_tri_inv      inverse of an upper triangular r x r matrix in LDS
-//   (GEMMs)        V_2 = B_2 U_1^{-1};  G = V^T V
-//   k_tri_inv      T = (striu(G) + diag(G)/2)^{-1}
-// ---------------------------------------------------------------------------
-
-template <typename T, int RMAX>
-__global__ __launch_bounds__(256) void k_lu_top(const NodeDesc* __restrict__ nodes, int first,
-                                                const T* __restrict__ Bbase, T* __restrict__ Vbase,
-                                                T* __restrict__ Ubase, T* __restrict__ Sgbase) {
-  const NodeDesc nd = nodes[first + blockIdx.x];
-  const int n = nd.n, r = nd.r;
-  if (r == 0) return;
-  const T* B = Bbase + nd.offB;
-  T* V = Vbase + nd.offV;
-  T* U = Ubase + nd.offT;
-  T* Sg = Sgbase + nd.offSg;
-  __shared__ double X[RMAX][RMAX + 1];
-  __shared__ double sg[RMAX];
-  const int tid = threadIdx.x;
-  for (int e = tid; e < r * r; e += 256) {
-    const int i = e % r, c = e / r;
-    X[i][c] = (double)B[i + (int64_t)c * n];
-  }
-  __syncthreads();
-  const int tx = tid & 15, ty = tid >> 4;  // 16 x 16 thread grid over the trailing block
-  for (int j = 0; j < r; ++j) {
-    if (tid == 0) {
-      const double u = X[j][j];
-      const double s = (u >= 0.0) ? -1.0 : 1.0;
-      X[j][j] = u - s;
-      sg[j] = s;
-    }
-    __syncthreads();
-    const double pinv = 1.0 / X[j][j];
-    for (int i = j + 1 + tid; i < r; i += 256) X[i][j] *= pinv;
-    __syncthreads();
-    for (int i = j + 1 + tx; i < r; i += 16) {
-      const double l = X[i][j];
-      for (int c = j + 1 + ty; c < r; c += 16) X[i][c] -= l * X[j][c];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < r * r; e += 256) {
-    const int i = e % r, c = e / r;
-    V[i + (int64_t)c * n] = (T)(c < i ? X[i][c] : (c == i ? 1.0 : 0.0));
-    U[e] = (T)(c >= i ? X[i][c] : 0.0);
-  }
-  for (int c = tid; c < r; c += 256) Sg[c] = (T)sg[c];
-}
-
-// Inverse of an upper triangular r x r matrix (column-major, ld r), blocked in
-// 16 x 16 tiles in LDS (padded to RMAX with the identity): the diagonal tiles are
-// inverted independently, then block rows are finished from the bottom up with
-// X_IJ = -X_II sum_{K=I+1..J} G_IK X_KJ on the matrix cores (FP64 16x16x4).
-// mode 0: the input is the triangle; mode 1: the input is a Gram matrix G and the
-// triangle is striu(G) + diag(G)/2. Selectors: 0 = T slot, 1/2 = first/second half of X.
-template <typename T, int RMAX>
-__global__ __launch_bounds__(256) void k_tri_inv(const NodeDesc* __restrict__ nodes, int first,
-                                                 const T* __restrict__ in, int in_sel, T* __restrict__ out,
-                                                 int out_sel, int mode) {
-  constexpr int NB = RMAX / 16;
-  const NodeDesc nd = nodes[first + blockIdx.x];
-  const int r = nd.r;
-  if (r == 0) return;
-  const int64_t rr = (int64_t)r * r;
-  const T* A = in + (in_sel == 0 ? nd.offT : nd.offX + (in_sel == 2 ? rr : 0));
-  T* Xo = out + (out_sel == 0 ? nd.offT : nd.offX + (out_sel == 2 ? rr : 0));
-  __shared__ double X[RMAX][RMAX + 1];
-  __shared__ double P[NB][16][17];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int e = tid; e < RMAX * RMAX; e += 256) {
-    const int i = e % RMAX, c = e / RMAX;
-    double v = 0.0;
-    if (i < r && c < r) {
-      if (i < c) v = (double)A[i + (int64_t)c * r];
-      else if (i == c) v = mode ? 0.5 * (double)A[i + (int64_t)c * r] : (double)A[i + (int64_t)c * r];
-    } else if (i == c) {
-      v = 1.0;
-    }
-    X[i][c] = v;
-  }
-  __syncthreads();
-  // diagonal tiles: thread (b, c) computes column c of inv(G_bb) by back substitution
-  double x[16];
-  const int b = tid >> 4, cc = tid & 15;
-  if (b < NB) {
-    const int o = b * 16;
-#pragma unroll
-    for (int i = 15; i >= 0; --i) {
-      double acc = 0.0;
-#pragma unroll
-      for (int k = i + 1; k < 16; ++k) acc += X[o + i][o + k] * x[k];
-      x[i] = (i == cc) ? 1.0 / X[o + i][o + i] : (i < cc ? -acc / X[o + i][o + i] : 0.0);
-    }
-  }
-  __syncthreads();
-  if (b < NB) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) X[b * 16 + i][b * 16 + cc] = x[i];
-  }
-  __syncthreads();
-  for (int I = NB - 2; I >= 0; --I) {
-    // P_J = sum_{K=I+1..J} G_IK X_KJ for J > I
-    for (int J = I + 1 + wid; J < NB; J += 4) {
-      v4d acc = {0.0, 0.0, 0.0, 0.0};
-      for (int K = I + 1; K <= J; ++K) {
-#pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-          const double a = X[I * 16 + (lane & 15)][K * 16 + kk + (lane >> 4)];
-          const double bb = X[K * 16 + kk + (lane >> 4)][J * 16 + (lane & 15)];
-          acc = mfma16x(a, bb, acc);
-        }
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) P[J][mfma_out_row(0.0, lane, v)][lane & 15] = acc[v];
-    }
-    __syncthreads();
-    // X_IJ = -X_II P_J
-    for (int J = I + 1 + wid; J < NB; J += 4) {
-      v4d acc = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int kk = 0; kk < 16; kk += 4) {
-        const double a = X[I * 16 + (lane & 15)][I * 16 + kk + (lane >> 4)];
-        const double bb = P[J][kk + (lane >> 4)][lane & 15];
-        acc = mfma16x(a, bb, acc);
-      }
-#pragma unroll
-      for (int v = 0; v < 4; ++v) X[I * 16 + mfma_out_row(0.0, lane, v)][J * 16 + (lane & 15)] = -acc[v];
-    }
-    __syncthreads();
-  }
-  for (int e = tid; e < r * r; e += 256) {
-    const int i = e % r, c = e / r;
-    Xo[e] = (T)(i <= c ? X[i][c] : 0.0);
-  }
-}
-
-// ---------------------------------------------------------------------------
 // Basis QR for ranks above 128 (one workgroup per node, in global memory): the
 // Householder QR of the orthonormal basis B (n x r), H_j = I - tau_j v_j v_j^T
 // with v_j unit lower trapezoidal, accumulated as H = H_1 ... H_r = I - V T V^T
@@ -347,7 +204,11 @@ __global__ __launch_bounds__(256) void k_house_basis(const NodeDesc* __restrict_
 }
 
 // ---------------------------------------------------------------------------
-// Fused basis QR for r <= RM <= 96 (one workgroup per node, everything in LDS):
+// Householder reconstruction of an orthonormal basis B (n x r) -> V, T, Sg.
+// With Sg chosen during the LU, B - [Sg; 0] = V U_lu where V is unit lower
+// trapezoidal. The LU only needs the top r x r block (rows below follow from
+// V_2 = B_2 U_1^{-1}), and T = -U_1 Sg L_1^{-T}.
+// Fused basis QR for r <= RM <= 128 (one workgroup per node, everything in LDS):
 //   blocked LU without pivoting of the top r x r block of B - [Sg; 0]
 //   (16-column panels factored by one wave, U_12 by a unit-lower solve per
 //   column, trailing update on the matrix cores), then U_1^{-1} and L_1^{-1}
@@ -1503,40 +1364,6 @@ __global__ void k_sum_logdet(const double* __restrict__ part, int count, double*
 // host side
 // ---------------------------------------------------------------------------
 
-template <typename T>
-static void launch_lu_top(const hss_matrix_t m, const LevelPlan& lp, const T* B, T* V, T* Ubuf, T* Sg,
-                          hipStream_t s) {
-  dim3 grid(lp.count), block(256);
-  const int r = lp.rmax;
-  if (r <= 32)
-    hipLaunchKernelGGL((k_lu_top<T, 32>), grid, block, 0, s, m->dnodes, lp.first, B, V, Ubuf, Sg);
-  else if (r <= 64)
-    hipLaunchKernelGGL((k_lu_top<T, 64>), grid, block, 0, s, m->dnodes, lp.first, B, V, Ubuf, Sg);
-  else if (r <= 96)
-    hipLaunchKernelGGL((k_lu_top<T, 96>), grid, block, 0, s, m->dnodes, lp.first, B, V, Ubuf, Sg);
-  else if (r <= 128)
-    hipLaunchKernelGGL((k_lu_top<T, 128>), grid, block, 0, s, m->dnodes, lp.first, B, V, Ubuf, Sg);
-  else
-    HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "basis rank above 128");
-  HSS_HIP(hipGetLastError());
-}
-
-template <typename T>
-static void launch_tri_inv(const hss_matrix_t m, const LevelPlan& lp, const T* in, int in_sel, T* out, int out_sel,
-                           int mode, hipStream_t s) {
-  dim3 grid(lp.count), block(256);
-  const int r = lp.rmax;
-#define TINV(RM) \
-  hipLaunchKernelGGL((k_tri_inv<T, RM>), grid, block, 0, s, m->dnodes, lp.first, in, in_sel, out, out_sel, mode)
-  if (r <= 32) TINV(32);
-  else if (r <= 64) TINV(64);
-  else if (r <= 96) TINV(96);
-  else if (r <= 128) TINV(128);
-  else HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "basis rank above 128");
-#undef TINV
-  HSS_HIP(hipGetLastError());
-}
-
 // Narrow launches (a few blocks, e.g. the roots) get 512 threads per block:
 // their time is the per-block chain, not the device throughput.
 template <typename T>
@@ -1563,7 +1390,7 @@ static void launch_pchol(const hss_matrix_t m, int first, int count, int nmax, T
 // L_RR by the right-looking sweep restricted to the R block, then L_SR and
 // Sigma from LDS.
 template <typename T>
-static void launch_pchol_split(const hss_matrix_t m, int first, int count, T* F, T* Msink, const T* Sg,
+static void launch_pchol_split(const hss_matrix_t m, int first, int count, int rmax, T* F, T* Msink, const T* Sg,
                                hipStream_t s, hss_ctx_t cx, int level) {
   {
     Prof pf(cx, "pchol_RR", level);
@@ -1572,8 +1399,19 @@ static void launch_pchol_split(const hss_matrix_t m, int first, int count, T* F,
     HSS_HIP(hipGetLastError());
   }
   Prof pf(cx, "sr_schur", level);
-  hipLaunchKernelGGL((k_sr_schur<T, 96, 160>), dim3(count), dim3(512), 0, s, m->dnodes, first, F, Msink, Sg);
+  // the S-row frame (RMAX x MMAX doubles in LDS): r <= 96 with m <= 160, or
+  // r <= 128 with m <= 128 (split_fits)
+  if (rmax <= 96)
+    hipLaunchKernelGGL((k_sr_schur<T, 96, 160>), dim3(count), dim3(512), 0, s, m->dnodes, first, F, Msink, Sg);
+  else
+    hipLaunchKernelGGL((k_sr_schur<T, 128, 128>), dim3(count), dim3(512), 0, s, m->dnodes, first, F, Msink, Sg);
   HSS_HIP(hipGetLastError());
+}
+
+// Whether the partial Cholesky of non-root nodes of these extents runs as the
+// R-block LDS Cholesky followed by the S-row kernel.
+static bool split_fits(int rmax, int mmax, int nmax) {
+  return nmax <= 256 && ((rmax <= 96 && mmax <= 160) || (rmax <= 128 && mmax <= 128));
 }
 
 // Full Cholesky of a batch of blocks (NodeDesc n = m = block size, offF = offset).
@@ -1600,9 +1438,11 @@ struct FBufs {
 };
 
 // The basis QR of a node depends on its basis only, not on the factorization
-// below it: when every node above the leaves has r <= 96 (the fused kernel),
-// their QRs run in one launch on a second stream, concurrently with the leaf
-// stage. Returns the contiguous node range [lo, hi) of the stages above the leaves.
+// below it: when every node above the leaves has r <= 128, their QRs run on a
+// second stream, concurrently with the leaf stage, each step in one launch over
+// all of them (the fused kernel for r <= 96, the LU / inverse / GEMM sequence
+// up to 128). Returns the contiguous node range [lo, hi) of the stages above
+// the leaves.
 static bool basis_hoisted(hss_matrix_t m, int& lo, int& hi) {
   if (m->stages.size() < 2) return false;
   const LevelPlan& l0 = m->stages[0];
@@ -1616,7 +1456,7 @@ static bool basis_hoisted(hss_matrix_t m, int& lo, int& hi) {
   }
   if (hi - lo < 1 || hi - lo > 65535) return false;
   for (int k = lo; k < hi; ++k)
-    if (m->nodes[k].r > 96) return false;
+    if (m->nodes[k].r > 128) return false;
   return true;
 }
 
@@ -1645,7 +1485,7 @@ static std::vector<std::vector<GemmBatch>> build_gemm_plan(hss_matrix_t m, const
       T* F = b.F + nd.offF;
       const T* Bn = b.B + nd.offB;
       steps[0].host.push_back({Bn + r, X2, nullptr, V + r, n - r, r, r, n, r, 0, n, 0, 0});  // V_2 = B_2 U_1^{-1}
-      steps[1].host.push_back({V, V, nullptr, X1, r, r, n, n, n, 0, r, 0, 0});             // G = V^T V
+      // (step 1 is an unused slot: the step numbers stay those of the profiles)
       steps[2].host.push_back({V, Tm, nullptr, Y, n, r, r, n, r, 0, n, 0, 0});            // Y = V T
       steps[3].host.push_back({Mp, Y, nullptr, W, n, r, n, n, n, 0, n, 0, 0});            // W = M Y
       steps[4].host.push_back({Y, W, nullptr, X1, r, r, n, n, n, 0, r, 0, 0});            // C = Y^T W
@@ -1789,8 +1629,12 @@ static void launch_basis_top(int rmax, int first, int count, const NodeDesc* nod
     hipLaunchKernelGGL((k_basis_top<T, 32>), grid, block, 0, s, nodes, first, b.B, b.V, b.Tm, b.Sg, b.X);
   else if (rmax <= 64)
     hipLaunchKernelGGL((k_basis_top<T, 64>), grid, block, 0, s, nodes, first, b.B, b.V, b.Tm, b.Sg, b.X);
-  else
+  else if (rmax <= 96)
     hipLaunchKernelGGL((k_basis_top<T, 96>), grid, block, 0, s, nodes, first, b.B, b.V, b.Tm, b.Sg, b.X);
+  else if (rmax <= 128)
+    hipLaunchKernelGGL((k_basis_top<T, 128>), grid, block, 0, s, nodes, first, b.B, b.V, b.Tm, b.Sg, b.X);
+  else
+    HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "fused basis QR above rank 128");
   HSS_HIP(hipGetLastError());
 }
 
@@ -1873,8 +1717,8 @@ static int stage_cholesky(hss_matrix_t m, const LevelPlan& lp, const FBufs<T>& b
   }
   int rmax_nr = 0, mmax_nr = 0, nmax_nr = 0;
   nonroot_extent(m, lp, rmax_nr, mmax_nr, nmax_nr);
-  if (nonroot > 0 && rmax_nr <= 96 && mmax_nr <= 160 && nmax_nr <= 256) {
-    launch_pchol_split<T>(m, lp.first, nonroot, b.F, msink, (const T*)b.Sg, s, cx, l);
+  if (nonroot > 0 && split_fits(rmax_nr, mmax_nr, nmax_nr)) {
+    launch_pchol_split<T>(m, lp.first, nonroot, rmax_nr, b.F, msink, (const T*)b.Sg, s, cx, l);
   } else if (nonroot > 0) {
     Prof pf(cx, "pchol", l);
     launch_pchol<T>(m, lp.first, nonroot, lp.nmax, b.F, s);
@@ -2099,7 +1943,7 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
     } else {
       int rmax_nr = 0, mmax_nr = 0, nmax_nr = 0;
       nonroot_extent(m, lp, rmax_nr, mmax_nr, nmax_nr);
-      direct = direct && rmax_nr <= 96 && mmax_nr <= 160 && nmax_nr <= 256;
+      direct = direct && split_fits(rmax_nr, mmax_nr, nmax_nr);
     }
   }
   T* msink = direct ? b.M : nullptr;
@@ -2160,25 +2004,18 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
     }
     auto& st = plan[si];
     if (lp.rmax > 0 && !basis_done) {
-      if (lp.rmax <= 96) {
+      if (lp.rmax <= 128) {
         {
           Prof pf(cx, "basis_top", l);
           launch_basis_top<T>(lp.rmax, lp.first, lp.count, m->dnodes, b, s);
         }
         Prof pf(cx, "gemm_V2", l);
         gemm_run<T>(st[0], false, false, 1.0, 0.0, s);    // V_2 = B_2 U_1^{-1}
-      } else if (lp.rmax > 128) {
+      } else {
         Prof pf(cx, "basis_qr", l);
         hipLaunchKernelGGL((k_house_basis<T>), dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, b.B, b.V,
                            b.Tm, b.Sg);
         HSS_HIP(hipGetLastError());
-      } else {
-        Prof pf(cx, "basis_qr", l);
-        launch_lu_top<T>(m, lp, b.B, b.V, b.Tm, b.Sg, s);   // V_1, U_1 (in the T slot), Sg
-        launch_tri_inv<T>(m, lp, b.Tm, 0, b.X, 2, 0, s);    // U_1^{-1} -> second half of X
-        gemm_run<T>(st[0], false, false, 1.0, 0.0, s);      // V_2 = B_2 U_1^{-1}
-        gemm_run<T>(st[1], true, false, 1.0, 0.0, s);       // G = V^T V -> first half of X
-        launch_tri_inv<T>(m, lp, b.X, 1, b.Tm, 0, 1, s);    // T = (striu G + diag G / 2)^{-1}
       }
     }
     if (!basis_done) {

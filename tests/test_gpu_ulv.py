@@ -91,7 +91,10 @@ def test_exp2d_n2048_plain_vs_oracle_and_dense(ctx, torch_dev):
                                                (2, 128, 16), (1, 200, 40), (3, 250, 90),
                                                # ranks above 128 (generic Householder basis, rank-256 solves):
                                                # Table 2's (200, 256) and (200, 512) shapes and the largest blocks
-                                               (3, 256, 200), (2, 512, 200), (2, 512, 256), (2, 300, 136)])
+                                               (3, 256, 200), (2, 512, 200), (2, 512, 256), (2, 300, 136),
+                                               # ranks 97..128: the fused LDS basis QR with its 128 frame, and the
+                                               # R-block Cholesky + 128-row S-row kernel above the leaves
+                                               (3, 256, 100), (3, 200, 112), (4, 128, 120)])
 def test_random_hss_shapes(ctx, torch_dev, levels, leaf, rank):
     d = synth.random_hss(levels, leaf, rank, seed=levels * 100 + rank)
     h = O.HSS(d["n"], d["levels"], d["ranges"], d["rank"], d["D"], d["U"], d["E"], d["S"])
@@ -217,6 +220,7 @@ def test_export_roundtrip(ctx, torch_dev):
 
 
 @pytest.mark.parametrize("levels,leaf,rank,nrhs", [(3, 64, 16, 1), (2, 256, 96, 1), (5, 32, 12, 3), (3, 250, 90, 6),
+                                                    (3, 256, 100, 2),
                                                    (1, 200, 40, 1)])
 def test_fused_factor_solve_equals_separate_calls(ctx, torch_dev, levels, leaf, rank, nrhs):
     # the fused call reorders independent launches across two streams only:
