@@ -83,7 +83,7 @@ def main():
     ap.add_argument("--load-tiles", default="", help="use the GEMM tile choice saved in this JSON file")
     ap.add_argument("--no-graph", action="store_true", help="time the tuned configuration with eager launches")
     ap.add_argument("--no-fused", action="store_true", help="skip the one-call factor + solve")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32 + refinement leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs (FP32 and BF16 forms + refinement)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-rank ablation leg")
     ap.add_argument("--no-config2", action="store_true",
                     help="skip the 16-right-hand-side leg (HSS-ULV and BLR^2-ULV at N = 65536)")
@@ -327,6 +327,10 @@ def main():
                  "fp32_products_used": int(minfo.promoted_nodes) < leaves,
                  "reading": ("the leaf products in FP32 perturb each leaf block by about u32 |D|, above the "
                              "smallest pivots of these leaves: the accuracy guard factors them in FP64")}
+        # the BF16 forms' guards (2^-10 and 2^-2 |D|_inf) on the same leaves: one factorization each
+        for name, prec in (("bf16x3", hss.HSS_P_BF16X3), ("bf16", hss.HSS_P_BF16)):
+            hss.hss_ulv_factor(ctx, m, prec)
+            mixed[f"first_factor_promoted_leaves_{name}"] = int(hss.hss_get_info(m).promoted_nodes)
     except Exception as e:  # report, keep the FP64 result
         mixed = {"error": str(e)}
     # leave the matrix factored in FP64 for anything after
@@ -511,11 +515,30 @@ def mixed_exp_leg(hss, torch, np, ctx, steps, warmup, no_tune):
         rr_check = float(torch.linalg.norm(b - hss.hss_matvec(ctx, m, xm)) / torch.linalg.norm(b))
         f64 = float(np.median([fac(hss.HSS_P_FP64) for _ in range(steps)]))
         f32 = float(np.median([fac(hss.HSS_P_FP32) for _ in range(steps)]))
+        # the BF16 forms (sharing the FP32 form's tile choices): the split products
+        # and plain BF16, each with its own accuracy guard
+        low = {}
+        for name, prec in (("bf16x3", hss.HSS_P_BF16X3), ("bf16", hss.HSS_P_BF16)):
+            hss.hss_ulv_factor(ctx, m, prec)
+            first = int(hss.hss_get_info(m).promoted_nodes)
+
+            def low_step(p=prec):
+                hss.hss_ulv_factor(ctx, m, p)
+                return hss.hss_ulv_solve_refined(ctx, m, b, 1e-8, 50)
+
+            low_step()
+            tq, (xq, itq, rq, okq) = timed(low_step, steps)
+            rq_check = float(torch.linalg.norm(b - hss.hss_matvec(ctx, m, xq)) / torch.linalg.norm(b))
+            low[name] = {"first_factor_promoted_leaves": first,
+                         "promoted_leaves": int(hss.hss_get_info(m).promoted_nodes),
+                         "factor_plus_refined_solve_s": round(tq, 6), "converged": bool(okq) and rq_check <= 1e-8,
+                         "corrections": itq, "relres_recomputed": rq_check,
+                         "factor_ms_events": round(float(np.median([fac(prec) for _ in range(steps)])), 3)}
         return {"workload": w.name, "kernel": "exponential", "length": w.length, "nugget": w.nugget,
                 "fp64_fused_factor_solve_s": round(t64, 6), "mixed_factor_plus_refined_solve_s": round(tmx, 6),
                 "speedup_mixed_vs_fp64": round(t64 / tmx, 3), "converged": bool(ok) and rr_check <= 1e-8,
                 "corrections": iters, "relres_recomputed": rr_check, "promoted_leaves": promoted,
-                "factor_ms_fp64_events": round(f64, 3), "factor_ms_mixed_events": round(f32, 3)}
+                "factor_ms_fp64_events": round(f64, 3), "factor_ms_mixed_events": round(f32, 3), **low}
     finally:
         hss.hss_matrix_destroy(m)
 

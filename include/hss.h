@@ -105,7 +105,7 @@ typedef struct {
 } hss_construct_opts;
 
 /* Precision of the factorization (the mixed-precision form of the path; the paper
- * itself is FP64). Both leave FP64 factors, applied by the same FP64 solve.
+ * itself is FP64). All leave FP64 factors, applied by the same FP64 solve.
  *  FP64: every step in FP64.
  *  FP32: the leaf stage's four contractions of the diagonal product (Eq. 7:
  *        W = M Y, C = Y^T W, Z = W - V C / 2 and the rank-2r update of M) run
@@ -116,19 +116,34 @@ typedef struct {
  *        stages above the leaves (whose blocks carry the growing norms of the
  *        merged Schur complements) stay FP64. Accuracy guard, in the same
  *        call: a leaf whose FP64 pivot fails after the FP32 products, or whose
- *        smallest pivot is below 2^-18 trace(D) (where the FP32 rounding of its
- *        products, about u32 |D|, would be an O(1) relative error), is redone
- *        in FP64 before the stage above; a node above the leaves whose pivot
+ *        smallest pivot is below 2^-18 |D|_inf (largest absolute row sum;
+ *        there the FP32 rounding of its products, about u32 |D|_inf, would be
+ *        an O(1) relative error), is redone in FP64 before the stage above;
+ *        a node above the leaves whose pivot
  *        fails (its block made indefinite by the perturbation below it) has
  *        its whole subtree and its ancestors redone in FP64. When at least half
  *        of the leaves are redone, later FP32 factorizations of the same matrix
  *        run FP64 from the start. hss_info.promoted_nodes counts the leaves
  *        factored in FP64. The result factors the HSS matrix with its other
  *        leaf blocks perturbed by the FP32 rounding: refine with
- *        hss_ulv_solve_refined. */
+ *        hss_ulv_solve_refined.
+ *  BF16: as FP32, with the four contractions on BF16 matrix cores (operands
+ *        rounded to BF16, FP32 accumulation). Guard: smallest pivot below
+ *        2^-2 |D|_inf, so only leaves whose redundant blocks keep pivots
+ *        within a factor 4 of |D|_inf stay BF16 (strongly diagonally
+ *        dominant leaves); the leaves of smooth kernels are redone in FP64.
+ *  BF16X3: as BF16 with each operand split into two BF16 parts, x = hi + lo,
+ *        and the products formed as hi*hi + hi*lo + lo*hi (FP32
+ *        accumulation): about 2^-16 relative error per product. Guard:
+ *        smallest pivot below 2^-10 |D|_inf.
+ * The guard and the switch to FP64 after half of the leaves were redone apply
+ * per precision; the three low precisions share one set of GEMM tile shapes
+ * (hss_autotune, hss_set_gemm_variants). */
 typedef enum {
   HSS_P_FP64 = 0,
-  HSS_P_FP32 = 1
+  HSS_P_FP32 = 1,
+  HSS_P_BF16 = 2,
+  HSS_P_BF16X3 = 3
 } hss_precision;
 
 typedef struct {
@@ -274,7 +289,8 @@ hss_status hss_ulv_factor(hss_ctx_t ctx, hss_matrix_t m, const hss_factor_opts* 
 /* ULV solve (Eq. 17): x = A^{-1} b for nrhs columns. d_b, d_x: N x nrhs,
  * column-major with leading dimension ld >= N, caller's order, device memory;
  * d_x may equal d_b. Requires a successful factorization (BAD_STATE otherwise).
- * The solve runs in the precision of the factorization. */
+ * The solve is FP64 whatever the precision of the factorization (every
+ * precision leaves FP64 factors). */
 hss_status hss_ulv_solve(hss_ctx_t ctx, hss_matrix_t m, const double* d_b, double* d_x,
                          int64_t nrhs, int64_t ld);
 
@@ -428,9 +444,10 @@ hss_status hss_batch_query(hss_ctx_t ctx, hss_matrix_t m, int32_t count, int64_t
                            double* h_logdet);
 
 /* ---- launch recording and tuning ---------------------------------------- */
-/* When on, hss_ulv_factor records its whole launch sequence (every stage,
- * every step) into a HIP graph on first use per precision and afterwards
- * replays it with a single graph launch; hss_ulv_solve (and the solves inside
+/* When on, an FP64 hss_ulv_factor records its whole launch sequence (every
+ * stage, every step) into a HIP graph on first use and afterwards replays it
+ * with a single graph launch (the mixed-precision factorizations read their
+ * promotion counts back between stages and are never recorded); hss_ulv_solve (and the solves inside
  * hss_ulv_solve_refined) does the same per (precision, b, x, nrhs, ld). The
  * recording uses a private non-blocking stream; replays go to the context
  * stream. Ignored while profiling is enabled. Switching drops all graphs.

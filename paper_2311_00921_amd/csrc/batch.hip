@@ -194,7 +194,7 @@ static void factor_direct(hss_matrix_t m, int precision) {
   if (precision == HSS_P_FP64)
     factor_fp64(m);
   else
-    factor_mixed(m);
+    factor_mixed(m, precision);
 }
 
 void factor_run(hss_matrix_t m, int precision) {
@@ -419,7 +419,7 @@ hss_status hss_autotune(hss_ctx_t ctx, hss_matrix_t m, int32_t precision, int32_
   HSS_API_BEGIN
   hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
-  HSS_CHECK(precision == HSS_P_FP64 || precision == HSS_P_FP32, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
+  HSS_CHECK(precision >= HSS_P_FP64 && precision <= HSS_P_BF16X3, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
   HSS_CHECK(reps >= 1 && reps <= 100, HSS_ERR_INVALID_ARGUMENT, "reps must be in [1, 100]");
   std::vector<float> rep;
   autotune(m, precision, reps, &rep);
@@ -447,7 +447,7 @@ hss_status hss_set_gemm_variants(hss_ctx_t ctx, hss_matrix_t m, int32_t precisio
   HSS_API_BEGIN
   hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m && h_variants, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
-  HSS_CHECK(precision == HSS_P_FP64 || precision == HSS_P_FP32, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
+  HSS_CHECK(precision >= HSS_P_FP64 && precision <= HSS_P_BF16X3, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
   prepare_factor(m, precision);
   auto& plan = precision == HSS_P_FP64 ? m->gemm_plan : m->gemm_plan32;
   int64_t k = 0;

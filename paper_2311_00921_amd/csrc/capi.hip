@@ -637,7 +637,7 @@ hss_status hss_ulv_factor(hss_ctx_t ctx, hss_matrix_t m, const hss_factor_opts* 
   hss::CtxScope cs_(ctx);
   HSS_CHECK(ctx && m, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
   const int prec = opts ? opts->precision : HSS_P_FP64;
-  HSS_CHECK(prec == HSS_P_FP64 || prec == HSS_P_FP32, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
+  HSS_CHECK(prec >= HSS_P_FP64 && prec <= HSS_P_BF16X3, HSS_ERR_INVALID_ARGUMENT, "unknown precision");
   factor_checked(ctx, m, prec, [&] { factor_run(m, prec); });
   HSS_API_END
 }

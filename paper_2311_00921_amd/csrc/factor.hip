@@ -1554,25 +1554,31 @@ static void alloc_factor(hss_matrix_t m) {
   m->factor_ready = true;
 }
 
-// The GEMM steps of a stage that the mixed factorization runs on FP32 matrix
-// cores: W = M Y, C = Y^T W, Z = W - V C / 2 and the rank-2r update of the
+// The GEMM steps of a stage that the mixed factorization runs on FP32 or BF16
+// matrix cores: W = M Y, C = Y^T W, Z = W - V C / 2 and the rank-2r update of the
 // leaf stage (the bulk of the flops, and the smallest block norms). The basis
 // QR and Y = V T stay FP64: they define the orthogonal transform itself, which
 // the solve applies again and whose exactness keeps the redundant rows of the
 // off-diagonal blocks zero (Eq. 8).
 static bool mixed_step(const LevelPlan& lp, int step) { return lp.leaf && step >= 3 && step <= 6; }
 
-// trace(D) of every leaf (one workgroup per leaf)
-__global__ void k_leaf_trace(const NodeDesc* __restrict__ nodes, int first, const double* __restrict__ Db,
-                             double* __restrict__ out) {
+// |D|_inf (largest absolute row sum) of every leaf (one workgroup per leaf;
+// D is symmetric, so thread i sums row i down the columns, coalesced)
+__global__ void k_leaf_rownorm(const NodeDesc* __restrict__ nodes, int first, const double* __restrict__ Db,
+                               double* __restrict__ out) {
   const NodeDesc nd = nodes[first + blockIdx.x];
   __shared__ double part[256];
-  double acc = 0.0;
-  for (int i = threadIdx.x; i < nd.n; i += blockDim.x) acc += Db[nd.offD + i + (int64_t)i * nd.n];
-  part[threadIdx.x] = acc;
+  const double* D = Db + nd.offD;
+  double mx = 0.0;
+  for (int i = threadIdx.x; i < nd.n; i += blockDim.x) {
+    double acc = 0.0;
+    for (int j = 0; j < nd.n; ++j) acc += fabs(D[i + (int64_t)j * nd.n]);
+    mx = fmax(mx, acc);
+  }
+  part[threadIdx.x] = mx;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    if ((int)threadIdx.x < w) part[threadIdx.x] = fmax(part[threadIdx.x], part[threadIdx.x + w]);
     __syncthreads();
   }
   if (threadIdx.x == 0) out[blockIdx.x] = part[0];
@@ -1582,11 +1588,12 @@ static void alloc_mixed(hss_matrix_t m) {
   alloc_factor(m);
   if (m->mixed_ready) return;
   {
-    // the scale of the FP32 rounding of each leaf's products, once per matrix
+    // the scale of the rounding of each leaf's low-precision products, once per matrix
     const LevelPlan& lp = m->stages[0];
     hipStream_t s = m->ctx->stream;
     double* tr = (double*)dev_alloc(sizeof(double) * lp.count);
-    hipLaunchKernelGGL(k_leaf_trace, dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const double*)m->dD, tr);
+    hipLaunchKernelGGL(k_leaf_rownorm, dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, (const double*)m->dD,
+                       tr);
     std::vector<double> h(lp.count);
     const hipError_t e1 = hipGetLastError();
     const hipError_t e2 = hipMemcpyAsync(h.data(), tr, sizeof(double) * lp.count, hipMemcpyDeviceToHost, s);
@@ -1595,13 +1602,13 @@ static void alloc_mixed(hss_matrix_t m) {
     HSS_HIP(e1);
     HSS_HIP(e2);
     HSS_HIP(e3);
-    m->leaf_trace.assign(m->nnodes, 0.0);
-    for (int k = 0; k < lp.count; ++k) m->leaf_trace[lp.first + k] = h[k];
+    m->leaf_scale.assign(m->nnodes, 0.0);
+    for (int k = 0; k < lp.count; ++k) m->leaf_scale[lp.first + k] = h[k];
   }
   m->gemm_plan32 = build_gemm_plan<double>(m, fbufs(m));
   for (size_t si = 0; si < m->stages.size(); ++si)
     for (int st = 0; st < (int)m->gemm_plan32[si].size(); ++st)
-      m->gemm_plan32[si][st].fp32_compute = mixed_step(m->stages[si], st);
+      m->gemm_plan32[si][st].compute = mixed_step(m->stages[si], st) ? HSS_P_FP32 : HSS_P_FP64;
   m->mixed_ready = true;
 }
 
@@ -1804,15 +1811,25 @@ static void redo_nodes_fp64(hss_matrix_t m, int si, const std::vector<int>& list
   for (auto& g : sub) gemm_free(g);
 }
 
-// Accuracy test of the FP32 leaf products. Rounding the products of a leaf to
-// FP32 perturbs its transformed block by about u32 * |D| (absolute: the
-// redundant block is formed from D by cancellation), and a redundant block
-// whose smallest pivot is not well above that is then factored with an O(1)
-// relative error, which refinement cannot remove in a few steps. Such leaves,
-// and those whose pivot failed outright, are redone in FP64 before the stage
-// above starts. Threshold: smallest pivot < 2^6 u32 trace(D) (trace(D) >= |D|_2;
-// the rounding measured on the benchmark's leaves is about 3 u32 trace(D)).
-constexpr double kMixedPivotRatio = 64.0 * 0x1p-24;
+// Accuracy test of the low-precision leaf products. Rounding the operands of a
+// leaf's products to unit roundoff u perturbs its transformed block by about
+// u * |D|_inf (the entrywise product bound |fl(MY) - MY| <= c u |M||Y| in the
+// 2-norm, with ||M|| |_2 <= |M|_inf for symmetric M and Y orthogonal up to
+// scaling; absolute, since the redundant block is formed from D by
+// cancellation), and a redundant block whose smallest pivot is not well above
+// that is then factored with an O(1) relative error, which refinement cannot
+// remove in a few steps. Such leaves, and those whose pivot failed outright,
+// are redone in FP64 before the stage above starts. Threshold: smallest pivot
+// < 2^6 u |D|_inf (the FP32 rounding measured on the benchmark's leaves is
+// about 3 u trace(D), and |D|_inf is 0.92 trace(D) there: a kept leaf's
+// perturbation is about 1/20 of its smallest pivot).
+// u: 2^-24 for FP32, 2^-8 for BF16, and 2^-16 for the split BF16 products (the
+// left-out lo*lo term and the split's own residual are each within 2^-16 of
+// the product).
+static double mixed_pivot_ratio(int prec) {
+  const double u = prec == HSS_P_BF16 ? 0x1p-8 : prec == HSS_P_BF16X3 ? 0x1p-16 : 0x1p-24;
+  return 64.0 * u;
+}
 
 template <typename T>
 static int promote_leaves(hss_matrix_t m, int si, const FBufs<T>& b, T* msink) {
@@ -1823,10 +1840,11 @@ static int promote_leaves(hss_matrix_t m, int si, const FBufs<T>& b, T* msink) {
   HSS_HIP(hipMemcpyAsync(pm.data(), m->dpmin + lp.first, sizeof(double) * lp.count, hipMemcpyDeviceToHost, s));
   HSS_HIP(hipStreamSynchronize(s));
   std::vector<int> list;
+  const double ratio = mixed_pivot_ratio(m->mixed_prec);
   for (int k = 0; k < lp.count; ++k) {
     const int p = lp.first + k;
-    if (p >= lp.root_first) continue;  // roots have no FP32 products
-    if (std::isnan(ld[k]) || !(pm[k] >= kMixedPivotRatio * m->leaf_trace[p])) list.push_back(p);
+    if (p >= lp.root_first) continue;  // roots have no low-precision products
+    if (std::isnan(ld[k]) || !(pm[k] >= ratio * m->leaf_scale[p])) list.push_back(p);
   }
   if (list.empty()) return 0;
   clear_status(m, s, false);
@@ -1844,7 +1862,7 @@ static int promote_leaves(hss_matrix_t m, int si, const FBufs<T>& b, T* msink) {
 
 // Mixed precision: after the sweep, the nodes whose FP64 pivots failed are
 // found (the kernels mark a failed node with a NaN log-determinant and count it
-// in info[3]). A failure anywhere -- at a leaf, or above it where the FP32
+// in info[3]). A failure anywhere -- at a leaf, or above it where the rounding
 // perturbation of the leaves below has made a merged block indefinite -- is
 // repaired by redoing the failed node's whole subtree in FP64 and then every
 // ancestor of it (their blocks were formed from the failed values), stage by
@@ -1910,7 +1928,7 @@ static int promote_failed(hss_matrix_t m, const FBufs<T>& b, T* msink) {
       for (int k = 0; k < nn; ++k)
         if (done[k] && m->nodes[k].c1 < 0) m->fp64_leaf[k] = 1;
     }
-    propagate();  // the stages above the leaves never use FP32
+    propagate();  // the stages above the leaves never use low precision
   }
   int leaves = 0;
   for (int k = 0; k < nn; ++k) leaves += (m->fp64_leaf[k] && m->nodes[k].c1 < 0 && m->nodes[k].parent >= 0) ? 1 : 0;
@@ -1919,7 +1937,7 @@ static int promote_failed(hss_matrix_t m, const FBufs<T>& b, T* msink) {
 
 // One sweep of Alg. 2 over the stages (leaves first, roots included). A root
 // has rank 0: its transform is the identity and its "partial" Cholesky is
-// complete. `mixed`: the plan runs some products on FP32 matrix cores, and the
+// complete. `mixed`: the plan runs some products in low precision, and the
 // nodes of those stages whose pivots fail are promoted to FP64.
 template <typename T>
 static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::vector<GemmBatch>>& plan,
@@ -2040,7 +2058,7 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
       gemm_run<T>(st[6], false, true, -1.0, 1.0, s);      // F = P^T (M - Z V^T - V Z^T) P
     }
     m->inv_used64[si] = (char)stage_cholesky<T>(m, lp, b, st, msink, s);
-    if (mixed && st.size() > 6 && st[6].fp32_compute) promote_leaves<T>(m, (int)si, b, msink);
+    if (mixed && st.size() > 6 && st[6].compute != HSS_P_FP64) promote_leaves<T>(m, (int)si, b, msink);
     if (m->after_stage) m->after_stage((int)si);
   }
   if (mixed) m->promoted = promote_failed<T>(m, b, msink);
@@ -2064,31 +2082,38 @@ void factor_fp64(hss_matrix_t m) {
   HSS_HIP(hipGetLastError());
 }
 
-// Mixed precision (hss_precision FP32): the same FP64 buffers and launch
-// sequence as factor_fp64, with the products W, C, Z and F of the leaf stage on
-// FP32 matrix cores (operands rounded to FP32, FP32 accumulation, the FP64 block
-// M added to the product in FP64); every pivot, Cholesky, triangular solve and
-// Schur complement, the basis QR and the stages above stay FP64, and a leaf
-// whose pivot fails is redone in FP64 (promote_failed). The result is the exact
-// factorization of the HSS matrix with its leaf blocks perturbed by the FP32
-// rounding of those products; the FP64 solve applies it, and refinement with
-// the FP64 matvec removes the perturbation.
-void factor_mixed(hss_matrix_t m) {
+// Mixed precision (hss_precision FP32, BF16 or BF16X3): the same FP64 buffers
+// and launch sequence as factor_fp64, with the products W, C, Z and F of the
+// leaf stage on FP32 or BF16 matrix cores (operands rounded to FP32, to BF16,
+// or split into two BF16 parts; FP32 accumulation; the FP64 block M added to
+// the product in FP64); every pivot, Cholesky, triangular solve and Schur
+// complement, the basis QR and the stages above stay FP64, and a leaf whose
+// pivot fails or falls under the accuracy guard is redone in FP64
+// (promote_leaves, promote_failed). The result is the exact factorization of
+// the HSS matrix with its leaf blocks perturbed by the rounding of those
+// products; the FP64 solve applies it, and refinement with the FP64 matvec
+// removes the perturbation.
+void factor_mixed(hss_matrix_t m, int precision) {
   hipStream_t s = m->ctx->stream;
   alloc_mixed(m);
   clear_status(m, s);
   m->fp64_leaf.assign(m->nnodes, 0);
-  if (m->mixed_all64) {
-    // an earlier mixed factorization of this matrix redid at least half of its
-    // leaves in FP64: the FP32 products are skipped altogether
+  m->mixed_prec = precision;
+  bool& all64 = m->mixed_all64[precision];
+  if (all64) {
+    // an earlier factorization of this matrix in this precision redid at least
+    // half of its leaves in FP64: the low-precision products are skipped altogether
     factor_stages<double>(m, fbufs(m), m->gemm_plan, false);
     m->promoted = 0;
     for (const NodeDesc& d : m->nodes) m->promoted += (d.c1 < 0 && d.parent >= 0) ? 1 : 0;
   } else {
+    for (auto& lv : m->gemm_plan32)
+      for (auto& b : lv)
+        if (b.compute != HSS_P_FP64) b.compute = precision;
     factor_stages<double>(m, fbufs(m), m->gemm_plan32, true);
     int leaves = 0;
     for (const NodeDesc& d : m->nodes) leaves += (d.c1 < 0 && d.parent >= 0) ? 1 : 0;
-    m->mixed_all64 = leaves > 0 && 2 * m->promoted >= leaves;
+    all64 = leaves > 0 && 2 * m->promoted >= leaves;
   }
   hipLaunchKernelGGL(k_sum_logdet, dim3(1), dim3(256), 0, s, (const double*)m->dlogdet, m->nnodes,
                      m->dlogdet + m->nnodes);

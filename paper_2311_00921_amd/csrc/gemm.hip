@@ -1,6 +1,6 @@
-// Batched GEMM on the matrix cores (MFMA 16x16x4, FP64 and FP32) for the
-// contraction steps of the HSS-ULV factorization: the diagonal product
-// Q^T A Q in compact WY form (Eq. 7) and the products around it.
+// Batched GEMM on the matrix cores (MFMA 16x16x4 FP64 and FP32, 16x16x16
+// BF16) for the contraction steps of the HSS-ULV factorization: the diagonal
+// product Q^T A Q in compact WY form (Eq. 7) and the products around it.
 //
 // One launch covers every node of a stage: grid.y indexes the batch entry,
 // grid.x the BM x BN output tiles of that entry. Each 256-thread workgroup
@@ -16,6 +16,15 @@ namespace hss {
 typedef double v4d __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
+typedef short v4s __attribute__((ext_vector_type(4)));
+
+// BF16 compute types: operands rounded to BF16 (Bf16) or split into two BF16
+// parts, x = hi + lo + O(2^-16 |x|) (Bf16x3), multiplied on the BF16 matrix
+// cores with FP32 accumulation; Bf16x3 forms hi*hi + hi*lo + lo*hi, which
+// leaves out only the lo*lo term.
+struct Bf16 {};
+struct Bf16x3 {};
+
 template <typename T>
 struct AccT;
 template <>
@@ -26,6 +35,21 @@ template <>
 struct AccT<float> {
   typedef v4f type;
 };
+template <>
+struct AccT<Bf16> {
+  typedef v4f type;
+};
+template <>
+struct AccT<Bf16x3> {
+  typedef v4f type;
+};
+
+template <typename TC>
+constexpr int kBfParts = 0;  // BF16 parts per operand (0: not a BF16 type)
+template <>
+constexpr int kBfParts<Bf16> = 1;
+template <>
+constexpr int kBfParts<Bf16x3> = 2;
 
 __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -33,9 +57,17 @@ __device__ __forceinline__ v4d mfma16(double a, double b, v4d c) {
 __device__ __forceinline__ v4f mfma16(float a, float b, v4f c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+// 16x16x16 BF16: each lane holds 4 consecutive k of its row (A) or column (B)
+__device__ __forceinline__ v4f mfma16(v4s a, v4s b, v4f c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
 
-// Row padding of the LDS tiles (one element; measured best among 1 and 16).
-constexpr int LPAD = 1;
+// BF16 bits of x, rounded to nearest (through FP32)
+__device__ __forceinline__ uint16_t bf16_bits(float x) { return __builtin_bit_cast(uint16_t, (__bf16)x); }
+__device__ __forceinline__ double bf16_value(uint16_t h) {
+  return (double)__builtin_bit_cast(float, (uint32_t)h << 16);
+}
+
 
 // tile variants: {BM, BN, BK}; the deep-K ones (BK 32 and 64) halve or quarter
 // the number of dependent global-load rounds, which is what bounds the small
@@ -46,9 +78,42 @@ constexpr int kTileN[kGemmVariants] = {64, 32, 64, 128, 32, 64, 96, 96};
 constexpr int kTileK[kGemmVariants] = {16, 16, 16, 16, 64, 32, 16, 16};
 
 // Row of the 16x16 MFMA output held by lane `lane` in accumulator slot v.
-// FP64 16x16x4 interleaves rows across slots; FP32 16x16x4 stacks them.
+// FP64 16x16x4 interleaves rows across slots; the FP32-accumulating ones
+// (FP32 16x16x4, BF16 16x16x16) stack them.
 __device__ __forceinline__ int mfma_row(double, int lane, int v) { return (lane >> 4) + 4 * v; }
 __device__ __forceinline__ int mfma_row(float, int lane, int v) { return 4 * (lane >> 4) + v; }
+__device__ __forceinline__ int mfma_row(Bf16, int lane, int v) { return 4 * (lane >> 4) + v; }
+__device__ __forceinline__ int mfma_row(Bf16x3, int lane, int v) { return 4 * (lane >> 4) + v; }
+
+// LDS tiles of one K slice. FP64 / FP32: [k][row] of op(A) and [k][col] of
+// op(B), one 16x16x4 operand per k row. BF16: [part][row][k] with 4 k of
+// a row adjacent (one 8-byte read per lane and 16x16x16 operand); the row
+// pitch BK + 4 keeps those reads 8-byte aligned and spreads the 16 rows
+// that one read touches over the banks.
+// (The one-element row padding of the FP64 / FP32 tiles measured best among 1 and 16.)
+template <typename TC, int BM, int BN, int BK, int P = kBfParts<TC>>
+struct GemmLds {
+  TC A[BK][BM + 1];
+  TC B[BK][BN + 1];
+};
+template <typename TC, int BM, int BN, int BK>
+struct GemmLds<TC, BM, BN, BK, 1> {
+  alignas(16) uint16_t A[1][BM][BK + 4];
+  alignas(16) uint16_t B[1][BN][BK + 4];
+};
+template <typename TC, int BM, int BN, int BK>
+struct GemmLds<TC, BM, BN, BK, 2> {
+  alignas(16) uint16_t A[2][BM][BK + 4];
+  alignas(16) uint16_t B[2][BN][BK + 4];
+};
+
+// Rounds x into the BF16 part(s) at A[.][r][k] of an LDS tile
+template <int P, int R, int K>
+__device__ __forceinline__ void stage_bf16(uint16_t (&A)[P][R][K], int r, int k, double x) {
+  const uint16_t hi = bf16_bits((float)x);
+  A[0][r][k] = hi;
+  if constexpr (P == 2) A[1][r][k] = bf16_bits((float)(x - bf16_value(hi)));  // x - hi is exact in FP64
+}
 
 __device__ __forceinline__ int perm_index(int t, int dim, int r) {
   return r > 0 ? (t < r ? t + (dim - r) : t - r) : t;
@@ -92,8 +157,9 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
     const int minp = (c1 >= r) ? max(col0, r) - r : col0 + mm;
     if (maxp < minp) return;  // every element of the tile lies strictly above the diagonal
   }
-  __shared__ TC As[BK][BM + LPAD];
-  __shared__ TC Bs[BK][BN + LPAD];
+  constexpr int NP = kBfParts<TC>;
+  static_assert(NP == 0 || BK % 16 == 0, "a BF16 K slice holds whole 16x16x16 steps");
+  __shared__ GemmLds<TC, BM, BN, BK> lds;
   constexpr int QA = BM * BK / 256, QB = BN * BK / 256;  // elements per thread and K slice
   const T* __restrict__ A = (const T*)d.A;
   const T* __restrict__ B = (const T*)d.B;
@@ -169,25 +235,57 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
   // matrix cores consume the current one from LDS
   if (d.k > 0) load(0);
   for (int k0 = 0; k0 < d.k; k0 += BK) {
+    if constexpr (NP == 0) {
 #pragma unroll
-    for (int q = 0; q < QA; ++q) As[ak[q]][ar[q]] = (TC)ra[q];
+      for (int q = 0; q < QA; ++q) lds.A[ak[q]][ar[q]] = (TC)ra[q];
 #pragma unroll
-    for (int q = 0; q < QB; ++q) Bs[bk[q]][bc[q]] = (TC)rb[q];
+      for (int q = 0; q < QB; ++q) lds.B[bk[q]][bc[q]] = (TC)rb[q];
+    } else {
+#pragma unroll
+      for (int q = 0; q < QA; ++q) stage_bf16(lds.A, ar[q], ak[q], (double)ra[q]);
+#pragma unroll
+      for (int q = 0; q < QB; ++q) stage_bf16(lds.B, bc[q], bk[q], (double)rb[q]);
+    }
     __syncthreads();
     if (k0 + BK < d.k) load(k0 + BK);
+    if constexpr (NP == 0) {
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      TC a[IM], b[JN];
+      for (int kk = 0; kk < BK; kk += 4) {
+        TC a[IM], b[JN];
 #pragma unroll
-      for (int i = 0; i < IM; ++i) a[i] = As[kk + lk][wm + 16 * i + lr];
+        for (int i = 0; i < IM; ++i) a[i] = lds.A[kk + lk][wm + 16 * i + lr];
 #pragma unroll
-      for (int j = 0; j < JN; ++j) b[j] = Bs[kk + lk][wn + 16 * j + lr];
-      // operands swapped: the accumulator holds the transposed 16 x 16 tile,
-      // so that lanes run along the output's rows (column-major stores coalesce)
+        for (int j = 0; j < JN; ++j) b[j] = lds.B[kk + lk][wn + 16 * j + lr];
+        // operands swapped: the accumulator holds the transposed 16 x 16 tile,
+        // so that lanes run along the output's rows (column-major stores coalesce)
 #pragma unroll
-      for (int i = 0; i < IM; ++i)
+        for (int i = 0; i < IM; ++i)
 #pragma unroll
-        for (int j = 0; j < JN; ++j) acc[i][j] = mfma16(b[j], a[i], acc[i][j]);
+          for (int j = 0; j < JN; ++j) acc[i][j] = mfma16(b[j], a[i], acc[i][j]);
+      }
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 16) {
+        v4s a[NP][IM], b[NP][JN];
+#pragma unroll
+        for (int p = 0; p < NP; ++p) {
+#pragma unroll
+          for (int i = 0; i < IM; ++i) a[p][i] = *(const v4s*)&lds.A[p][wm + 16 * i + lr][kk + 4 * lk];
+#pragma unroll
+          for (int j = 0; j < JN; ++j) b[p][j] = *(const v4s*)&lds.B[p][wn + 16 * j + lr][kk + 4 * lk];
+        }
+        // swapped as above; the small cross terms first
+#pragma unroll
+        for (int i = 0; i < IM; ++i)
+#pragma unroll
+          for (int j = 0; j < JN; ++j) {
+            if constexpr (NP == 2) {
+              acc[i][j] = mfma16(b[1][j], a[0][i], acc[i][j]);
+              acc[i][j] = mfma16(b[0][j], a[1][i], acc[i][j]);
+            }
+            acc[i][j] = mfma16(b[0][j], a[0][i], acc[i][j]);
+          }
+      }
     }
     __syncthreads();
   }
@@ -201,7 +299,7 @@ __global__ __launch_bounds__(256) void k_gemm(const GemmDesc* __restrict__ descs
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
         const int row = row0 + wm + 16 * i + lr;
-        const int col = col0 + wn + 16 * j + mfma_row((TC)0, lane, v);
+        const int col = col0 + wn + 16 * j + mfma_row(TC{}, lane, v);
         if (row < d.m && col < d.n) {
           const int prow = perm_index(row, d.m, d.perm_r);
           const int pcol = perm_index(col, d.n, d.perm_r);
@@ -296,10 +394,12 @@ static void launch(const GemmBatch& b, bool ta, bool tb, T alpha, T beta, hipStr
 }
 
 void gemm_launch_f64(const GemmBatch& b, bool ta, bool tb, double alpha, double beta, hipStream_t s) {
-  if (b.fp32_compute)
-    launch<double, float>(b, ta, tb, alpha, beta, s);
-  else
-    launch<double, double>(b, ta, tb, alpha, beta, s);
+  switch (b.compute) {
+    case HSS_P_FP32: launch<double, float>(b, ta, tb, alpha, beta, s); break;
+    case HSS_P_BF16: launch<double, Bf16>(b, ta, tb, alpha, beta, s); break;
+    case HSS_P_BF16X3: launch<double, Bf16x3>(b, ta, tb, alpha, beta, s); break;
+    default: launch<double, double>(b, ta, tb, alpha, beta, s); break;
+  }
 }
 void gemm_launch_f32(const GemmBatch& b, bool ta, bool tb, float alpha, float beta, hipStream_t s) {
   launch<float, float>(b, ta, tb, alpha, beta, s);

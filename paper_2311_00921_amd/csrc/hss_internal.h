@@ -108,7 +108,7 @@ struct GemmBatch {
   int32_t count = 0;
   int32_t mmax = 0, nmax = 0;
   int32_t variant = 0;  // tile shape, set by the autotuner
-  bool fp32_compute = false;  // FP64 storage, operands rounded to FP32 for FP32 MFMA
+  int32_t compute = HSS_P_FP64;  // hss_precision of the products (storage stays FP64)
 };
 
 // Autotuning: while a recorder is installed on the calling thread, every
@@ -212,12 +212,14 @@ struct hss_matrix_s {
   std::function<void(int)> after_stage;
 
   // mixed precision: the same FP64 buffers and GEMM batches, with the leaf
-  // stage's products computed on FP32 matrix cores (own tile choices)
+  // stage's products computed on FP32 or BF16 matrix cores (own tile
+  // choices, shared by the three low precisions)
   bool mixed_ready = false;
   int32_t promoted = 0;  // leaves of the last mixed factorization redone in FP64
-  bool mixed_all64 = false;  // FP32 found unsuitable for this matrix: mixed runs FP64
+  int32_t mixed_prec = HSS_P_FP32;  // precision of the leaf products of the mixed factorization
+  bool mixed_all64[4] = {};  // per hss_precision: found unsuitable for this matrix, mixed runs FP64
   double* dpmin = nullptr;   // per node: smallest pivot of its last partial Cholesky
-  std::vector<double> leaf_trace;  // per node (leaves): trace of D, the FP32 error scale
+  std::vector<double> leaf_scale;  // per node (leaves): |D|_inf, the rounding error scale
   std::vector<char> fp64_leaf;     // per node: leaf redone in FP64 by the last mixed factorization
   std::vector<std::vector<hss::GemmBatch>> gemm_plan32;
 
@@ -306,7 +308,7 @@ void gemm_launch_f32(const GemmBatch& b, bool ta, bool tb, float alpha, float be
 
 // factor.hip
 void factor_fp64(hss_matrix_t m);
-void factor_mixed(hss_matrix_t m);
+void factor_mixed(hss_matrix_t m, int precision);
 double read_logdet(hss_matrix_t m);
 void factor_leaf_stage_fp64(hss_matrix_t m);
 void free_factor(hss_matrix_t m);

@@ -27,6 +27,8 @@ HSS_ERR_UNSUPPORTED = 7
 KERNELS = {"exponential": 0, "matern32": 1, "gaussian": 2, "laplace2d": 3, "yukawa": 4}
 HSS_P_FP64 = 0
 HSS_P_FP32 = 1
+HSS_P_BF16 = 2
+HSS_P_BF16X3 = 3
 HSS_COMPRESS_PLAIN = 0
 HSS_COMPRESS_SCALED = 1
 MODES = {"plain": HSS_COMPRESS_PLAIN, "scaled": HSS_COMPRESS_SCALED}

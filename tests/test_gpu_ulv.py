@@ -104,8 +104,11 @@ def test_random_hss_shapes(ctx, torch_dev, levels, leaf, rank):
 @pytest.mark.parametrize("levels,leaf,rank", [(2, 256, 96), (3, 250, 90), (2, 512, 200), (5, 32, 13)])
 def test_every_tile_shape_gives_the_oracle_factorization(ctx, torch_dev, levels, leaf, rank):
     # every GEMM batch forced to one tile shape in turn (rank 13 leaves ragged
-    # tiles and a partial K slice), FP64 against the oracle, and the mixed
-    # factorization + refinement with the FP32 products on two of the shapes
+    # tiles and a partial K slice), FP64 against the oracle; the mixed
+    # factorization + refinement with the FP32 products on two of the shapes,
+    # and with the split-BF16 products on every shape (these leaves keep their
+    # pivots far above 2^-10 |D|_inf, so none is redone in FP64 and the
+    # unrefined solve shows the products' own error, about 2^-16)
     from paper_2311_00921_amd import hss
 
     torch = torch_dev
@@ -133,6 +136,16 @@ def test_every_tile_shape_gives_the_oracle_factorization(ctx, torch_dev, levels,
             hss.hss_ulv_factor(ctx, m, hss.HSS_P_FP32)
             x, it, rr, ok = hss.hss_ulv_solve_refined(ctx, m, bd, 1e-12, 20)
             assert ok, (v, it, rr)
+            assert rel(x.cpu().numpy(), x_or) <= 1e-10, (v, rel(x.cpu().numpy(), x_or))
+        for v in range(len(hss.GEMM_TILES)):
+            print(f"case tile {hss.GEMM_TILES[v]} BF16x3 n={h.n} rank={rank}", flush=True)
+            hss.hss_set_gemm_variants(ctx, m, [v] * n32, hss.HSS_P_BF16X3)
+            hss.hss_ulv_factor(ctx, m, hss.HSS_P_BF16X3)
+            assert hss.hss_get_info(m).promoted_nodes == 0
+            x0 = hss.hss_ulv_solve(ctx, m, bd).cpu().numpy()
+            assert 1e-9 < rel(x0, x_or) <= 1e-3, (v, rel(x0, x_or))
+            x, it, rr, ok = hss.hss_ulv_solve_refined(ctx, m, bd, 1e-12, 20)
+            assert ok and it <= 6, (v, it, rr)
             assert rel(x.cpu().numpy(), x_or) <= 1e-10, (v, rel(x.cpu().numpy(), x_or))
     finally:
         hss.hss_matrix_destroy(m)
