@@ -28,6 +28,10 @@ CFLAGS = [
     "-Wno-unused-function",
     "-Wno-unused-variable",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core accumulators in ordinary VGPRs: without it the compiler moves
+    # the GEMM accumulators between AGPRs and VGPRs around every K slice
+    # (waiting for the MFMA chain to drain); 5% faster leaf rank-2r update
+    "-mllvm", "-amdgpu-mfma-vgpr-form=1",
     "-I", INCLUDE,
     "-I", CSRC,
 ]
