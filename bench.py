@@ -548,8 +548,7 @@ def sweep_leg(hss, torch, np, ctx, steps, warmup):
     claims (Sec. 5.4-5.5): the FP64 one-call factor + solve (autotuned tiles)
     of the Matern-3/2 workload (3-D uniform points, length 0.2, nugget 1e-6,
     scaled construction, rank 100) for N = 4096 .. 262144 at leaf 256, and for
-    leaf 128, 512 and 1024 at N = 262144 (leaf 1024 exceeds the 512-row block
-    limit and is reported as unsupported)."""
+    leaf 128, 512 and 1024 at N = 262144."""
     import dataclasses
 
     import synth
@@ -561,10 +560,6 @@ def sweep_leg(hss, torch, np, ctx, steps, warmup):
     out = []
     for w in configs:
         print(f"# sweep: {w.name} N={w.n} leaf={w.leaf}", file=sys.stderr, flush=True)
-        if w.leaf > 512:
-            out.append({"workload": w.name, "N": w.n, "leaf": w.leaf, "rank": w.rank,
-                        "error": "unsupported: leaf blocks above 512 rows"})
-            continue
         s = w.rank + w.oversample
         X = torch.from_numpy(w.points()).cuda()
         Om = torch.from_numpy(np.ascontiguousarray(w.omega(s).T)).cuda().t()
@@ -600,7 +595,7 @@ def table2_leg(hss, torch, np, ctx):
     the off-diagonal row blocks, here seen through rank + 16 random samples).
     Eq. 18 (construction error) on 256 sampled rows of A b with the exact rows
     by direct kernel evaluation; Eq. 19 (solve error) in full. The (400, 512)
-    row needs blocks of 800 rows above the leaves, beyond this library's 512."""
+    row has blocks of 800 rows above the leaves."""
     import dataclasses
     import csv
 
@@ -620,10 +615,6 @@ def table2_leg(hss, torch, np, ctx):
             rec = {"kernel": name, "N": base.n, "max_rank": rank, "leaf": leaf, "construction": "plain",
                    "paper_construct_error": printed[(rank, leaf)][col],
                    "paper_solve_error": printed[(rank, leaf)][col + 1]}
-            if 2 * rank > 512:
-                rec["error"] = f"unsupported: blocks of {2 * rank} rows above the leaves (limit 512)"
-                out.append(rec)
-                continue
             w = dataclasses.replace(base, name=f"table2_{name}_r{rank}_l{leaf}", rank=rank, leaf=leaf, **kw)
             print(f"# table2 leg: {name} rank {rank} leaf {leaf}", file=sys.stderr, flush=True)
             s = rank + 16

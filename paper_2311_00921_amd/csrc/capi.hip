@@ -430,14 +430,14 @@ hss_status hss_import(hss_ctx_t ctx, const hss_desc* d, hss_matrix_t* out) {
     NodeDesc& nd = m->nodes[nleaves - 1 + i];
     nd.lo = d->leaf_lo[i];
     nd.npts = (int32_t)(d->leaf_lo[i + 1] - d->leaf_lo[i]);
-    HSS_CHECK(nd.npts >= 1 && nd.npts <= 512, HSS_ERR_INVALID_ARGUMENT, "leaf sizes must be in [1, 512]");
+    HSS_CHECK(nd.npts >= 1 && nd.npts <= kMaxBlock, HSS_ERR_INVALID_ARGUMENT, "leaf sizes must be in [1, 1024]");
   }
   for (int k = 1; k < m->nnodes; ++k) m->nodes[k].r = d->rank[k];
   layout_representation(m);
   for (int k = 1; k < m->nnodes; ++k)
-    HSS_CHECK(m->nodes[k].n <= 512 && m->nodes[k].r <= 256, HSS_ERR_UNSUPPORTED,
-              "blocks above 512 rows or ranks above 256 are not supported");
-  HSS_CHECK(m->nodes[0].n <= 512, HSS_ERR_UNSUPPORTED, "root block above 512 rows");
+    HSS_CHECK(m->nodes[k].n <= kMaxBlock && m->nodes[k].r <= kMaxRank, HSS_ERR_UNSUPPORTED,
+              "blocks above 1024 rows or ranks above 512 are not supported");
+  HSS_CHECK(m->nodes[0].n <= kMaxBlock, HSS_ERR_UNSUPPORTED, "root block above 1024 rows");
   hipStream_t s = ctx->stream;
   HSS_HIP(hipMemcpyAsync(m->dD, d->D, sizeof(double) * m->lenD, hipMemcpyHostToDevice, s));
   if (L > 0) {
@@ -486,8 +486,9 @@ hss_status hss_construct(hss_ctx_t ctx, const double* d_points, int64_t n, int32
     HSS_CHECK(ctx && d_points && kernel && opts && out, HSS_ERR_INVALID_ARGUMENT, "NULL argument");
     HSS_CHECK(n >= 1, HSS_ERR_INVALID_ARGUMENT, "n must be >= 1");
     HSS_CHECK(dim >= 1 && dim <= 3, HSS_ERR_INVALID_ARGUMENT, "dim must be 1, 2 or 3");
-    HSS_CHECK(opts->leaf_size >= 2 && opts->leaf_size <= 512, HSS_ERR_INVALID_ARGUMENT, "leaf_size must be in [2, 512]");
-    HSS_CHECK(opts->rank >= 0 && opts->rank <= 256, HSS_ERR_INVALID_ARGUMENT, "rank must be in [0, 256]");
+    HSS_CHECK(opts->leaf_size >= 2 && opts->leaf_size <= kMaxBlock, HSS_ERR_INVALID_ARGUMENT,
+              "leaf_size must be in [2, 1024]");
+    HSS_CHECK(opts->rank >= 0 && opts->rank <= kMaxRank, HSS_ERR_INVALID_ARGUMENT, "rank must be in [0, 512]");
     HSS_CHECK(opts->rank > 0 || opts->tol > 0.0, HSS_ERR_INVALID_ARGUMENT, "adaptive rank needs tol > 0");
     HSS_CHECK(opts->max_rank >= 0, HSS_ERR_INVALID_ARGUMENT, "max_rank must be >= 0");
     HSS_CHECK(opts->mode == HSS_COMPRESS_SCALED || opts->mode == HSS_COMPRESS_PLAIN, HSS_ERR_INVALID_ARGUMENT,
@@ -501,7 +502,8 @@ hss_status hss_construct(hss_ctx_t ctx, const double* d_points, int64_t n, int32
     HSS_CHECK(opts->levels == 0 || opts->levels == L, HSS_ERR_INVALID_ARGUMENT,
               "levels must equal ceil(log2(N / leaf_size)) = " + std::to_string(L));
     HSS_CHECK(L <= 20, HSS_ERR_UNSUPPORTED, "too many levels");
-    HSS_CHECK(L == 0 || (d_omega && s >= 1 && s <= 512), HSS_ERR_INVALID_ARGUMENT, "need a test matrix with 1..512 columns");
+    HSS_CHECK(L == 0 || (d_omega && s >= 1 && s <= kMaxSamples), HSS_ERR_INVALID_ARGUMENT,
+              "need a test matrix with 1..512 columns");
     HSS_CHECK(L == 0 || opts->rank == 0 || s >= opts->rank, HSS_ERR_INVALID_ARGUMENT, "need s >= rank");
     const bool sized = opts->rank == 0 && (opts->rank_model != nullptr || opts->sample_start > 0);
     HSS_CHECK(opts->sample_start >= 0 && opts->probes >= 0 && opts->probes <= 64 && opts->judge_factor >= 0.0,

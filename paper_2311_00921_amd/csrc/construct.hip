@@ -255,8 +255,8 @@ __global__ __launch_bounds__(256) void k_qrcp(CNode* __restrict__ cn, double* __
   double* H = Hb + c.offH;
   double* Q = Qb + c.offQ;
   double* R = Rb + c.offR;
-  __shared__ double cnorm[512];
-  __shared__ double sgn[512];
+  __shared__ double cnorm[kMaxSamples];
+  __shared__ double sgn[kMaxSamples];
   __shared__ int sp, sk;
   __shared__ double salpha, sR00;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
@@ -400,8 +400,8 @@ __global__ __launch_bounds__(256) void k_judge(const CNode* __restrict__ cn, con
   const int n = c.n, k = c.k;
   const double* Y = Yb + c.offY + (int64_t)sb * n;
   const double* Q = Qb + c.offQ;
-  __shared__ double y[512];
-  __shared__ double cq[256];
+  __shared__ double y[kMaxBlock];
+  __shared__ double cq[kMaxRank];
   __shared__ double red[2][256];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   double num = 0.0, den = 0.0;
@@ -606,7 +606,7 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
     NodeDesc& nd = m->nodes[nleaves - 1 + i];
     nd.lo = leaf_lo[i];
     nd.npts = (int32_t)(leaf_lo[i + 1] - leaf_lo[i]);
-    HSS_CHECK(nd.npts >= 1 && nd.npts <= 512, HSS_ERR_UNSUPPORTED, "leaf sizes must be in [1, 512]");
+    HSS_CHECK(nd.npts >= 1 && nd.npts <= kMaxBlock, HSS_ERR_UNSUPPORTED, "leaf sizes must be in [1, 1024]");
   }
   // provisional ranks: the leaf layout (D offsets) depends on the leaves only
   for (int k = 1; k < m->nnodes; ++k) m->nodes[k].r = 1;
@@ -631,7 +631,7 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
   }
   const int kfix = o.rank;
   int kcap = o.rank > 0 ? o.rank : (o.max_rank > 0 ? o.max_rank : 128);
-  kcap = std::min(kcap, 256);
+  kcap = std::min(kcap, kMaxRank);
   if (sp.s_basis == 0) {
     // sample count from the learned rank model: largest predicted node rank + 8
     std::vector<double> hb((size_t)nleaves * 6);
@@ -730,7 +730,7 @@ bool construct(hss_matrix_t m, const double* d_points, int32_t dim, const hss_ke
       oR += (int64_t)kcap * s;
       nmax = std::max(nmax, c.n);
     }
-    HSS_CHECK(nmax <= 512, HSS_ERR_UNSUPPORTED, "diagonal block larger than 512");
+    HSS_CHECK(nmax <= kMaxBlock, HSS_ERR_UNSUPPORTED, "diagonal block larger than 1024");
     Lb.ensure(oM);
     Ib.ensure(oM);
     Yb.ensure(oY);

@@ -126,8 +126,8 @@ __global__ __launch_bounds__(256) void k_house_basis(const NodeDesc* __restrict_
   T* Tm = Tbase + nd.offT;
   T* Sg = Sgbase + nd.offSg;
   __shared__ double red[256];
-  __shared__ double tau[256];     // r <= 256
-  __shared__ double w[256];
+  __shared__ double tau[kMaxRank];
+  __shared__ double w[kMaxRank];
   __shared__ double bcast[2];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
   for (int64_t e = tid; e < (int64_t)n * r; e += 256) V[e] = B[e];
@@ -1368,7 +1368,7 @@ __global__ void k_sum_logdet(const double* __restrict__ part, int count, double*
 // their time is the per-block chain, not the device throughput.
 template <typename T>
 static void launch_pchol(const hss_matrix_t m, int first, int count, int nmax, T* F, hipStream_t s) {
-  HSS_CHECK(nmax <= 512, HSS_ERR_UNSUPPORTED, "diagonal block larger than 512");
+  HSS_CHECK(nmax <= kMaxBlock, HSS_ERR_UNSUPPORTED, "diagonal block larger than 1024");
   dim3 grid(count);
   const bool narrow = count <= 64;
   if (nmax <= 256 && !narrow)
@@ -1377,11 +1377,14 @@ static void launch_pchol(const hss_matrix_t m, int first, int count, int nmax, T
   else if (nmax <= 256)
     hipLaunchKernelGGL((k_pchol<T, 256, false, 512>), grid, dim3(512), 0, s, m->dnodes, first, F, m->dinfo,
                        m->dlogdet, m->dpmin);
-  else if (!narrow)
+  else if (nmax <= 512 && !narrow)
     hipLaunchKernelGGL((k_pchol<T, 512, false, 256>), grid, dim3(256), 0, s, m->dnodes, first, F, m->dinfo,
                        m->dlogdet, m->dpmin);
-  else
+  else if (nmax <= 512)
     hipLaunchKernelGGL((k_pchol<T, 512, false, 512>), grid, dim3(512), 0, s, m->dnodes, first, F, m->dinfo,
+                       m->dlogdet, m->dpmin);
+  else  // the panel frame (16 x 1025 values) takes most of the LDS: one block per compute unit
+    hipLaunchKernelGGL((k_pchol<T, kMaxBlock, false, 512>), grid, dim3(512), 0, s, m->dnodes, first, F, m->dinfo,
                        m->dlogdet, m->dpmin);
   HSS_HIP(hipGetLastError());
 }
@@ -1424,8 +1427,11 @@ void launch_pchol_external(const NodeDesc* nodes, int first, int count, int nmax
   else if (nmax <= 512)
     hipLaunchKernelGGL((k_pchol<double, 512, true>), grid, block, 0, s, nodes, first, F, info, logdet,
                        (double*)nullptr);
+  else if (nmax <= kMaxBlock)
+    hipLaunchKernelGGL((k_pchol<double, kMaxBlock, true, 512>), grid, dim3(512), 0, s, nodes, first, F, info,
+                       logdet, (double*)nullptr);
   else
-    HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "diagonal block larger than 512");
+    HSS_CHECK(false, HSS_ERR_UNSUPPORTED, "diagonal block larger than 1024");
   HSS_HIP(hipGetLastError());
 }
 

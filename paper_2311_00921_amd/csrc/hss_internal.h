@@ -85,6 +85,12 @@ struct LevelPlan {
 // Split point of a root factored in two LDS blocks (LevelPlan::root_split).
 __host__ __device__ inline int root_split_h(int n) { return (n + 1) / 2; }
 
+// Size limits: rows of a diagonal block (a leaf, or two children's skeletons
+// merged), the rank of a node, and the sample columns of a construction.
+constexpr int kMaxBlock = 1024;
+constexpr int kMaxRank = 512;
+constexpr int kMaxSamples = 512;
+
 // Batched GEMM entry: C = alpha * op(A) op(B) + beta * Cin, optional symmetric
 // permutation of the output from [S;R] to [R;S] order (perm_r = r > 0).
 struct GemmDesc {

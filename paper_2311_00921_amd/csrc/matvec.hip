@@ -73,8 +73,8 @@ __global__ __launch_bounds__(MV_NT) void k_mv_leaf_up(const NodeDesc* __restrict
                                                       double* __restrict__ xt) {
   const NodeDesc nd = nodes[first + blockIdx.x];
   const int n = nd.n, r = nd.r;
-  __shared__ double sx[512];
-  __shared__ double sy[512];
+  __shared__ double sx[kMaxBlock];
+  __shared__ double sy[kMaxBlock];
   for (int64_t c = 0; c < nrhs; ++c) {
     for (int i = threadIdx.x; i < n; i += MV_NT) sx[i] = x[perm[nd.lo + i] + c * ld];
     __syncthreads();
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(MV_NT) void k_mv_up(const NodeDesc* __restrict__ no
   if (nd.r == 0) return;
   const NodeDesc c1 = nodes[nd.c1], c2 = nodes[nd.c2];
   const int n = nd.n;
-  __shared__ double sv[512];
+  __shared__ double sv[kMaxBlock];
   for (int64_t c = 0; c < nrhs; ++c) {
     for (int i = threadIdx.x; i < n; i += MV_NT)
       sv[i] = i < c1.r ? xt[c1.offR * nrhs + i + c * c1.r] : xt[c2.offR * nrhs + (i - c1.r) + c * c2.r];
@@ -114,7 +114,7 @@ __global__ __launch_bounds__(MV_NT) void k_mv_down(const NodeDesc* __restrict__ 
   const NodeDesc c1 = nodes[nd.c1], c2 = nodes[nd.c2];
   const int r1 = c1.r, r2 = c2.r, r = nd.r;
   const double* S = Sb + nd.offS;
-  __shared__ double s1[256], s2[256], sp[256], o[512];
+  __shared__ double s1[kMaxRank], s2[kMaxRank], sp[kMaxRank], o[kMaxBlock];
   for (int64_t c = 0; c < nrhs; ++c) {
     for (int i = threadIdx.x; i < r1; i += MV_NT) s1[i] = xt[c1.offR * nrhs + i + c * r1];
     for (int i = threadIdx.x; i < r2; i += MV_NT) s2[i] = xt[c2.offR * nrhs + i + c * r2];
@@ -143,8 +143,8 @@ __global__ __launch_bounds__(MV_NT) void k_mv_leaf_down(const NodeDesc* __restri
   const NodeDesc nd = nodes[first + blockIdx.x];
   const int n = nd.n, r = nd.r;
   if (r == 0) return;
-  __shared__ double sw[256];
-  __shared__ double sy[512];
+  __shared__ double sw[kMaxRank];
+  __shared__ double sy[kMaxBlock];
   for (int64_t c = 0; c < nrhs; ++c) {
     for (int j = threadIdx.x; j < r; j += MV_NT) sw[j] = yt[nd.offR * nrhs + j + c * r];
     __syncthreads();
@@ -155,8 +155,8 @@ __global__ __launch_bounds__(MV_NT) void k_mv_leaf_down(const NodeDesc* __restri
   }
 }
 
-// y = A x over the stages (leaves first). Block sizes up to 512 and ranks up to
-// 256 (checked at construction and import).
+// y = A x over the stages (leaves first). Block sizes up to kMaxBlock and ranks
+// up to kMaxRank (checked at construction and import).
 void matvec_fp64(hss_matrix_t m, const double* x, double* y, int64_t nrhs, int64_t ld) {
   hipStream_t s = m->ctx->stream;
   ensure_vec_ws(m, nrhs);

@@ -457,7 +457,7 @@ __device__ __forceinline__ void lower_t_solve_cols(const T* __restrict__ F, int 
   }
 }
 
-template <typename T, int NT, int RMX>
+template <typename T, int NT, int RMX, int NMX>
 __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_fwd(const NodeDesc* __restrict__ nodes, int first,
                                                   const T* __restrict__ Fb, const T* __restrict__ Vb,
                                                   const T* __restrict__ Yb, const T* __restrict__ Sgb,
@@ -469,7 +469,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_fwd(const NodeDesc* __r
   const int p = first + blockIdx.x;
   const NodeDesc nd = nodes[p];
   const int n = nd.n, r = nd.r, m = nd.m;
-  __shared__ T sb[512 * RC];
+  __shared__ T sb[NMX * RC];
   __shared__ T st[RMX * RC];
   __shared__ T su[RMX * RC];
   __shared__ T tm[RMX * RC];
@@ -540,7 +540,7 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_fwd(const NodeDesc* __r
     for (int c = 0; c < nc; ++c) pp[nd.child_row + j + (int64_t)(c0 + c) * par.n] = Sg[j] * sb[j + c * n];
 }
 
-template <typename T, int NT, int RMX>
+template <typename T, int NT, int RMX, int NMX>
 __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_bwd(const NodeDesc* __restrict__ nodes, int first,
                                                   const T* __restrict__ Fb, const T* __restrict__ Vb,
                                                   const T* __restrict__ Yb, const T* __restrict__ Sgb,
@@ -552,11 +552,11 @@ __global__ __launch_bounds__(NT, 1024 / NT) void k_solve_bwd(const NodeDesc* __r
   const int p = first + blockIdx.x;
   const NodeDesc nd = nodes[p];
   const int n = nd.n, r = nd.r, m = nd.m;
-  __shared__ T sx[512 * RC];
+  __shared__ T sx[NMX * RC];
   __shared__ T st[RMX * RC];
   __shared__ T su[RMX * RC];
   __shared__ T scr[SNB * RC];
-  __shared__ T tm[512 * RC];
+  __shared__ T tm[NMX * RC];
   __shared__ T red[NT * RC];  // row_gemv_wide needs (NT / 256) * 512, col_dots_split NT * RC
   T* vp = vec + nd.offVec * nrhs;
   const T* F = Fb + nd.offF;
@@ -652,21 +652,40 @@ void ensure_vec_ws(hss_matrix_t m, int64_t nrhs) {
   m->ws_nrhs = nrhs;
 }
 
+// LDS frame of a stage's solve kernels: (rank, rows) up to (128, 512),
+// (256, 512), (128, 1024) or (512, 1024).
+static int solve_shape(const LevelPlan& lp) {
+  if (lp.nmax <= 512) return lp.rmax <= 128 ? 0 : 1;
+  return lp.rmax <= 128 ? 2 : 3;
+}
+
 // One stage of the forward sweep (roots finish with y = L^{-1} b) and of the
 // backward sweep, for right-hand sides c0 .. c0 + nc - 1, on stream s.
 template <typename T>
 static void launch_fwd(hss_matrix_t m, int si, const T* F, const T* V, const T* Yw, const T* Sg, T* vec, const T* Li,
                        int inv, const double* b, int64_t nrhs, int64_t c0, int nc, int64_t ld, hipStream_t s) {
   const LevelPlan& lp = m->stages[si];
-#define HSS_FWD(NT, RMX)                                                                                          \
-  hipLaunchKernelGGL((k_solve_fwd<T, NT, RMX>), dim3(lp.count), dim3(NT), 0, s, m->dnodes, lp.first, F, V, Yw, Sg, \
-                     vec, nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, lp.leaf, Li, (const int64_t*)m->dOffLi, \
-                     inv)
-  HSS_CHECK(lp.rmax <= 256 && lp.nmax <= 512, HSS_ERR_UNSUPPORTED, "solve: rank above 256 or block above 512");
+#define HSS_FWD(NT, RMX, NMX)                                                                                   \
+  hipLaunchKernelGGL((k_solve_fwd<T, NT, RMX, NMX>), dim3(lp.count), dim3(NT), 0, s, m->dnodes, lp.first, F, V, Yw, \
+                     Sg, vec, nrhs, (int)c0, nc, b, ld, (const int64_t*)m->dperm, lp.leaf, Li,                     \
+                     (const int64_t*)m->dOffLi, inv)
+  HSS_CHECK(lp.rmax <= kMaxRank && lp.nmax <= kMaxBlock, HSS_ERR_UNSUPPORTED,
+            "solve: rank above 512 or block above 1024");
+  const int shape = solve_shape(lp);
   if (lp.count <= kSolveWideNodes) {
-    if (lp.rmax <= 128) HSS_FWD(1024, 128); else HSS_FWD(1024, 256);
+    switch (shape) {
+      case 0: HSS_FWD(1024, 128, 512); break;
+      case 1: HSS_FWD(1024, 256, 512); break;
+      case 2: HSS_FWD(1024, 128, 1024); break;
+      default: HSS_FWD(1024, 512, 1024); break;
+    }
   } else {
-    if (lp.rmax <= 128) HSS_FWD(256, 128); else HSS_FWD(256, 256);
+    switch (shape) {
+      case 0: HSS_FWD(256, 128, 512); break;
+      case 1: HSS_FWD(256, 256, 512); break;
+      case 2: HSS_FWD(256, 128, 1024); break;
+      default: HSS_FWD(256, 512, 1024); break;
+    }
   }
 #undef HSS_FWD
   HSS_HIP(hipGetLastError());
@@ -676,14 +695,25 @@ template <typename T>
 static void launch_bwd(hss_matrix_t m, int si, const T* F, const T* V, const T* Yw, const T* Sg, T* vec, const T* Li,
                        int inv, double* x, int64_t nrhs, int64_t c0, int nc, int64_t ld, hipStream_t s) {
   const LevelPlan& lp = m->stages[si];
-#define HSS_BWD(NT, RMX)                                                                                          \
-  hipLaunchKernelGGL((k_solve_bwd<T, NT, RMX>), dim3(lp.count), dim3(NT), 0, s, m->dnodes, lp.first, F, V, Yw, Sg, \
-                     vec, nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, lp.leaf, Li, (const int64_t*)m->dOffLi, \
-                     inv)
+#define HSS_BWD(NT, RMX, NMX)                                                                                   \
+  hipLaunchKernelGGL((k_solve_bwd<T, NT, RMX, NMX>), dim3(lp.count), dim3(NT), 0, s, m->dnodes, lp.first, F, V, Yw, \
+                     Sg, vec, nrhs, (int)c0, nc, x, ld, (const int64_t*)m->dperm, lp.leaf, Li,                     \
+                     (const int64_t*)m->dOffLi, inv)
+  const int shape = solve_shape(lp);
   if (lp.count <= kSolveWideNodes) {
-    if (lp.rmax <= 128) HSS_BWD(1024, 128); else HSS_BWD(1024, 256);
+    switch (shape) {
+      case 0: HSS_BWD(1024, 128, 512); break;
+      case 1: HSS_BWD(1024, 256, 512); break;
+      case 2: HSS_BWD(1024, 128, 1024); break;
+      default: HSS_BWD(1024, 512, 1024); break;
+    }
   } else {
-    if (lp.rmax <= 128) HSS_BWD(256, 128); else HSS_BWD(256, 256);
+    switch (shape) {
+      case 0: HSS_BWD(256, 128, 512); break;
+      case 1: HSS_BWD(256, 256, 512); break;
+      case 2: HSS_BWD(256, 128, 1024); break;
+      default: HSS_BWD(256, 512, 1024); break;
+    }
   }
 #undef HSS_BWD
   HSS_HIP(hipGetLastError());

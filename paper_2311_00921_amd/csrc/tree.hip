@@ -22,7 +22,7 @@ namespace {
 
 constexpr int TB_NT = 256;
 constexpr int TB_CHUNK = 4096;     // points per workgroup in the per-node passes
-constexpr int TB_SORT = 1024;      // largest node the last-level sort takes (leaves up to 512)
+constexpr int TB_SORT = 2 * kMaxBlock;  // largest node the last-level sort takes (two largest leaves)
 constexpr int TB_IDX_BITS = 40;    // point indices below 2^40
 
 // Order-preserving map of a double to uint64 (-0 taken as +0, so that equal

@@ -94,7 +94,12 @@ def test_exp2d_n2048_plain_vs_oracle_and_dense(ctx, torch_dev):
                                                (3, 256, 200), (2, 512, 200), (2, 512, 256), (2, 300, 136),
                                                # ranks 97..128: the fused LDS basis QR with its 128 frame, and the
                                                # R-block Cholesky + 128-row S-row kernel above the leaves
-                                               (3, 256, 100), (3, 200, 112), (4, 128, 120)])
+                                               (3, 256, 100), (3, 200, 112), (4, 128, 120),
+                                               # blocks above 512 rows (the 1024-row partial Cholesky and solve
+                                               # frames): leaf 1024; Table 2's (400, 512) shape with 800-row
+                                               # blocks above the leaves and an 800-row root; the largest block
+                                               # and rank (1024, 512)
+                                               (1, 1024, 100), (2, 512, 400), (1, 1024, 512)])
 def test_random_hss_shapes(ctx, torch_dev, levels, leaf, rank):
     d = synth.random_hss(levels, leaf, rank, seed=levels * 100 + rank)
     h = O.HSS(d["n"], d["levels"], d["ranges"], d["rank"], d["D"], d["U"], d["E"], d["S"])
