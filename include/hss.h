@@ -84,10 +84,10 @@ typedef struct {
 typedef enum { HSS_COMPRESS_PLAIN = 0, HSS_COMPRESS_SCALED = 1 } hss_compress_mode;
 
 typedef struct {
-  int32_t leaf_size;   /* >= 2: maximum points per leaf */
+  int32_t leaf_size;   /* 2..1024: maximum points per leaf */
   int32_t levels;      /* 0 = derive ceil(log2(N/leaf_size)); otherwise must equal it */
-  int32_t rank;        /* 1..256 fixed rank per node; 0 = adaptive by tol */
-  int32_t max_rank;    /* cap for adaptive ranks (0 = 128; at most 256) */
+  int32_t rank;        /* 1..512 fixed rank per node; 0 = adaptive by tol */
+  int32_t max_rank;    /* cap for adaptive ranks (0 = 128; at most 512) */
   double tol;          /* adaptive truncation: keep pivots with |R_jj| > tol*|R_00| */
   int32_t mode;        /* hss_compress_mode */
   /* Sample sizing (adaptive ranks, tol > 0). With neither of the two below,
@@ -266,8 +266,8 @@ hss_status hss_get_construct_stats(hss_matrix_t m, hss_construct_stats* out);
  * skeleton couplings S of sibling pairs; layout in hss_desc. Copies everything
  * (the host buffers may be freed on return) and synchronizes. Leaves the
  * matrix CONSTRUCTED. Errors: INVALID_ARGUMENT for NULL or inconsistent sizes
- * or a perm that is not a permutation; UNSUPPORTED for blocks above 512 rows
- * or ranks above 256. */
+ * or a perm that is not a permutation (leaves of more than 1024 points
+ * included); UNSUPPORTED for blocks above 1024 rows or ranks above 512. */
 hss_status hss_import(hss_ctx_t ctx, const hss_desc* desc, hss_matrix_t* out);
 
 /* Sizes (in elements) of the arrays hss_export writes: leaf_lo, rank, D, U, E, S, perm. */
