@@ -105,19 +105,29 @@ __device__ __forceinline__ void stage_frame(double (*X)[RM + kLdsPad], const T* 
 }
 
 // ---------------------------------------------------------------------------
-// Basis QR for ranks above 128 (one workgroup per node, in global memory): the
-// Householder QR of the orthonormal basis B (n x r), H_j = I - tau_j v_j v_j^T
-// with v_j unit lower trapezoidal, accumulated as H = H_1 ... H_r = I - V T V^T
-// (T upper triangular, T_jj = tau_j, T[:j, j] = -tau_j T[:j, :j] V[:, :j]^T v_j).
-// B = H R with R = diag(beta) up to rounding (B is orthonormal), so the first r
-// columns of H are B diag(Sg) with Sg_j = sign(beta_j). Writes V (into its slot,
-// unit diagonal and zeros above it), T and Sg; Y = V T follows as a GEMM.
+// Basis QR for ranks above 128 (one workgroup per node): the Householder QR of
+// the orthonormal basis B (n x r), H_j = I - tau_j v_j v_j^T with v_j unit
+// lower trapezoidal, accumulated as H = H_1 ... H_r = I - V T V^T (T upper
+// triangular). B = H R with R = diag(beta) up to rounding (B is orthonormal),
+// so the first r columns of H are B diag(Sg) with Sg_j = sign(beta_j). Writes V
+// (into its slot, unit diagonal and zeros above it), T and Sg; Y = V T follows
+// as a GEMM.
+// Blocked by panels of HB columns: a panel is factored in LDS one column at a
+// time; its block reflector I - V_p T_p V_p^T is applied to the trailing
+// columns in global memory (one wave per column, the column kept in registers
+// between the kb dot products and the update); and the panel's columns of T
+// follow from the earlier reflectors:
+//   T[0:k0, k0:k0+kb] = -T[0:k0, 0:k0] (V[:, 0:k0]^T V_p) T_p.
 // ---------------------------------------------------------------------------
 
+constexpr int kHouseNT = 512;
+constexpr int kHousePanel = 8;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_house_basis(const NodeDesc* __restrict__ nodes, int first,
-                                                     const T* __restrict__ Bbase, T* __restrict__ Vbase,
-                                                     T* __restrict__ Tbase, T* __restrict__ Sgbase) {
+__global__ __launch_bounds__(kHouseNT) void k_house_basis(const NodeDesc* __restrict__ nodes, int first,
+                                                          const T* __restrict__ Bbase, T* __restrict__ Vbase,
+                                                          T* __restrict__ Tbase, T* __restrict__ Sgbase) {
+  constexpr int NT = kHouseNT, NW = NT / 64, HB = kHousePanel, RPL = kMaxBlock / 64, CW = 3;
   const NodeDesc nd = nodes[first + blockIdx.x];
   const int n = nd.n, r = nd.r;
   if (r == 0) return;
@@ -125,81 +135,228 @@ __global__ __launch_bounds__(256) void k_house_basis(const NodeDesc* __restrict_
   T* V = Vbase + nd.offV;
   T* Tm = Tbase + nd.offT;
   T* Sg = Sgbase + nd.offSg;
-  __shared__ double red[256];
+  __shared__ double P[HB][kMaxBlock];  // the panel's columns (absolute row index)
+  __shared__ double Z[kMaxRank][HB];   // V[:, 0:k0]^T V_p, then times T_p
+  __shared__ double G[HB][HB + 1];     // V_p^T V_p
+  __shared__ double Tp[HB][HB + 1];
   __shared__ double tau[kMaxRank];
-  __shared__ double w[kMaxRank];
-  __shared__ double bcast[2];
+  __shared__ double red[NW];
+  __shared__ double bcast;
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  for (int64_t e = tid; e < (int64_t)n * r; e += 256) V[e] = B[e];
+  auto wsum = [](double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+  };
+  for (int64_t e = tid; e < (int64_t)n * r; e += NT) V[e] = B[e];
   __syncthreads();
-  for (int j = 0; j < r; ++j) {
-    T* x = V + (int64_t)j * n;
-    // norm of x[j+1:n] and x0 = x[j]
-    double p = 0.0;
-    for (int i = j + 1 + tid; i < n; i += 256) p += (double)x[i] * (double)x[i];
-    red[tid] = p;
+  for (int k0 = 0; k0 < r; k0 += HB) {
+    const int kb = min(HB, r - k0);
+    for (int c = 0; c < kb; ++c)
+      for (int i = k0 + tid; i < n; i += NT) P[c][i] = (double)V[i + (int64_t)(k0 + c) * n];
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (tid < o) red[tid] += red[tid + o];
+    // (1) the panel, column by column
+    for (int j = 0; j < kb; ++j) {
+      const int jj = k0 + j;
+      double p = 0.0;
+      for (int i = jj + 1 + tid; i < n; i += NT) p += P[j][i] * P[j][i];
+      p = wsum(p);
+      if (lane == 0) red[wid] = p;
+      __syncthreads();
+      if (tid == 0) {
+        double sig = 0.0;
+        for (int w = 0; w < NW; ++w) sig += red[w];
+        const double x0 = P[j][jj];
+        const double alpha = sqrt(x0 * x0 + sig);
+        // beta = -sign(x0) alpha, tau = (beta - x0) / beta, v = x / (x0 - beta) with v_0 = 1
+        const double beta = x0 >= 0.0 ? -alpha : alpha;
+        tau[jj] = alpha > 0.0 ? (beta - x0) / beta : 0.0;
+        bcast = alpha > 0.0 ? 1.0 / (x0 - beta) : 0.0;
+        Sg[jj] = (T)(beta >= 0.0 ? 1.0 : -1.0);
+      }
+      __syncthreads();
+      const double scale = bcast, tj = tau[jj];
+      for (int i = jj + 1 + tid; i < n; i += NT) P[j][i] *= scale;
+      // v_j: unit at row jj, zero above it (the panel rows above hold R, not needed)
+      for (int i = k0 + tid; i <= jj; i += NT) P[j][i] = (i == jj) ? 1.0 : 0.0;
+      __syncthreads();
+      for (int c = j + 1 + wid; c < kb; c += NW) {
+        double d = 0.0;
+        for (int i = jj + lane; i < n; i += 64) d += P[j][i] * P[c][i];
+        d = wsum(d) * tj;
+        for (int i = jj + lane; i < n; i += 64) P[c][i] -= d * P[j][i];
+      }
       __syncthreads();
     }
-    if (tid == 0) {
-      const double x0 = (double)x[j], sig = red[0];
-      const double alpha = sqrt(x0 * x0 + sig);
-      // beta = -sign(x0) alpha, tau = (beta - x0) / beta, v = x / (x0 - beta) with v_0 = 1
-      const double beta = x0 >= 0.0 ? -alpha : alpha;
-      const double t = alpha > 0.0 ? (beta - x0) / beta : 0.0;
-      const double scale = alpha > 0.0 ? 1.0 / (x0 - beta) : 0.0;
-      tau[j] = t;
-      bcast[0] = scale;
-      Sg[j] = (T)(beta >= 0.0 ? 1.0 : -1.0);
+    for (int c = 0; c < kb; ++c)
+      for (int i = k0 + tid; i < n; i += NT) V[i + (int64_t)(k0 + c) * n] = (T)P[c][i];
+    // (2) T_p: G = V_p^T V_p (a < j), T_p[j][j] = tau_j, T_p[0:j, j] = -tau_j T_p[0:j, 0:j] G[0:j, j]
+    for (int t = wid; t < kb * (kb - 1) / 2; t += NW) {
+      int j = 1;
+      while (j * (j + 1) / 2 <= t) ++j;
+      const int a = t - j * (j - 1) / 2;
+      double d = 0.0;
+      for (int i = k0 + j + lane; i < n; i += 64) d += P[a][i] * P[j][i];
+      d = wsum(d);
+      if (lane == 0) G[a][j] = d;
+    }
+    // Z = V[:, 0:k0]^T V_p: CW earlier columns per wave (each panel value read
+    // from LDS serves all of them), rows k0..n-1 (V_p is zero above k0), loaded
+    // four row blocks at a time
+    for (int c0 = wid * CW; c0 < k0; c0 += NW * CW) {
+      double acc[CW][HB];
+#pragma unroll
+      for (int q = 0; q < CW; ++q)
+#pragma unroll
+        for (int a = 0; a < HB; ++a) acc[q][a] = 0.0;
+      for (int u = 0; u < RPL; u += 4) {
+        double v[CW][4];
+#pragma unroll
+        for (int q = 0; q < CW; ++q)
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const int i = k0 + lane + 64 * (u + h);
+            v[q][h] = (c0 + q < k0 && i < n) ? (double)V[i + (int64_t)(c0 + q) * n] : 0.0;
+          }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int i = k0 + lane + 64 * (u + h);
+          if (i < n)
+#pragma unroll
+            for (int a = 0; a < HB; ++a) {
+              const double pa = a < kb ? P[a][i] : 0.0;
+#pragma unroll
+              for (int q = 0; q < CW; ++q) acc[q][a] += v[q][h] * pa;
+            }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < CW; ++q)
+#pragma unroll
+        for (int a = 0; a < HB; ++a) {
+          const double d = wsum(acc[q][a]);
+          if (lane == 0 && a < kb && c0 + q < k0) Z[c0 + q][a] = d;
+        }
     }
     __syncthreads();
-    const double scale = bcast[0], tj = tau[j];
-    for (int i = j + 1 + tid; i < n; i += 256) x[i] = (T)((double)x[i] * scale);
-    if (tid == 0) x[j] = (T)1.0;
+    if (tid == 0) {
+      for (int j = 0; j < kb; ++j) {
+        const double tj = tau[k0 + j];
+        for (int i = 0; i < j; ++i) {
+          double t = 0.0;
+          for (int c = i; c < j; ++c) t += Tp[i][c] * G[c][j];
+          Tp[i][j] = -tj * t;
+        }
+        Tp[j][j] = tj;
+        for (int i = j + 1; i < HB; ++i) Tp[i][j] = 0.0;
+      }
+    }
     __syncthreads();
-    // apply H_j to the remaining columns: y -= tau v (v^T y), one column per wave
-    for (int c = j + 1 + wid; c < r; c += 4) {
-      T* y = V + (int64_t)c * n;
-      double d = 0.0;
-      for (int i = j + lane; i < n; i += 64) d += (double)x[i] * (double)y[i];
+    // Z <- Z T_p (row by row), then T[0:k0, k0:k0+kb] = -T[0:k0, 0:k0] Z
+    for (int c = tid; c < k0; c += NT) {
+      double z[HB];
 #pragma unroll
-      for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
-      d *= tj;
-      for (int i = j + lane; i < n; i += 64) y[i] = (T)((double)y[i] - d * (double)x[i]);
+      for (int a = 0; a < HB; ++a) z[a] = a < kb ? Z[c][a] : 0.0;
+#pragma unroll
+      for (int j = HB - 1; j >= 0; --j) {
+        double t = 0.0;
+#pragma unroll
+        for (int a = 0; a <= j; ++a) t += z[a] * Tp[a][j];
+        if (j < kb) Z[c][j] = t;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < r; i += NT) {
+      double t[HB];
+#pragma unroll
+      for (int a = 0; a < HB; ++a) t[a] = 0.0;
+      if (i < k0) {
+        // eight independent loads of row i of T per step
+        for (int c0 = i; c0 < k0; c0 += 8) {
+          double tic[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) tic[q] = c0 + q < k0 ? (double)Tm[i + (int64_t)(c0 + q) * r] : 0.0;
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (c0 + q < k0)
+#pragma unroll
+              for (int a = 0; a < HB; ++a) t[a] -= tic[q] * Z[c0 + q][a];
+        }
+      } else if (i < k0 + kb) {
+#pragma unroll
+        for (int a = 0; a < HB; ++a) t[a] = Tp[i - k0][a];
+      }
+#pragma unroll
+      for (int a = 0; a < HB; ++a)
+        if (a < kb) Tm[i + (int64_t)(k0 + a) * r] = (T)t[a];
+    }
+    // (3) trailing columns: A <- (I - V_p T_p V_p^T)^T A = A - V_p T_p^T (V_p^T A),
+    // rows k0..n-1; CW columns per wave, read twice (dot products, then update)
+    for (int c0 = k0 + kb + wid * CW; c0 < r; c0 += NW * CW) {
+      double w[CW][HB];
+#pragma unroll
+      for (int q = 0; q < CW; ++q)
+#pragma unroll
+        for (int a = 0; a < HB; ++a) w[q][a] = 0.0;
+      for (int u = 0; u < RPL; u += 4) {
+        double v[CW][4];
+#pragma unroll
+        for (int q = 0; q < CW; ++q)
+#pragma unroll
+          for (int h = 0; h < 4; ++h) {
+            const int i = k0 + lane + 64 * (u + h);
+            v[q][h] = (c0 + q < r && i < n) ? (double)V[i + (int64_t)(c0 + q) * n] : 0.0;
+          }
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+          const int i = k0 + lane + 64 * (u + h);
+          if (i < n)
+#pragma unroll
+            for (int a = 0; a < HB; ++a) {
+              const double pa = a < kb ? P[a][i] : 0.0;
+#pragma unroll
+              for (int q = 0; q < CW; ++q) w[q][a] += v[q][h] * pa;
+            }
+        }
+      }
+      // w <- T_p^T w in place (from the last entry down: entry a needs w[0..a])
+#pragma unroll
+      for (int q = 0; q < CW; ++q) {
+#pragma unroll
+        for (int a = 0; a < HB; ++a) w[q][a] = a < kb ? wsum(w[q][a]) : 0.0;
+#pragma unroll
+        for (int a = HB - 1; a >= 0; --a) {
+          double t = 0.0;
+#pragma unroll
+          for (int b = 0; b <= a; ++b) t += Tp[b][a] * w[q][b];
+          w[q][a] = a < kb ? t : 0.0;
+        }
+      }
+      for (int u = 0; u < RPL; ++u) {
+        const int i = k0 + lane + 64 * u;
+        if (i < n) {
+          double pv[HB];
+#pragma unroll
+          for (int a = 0; a < HB; ++a) pv[a] = a < kb ? P[a][i] : 0.0;
+#pragma unroll
+          for (int q = 0; q < CW; ++q) {
+            if (c0 + q < r) {
+              T* ac = V + (int64_t)(c0 + q) * n + i;
+              double x = (double)*ac;
+#pragma unroll
+              for (int a = 0; a < HB; ++a) x -= pv[a] * w[q][a];
+              *ac = (T)x;
+            }
+          }
+        }
+      }
     }
     __syncthreads();
   }
-  // unit diagonal, zeros above it
-  for (int64_t e = tid; e < (int64_t)r * r; e += 256) {
+  // unit diagonal, zeros above it (rows above each panel hold R)
+  for (int64_t e = tid; e < (int64_t)r * r; e += NT) {
     const int i = (int)(e % r), c = (int)(e / r);
     if (i < c) V[i + (int64_t)c * n] = (T)0;
-  }
-  __syncthreads();
-  // T column by column: w = V[:, :j]^T v_j, T[:j, j] = -tau_j T[:j, :j] w
-  for (int j = 0; j < r; ++j) {
-    const T* vj = V + (int64_t)j * n;
-    for (int c = wid; c < j; c += 4) {
-      const T* vc = V + (int64_t)c * n;
-      double d = 0.0;
-      for (int i = j + lane; i < n; i += 64) d += (double)vc[i] * (double)vj[i];  // v_j is zero above row j
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) d += __shfl_xor(d, o, 64);
-      if (lane == 0) w[c] = d;
-    }
-    __syncthreads();
-    for (int i = tid; i < r; i += 256) {
-      double t = 0.0;
-      if (i < j) {
-        for (int c = i; c < j; ++c) t += (double)Tm[i + (int64_t)c * r] * w[c];
-        t *= -tau[j];
-      } else if (i == j) {
-        t = tau[j];
-      }
-      Tm[i + (int64_t)j * r] = (T)t;
-    }
-    __syncthreads();
   }
 }
 
@@ -2037,7 +2194,7 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
         gemm_run<T>(st[0], false, false, 1.0, 0.0, s);    // V_2 = B_2 U_1^{-1}
       } else {
         Prof pf(cx, "basis_qr", l);
-        hipLaunchKernelGGL((k_house_basis<T>), dim3(lp.count), dim3(256), 0, s, m->dnodes, lp.first, b.B, b.V,
+        hipLaunchKernelGGL((k_house_basis<T>), dim3(lp.count), dim3(kHouseNT), 0, s, m->dnodes, lp.first, b.B, b.V,
                            b.Tm, b.Sg);
         HSS_HIP(hipGetLastError());
       }
