@@ -162,6 +162,15 @@ def test_multiple_rhs_ragged_chunk(ctx, torch_dev):
     factor_and_compare(ctx, torch_dev, h, nrhs=6)
 
 
+@pytest.mark.parametrize("levels,leaf,rank,nrhs", [(3, 64, 16, 11), (2, 512, 200, 6), (3, 256, 96, 17)])
+def test_multiple_rhs_column_passes(ctx, torch_dev, levels, leaf, rank, nrhs):
+    # right-hand sides in passes of four with a ragged last pass (11 = 4 + 4 + 3,
+    # 17 = 4 x 4 + 1, 6 = 4 + 2), on the 512-row and rank-200 frames too
+    d = synth.random_hss(levels, leaf, rank, seed=700 + rank)
+    h = O.HSS(d["n"], d["levels"], d["ranges"], d["rank"], d["D"], d["U"], d["E"], d["S"])
+    factor_and_compare(ctx, torch_dev, h, nrhs=nrhs, check_blocks=False)
+
+
 def test_ragged_tree_scaled_matern(ctx, torch_dev):
     # N not a multiple of the leaf: leaves of 46-47 points, scaled construction
     X = synth.points_uniform(1500, 3, 1002)
