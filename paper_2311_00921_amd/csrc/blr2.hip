@@ -12,10 +12,14 @@
 //      diagonal blocks and Phi_c1 S Phi_c2^T between the leaves under the two
 //      children of each node, Phi_c being the product of the transfer matrices
 //      from c down to its leaves (Phi = E one level above the leaves).
-//   3. Dense Cholesky of the skeleton matrix: right-looking, 64-column panels;
-//      each diagonal block is factored and inverted in LDS, the panel below is
-//      multiplied by that inverse in place (rows independent), and the trailing
-//      lower triangle is updated by the batched FP64 MFMA GEMM.
+//   3. Dense Cholesky of the skeleton matrix: right-looking, 64-column panels
+//      in outer blocks of four; each diagonal block is factored and inverted by
+//      one wave in registers, the panel below is multiplied by that inverse in
+//      place (rows independent), and the lower triangle right of the panel is
+//      updated by the FP64 MFMA GEMM: inside the outer block per panel, after
+//      it with the block's full depth, the part beyond the next block on a
+//      second stream while the next block is factored (a lookahead of one
+//      block).
 //   Solve (Eq. 14): the leaf forward sweep, the two dense triangular solves
 //   (panel by panel, with the inverted diagonal blocks), the leaf backward sweep.
 //
@@ -30,6 +34,7 @@
 namespace hss {
 
 constexpr int DNB = 64;                // panel width of the skeleton Cholesky
+constexpr int DOB = 4;                 // panels per outer block (trailing updates of depth 4 DNB)
 constexpr int64_t kBlr2MaxK = 65536;   // skeleton rows
 constexpr int kSolveCols = 16;         // right-hand sides per dense-solve pass
 
@@ -50,7 +55,14 @@ struct Blr2State {
   std::vector<int64_t> offPhi, offG;  // per node
   std::vector<GemmBatch> phi;  // per tree level, deepest first
   std::vector<GemmBatch> g1, g2;  // per tree level of the coupling's node: G = Phi_c2 S^T, block = G Phi_c1^T
-  GemmBatch syrk;              // one entry per panel, launched as single-entry views
+  // Cholesky updates, launched as single-entry views: inside an outer block, each
+  // panel's update of the block's later columns (all rows below); after the
+  // block, the update of depth DOB * DNB of the next block's columns (tnext) and
+  // of the rest of the trailing matrix (trest, on the second stream)
+  GemmBatch inblk, tnext, trest;
+  std::vector<int> inblk_of, tnext_of, trest_of;  // per panel / per outer block: entry index or -1
+  hipEvent_t ev_block = nullptr;  // an outer block's panels are factored
+  hipEvent_t ev_rest = nullptr;   // the rest of the trailing matrix is updated
   double* dZ = nullptr;        // solve: K x kSolveCols each
   double* dY = nullptr;
   double* dW = nullptr;
@@ -77,74 +89,83 @@ __global__ __launch_bounds__(256) void k_blr2_diag(const NodeDesc* __restrict__ 
   }
 }
 
-// Cholesky of the diagonal block (k0, k0) of order jb <= 64 in LDS, then its
-// inverse. Writes L back (lower triangle), L^{-1} into Linv (64 x 64, zero
-// above the diagonal), the sum of log pivots into *pld. A non-positive pivot
+// Value of v held by lane l (l wave-uniform), through scalar registers.
+__device__ __forceinline__ double lane_value(double v, int l) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), l);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), l);
+  return __hiloint2double(hi, lo);
+}
+
+// Cholesky of the diagonal block (k0, k0) of order jb <= 64, then its inverse,
+// by one wave: lane i holds row i of the block in registers (rows and columns
+// past jb are padded with the identity, so every step runs unmasked).
+//   Factor, right-looking: at step j the pivot comes from lane j, column j is
+//   scaled, and each later column c takes L(c, j) from lane c; the 63 - j
+//   updates of a step are independent.
+//   Inverse X = L^{-1} from X L = I, row i of X on lane i, columns from the
+//   last down: X(i, c) = acc_c / L(c, c), then acc_q -= X(i, c) L(c, q) for
+//   q < c, row c of L read from LDS (one broadcast address per step).
+// Writes L back (lower triangle), L^{-1} into Linv (64 x 64, zero above the
+// diagonal and past jb), the sum of log pivots into *pld. A non-positive pivot
 // is recorded (the first failing row over all panels) and replaced by 1.
-__global__ __launch_bounds__(256) void k_dchol_diag(double* __restrict__ A, int64_t lda, int64_t k0, int jb,
-                                                    double* __restrict__ Linv, double* __restrict__ pld,
-                                                    int32_t* __restrict__ info) {
-  __shared__ double a[DNB][DNB + 1];    // a[col][row]
-  __shared__ double iv[DNB][DNB + 1];   // iv[col][row]
-  __shared__ double rd[DNB];
-  __shared__ double red[256];
-  const int t = threadIdx.x;
+__global__ __launch_bounds__(64) void k_dchol_diag(double* __restrict__ A, int64_t lda, int64_t k0, int jb,
+                                                   double* __restrict__ Linv, double* __restrict__ pld,
+                                                   int32_t* __restrict__ info) {
+  __shared__ double Ls[DNB][DNB + 1];  // Ls[row][col] = L(row, col), col <= row
+  const int i = threadIdx.x;
   double* Ab = A + k0 + k0 * lda;
-  for (int e = t; e < DNB * DNB; e += 256) {
-    const int i = e % DNB, j = e / DNB;
-    a[j][i] = (i < jb && j < jb && i >= j) ? Ab[i + j * lda] : (i == j ? 1.0 : 0.0);
-    iv[j][i] = 0.0;
-  }
+  // staged through LDS: 64 loads in flight would hold 64 addresses besides the row
+#pragma unroll 8
+  for (int c = 0; c < DNB; ++c)
+    Ls[i][c] = (i < jb && c < jb && i >= c) ? Ab[i + c * lda] : (i == c ? 1.0 : 0.0);
   __syncthreads();
-  for (int j = 0; j < jb; ++j) {
-    double d = a[j][j];
+  double a[DNB];
+#pragma unroll
+  for (int c = 0; c < DNB; ++c) a[c] = Ls[i][c];
+  __syncthreads();
+  int bad = -1;
+  double mine = 1.0, rmine = 1.0;
+#pragma unroll
+  for (int j = 0; j < DNB; ++j) {
+    double d = lane_value(a[j], j);
     if (!(d > 0.0)) {
-      if (t == 0) {
-        atomicMin(&info[1], (int32_t)(k0 + j));
-        atomicExch(&info[0], 1);
-      }
+      if (bad < 0) bad = j;
       d = 1.0;
     }
     const double piv = sqrt(d);
     const double rs = 1.0 / piv;
-    __syncthreads();  // every thread has read a[j][j]
-    for (int i = j + 1 + t; i < jb; i += 256) a[j][i] *= rs;
-    if (t == 0) {
-      a[j][j] = piv;
-      rd[j] = rs;
-    }
-    __syncthreads();
-    // trailing lower triangle: a[c][i] -= L(i, j) L(c, j) for j < c <= i < jb
-    const int w = jb - j - 1;
-    for (int e = t; e < w * w; e += 256) {
-      const int ii = e % w, cc = e / w;
-      if (ii >= cc) a[j + 1 + cc][j + 1 + ii] -= a[j][j + 1 + ii] * a[j][j + 1 + cc];
-    }
-    __syncthreads();
+    const bool me = i == j;
+    a[j] = me ? piv : a[j] * rs;
+    mine = me ? piv : mine;
+    rmine = me ? rs : rmine;
+#pragma unroll
+    for (int c = j + 1; c < DNB; ++c) a[c] -= a[j] * lane_value(a[j], c);
   }
-  // inverse by forward substitution, row i of every column c <= i per step
-  for (int i = 0; i < jb; ++i) {
-    if (t <= i) {
-      double s = (t == i) ? 1.0 : 0.0;
-      for (int q = t; q < i; ++q) s -= a[q][i] * iv[t][q];
-      iv[t][i] = s * rd[i];
-    }
-    __syncthreads();
+  if (bad >= 0 && i == 0) {
+    atomicMin(&info[1], (int32_t)(k0 + bad));
+    atomicExch(&info[0], 1);
   }
-  double lg = 0.0;
-  for (int j = t; j < jb; j += 256) lg += 2.0 * log(a[j][j]);
-  red[t] = lg;
+#pragma unroll
+  for (int c = 0; c < DNB; ++c) {
+    const double v = c <= i ? a[c] : 0.0;
+    Ls[i][c] = v;
+    if (i < jb && c < jb && c <= i) Ab[i + c * lda] = v;
+  }
+  double lg = i < jb ? log(mine) : 0.0;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) lg += __shfl_xor(lg, o, 64);
+  if (i == 0) *pld = 2.0 * lg;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
-    if (t < o) red[t] += red[t + o];
-    __syncthreads();
+#pragma unroll
+  for (int c = 0; c < DNB; ++c) a[c] = (c == i) ? 1.0 : 0.0;
+#pragma unroll
+  for (int c = DNB - 1; c >= 0; --c) {
+    a[c] *= lane_value(rmine, c);
+#pragma unroll
+    for (int q = 0; q < c; ++q) a[q] -= a[c] * Ls[c][q];
   }
-  if (t == 0) *pld = red[0];
-  for (int e = t; e < DNB * DNB; e += 256) {
-    const int i = e % DNB, j = e / DNB;
-    if (i < jb && j < jb && i >= j) Ab[i + j * lda] = a[j][i];
-    Linv[i + j * DNB] = (i < jb && j < jb) ? iv[j][i] : 0.0;
-  }
+#pragma unroll
+  for (int c = 0; c < DNB; ++c) Linv[i + c * DNB] = (i < jb && c < jb) ? a[c] : 0.0;
 }
 
 // The panel below the diagonal block: rows k0 + jb + 64 b .. of columns
@@ -450,17 +471,47 @@ void alloc_state(hss_matrix_t m, Blr2State& st) {
   for (auto& g : st.phi) gemm_upload(g, s);
   for (auto& g : st.g1) gemm_upload(g, s);
   for (auto& g : st.g2) gemm_upload(g, s);
-  // trailing updates of the Cholesky: A22 -= L21 L21^T, lower triangle
+  // updates of the Cholesky, A22 -= L21 L21^T (lower triangle): within an outer
+  // block of DOB panels, panel k updates the block's columns right of it over all
+  // rows below; after the block, the trailing matrix is updated with depth the
+  // block's width in two parts, the next block's columns and the rest
+  st.inblk_of.assign(st.npanel, -1);
+  const int nblock = (st.npanel + DOB - 1) / DOB;
+  st.tnext_of.assign(nblock, -1);
+  st.trest_of.assign(nblock, -1);
   for (int k = 0; k < st.npanel; ++k) {
     const int64_t k0 = (int64_t)k * DNB;
     const int jb = (int)std::min<int64_t>(DNB, K - k0);
-    const int64_t rem = K - k0 - jb;
-    if (rem <= 0) break;
+    const int64_t bend = std::min<int64_t>((int64_t)(k / DOB + 1) * DOB * DNB, K);  // end of this panel's block
+    const int64_t cols = bend - k0 - jb, rows = K - k0 - jb;
+    if (cols <= 0 || rows <= 0) continue;
     const double* Lp = st.dK + (k0 + jb) + k0 * K;
     double* C = st.dK + (k0 + jb) * (K + 1);
-    st.syrk.host.push_back({Lp, Lp, C, C, (int)rem, (int)rem, jb, (int)K, (int)K, (int)K, (int)K, 0, 0, nullptr, 1});
+    st.inblk_of[k] = (int)st.inblk.host.size();
+    st.inblk.host.push_back({Lp, Lp, C, C, (int)rows, (int)cols, jb, (int)K, (int)K, (int)K, (int)K, 0, 0, nullptr, 1});
   }
-  gemm_upload(st.syrk, s);
+  for (int q = 0; q < nblock; ++q) {
+    const int64_t b0 = (int64_t)q * DOB * DNB, bend = std::min<int64_t>(b0 + DOB * DNB, K);
+    const int64_t rem = K - bend;
+    if (rem <= 0) continue;
+    const int64_t w = std::min<int64_t>(DOB * DNB, rem);  // the next block's width
+    const int kd = (int)(bend - b0);
+    const double* Lp = st.dK + bend + b0 * K;
+    double* C = st.dK + bend * (K + 1);
+    st.tnext_of[q] = (int)st.tnext.host.size();
+    st.tnext.host.push_back({Lp, Lp, C, C, (int)rem, (int)w, kd, (int)K, (int)K, (int)K, (int)K, 0, 0, nullptr, 1});
+    const int64_t rr = rem - w;
+    if (rr <= 0) continue;
+    const double* Lr = Lp + w;
+    double* Cr = C + w * (K + 1);
+    st.trest_of[q] = (int)st.trest.host.size();
+    st.trest.host.push_back({Lr, Lr, Cr, Cr, (int)rr, (int)rr, kd, (int)K, (int)K, (int)K, (int)K, 0, 0, nullptr, 1});
+  }
+  gemm_upload(st.inblk, s);
+  gemm_upload(st.tnext, s);
+  gemm_upload(st.trest, s);
+  HSS_HIP(hipEventCreateWithFlags(&st.ev_block, hipEventDisableTiming));
+  HSS_HIP(hipEventCreateWithFlags(&st.ev_rest, hipEventDisableTiming));
 }
 
 void free_state(Blr2State* st) {
@@ -468,7 +519,11 @@ void free_state(Blr2State* st) {
   for (auto& g : st->phi) gemm_free(g);
   for (auto& g : st->g1) gemm_free(g);
   for (auto& g : st->g2) gemm_free(g);
-  gemm_free(st->syrk);
+  gemm_free(st->inblk);
+  gemm_free(st->tnext);
+  gemm_free(st->trest);
+  if (st->ev_block) (void)hipEventDestroy(st->ev_block);
+  if (st->ev_rest) (void)hipEventDestroy(st->ev_rest);
   void* ptrs[] = {st->dK, st->dLinv, st->dPhi, st->dG, st->dpanel, st->dinfo, st->dlog, st->dZ, st->doffK};
   for (void* p : ptrs)
     if (p) dev_free(p);
@@ -526,7 +581,14 @@ void factor_blr2(hss_matrix_t m) {
     gemm_launch_f64(st.g1[q], false, true, 1.0, 0.0, s);
     gemm_launch_f64(st.g2[q], false, true, 1.0, 0.0, s);
   }
-  // 3. dense Cholesky of the skeleton matrix
+  // 3. dense Cholesky of the skeleton matrix, with a lookahead of one outer
+  // block: after block q, the next block's columns are updated on the first
+  // stream and its panels factored there, while the rest of the trailing
+  // matrix is updated on the second stream (the two write disjoint columns;
+  // the next block's own trailing update waits for that rest update)
+  if (!cx->aux_stream) HSS_HIP(hipStreamCreateWithFlags(&cx->aux_stream, hipStreamNonBlocking));
+  hipStream_t a = cx->aux_stream;
+  bool rest_pending = false;
   const int64_t K = st.K;
   for (int k = 0; k < st.npanel; ++k) {
     const int64_t k0 = (int64_t)k * DNB;
@@ -534,14 +596,32 @@ void factor_blr2(hss_matrix_t m) {
     const int64_t rem = K - k0 - jb;
     double* Li = st.dLinv + (int64_t)k * DNB * DNB;
     Prof pf(cx, "blr2_cholesky", -1);
-    hipLaunchKernelGGL(k_dchol_diag, dim3(1), dim3(256), 0, s, st.dK, K, k0, jb, Li, st.dpanel + k, st.dinfo);
+    hipLaunchKernelGGL(k_dchol_diag, dim3(1), dim3(64), 0, s, st.dK, K, k0, jb, Li, st.dpanel + k, st.dinfo);
     HSS_HIP(hipGetLastError());
     if (rem <= 0) continue;
     hipLaunchKernelGGL(k_dtrsm_rows, dim3((unsigned)((rem + DNB - 1) / DNB)), dim3(256), 0, s, st.dK, K, K, k0, jb,
                        (const double*)Li);
     HSS_HIP(hipGetLastError());
-    gemm_launch_f64(entry_view(st.syrk, k, 0), false, true, -1.0, 1.0, s);
+    if (st.inblk_of[k] >= 0) gemm_launch_f64(entry_view(st.inblk, st.inblk_of[k], 0), false, true, -1.0, 1.0, s);
+    if ((k + 1) % DOB == 0 || k + 1 == st.npanel) {
+      const int q = k / DOB;
+      if (st.trest_of[q] >= 0) {
+        HSS_HIP(hipEventRecord(st.ev_block, s));
+        HSS_HIP(hipStreamWaitEvent(a, st.ev_block, 0));
+      }
+      if (rest_pending) {  // the previous rest update wrote this update's columns too
+        HSS_HIP(hipStreamWaitEvent(s, st.ev_rest, 0));
+        rest_pending = false;
+      }
+      if (st.tnext_of[q] >= 0) gemm_launch_f64(entry_view(st.tnext, st.tnext_of[q], 0), false, true, -1.0, 1.0, s);
+      if (st.trest_of[q] >= 0) {
+        gemm_launch_f64(entry_view(st.trest, st.trest_of[q], 6), false, true, -1.0, 1.0, a);
+        HSS_HIP(hipEventRecord(st.ev_rest, a));
+        rest_pending = true;
+      }
+    }
   }
+  if (rest_pending) HSS_HIP(hipStreamWaitEvent(s, st.ev_rest, 0));
   hipLaunchKernelGGL(k_blr2_logdet, dim3(1), dim3(256), 0, s, (const double*)m->dlogdet, m->nnodes,
                      (const double*)st.dpanel, st.npanel, st.dlog);
   HSS_HIP(hipGetLastError());
