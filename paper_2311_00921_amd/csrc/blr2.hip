@@ -201,24 +201,34 @@ __global__ __launch_bounds__(256) void k_dtrsm_rows(double* __restrict__ A, int6
 }
 
 // Forward solve with the skeleton factor, panel k: y_k = Linv_k z_k (every
-// workgroup forms it; workgroup 0 stores it in Y), then z_i -= L(i, panel) y_k
-// for the rows below the panel, one row per thread.
+// workgroup forms it from an LDS copy of Linv_k; workgroup 0 stores it in Y),
+// then z_i -= L(i, panel) y_k for the 64 rows of the workgroup below the panel:
+// thread (row r, group g) accumulates the 4 right-hand sides 4g .. 4g + 3.
 __global__ __launch_bounds__(256) void k_dtrsv_fwd(const double* __restrict__ A, int64_t lda, int64_t K, int64_t k0,
                                                    int jb, const double* __restrict__ Linv, double* __restrict__ Z,
                                                    double* __restrict__ Y, int nc) {
+  constexpr int CG = kSolveCols / 4;
+  static_assert(CG * 64 == 256, "four column groups of four right-hand sides");
+  __shared__ double lq[DNB][DNB + 1];  // lq[q][i] = Linv(i, q)
   __shared__ double zk[DNB][kSolveCols];
   __shared__ double yk[DNB][kSolveCols];
-  const int t = threadIdx.x;
+  const int t = threadIdx.x, r = t & 63, g = t >> 6;
+  for (int e = t; e < DNB * DNB; e += 256) lq[e / DNB][e % DNB] = Linv[e];
   for (int e = t; e < DNB * kSolveCols; e += 256) {
     const int i = e % DNB, c = e / DNB;
     zk[i][c] = (i < jb && c < nc) ? Z[k0 + i + c * K] : 0.0;
   }
   __syncthreads();
-  for (int e = t; e < DNB * kSolveCols; e += 256) {
-    const int i = e % DNB, c = e / DNB;
-    double s = 0.0;
-    for (int q = 0; q <= i; ++q) s += Linv[i + q * DNB] * zk[q][c];
-    yk[i][c] = s;
+  {
+    double y[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 16
+    for (int q = 0; q < DNB; ++q) {  // Linv is zero above its diagonal and past jb
+      const double l = lq[q][r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) y[c] += l * zk[q][4 * g + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) yk[r][4 * g + c] = y[c];
   }
   __syncthreads();
   if (blockIdx.x == 0)
@@ -226,40 +236,50 @@ __global__ __launch_bounds__(256) void k_dtrsv_fwd(const double* __restrict__ A,
       const int i = e % DNB, c = e / DNB;
       if (i < jb && c < nc) Y[k0 + i + c * K] = yk[i][c];
     }
-  const int64_t row = k0 + jb + (int64_t)blockIdx.x * 256 + t;
+  const int64_t row = k0 + jb + (int64_t)blockIdx.x * 64 + r;
   if (row >= K) return;
-  double acc[kSolveCols];
-#pragma unroll
-  for (int c = 0; c < kSolveCols; ++c) acc[c] = 0.0;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
   const double* L = A + row + k0 * lda;
-  for (int q = 0; q < jb; ++q) {
-    const double l = L[q * lda];
+#pragma unroll 16
+  for (int q = 0; q < DNB; ++q) {
+    const double l = q < jb ? L[q * lda] : 0.0;
 #pragma unroll
-    for (int c = 0; c < kSolveCols; ++c) acc[c] += l * yk[q][c];
+    for (int c = 0; c < 4; ++c) acc[c] += l * yk[q][4 * g + c];
   }
-  for (int c = 0; c < nc; ++c) Z[row + c * K] -= acc[c];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+    if (4 * g + c < nc) Z[row + (4 * g + c) * K] -= acc[c];
 }
 
 // Backward solve with the skeleton factor, panel k: w_k = Linv_k^T y_k (every
-// workgroup forms it; workgroup 0 stores it in W), then y_j -= L(panel, j)^T w_k
-// for the rows j < k0, one column of L per 16-lane group (each group's loads
-// are one 128-byte line).
+// workgroup forms it from an LDS copy of Linv_k; workgroup 0 stores it in W),
+// then y_j -= L(panel, j)^T w_k for the 64 rows j < k0 of the workgroup, one
+// column of L per 4-lane group (lane s reads the panel rows s, s + 4, ...).
 __global__ __launch_bounds__(256) void k_dtrsv_bwd(const double* __restrict__ A, int64_t lda, int64_t K, int64_t k0,
                                                    int jb, const double* __restrict__ Linv, double* __restrict__ Y,
                                                    double* __restrict__ W, int nc) {
+  static_assert(kSolveCols == 16, "four lanes of four right-hand sides per column of L");
+  __shared__ double lt[DNB][DNB + 1];  // lt[q][i] = Linv(q, i)
   __shared__ double yk[DNB][kSolveCols];
-  __shared__ double wk[DNB][kSolveCols];
+  __shared__ double wk[DNB][kSolveCols + 1];
   const int t = threadIdx.x;
+  for (int e = t; e < DNB * DNB; e += 256) lt[e % DNB][e / DNB] = Linv[e];
   for (int e = t; e < DNB * kSolveCols; e += 256) {
     const int i = e % DNB, c = e / DNB;
     yk[i][c] = (i < jb && c < nc) ? Y[k0 + i + c * K] : 0.0;
   }
   __syncthreads();
-  for (int e = t; e < DNB * kSolveCols; e += 256) {
-    const int i = e % DNB, c = e / DNB;
-    double s = 0.0;
-    for (int q = i; q < jb; ++q) s += Linv[q + i * DNB] * yk[q][c];
-    wk[i][c] = s;
+  {
+    const int r = t & 63, g = t >> 6;
+    double w[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 16
+    for (int q = 0; q < DNB; ++q) {  // Linv is zero above its diagonal and past jb
+      const double l = lt[q][r];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) w[c] += l * yk[q][4 * g + c];
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) wk[r][4 * g + c] = w[c];
   }
   __syncthreads();
   if (blockIdx.x == 0)
@@ -267,24 +287,32 @@ __global__ __launch_bounds__(256) void k_dtrsv_bwd(const double* __restrict__ A,
       const int i = e % DNB, c = e / DNB;
       if (i < jb && c < nc) W[k0 + i + c * K] = wk[i][c];
     }
-  const int lane16 = t & 15;
-  const int64_t j = (int64_t)blockIdx.x * 16 + (t >> 4);
+  const int sub = t & 3;
+  const int64_t j = (int64_t)blockIdx.x * 64 + (t >> 2);
   if (j >= k0) return;
   double acc[kSolveCols];
 #pragma unroll
   for (int c = 0; c < kSolveCols; ++c) acc[c] = 0.0;
   const double* L = A + k0 + j * lda;
-  for (int q = lane16; q < jb; q += 16) {
-    const double l = L[q];
+#pragma unroll
+  for (int u = 0; u < DNB / 4; ++u) {
+    const int q = sub + 4 * u;
+    const double l = q < jb ? L[q] : 0.0;
 #pragma unroll
     for (int c = 0; c < kSolveCols; ++c) acc[c] += l * wk[q][c];
   }
 #pragma unroll
-  for (int c = 0; c < kSolveCols; ++c)
+  for (int c = 0; c < kSolveCols; ++c) {
+    acc[c] += __shfl_xor(acc[c], 1, 4);
+    acc[c] += __shfl_xor(acc[c], 2, 4);
+  }
+  // lane s of the group stores right-hand sides 4 s .. 4 s + 3
 #pragma unroll
-    for (int o = 8; o > 0; o >>= 1) acc[c] += __shfl_xor(acc[c], o, 16);
-  if (lane16 == 0)
-    for (int c = 0; c < nc; ++c) Y[j + c * K] -= acc[c];
+  for (int cc = 0; cc < 4; ++cc) {
+    const double v = sub == 0 ? acc[cc] : sub == 1 ? acc[4 + cc] : sub == 2 ? acc[8 + cc] : acc[12 + cc];
+    const int c = 4 * sub + cc;
+    if (c < nc) Y[j + c * K] -= v;
+  }
 }
 
 // Skeleton vector <-> the per-node vector slots of the leaves' parents (the
@@ -615,7 +643,7 @@ void factor_blr2(hss_matrix_t m) {
       }
       if (st.tnext_of[q] >= 0) gemm_launch_f64(entry_view(st.tnext, st.tnext_of[q], 0), false, true, -1.0, 1.0, s);
       if (st.trest_of[q] >= 0) {
-        gemm_launch_f64(entry_view(st.trest, st.trest_of[q], 6), false, true, -1.0, 1.0, a);
+        gemm_launch_f64(entry_view(st.trest, st.trest_of[q], 7), false, true, -1.0, 1.0, a);
         HSS_HIP(hipEventRecord(st.ev_rest, a));
         rest_pending = true;
       }
@@ -664,7 +692,7 @@ void solve_blr2(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_
       const int64_t k0 = (int64_t)k * DNB;
       const int jb = (int)std::min<int64_t>(DNB, K - k0);
       const int64_t rem = K - k0 - jb;
-      const unsigned g = (unsigned)std::max<int64_t>(1, (rem + 255) / 256);
+      const unsigned g = (unsigned)std::max<int64_t>(1, (rem + 63) / 64);
       hipLaunchKernelGGL(k_dtrsv_fwd, dim3(g), dim3(256), 0, s, (const double*)st.dK, K, K, k0, jb,
                          (const double*)(st.dLinv + (int64_t)k * DNB * DNB), st.dZ, st.dY, nc);
       HSS_HIP(hipGetLastError());
@@ -672,7 +700,7 @@ void solve_blr2(hss_matrix_t m, const double* b, double* x, int64_t nrhs, int64_
     for (int k = st.npanel - 1; k >= 0; --k) {
       const int64_t k0 = (int64_t)k * DNB;
       const int jb = (int)std::min<int64_t>(DNB, K - k0);
-      const unsigned g = (unsigned)std::max<int64_t>(1, (k0 + 15) / 16);
+      const unsigned g = (unsigned)std::max<int64_t>(1, (k0 + 63) / 64);
       hipLaunchKernelGGL(k_dtrsv_bwd, dim3(g), dim3(256), 0, s, (const double*)st.dK, K, K, k0, jb,
                          (const double*)(st.dLinv + (int64_t)k * DNB * DNB), st.dY, st.dW, nc);
       HSS_HIP(hipGetLastError());
