@@ -82,6 +82,8 @@ def test_exp2d_n2048_plain(ctx, torch_dev):
     (3, 24, 7, 1),      # K = 56: one partial panel
     (5, 32, 13, 3),     # K = 416: ragged last panel
     (4, 64, 40, 17),    # K = 640, 17 right-hand sides: two skeleton-solve passes, a ragged leaf pass
+    (5, 64, 37, 5),     # K = 1184: four-panel outer blocks whose trailing update is split between
+                        # the next block and the rest (three rests), a partial last block and panel
     (2, 256, 96, 2),    # the benchmark's leaf shape (m = 160)
     (2, 512, 200, 1),   # rank above 128
     (1, 40, 40, 2),     # uncompressed leaves (m = 0): the skeleton matrix is the whole matrix
