@@ -137,10 +137,10 @@ void assign_offsets(hss_matrix_t m) {
     oF += (int64_t)d.n * d.n;
     d.offM = leaf ? -1 : oM;
     if (!leaf) oM += (int64_t)d.n * d.n;
-    // V sits in the middle of an n x 3r slot: [Z V Z] lets the two-sided update
-    // read [Z V] and [V Z] as contiguous n x 2r operands
+    // V sits at the right of an n x 2r slot: the two-sided update reads [Z V] as
+    // one n x 2r operand (and [V Z] as the same operand with its columns rotated)
     d.offV = oV + (int64_t)d.n * d.r;
-    oV += 3 * (int64_t)d.n * d.r;
+    oV += 2 * (int64_t)d.n * d.r;
     d.offT = oT;
     oT += (int64_t)d.r * d.r;
     d.offSg = oSg;

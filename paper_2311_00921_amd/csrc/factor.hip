@@ -1638,8 +1638,7 @@ static std::vector<std::vector<GemmBatch>> build_gemm_plan(hss_matrix_t m, const
       const int n = nd.n, r = nd.r;
       const T* Mp = lp.leaf ? b.D + nd.offD : b.M + nd.offM;
       T* V = b.V + nd.offV;
-      T* Zl = V - (int64_t)n * r;  // Z copy left of V
-      T* Zr = V + (int64_t)n * r;  // Z copy right of V
+      T* Zl = V - (int64_t)n * r;  // Z, left of V: [Z V] is one n x 2r operand
       T* Tm = b.Tm + nd.offT;
       T* Y = b.W + nd.offW;
       T* W = Y + (int64_t)n * r;
@@ -1652,9 +1651,10 @@ static std::vector<std::vector<GemmBatch>> build_gemm_plan(hss_matrix_t m, const
       steps[2].host.push_back({V, Tm, nullptr, Y, n, r, r, n, r, 0, n, 0, 0});            // Y = V T
       steps[3].host.push_back({Mp, Y, nullptr, W, n, r, n, n, n, 0, n, 0, 0});            // W = M Y
       steps[4].host.push_back({Y, W, nullptr, X1, r, r, n, n, n, 0, r, 0, 0});            // C = Y^T W
-      steps[5].host.push_back({V, X1, W, Zl, n, r, r, n, r, n, n, 0, 0, Zr});             // Z = W - V C / 2
-      // F = P^T (M - [Z V][V Z]^T) P, lower triangle only (nothing reads F above its diagonal)
-      steps[6].host.push_back({Zl, V, Mp, F, n, n, 2 * r, n, n, n, n, r, 0, nullptr, 1});
+      steps[5].host.push_back({V, X1, W, Zl, n, r, r, n, r, n, n, 0, 0});                 // Z = W - V C / 2
+      // F = P^T (M - [Z V][V Z]^T) P, lower triangle only (nothing reads F above its
+      // diagonal); [V Z] is [Z V] with its k index rotated by r
+      steps[6].host.push_back({Zl, Zl, Mp, F, n, n, 2 * r, n, n, n, n, r, 0, nullptr, 1, r});
       if (lp.inv) {
         const int mm = nd.m;
         T* Li = b.Li + m->offLi[p];
@@ -2214,7 +2214,7 @@ static void factor_stages(hss_matrix_t m, const FBufs<T>& b, std::vector<std::ve
     }
     {
       Prof pf(cx, "gemm_Z", l);
-      gemm_run<T>(st[5], false, false, -0.5, 1.0, s);     // Z = W - V C / 2 (both copies)
+      gemm_run<T>(st[5], false, false, -0.5, 1.0, s);     // Z = W - V C / 2
     }
     {
       Prof pf(cx, "gemm_F_update", l);

@@ -214,6 +214,15 @@ __global__ __launch_bounds__(256, kMinWaves<BM * BN>) void k_gemm(const GemmDesc
       for (int v = 0; v < 4; ++v) acc[i][j][v] = 0;
   T ra[QA], rb[QB];
   auto load = [&](int k0) {
+    if (d.kswap > 0) {
+      // rotated k index of op(B): the addresses are formed per slice
+#pragma unroll
+      for (int q = 0; q < QB; ++q) {
+        int kr = k0 + bk[q] + d.kswap;
+        if (kr >= d.k) kr -= d.k;
+        pb[q] = TB ? B + (col0 + bc[q]) + (int64_t)kr * d.ldb : B + kr + (int64_t)(col0 + bc[q]) * d.ldb;
+      }
+    }
     if (interior) {
 #pragma unroll
       for (int q = 0; q < QA; ++q) {

@@ -104,6 +104,7 @@ struct GemmDesc {
   int32_t perm_in; // 1: Cin is read at the permuted position too (in-place update)
   void* C2;        // optional second output (same values, same layout as C)
   int32_t lower_only;  // 1: square output; skip tiles lying entirely above the diagonal after the permutation
+  int32_t kswap;       // > 0: op(B)'s k index is rotated, k -> (k + kswap) mod k (B = [X Y] read as [Y X])
 };
 
 constexpr int kGemmVariants = 8;  // compiled tile shapes of the batched GEMM
