@@ -97,75 +97,117 @@ __device__ __forceinline__ double lane_value(double v, int l) {
 }
 
 // Cholesky of the diagonal block (k0, k0) of order jb <= 64, then its inverse,
-// by one wave: lane i holds row i of the block in registers (rows and columns
-// past jb are padded with the identity, so every step runs unmasked).
-//   Factor, right-looking: at step j the pivot comes from lane j, column j is
-//   scaled, and each later column c takes L(c, j) from lane c; the 63 - j
-//   updates of a step are independent.
-//   Inverse X = L^{-1} from X L = I, row i of X on lane i, columns from the
-//   last down: X(i, c) = acc_c / L(c, c), then acc_q -= X(i, c) L(c, q) for
-//   q < c, row c of L read from LDS (one broadcast address per step).
+// by one workgroup of four waves, the block in LDS (rows and columns past jb
+// padded with the identity, so every step runs unmasked).
+//   Factor, blocked by 16 columns: wave 0 factors a panel with lane i holding
+//   row i's 16 panel entries in registers (the pivot from lane j, each later
+//   panel column c taking L(c, j) from lane c), then the four waves update the
+//   lower triangle right of the panel from LDS. A step of the serial chain
+//   touches at most 16 columns.
+//   Inverse X = L^{-1} by columns, forward substitution L x = e_j with four
+//   threads per column (thread part p sums the terms q = p, p + 4, ...; two
+//   shuffles complete each sum); L and X are read from LDS, and x_i is written
+//   there by the thread of part i mod 4 (the four threads of a column share a
+//   wave, whose LDS accesses stay in order).
 // Writes L back (lower triangle), L^{-1} into Linv (64 x 64, zero above the
 // diagonal and past jb), the sum of log pivots into *pld. A non-positive pivot
 // is recorded (the first failing row over all panels) and replaced by 1.
-__global__ __launch_bounds__(64) void k_dchol_diag(double* __restrict__ A, int64_t lda, int64_t k0, int jb,
-                                                   double* __restrict__ Linv, double* __restrict__ pld,
-                                                   int32_t* __restrict__ info) {
-  __shared__ double Ls[DNB][DNB + 1];  // Ls[row][col] = L(row, col), col <= row
-  const int i = threadIdx.x;
+__global__ __launch_bounds__(256) void k_dchol_diag(double* __restrict__ A, int64_t lda, int64_t k0, int jb,
+                                                    double* __restrict__ Linv, double* __restrict__ pld,
+                                                    int32_t* __restrict__ info) {
+  constexpr int PW = 16;               // panel width
+  __shared__ double Ls[DNB][DNB + 1];  // Ls[row][col]: the block, then L (zero above the diagonal)
+  __shared__ double Xs[DNB][DNB + 1];  // Xs[row][col] = Linv(row, col)
+  __shared__ double rdg[DNB];          // 1 / L(i, i)
+  const int t = threadIdx.x, lane = t & 63, wv = t >> 6;
   double* Ab = A + k0 + k0 * lda;
-  // staged through LDS: 64 loads in flight would hold 64 addresses besides the row
-#pragma unroll 8
-  for (int c = 0; c < DNB; ++c)
-    Ls[i][c] = (i < jb && c < jb && i >= c) ? Ab[i + c * lda] : (i == c ? 1.0 : 0.0);
-  __syncthreads();
-  double a[DNB];
+  {
+    double v[DNB / 4];
 #pragma unroll
-  for (int c = 0; c < DNB; ++c) a[c] = Ls[i][c];
-  __syncthreads();
-  int bad = -1;
-  double mine = 1.0, rmine = 1.0;
-#pragma unroll
-  for (int j = 0; j < DNB; ++j) {
-    double d = lane_value(a[j], j);
-    if (!(d > 0.0)) {
-      if (bad < 0) bad = j;
-      d = 1.0;
+    for (int u = 0; u < DNB / 4; ++u) {
+      const int c = wv + 4 * u;
+      v[u] = (lane < jb && c < jb && lane >= c) ? Ab[lane + c * lda] : (lane == c ? 1.0 : 0.0);
     }
-    const double piv = sqrt(d);
-    const double rs = 1.0 / piv;
-    const bool me = i == j;
-    a[j] = me ? piv : a[j] * rs;
-    mine = me ? piv : mine;
-    rmine = me ? rs : rmine;
 #pragma unroll
-    for (int c = j + 1; c < DNB; ++c) a[c] -= a[j] * lane_value(a[j], c);
+    for (int u = 0; u < DNB / 4; ++u) {
+      Ls[lane][wv + 4 * u] = v[u];
+      Xs[lane][wv + 4 * u] = 0.0;
+    }
   }
-  if (bad >= 0 && i == 0) {
-    atomicMin(&info[1], (int32_t)(k0 + bad));
-    atomicExch(&info[0], 1);
-  }
+  __syncthreads();
+  int bad = -1;       // wave 0
+  double mine = 1.0;  // wave 0: lane i's pivot
+#pragma unroll 1
+  for (int j0 = 0; j0 < DNB; j0 += PW) {
+    if (wv == 0) {
+      const int i = lane;
+      double a[PW];
 #pragma unroll
-  for (int c = 0; c < DNB; ++c) {
-    const double v = c <= i ? a[c] : 0.0;
-    Ls[i][c] = v;
-    if (i < jb && c < jb && c <= i) Ab[i + c * lda] = v;
-  }
-  double lg = i < jb ? log(mine) : 0.0;
+      for (int c = 0; c < PW; ++c) a[c] = Ls[i][j0 + c];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) lg += __shfl_xor(lg, o, 64);
-  if (i == 0) *pld = 2.0 * lg;
+      for (int k = 0; k < PW; ++k) {
+        double d = lane_value(a[k], j0 + k);
+        if (!(d > 0.0)) {
+          if (bad < 0) bad = j0 + k;
+          d = 1.0;
+        }
+        const double piv = sqrt(d);
+        const double rs = 1.0 / piv;
+        const bool me = i == j0 + k;
+        a[k] = me ? piv : a[k] * rs;
+        mine = me ? piv : mine;
+        if (me) rdg[i] = rs;
+#pragma unroll
+        for (int c = k + 1; c < PW; ++c) a[c] -= a[k] * lane_value(a[k], j0 + c);
+      }
+      if (i >= j0)
+#pragma unroll
+        for (int c = 0; c < PW; ++c) Ls[i][j0 + c] = (j0 + c <= i) ? a[c] : 0.0;
+    }
+    __syncthreads();
+    // lower triangle right of the panel: Ls[r][c] -= sum_k L(r, j0 + k) L(c, j0 + k)
+    const int n2 = DNB - j0 - PW;
+    for (int e = t; e < n2 * n2; e += 256) {
+      const int rr = j0 + PW + e % n2, cc = j0 + PW + e / n2;
+      if (rr >= cc) {
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < PW; ++k) sum += Ls[rr][j0 + k] * Ls[cc][j0 + k];
+        Ls[rr][cc] -= sum;
+      }
+    }
+    __syncthreads();
+  }
+  if (wv == 0) {
+    if (bad >= 0 && lane == 0) {
+      atomicMin(&info[1], (int32_t)(k0 + bad));
+      atomicExch(&info[0], 1);
+    }
+    double lg = lane < jb ? log(mine) : 0.0;
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) lg += __shfl_xor(lg, o, 64);
+    if (lane == 0) *pld = 2.0 * lg;
+  }
+  {
+    const int j = t >> 2, p = t & 3;
+#pragma unroll 1
+    for (int i = j; i < DNB; ++i) {  // x_i = 0 above the diagonal (Xs starts at zero)
+      double sum = 0.0;
+#pragma unroll
+      for (int u = 0; u < DNB / 4; ++u) sum += Ls[i][p + 4 * u] * Xs[p + 4 * u][j];  // L(i, q) = 0 for q >= i
+      sum += __shfl_xor(sum, 1, 4);
+      sum += __shfl_xor(sum, 2, 4);
+      if ((i & 3) == p) Xs[i][j] = ((i == j ? 1.0 : 0.0) - sum) * rdg[i];
+      __builtin_amdgcn_wave_barrier();  // the column's other threads read x_i at the next step
+    }
+  }
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < DNB; ++c) a[c] = (c == i) ? 1.0 : 0.0;
-#pragma unroll
-  for (int c = DNB - 1; c >= 0; --c) {
-    a[c] *= lane_value(rmine, c);
-#pragma unroll
-    for (int q = 0; q < c; ++q) a[q] -= a[c] * Ls[c][q];
+  for (int u = 0; u < DNB / 4; ++u) {
+    const int c = wv + 4 * u;
+    if (lane < jb && c < jb && c <= lane) Ab[lane + c * lda] = Ls[lane][c];
+    Linv[lane + c * DNB] = (lane < jb && c < jb) ? Xs[lane][c] : 0.0;
   }
-#pragma unroll
-  for (int c = 0; c < DNB; ++c) Linv[i + c * DNB] = (i < jb && c < jb) ? a[c] : 0.0;
 }
 
 // The panel below the diagonal block: rows k0 + jb + 64 b .. of columns
@@ -624,7 +666,7 @@ void factor_blr2(hss_matrix_t m) {
     const int64_t rem = K - k0 - jb;
     double* Li = st.dLinv + (int64_t)k * DNB * DNB;
     Prof pf(cx, "blr2_cholesky", -1);
-    hipLaunchKernelGGL(k_dchol_diag, dim3(1), dim3(64), 0, s, st.dK, K, k0, jb, Li, st.dpanel + k, st.dinfo);
+    hipLaunchKernelGGL(k_dchol_diag, dim3(1), dim3(256), 0, s, st.dK, K, k0, jb, Li, st.dpanel + k, st.dinfo);
     HSS_HIP(hipGetLastError());
     if (rem <= 0) continue;
     hipLaunchKernelGGL(k_dtrsm_rows, dim3((unsigned)((rem + DNB - 1) / DNB)), dim3(256), 0, s, st.dK, K, K, k0, jb,
